@@ -1,0 +1,222 @@
+/*
+ * mlblup.h -- C ABI of the multilevel spatial BLUP solve on AMD MI355X (gfx950).
+ *
+ * Method: J. E. Castrillon-Candas, "Spatial best linear unbiased prediction:
+ * a computational mathematics approach for high dimensional massive
+ * datasets", arXiv:1701.00285.  Observations Z = X beta + eps at N sites in
+ * d dimensions, eps ~ N(0, C(theta)) with a Matern covariance C, X the
+ * total-degree monomial design (Sec. 1).  A kd-tree (Sec. 2.1, algorithms
+ * Rule / InitialTree / MakeTree) and a multilevel basis W orthogonal to
+ * col(X) (Sec. 2.1 construction) turn the kriging system into the
+ * well-conditioned C_W gamma_W = W Z with C_W = W C W^T (Sec. 5,
+ * eqs. Spatial:eqn1-3), solved by a Krylov (PCG) iteration whose product is
+ * the three-step W^T -> C -> W chain (Sec. 4.2).
+ *
+ * Conventions for every entry point:
+ *   - Return value is a status code (MLBLUP_OK = 0, negative on error); the
+ *     message of the last error on the calling thread is mlblup_last_error().
+ *   - "_host" pointers are host memory, "_dev" pointers are device memory of
+ *     the current HIP device.  The caller owns every data buffer; the library
+ *     never allocates device memory.  Sizes of the scratch it needs are
+ *     reported by the *_workspace_bytes queries; the caller passes a device
+ *     workspace of at least that size (256-byte aligned).
+ *   - Device vectors of length N are in TREE ORDER (position k holds the
+ *     point mlblup_tree_perm()[k] of the input).  Coordinates are row-major
+ *     (point-major) N x d float64 arrays.
+ *   - `stream` is a hipStream_t passed as void* (NULL = legacy default
+ *     stream).  Device work is enqueued on it; calls that return scalars to
+ *     the host (pcg_solve, blup_predict, blup_grad) synchronise it.
+ *   - Handles (tree, basis) are immutable after construction and may be
+ *     used from several streams at once; a workspace must not be shared by
+ *     calls in flight at the same time.
+ */
+#ifndef MLBLUP_H
+#define MLBLUP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MLBLUP_OK 0
+#define MLBLUP_EINVAL (-1)     /* bad argument: shape, NULL, nu not in {1/2,3/2,5/2}, NaN input, small workspace */
+#define MLBLUP_ERANK (-2)      /* design matrix rank < p on the point set (e.g. collinear points, duplicates) */
+#define MLBLUP_ENOCONV (-3)    /* iteration limit reached; outputs hold the last iterate, info is filled */
+#define MLBLUP_EBREAKDOWN (-4) /* Krylov breakdown: p.q <= 0 or a non-finite scalar */
+#define MLBLUP_EHIP (-5)       /* HIP runtime error; the message names the call and the HIP error */
+#define MLBLUP_ESTATE (-6)     /* handle not ready (e.g. basis used on device before mlblup_basis_upload) */
+
+/* Arithmetic of the pair kernel (the dense covariance product). */
+#define MLBLUP_FP64 0          /* FP64 differences, sqrt, exp, sums */
+#define MLBLUP_FP32 1          /* FP64 differences and squared distance, FP32 sqrt/exp/kernel value, FP64 sums */
+#define MLBLUP_MFMA_FP32 2     /* distance Gram on FP32 matrix cores (d >= 8 intended), exact near tiles */
+#define MLBLUP_MFMA_BF16X3 3   /* distance Gram on BF16 matrix cores with a hi/lo split (3 products) */
+
+/* Output selection bitmask of mlblup_cov_matvec. */
+#define MLBLUP_VALUE 1         /* y  = C x            */
+#define MLBLUP_DLOGRHO 2       /* dy = (rho dC/drho) x */
+
+typedef struct mlblup_tree_s* mlblup_tree;
+typedef struct mlblup_basis_s* mlblup_basis;
+
+/* Matern covariance sigma2 * phi(r; nu, rho), Definition in Sec. 2.1 with the
+ * half-integer closed forms (nu = 1/2, 3/2, 5/2), rho > 0, sigma2 > 0. */
+typedef struct {
+  double nu;
+  double rho;
+  double sigma2;
+} mlblup_matern;
+
+/* Krylov solve options.  rtol: stop when |Z_W - C_W gamma_W|_2 <= rtol |Z_W|_2
+ * on the UNPRECONDITIONED system, measured with the FP64 product (remark on
+ * the stopping rule, Sec. 4.2).  precision: arithmetic of the inner product
+ * (MLBLUP_FP64 runs plain PCG with a final FP64 residual check; lower
+ * precisions run an FP64 iterative-refinement loop around inner PCG
+ * solves).  refine_max: outer refinement steps.  inner_rtol: relative
+ * reduction asked of each inner solve (lower precisions).  jacobi_diag_dev:
+ * NULL for P_W = I, else diag(C_W) (N - p doubles) as in the preconditioner
+ * remark of Sec. 5.  */
+typedef struct {
+  double rtol;
+  int32_t max_iter;
+  int32_t precision;
+  int32_t refine_max;
+  int32_t reserved;
+  double inner_rtol;
+  const double* jacobi_diag_dev;
+} mlblup_pcg_opts;
+
+typedef struct {
+  int32_t inner_iters;    /* total Krylov iterations */
+  int32_t outer_iters;    /* refinement steps (1 for a plain FP64 solve) */
+  int32_t fp64_matvecs;   /* FP64 C_W products (iterations + residual checks) */
+  int32_t lowp_matvecs;   /* reduced-precision C_W products */
+  double relres_fp64;     /* final |Z_W - C_W gamma_W| / |Z_W| with the FP64 product */
+  double zw_norm;         /* |Z_W|_2 */
+} mlblup_pcg_info;
+
+const char* mlblup_last_error(void);
+int32_t mlblup_version(void);
+
+/* ---- kd-tree (Sec. 2.1, algorithms Rule / InitialTree / MakeTree) ----------
+ * Splits each cell on the coordinate axis of maximal variance of its points
+ * at the median: points ordered by (coordinate, input index), the first
+ * ceil(m/2) go left.  A cell with <= leaf_max points is a leaf.  Nodes are
+ * numbered in preorder (root 0).  Inside a leaf, points are listed by input
+ * index.  pts_host: n x d row-major float64 (copied).  n >= 1, 1 <= d <= 64,
+ * leaf_max >= 1.  Non-finite coordinates -> MLBLUP_EINVAL. */
+int mlblup_build_tree(const double* pts_host, int64_t n, int32_t d, int32_t leaf_max, mlblup_tree* out);
+int mlblup_tree_info(mlblup_tree t, int64_t* n, int32_t* d, int32_t* n_nodes, int32_t* max_depth);
+/* perm_host[k] = input index of the point at tree position k (n entries). */
+int mlblup_tree_perm(mlblup_tree t, int64_t* perm_host);
+/* Node arrays (n_nodes entries each; any pointer may be NULL): point range
+ * [begin, end) in tree order, depth, split axis (-1 for leaves), children
+ * (-1 for leaves), threshold (largest left coordinate; 0 for leaves). */
+int mlblup_tree_nodes(mlblup_tree t, int64_t* begin, int64_t* end, int32_t* depth, int32_t* axis,
+                      int32_t* left, int32_t* right, double* threshold);
+void mlblup_tree_free(mlblup_tree t);
+
+/* ---- multilevel basis (Sec. 2.1 construction; operators W, L, P) ---------
+ * Bottom-up over the tree: for each cell the candidate vectors (leaf: unit
+ * vectors of its points; internal: the children's scaling vectors) are
+ * split by an orthogonal V into a scaling part spanning the range of
+ * M^T (M = X^T V_cand, moments against the degree-w monomials, taken in
+ * cell-local centred and scaled coordinates -- same span, better
+ * conditioning) and wavelets spanning null(M).  Numerical rank: Householder
+ * QR with column pivoting of M^T, |R_kk| > rank_rtol |R_00| (rank_rtol <= 0
+ * selects 1e-10).  Coefficient layout of W v (N - p entries): level-major
+ * from the finest level t down to 0, preorder cells within a level, V's
+ * column order within a cell.  L v (p entries) are the root scaling
+ * coefficients.  The basis keeps a reference to nothing: the tree may be
+ * freed afterwards.  Root rank < p -> MLBLUP_ERANK; degree_w in [0, 16]. */
+int mlblup_build_multilevel_basis(mlblup_tree t, int32_t degree_w, double rank_rtol, mlblup_basis* out);
+/* p = binomial(d + w, w); levels = t + 1; device_bytes = size of the device
+ * image mlblup_basis_upload writes. */
+int mlblup_basis_info(mlblup_basis b, int32_t* p, int32_t* levels, int64_t* n_minus_p, int64_t* device_bytes);
+/* Number of wavelets at level q = 0..t (levels entries). */
+int mlblup_basis_level_counts(mlblup_basis b, int64_t* counts_host);
+/* Dense W ((N-p) x N) and L (p x N), row-major, columns in TREE order.  For
+ * tests on small N (N^2 doubles); either pointer may be NULL. */
+int mlblup_basis_dense(mlblup_basis b, double* W_host, double* L_host);
+/* Copies the basis device image (per-cell orthogonal blocks, the schedule,
+ * the points in tree order, trend data) into dev_buf (>= device_bytes,
+ * caller-owned, must outlive every device use of the basis).  Required once
+ * before any call below that takes a basis. */
+int mlblup_basis_upload(mlblup_basis b, void* dev_buf, int64_t bytes, void* stream);
+/* Device pointer of the tree-ordered points inside the uploaded image. */
+int mlblup_basis_points_dev(mlblup_basis b, const double** pts_dev);
+void mlblup_basis_free(mlblup_basis b);
+
+/* ---- dense covariance product (Sec. 4.2, step (2) of the chain) ----------
+ * y_i = sum_j sigma2 phi(|r_i - c_j|) x_j over all m x n pairs (rows_dev:
+ * m x d, cols_dev: n x d, row-major float64), and/or dy = (rho dC/drho) x.
+ * The same pointer for rows and cols is allowed (square product).  Sums
+ * are deterministic (fixed order, no atomics).  m = 0 or n = 0 gives y = 0.
+ * precision: one of MLBLUP_FP64 .. MLBLUP_MFMA_BF16X3.  work_dev: at least
+ * mlblup_cov_workspace_bytes(m, n, d, precision, outputs). */
+int mlblup_cov_workspace_bytes(int64_t m, int64_t n, int32_t d, int32_t precision, int32_t outputs, int64_t* bytes);
+int mlblup_cov_matvec(const mlblup_matern* k, const double* rows_dev, int64_t m, const double* cols_dev, int64_t n,
+                      int32_t d, int32_t precision, int32_t outputs, const double* x_dev, double* y_dev,
+                      double* dy_dev, void* work_dev, int64_t work_bytes, void* stream);
+
+/* ---- multilevel transform (operators W and W^T, Sec. 2.1 and Sec. 4.2) -----
+ * apply_W:  vw = W v (N - p), vl = L v (p; NULL to skip).
+ * apply_Wt: v = W^T vw + L^T vl (vl NULL = 0).
+ * work_dev: at least mlblup_transform_workspace_bytes(b). */
+int mlblup_transform_workspace_bytes(mlblup_basis b, int64_t* bytes);
+int mlblup_apply_W(mlblup_basis b, const double* v_dev, double* vw_dev, double* vl_dev, void* work_dev,
+                   int64_t work_bytes, void* stream);
+int mlblup_apply_Wt(mlblup_basis b, const double* vw_dev, const double* vl_dev, double* v_dev, void* work_dev,
+                    int64_t work_bytes, void* stream);
+
+/* ---- solve, predict, gradient (Sec. 4.2 predictor; Sec. 5 eqs. Spatial:eqn2-3)
+ * Workspace for every call below: mlblup_solve_workspace_bytes(b, opts,
+ * m_targets) (m_targets = largest target count used with it, 0 if none). */
+int mlblup_solve_workspace_bytes(mlblup_basis b, const mlblup_pcg_opts* opts, int64_t m_targets, int64_t* bytes);
+
+/* Solves C_W gamma_W = zw by PCG (initial guess: gw_dev on entry when
+ * use_x0 != 0, else 0).  An all-zero right-hand side returns gamma_W = 0.
+ * Returns MLBLUP_ENOCONV with the last iterate if rtol is not reached. */
+int mlblup_pcg_solve(mlblup_basis b, const mlblup_matern* k, const double* zw_dev, double* gw_dev, int32_t use_x0,
+                     const mlblup_pcg_opts* opts, void* work_dev, int64_t work_bytes, mlblup_pcg_info* info,
+                     void* stream);
+
+/* Full predictor: Z_W = W z, solve, gamma = W^T gamma_W, beta from the least
+ * squares of eq. Spatial:eqn3, Zhat(t) = k(t)^T beta + sum_j phi(|t - x_j|)
+ * gamma_j at m_t targets (tgt_dev: m_t x d row-major).  beta_host: p
+ * coefficients of the raw-coordinate monomials in graded lexicographic
+ * order (1, x1, .., xd, x1^2, x1 x2, ..).  gamma_dev (N, tree order) and
+ * gamma_w_dev (N - p) receive the solution; interp_res_host (may be NULL)
+ * receives |W (z - C gamma)|_2, which equals |Zhat(S) - z|_2.  The final
+ * products run in FP64 unless predict_precision says otherwise. */
+int mlblup_blup_predict(mlblup_basis b, const mlblup_matern* k, const double* z_dev, const double* tgt_dev,
+                        int64_t m_t, const mlblup_pcg_opts* opts, int32_t predict_precision, double* zhat_dev,
+                        double* beta_host, double* gamma_dev, double* gamma_w_dev, double* interp_res_host,
+                        void* work_dev, int64_t work_bytes, mlblup_pcg_info* info, void* stream);
+
+/* Quadratic form and its log-rho derivative (data term of the multilevel
+ * likelihood, Sec. 2): Q = z . gamma (= Z_W . gamma_W) and
+ * dQ/dlog rho = -lambda^T (rho dC/drho) gamma, lambda = gamma when
+ * lambda_dev is NULL (the adjoint of Q is gamma itself), else the W^T image
+ * of an adjoint solve.  One fused value/derivative pass over the pairs. */
+int mlblup_blup_grad(mlblup_basis b, const mlblup_matern* k, const double* z_dev, const double* gamma_dev,
+                     const double* lambda_dev, int32_t precision, double* Q_host, double* dQ_dlogrho_host,
+                     void* work_dev, int64_t work_bytes, void* stream);
+
+/* ---- instrumentation --------------------------------------------------------
+ * When enabled, each pair-kernel launch is bracketed by HIP events on its
+ * own stream.  mlblup_profile_read fills three arrays of MLBLUP_PROF_BUCKETS
+ * entries indexed by precision * 4 + outputs (precision MLBLUP_FP64 ..
+ * MLBLUP_MFMA_BF16X3, outputs 1..3): summed kernel time in ms, launch
+ * count, logical pair count since the last read, then resets them.  Any
+ * pointer may be NULL.  Event timestamps are read with
+ * hipEventSynchronize, so the streams used must be live. */
+#define MLBLUP_PROF_BUCKETS 16
+int mlblup_profile_enable(int32_t on);
+int mlblup_profile_read(double* pair_ms, int64_t* launches, double* pairs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLBLUP_H */

@@ -1,0 +1,731 @@
+// C ABI entry points and the host drivers of the solve (Sec. 4.2 predictor
+// iteration; Sec. 5 eqs. Spatial:eqn2-3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "internal.h"
+
+struct mlblup_tree_s {
+  mlb::Tree t;
+};
+struct mlblup_basis_s {
+  mlb::Basis b;
+};
+
+namespace mlb {
+
+namespace {
+thread_local std::string g_err;
+}
+
+int fail(int status, const std::string& msg) {
+  g_err = msg;
+  return status;
+}
+void clear_error() { g_err.clear(); }
+
+namespace {
+
+constexpr int64_t kAlign = 256;
+int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int nu2_of(const mlblup_matern* k) {
+  if (!k) return -1;
+  const double n2 = 2.0 * k->nu;
+  for (int c : {1, 3, 5})
+    if (std::fabs(n2 - c) < 1e-12) return c;
+  return -1;
+}
+
+int check_kernel(const mlblup_matern* k) {
+  if (!k) return fail(MLBLUP_EINVAL, "NULL covariance parameters");
+  if (nu2_of(k) < 0) return fail(MLBLUP_EINVAL, "nu must be 0.5, 1.5 or 2.5");
+  if (!(k->rho > 0) || !std::isfinite(k->rho)) return fail(MLBLUP_EINVAL, "rho must be finite and > 0");
+  if (!(k->sigma2 > 0) || !std::isfinite(k->sigma2)) return fail(MLBLUP_EINVAL, "sigma2 must be finite and > 0");
+  return MLBLUP_OK;
+}
+
+// Coefficients of x^g in prod_k (s x_k + b_k)^(a_k):  S[a][g] = prod_k C(a_k, g_k) s^g_k b_k^(a_k - g_k)
+std::vector<double> shift_matrix(const std::vector<std::vector<int32_t>>& E, double s, const std::vector<double>& b) {
+  const int p = (int)E.size(), d = (int)b.size();
+  auto binom = [](int n, int k) {
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+  };
+  std::vector<double> S((size_t)p * p, 0.0);
+  for (int a = 0; a < p; ++a)
+    for (int g = 0; g < p; ++g) {
+      double t = 1.0;
+      for (int k = 0; k < d; ++k) {
+        const int A = E[a][k], G = E[g][k];
+        if (G > A) {
+          t = 0.0;
+          break;
+        }
+        t *= binom(A, G) * std::pow(s, G) * std::pow(b[k], A - G);
+      }
+      S[(size_t)a * p + g] = t;
+    }
+  return S;
+}
+
+// Solve A x = y (p x p row-major) by Gaussian elimination with partial pivoting.
+bool dense_solve(std::vector<double> A, std::vector<double>& y, int p) {
+  for (int k = 0; k < p; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < p; ++i)
+      if (std::fabs(A[(size_t)i * p + k]) > std::fabs(A[(size_t)piv * p + k])) piv = i;
+    if (A[(size_t)piv * p + k] == 0.0) return false;
+    if (piv != k) {
+      for (int j = 0; j < p; ++j) std::swap(A[(size_t)k * p + j], A[(size_t)piv * p + j]);
+      std::swap(y[k], y[piv]);
+    }
+    for (int i = k + 1; i < p; ++i) {
+      const double f = A[(size_t)i * p + k] / A[(size_t)k * p + k];
+      for (int j = k; j < p; ++j) A[(size_t)i * p + j] -= f * A[(size_t)k * p + j];
+      y[i] -= f * y[k];
+    }
+  }
+  for (int k = p - 1; k >= 0; --k) {
+    double s = y[k];
+    for (int j = k + 1; j < p; ++j) s -= A[(size_t)k * p + j] * y[j];
+    y[k] = s / A[(size_t)k * p + k];
+  }
+  return true;
+}
+
+// Layout of the device image written by mlblup_basis_upload.
+void image_layout(Basis& B) {
+  const int64_t nn = (int64_t)B.desc.size();
+  const int64_t nv = (int64_t)B.V.size();
+  int64_t off = 0;
+  B.off_desc = off;
+  off = align_up(off + nn * (int64_t)sizeof(NodeDesc));
+  B.off_levels = off;
+  off = align_up(off + nn * (int64_t)sizeof(int32_t));
+  B.off_exps = off;
+  off = align_up(off + (int64_t)B.p * B.d * (int64_t)sizeof(int32_t) + B.d * (int64_t)sizeof(double));
+  B.off_V = off;
+  off = align_up(off + nv * (int64_t)sizeof(double));
+  B.off_Vt = off;
+  off = align_up(off + nv * (int64_t)sizeof(double));
+  B.off_pts = off;
+  off = align_up(off + B.n * B.d * (int64_t)sizeof(double));
+  B.dev_bytes = off;
+}
+
+// Workspace of the solve/predict/grad drivers.
+struct Ws {
+  int64_t r, p, q, z, dx, a, b, scal, part, sc, cov, zw, v, vw, lv, beta, gam, gamw, total;
+  int64_t cov_bytes;
+};
+
+Ws ws_layout(const Basis& B, int64_t mt) {
+  Ws w{};
+  const int64_t N = B.n, nw = B.n - B.p, D = sizeof(double);
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  w.r = take(nw * D);
+  w.p = take(nw * D);
+  w.q = take(nw * D);
+  w.z = take(nw * D);
+  w.dx = take(nw * D);
+  w.a = take(N * D);
+  w.b = take(N * D);
+  w.scal = take(std::max<int64_t>(B.scal_total, 1) * D);
+  w.part = take(2 * kRedBlocks * D);
+  w.sc = take(S_COUNT * D);
+  int64_t cb = 0;
+  for (int prec = MLBLUP_FP64; prec <= MLBLUP_MFMA_BF16X3; ++prec) {
+    cb = std::max(cb, pair_workspace_bytes(N, N, B.d, prec, 3));
+    if (mt > 0) cb = std::max(cb, pair_workspace_bytes(mt, N, B.d, prec, 3));
+  }
+  w.cov_bytes = std::max<int64_t>(cb, kAlign);
+  w.cov = take(w.cov_bytes);
+  w.zw = take(nw * D);
+  w.v = take(N * D);
+  w.vw = take(nw * D);
+  w.lv = take(B.p * D);
+  w.beta = take(B.p * D);
+  w.gam = take(N * D);
+  w.gamw = take(nw * D);
+  w.total = off;
+  return w;
+}
+
+struct Ctx {
+  const Basis& B;
+  hipStream_t s;
+  char* base;
+  Ws w;
+  TransformDev T;
+  const double* pts;
+  mlblup_matern k;
+  int nu2;
+  double sc_host[S_COUNT];
+
+  double* at(int64_t off) const { return (double*)(base + off); }
+
+  Ctx(const Basis& b, const mlblup_matern& km, void* work, const Ws& ws, hipStream_t st)
+      : B(b), s(st), base((char*)work), w(ws), k(km) {
+    const char* img = (const char*)B.dev_base;
+    T.desc = (const NodeDesc*)(img + B.off_desc);
+    T.level_nodes = (const int32_t*)(img + B.off_levels);
+    T.lvl_begin_host = B.lvl_begin.data();
+    T.levels = B.levels;
+    T.V = (const double*)(img + B.off_V);
+    T.Vt = (const double*)(img + B.off_Vt);
+    pts = (const double*)(img + B.off_pts);
+    nu2 = nu2_of(&km);
+  }
+
+  int pair(const double* rows, int64_t m, const double* x, double* y, double* dy, int prec, int outputs) {
+    PairArgs a{rows, m, pts, B.n, B.d, nu2, k.rho, k.sigma2, prec, outputs, x, y, dy};
+    return pair_launch(a, at(w.cov), w.cov_bytes, s);
+  }
+
+  // out = W C W^T in  (N - p vectors)
+  int matvec_cw(const double* in, double* out, int prec) {
+    int st = transform_synthesis(T, in, nullptr, at(w.a), at(w.scal), s);
+    if (st) return st;
+    st = pair(pts, B.n, at(w.a), at(w.b), nullptr, prec, MLBLUP_VALUE);
+    if (st) return st;
+    return transform_analysis(T, at(w.b), out, nullptr, at(w.scal), s);
+  }
+
+  int read_scalars() {
+    MLB_HIP(hipMemcpyAsync(sc_host, at(w.sc), sizeof(sc_host), hipMemcpyDeviceToHost, s));
+    MLB_HIP(hipStreamSynchronize(s));
+    return MLBLUP_OK;
+  }
+
+  // |a|_2 read back to the host
+  int norm(const double* a, int64_t n, double* out) {
+    int st = vec_dot(a, a, n, at(w.part), at(w.sc) + S_DOT, s);
+    if (st) return st;
+    st = read_scalars();
+    if (st) return st;
+    *out = std::sqrt(sc_host[S_DOT]);
+    return MLBLUP_OK;
+  }
+
+  int dot(const double* a, const double* b, int64_t n, double* out) {
+    int st = vec_dot(a, b, n, at(w.part), at(w.sc) + S_DOT, s);
+    if (st) return st;
+    st = read_scalars();
+    if (st) return st;
+    *out = sc_host[S_DOT];
+    return MLBLUP_OK;
+  }
+
+  // PCG on C_W x = zw with FP64 residual checks and (for reduced precision)
+  // iterative refinement.  Stopping rule on the unpreconditioned residual.
+  int solve(const double* zw, double* x, bool use_x0, const mlblup_pcg_opts& o, mlblup_pcg_info& info) {
+    const int64_t nw = B.n - B.p;
+    info = mlblup_pcg_info{};
+    double bnorm = 0.0;
+    int st = norm(zw, nw, &bnorm);
+    if (st) return st;
+    if (!std::isfinite(bnorm)) return fail(MLBLUP_EINVAL, "pcg_solve: non-finite right-hand side");
+    info.zw_norm = bnorm;
+    if (bnorm == 0.0) {
+      info.relres_fp64 = 0.0;
+      return vec_zero(x, nw, s);
+    }
+    if (!use_x0) {
+      st = vec_zero(x, nw, s);
+      if (st) return st;
+    }
+    const int prec = o.precision;
+    const double* diag = o.jacobi_diag_dev;
+    int iters_left = o.max_iter;
+    double* r = at(w.r);
+    double* p = at(w.p);
+    double* q = at(w.q);
+    double* z = at(w.z);
+    double* dx = at(w.dx);
+    for (int outer = 0;; ++outer) {
+      double rnorm;
+      if (outer == 0 && !use_x0) {
+        st = vec_copy(zw, r, nw, s);
+        if (st) return st;
+        rnorm = bnorm;
+      } else {
+        st = matvec_cw(x, q, MLBLUP_FP64);
+        if (st) return st;
+        info.fp64_matvecs++;
+        st = vec_sub_from(zw, q, nw, s);  // q = zw - C_W x
+        if (st) return st;
+        st = vec_copy(q, r, nw, s);
+        if (st) return st;
+        st = norm(r, nw, &rnorm);
+        if (st) return st;
+      }
+      const double relres = rnorm / bnorm;
+      info.relres_fp64 = relres;
+      if (!std::isfinite(relres)) return fail(MLBLUP_EBREAKDOWN, "pcg_solve: non-finite residual");
+      if (relres <= o.rtol) return MLBLUP_OK;
+      if (outer >= std::max(o.refine_max, 1) || iters_left <= 0)
+        return fail(MLBLUP_ENOCONV, "pcg_solve: tolerance not reached (relres " + std::to_string(relres) + ")");
+      info.outer_iters++;
+      // inner PCG on the correction, from 0
+      double target = 0.7 * o.rtol * bnorm / rnorm;
+      if (prec != MLBLUP_FP64) target = std::max(target, o.inner_rtol > 0 ? o.inner_rtol : 1e-5);
+      st = vec_zero(dx, nw, s);
+      if (st) return st;
+      const double* zz = r;
+      if (diag) {
+        st = vec_div(r, diag, z, nw, s);
+        if (st) return st;
+        zz = z;
+      }
+      st = vec_copy(zz, p, nw, s);
+      if (st) return st;
+      st = pcg_start(r, zz, nw, at(w.part), at(w.sc), s);
+      if (st) return st;
+      while (iters_left > 0) {
+        st = matvec_cw(p, q, prec);
+        if (st) return st;
+        if (prec == MLBLUP_FP64) info.fp64_matvecs++;
+        else info.lowp_matvecs++;
+        st = pcg_alpha(p, q, nw, at(w.part), at(w.sc), s);
+        if (st) return st;
+        st = pcg_update(dx, r, p, q, diag, z, nw, at(w.part), at(w.sc), s);
+        if (st) return st;
+        st = read_scalars();
+        if (st) return st;
+        --iters_left;
+        info.inner_iters++;
+        if (sc_host[S_FLAG] != 0.0) {
+          // fold what was gained so far into x, then report the breakdown
+          (void)vec_axpy(1.0, dx, x, nw, s);
+          return fail(MLBLUP_EBREAKDOWN, "pcg_solve: breakdown (p.q <= 0 or non-finite scalar)");
+        }
+        if (std::sqrt(sc_host[S_RR]) <= target * rnorm) break;
+        st = pcg_update_p(p, zz, nw, at(w.sc), s);
+        if (st) return st;
+      }
+      st = vec_axpy(1.0, dx, x, nw, s);
+      if (st) return st;
+    }
+  }
+};
+
+int check_basis_dev(const mlblup_basis b) {
+  if (!b) return fail(MLBLUP_EINVAL, "NULL basis");
+  if (!b->b.uploaded) return fail(MLBLUP_ESTATE, "basis not uploaded (call mlblup_basis_upload first)");
+  return MLBLUP_OK;
+}
+
+int check_ws(const mlblup_basis b, int64_t mt, void* work, int64_t bytes, Ws* out) {
+  *out = ws_layout(b->b, mt);
+  if (!work || bytes < out->total)
+    return fail(MLBLUP_EINVAL, "workspace too small (need " + std::to_string(out->total) + " bytes)");
+  if (((uintptr_t)work) % kAlign) return fail(MLBLUP_EINVAL, "workspace must be 256-byte aligned");
+  return MLBLUP_OK;
+}
+
+mlblup_pcg_opts default_opts() {
+  mlblup_pcg_opts o{};
+  o.rtol = 1e-8;
+  o.max_iter = 1000;
+  o.precision = MLBLUP_FP64;
+  o.refine_max = 8;
+  o.inner_rtol = 1e-5;
+  o.jacobi_diag_dev = nullptr;
+  return o;
+}
+
+}  // namespace
+}  // namespace mlb
+
+using namespace mlb;
+
+extern "C" {
+
+const char* mlblup_last_error(void) { return g_err.c_str(); }
+int32_t mlblup_version(void) { return 100; }
+
+int mlblup_build_tree(const double* pts_host, int64_t n, int32_t d, int32_t leaf_max, mlblup_tree* out) {
+  clear_error();
+  if (!out) return fail(MLBLUP_EINVAL, "build_tree: out is NULL");
+  *out = nullptr;
+  std::unique_ptr<mlblup_tree_s> t(new (std::nothrow) mlblup_tree_s);
+  if (!t) return fail(MLBLUP_EINVAL, "build_tree: out of host memory");
+  const int st = build_tree(pts_host, n, d, leaf_max, t->t);
+  if (st) return st;
+  *out = t.release();
+  return MLBLUP_OK;
+}
+
+int mlblup_tree_info(mlblup_tree t, int64_t* n, int32_t* d, int32_t* n_nodes, int32_t* max_depth) {
+  clear_error();
+  if (!t) return fail(MLBLUP_EINVAL, "NULL tree");
+  if (n) *n = t->t.n;
+  if (d) *d = t->t.d;
+  if (n_nodes) *n_nodes = t->t.n_nodes();
+  if (max_depth) *max_depth = t->t.max_depth;
+  return MLBLUP_OK;
+}
+
+int mlblup_tree_perm(mlblup_tree t, int64_t* perm_host) {
+  clear_error();
+  if (!t || !perm_host) return fail(MLBLUP_EINVAL, "NULL argument");
+  std::memcpy(perm_host, t->t.perm.data(), t->t.perm.size() * sizeof(int64_t));
+  return MLBLUP_OK;
+}
+
+int mlblup_tree_nodes(mlblup_tree t, int64_t* begin, int64_t* end, int32_t* depth, int32_t* axis, int32_t* left,
+                      int32_t* right, double* threshold) {
+  clear_error();
+  if (!t) return fail(MLBLUP_EINVAL, "NULL tree");
+  const Tree& T = t->t;
+  const size_t nn = T.begin.size();
+  if (begin) std::memcpy(begin, T.begin.data(), nn * sizeof(int64_t));
+  if (end) std::memcpy(end, T.end.data(), nn * sizeof(int64_t));
+  if (depth) std::memcpy(depth, T.depth.data(), nn * sizeof(int32_t));
+  if (axis) std::memcpy(axis, T.axis.data(), nn * sizeof(int32_t));
+  if (left) std::memcpy(left, T.left.data(), nn * sizeof(int32_t));
+  if (right) std::memcpy(right, T.right.data(), nn * sizeof(int32_t));
+  if (threshold) std::memcpy(threshold, T.threshold.data(), nn * sizeof(double));
+  return MLBLUP_OK;
+}
+
+void mlblup_tree_free(mlblup_tree t) { delete t; }
+
+int mlblup_build_multilevel_basis(mlblup_tree t, int32_t degree_w, double rank_rtol, mlblup_basis* out) {
+  clear_error();
+  if (!t || !out) return fail(MLBLUP_EINVAL, "NULL argument");
+  *out = nullptr;
+  std::unique_ptr<mlblup_basis_s> b(new (std::nothrow) mlblup_basis_s);
+  if (!b) return fail(MLBLUP_EINVAL, "out of host memory");
+  const int st = build_basis(t->t, degree_w, rank_rtol, b->b);
+  if (st) return st;
+  image_layout(b->b);
+  *out = b.release();
+  return MLBLUP_OK;
+}
+
+int mlblup_basis_info(mlblup_basis b, int32_t* p, int32_t* levels, int64_t* n_minus_p, int64_t* device_bytes) {
+  clear_error();
+  if (!b) return fail(MLBLUP_EINVAL, "NULL basis");
+  if (p) *p = b->b.p;
+  if (levels) *levels = b->b.levels;
+  if (n_minus_p) *n_minus_p = b->b.n - b->b.p;
+  if (device_bytes) *device_bytes = b->b.dev_bytes;
+  return MLBLUP_OK;
+}
+
+int mlblup_basis_level_counts(mlblup_basis b, int64_t* counts_host) {
+  clear_error();
+  if (!b || !counts_host) return fail(MLBLUP_EINVAL, "NULL argument");
+  std::memcpy(counts_host, b->b.level_counts.data(), b->b.level_counts.size() * sizeof(int64_t));
+  return MLBLUP_OK;
+}
+
+int mlblup_basis_dense(mlblup_basis bb, double* W_host, double* L_host) {
+  clear_error();
+  if (!bb) return fail(MLBLUP_EINVAL, "NULL basis");
+  const Basis& B = bb->b;
+  const int64_t N = B.n;
+  if (W_host) std::fill(W_host, W_host + (size_t)(N - B.p) * N, 0.0);
+  // Expand every cell's vectors bottom-up as dense columns over the cell's
+  // point range [begin, end): candidates times the cell's orthogonal block.
+  const int32_t nn = (int32_t)B.desc.size();
+  std::vector<std::vector<double>> scal(nn);  // (end-begin) x a, row-major
+  for (int q = B.levels - 1; q >= 0; --q)
+    for (int32_t s = B.lvl_begin[q]; s < B.lvl_begin[q + 1]; ++s) {
+      const int32_t v = B.level_nodes[s];
+      const NodeDesc& D = B.desc[v];
+      const int64_t lo = B.begin[v], len = B.end[v] - B.begin[v];
+      std::vector<double> cand((size_t)len * D.m, 0.0);
+      if (D.leaf) {
+        for (int i = 0; i < D.m; ++i) cand[(size_t)i * D.m + i] = 1.0;
+      } else {
+        int col = 0;
+        for (int32_t c : {B.left[v], B.right[v]}) {
+          const int ac = B.desc[c].a;
+          for (int64_t i = 0; i < B.end[c] - B.begin[c]; ++i)
+            for (int j = 0; j < ac; ++j)
+              cand[(size_t)(B.begin[c] - lo + i) * D.m + col + j] = scal[c][(size_t)i * ac + j];
+          col += ac;
+          std::vector<double>().swap(scal[c]);
+        }
+      }
+      const double* Vb = &B.V[D.v_off];
+      std::vector<double> out((size_t)len * D.m, 0.0);
+      for (int64_t i = 0; i < len; ++i)
+        for (int kk = 0; kk < D.m; ++kk) {
+          const double c = cand[(size_t)i * D.m + kk];
+          if (c == 0.0) continue;
+          for (int j = 0; j < D.m; ++j) out[(size_t)i * D.m + j] += c * Vb[(size_t)kk * D.m + j];
+        }
+      scal[v].assign((size_t)len * D.a, 0.0);
+      for (int64_t i = 0; i < len; ++i)
+        for (int j = 0; j < D.m; ++j) {
+          const double val = out[(size_t)i * D.m + j];
+          if (j < D.a) scal[v][(size_t)i * D.a + j] = val;
+          else if (W_host) W_host[(size_t)(D.w_off + j - D.a) * N + lo + i] = val;
+        }
+    }
+  if (L_host)
+    for (int j = 0; j < B.p; ++j)
+      for (int64_t i = 0; i < N; ++i) L_host[(size_t)j * N + i] = scal[0][(size_t)i * B.p + j];
+  return MLBLUP_OK;
+}
+
+int mlblup_basis_upload(mlblup_basis bb, void* dev_buf, int64_t bytes, void* stream) {
+  clear_error();
+  if (!bb || !dev_buf) return fail(MLBLUP_EINVAL, "NULL argument");
+  Basis& B = bb->b;
+  if (bytes < B.dev_bytes)
+    return fail(MLBLUP_EINVAL, "basis_upload: buffer too small (need " + std::to_string(B.dev_bytes) + ")");
+  if (((uintptr_t)dev_buf) % kAlign) return fail(MLBLUP_EINVAL, "basis_upload: buffer must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)dev_buf;
+  const int32_t nn = (int32_t)B.desc.size();
+  MLB_HIP(hipMemcpyAsync(base + B.off_desc, B.desc.data(), nn * sizeof(NodeDesc), hipMemcpyHostToDevice, s));
+  MLB_HIP(hipMemcpyAsync(base + B.off_levels, B.level_nodes.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  std::vector<int32_t> ex((size_t)B.p * B.d);
+  for (int b = 0; b < B.p; ++b)
+    for (int k = 0; k < B.d; ++k) ex[(size_t)b * B.d + k] = B.exps[b][k];
+  std::vector<double> vt(B.V.size());
+  for (const NodeDesc& D : B.desc)
+    for (int i = 0; i < D.m; ++i)
+      for (int j = 0; j < D.m; ++j) vt[D.v_off + (size_t)j * D.m + i] = B.V[D.v_off + (size_t)i * D.m + j];
+  MLB_HIP(hipMemcpyAsync(base + B.off_exps, ex.data(), ex.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  MLB_HIP(hipMemcpyAsync(base + B.off_exps + ex.size() * sizeof(int32_t), B.root_c.data(), B.d * sizeof(double),
+                         hipMemcpyHostToDevice, s));
+  MLB_HIP(hipMemcpyAsync(base + B.off_V, B.V.data(), B.V.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  MLB_HIP(hipMemcpyAsync(base + B.off_Vt, vt.data(), vt.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  MLB_HIP(hipMemcpyAsync(base + B.off_pts, B.pts_tree.data(), B.pts_tree.size() * sizeof(double),
+                         hipMemcpyHostToDevice, s));
+  MLB_HIP(hipStreamSynchronize(s));  // host staging buffers die here
+  B.dev_base = dev_buf;
+  B.uploaded = true;
+  return MLBLUP_OK;
+}
+
+int mlblup_basis_points_dev(mlblup_basis b, const double** pts_dev) {
+  clear_error();
+  const int st = check_basis_dev(b);
+  if (st) return st;
+  if (!pts_dev) return fail(MLBLUP_EINVAL, "NULL argument");
+  *pts_dev = (const double*)((const char*)b->b.dev_base + b->b.off_pts);
+  return MLBLUP_OK;
+}
+
+void mlblup_basis_free(mlblup_basis b) { delete b; }
+
+int mlblup_cov_workspace_bytes(int64_t m, int64_t n, int32_t d, int32_t precision, int32_t outputs, int64_t* bytes) {
+  clear_error();
+  if (!bytes || m < 0 || n < 0 || d < 1 || d > 64 || outputs < 1 || outputs > 3)
+    return fail(MLBLUP_EINVAL, "cov_workspace_bytes: bad argument");
+  *bytes = pair_workspace_bytes(m, n, d, precision, outputs);
+  return MLBLUP_OK;
+}
+
+int mlblup_cov_matvec(const mlblup_matern* k, const double* rows_dev, int64_t m, const double* cols_dev, int64_t n,
+                      int32_t d, int32_t precision, int32_t outputs, const double* x_dev, double* y_dev,
+                      double* dy_dev, void* work_dev, int64_t work_bytes, void* stream) {
+  clear_error();
+  int st = check_kernel(k);
+  if (st) return st;
+  PairArgs a{rows_dev, m, cols_dev, n, d, nu2_of(k), k->rho, k->sigma2, precision, outputs, x_dev, y_dev, dy_dev};
+  return pair_launch(a, work_dev, work_bytes, (hipStream_t)stream);
+}
+
+int mlblup_transform_workspace_bytes(mlblup_basis b, int64_t* bytes) {
+  clear_error();
+  if (!b || !bytes) return fail(MLBLUP_EINVAL, "NULL argument");
+  *bytes = align_up(std::max<int64_t>(b->b.scal_total, 1) * (int64_t)sizeof(double));
+  return MLBLUP_OK;
+}
+
+static int transform_common(mlblup_basis b, void* work, int64_t work_bytes, TransformDev* T) {
+  int st = check_basis_dev(b);
+  if (st) return st;
+  const Basis& B = b->b;
+  if (!work || work_bytes < std::max<int64_t>(B.scal_total, 1) * (int64_t)sizeof(double))
+    return fail(MLBLUP_EINVAL, "transform workspace too small");
+  const char* img = (const char*)B.dev_base;
+  T->desc = (const NodeDesc*)(img + B.off_desc);
+  T->level_nodes = (const int32_t*)(img + B.off_levels);
+  T->lvl_begin_host = B.lvl_begin.data();
+  T->levels = B.levels;
+  T->V = (const double*)(img + B.off_V);
+  T->Vt = (const double*)(img + B.off_Vt);
+  return MLBLUP_OK;
+}
+
+int mlblup_apply_W(mlblup_basis b, const double* v_dev, double* vw_dev, double* vl_dev, void* work_dev,
+                   int64_t work_bytes, void* stream) {
+  clear_error();
+  TransformDev T;
+  int st = transform_common(b, work_dev, work_bytes, &T);
+  if (st) return st;
+  if (!v_dev || !vw_dev) return fail(MLBLUP_EINVAL, "apply_W: NULL vector");
+  return transform_analysis(T, v_dev, vw_dev, vl_dev, (double*)work_dev, (hipStream_t)stream);
+}
+
+int mlblup_apply_Wt(mlblup_basis b, const double* vw_dev, const double* vl_dev, double* v_dev, void* work_dev,
+                    int64_t work_bytes, void* stream) {
+  clear_error();
+  TransformDev T;
+  int st = transform_common(b, work_dev, work_bytes, &T);
+  if (st) return st;
+  if (!v_dev || !vw_dev) return fail(MLBLUP_EINVAL, "apply_Wt: NULL vector");
+  return transform_synthesis(T, vw_dev, vl_dev, v_dev, (double*)work_dev, (hipStream_t)stream);
+}
+
+int mlblup_solve_workspace_bytes(mlblup_basis b, const mlblup_pcg_opts* opts, int64_t m_targets, int64_t* bytes) {
+  clear_error();
+  (void)opts;
+  if (!b || !bytes || m_targets < 0) return fail(MLBLUP_EINVAL, "bad argument");
+  *bytes = ws_layout(b->b, m_targets).total;
+  return MLBLUP_OK;
+}
+
+static int check_opts(const mlblup_pcg_opts* opts, mlblup_pcg_opts* o) {
+  *o = opts ? *opts : default_opts();
+  if (!(o->rtol > 0) || o->max_iter < 0 || o->precision < MLBLUP_FP64 || o->precision > MLBLUP_MFMA_BF16X3)
+    return fail(MLBLUP_EINVAL, "pcg options: need rtol > 0, max_iter >= 0, known precision");
+  if (o->refine_max <= 0) o->refine_max = 8;
+  return MLBLUP_OK;
+}
+
+int mlblup_pcg_solve(mlblup_basis b, const mlblup_matern* k, const double* zw_dev, double* gw_dev, int32_t use_x0,
+                     const mlblup_pcg_opts* opts, void* work_dev, int64_t work_bytes, mlblup_pcg_info* info,
+                     void* stream) {
+  clear_error();
+  int st = check_basis_dev(b);
+  if (st) return st;
+  if ((st = check_kernel(k))) return st;
+  mlblup_pcg_opts o;
+  if ((st = check_opts(opts, &o))) return st;
+  if (!zw_dev || !gw_dev) return fail(MLBLUP_EINVAL, "pcg_solve: NULL vector");
+  Ws w;
+  if ((st = check_ws(b, 0, work_dev, work_bytes, &w))) return st;
+  Ctx c(b->b, *k, work_dev, w, (hipStream_t)stream);
+  mlblup_pcg_info inf{};
+  st = c.solve(zw_dev, gw_dev, use_x0 != 0, o, inf);
+  if (info) *info = inf;
+  return st;
+}
+
+int mlblup_blup_predict(mlblup_basis b, const mlblup_matern* k, const double* z_dev, const double* tgt_dev,
+                        int64_t m_t, const mlblup_pcg_opts* opts, int32_t predict_precision, double* zhat_dev,
+                        double* beta_host, double* gamma_dev, double* gamma_w_dev, double* interp_res_host,
+                        void* work_dev, int64_t work_bytes, mlblup_pcg_info* info, void* stream) {
+  clear_error();
+  int st = check_basis_dev(b);
+  if (st) return st;
+  if ((st = check_kernel(k))) return st;
+  mlblup_pcg_opts o;
+  if ((st = check_opts(opts, &o))) return st;
+  if (!z_dev || m_t < 0 || (m_t > 0 && (!tgt_dev || !zhat_dev)))
+    return fail(MLBLUP_EINVAL, "blup_predict: bad z / target arguments");
+  if (predict_precision < MLBLUP_FP64 || predict_precision > MLBLUP_MFMA_BF16X3)
+    return fail(MLBLUP_EINVAL, "blup_predict: unknown predict precision");
+  Ws w;
+  if ((st = check_ws(b, m_t, work_dev, work_bytes, &w))) return st;
+  const Basis& B = b->b;
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c(B, *k, work_dev, w, s);
+  const int64_t N = B.n, nw = B.n - B.p;
+  double* zw = c.at(w.zw);
+  double* gw = gamma_w_dev ? gamma_w_dev : c.at(w.gamw);
+  double* gam = gamma_dev ? gamma_dev : c.at(w.gam);
+  // Z_W = W z
+  if ((st = transform_analysis(c.T, z_dev, zw, nullptr, c.at(w.scal), s))) return st;
+  mlblup_pcg_info inf{};
+  const int solve_st = c.solve(zw, gw, false, o, inf);
+  if (info) *info = inf;
+  if (solve_st != MLBLUP_OK && solve_st != MLBLUP_ENOCONV) return solve_st;
+  const std::string solve_msg = solve_st ? std::string(mlblup_last_error()) : std::string();
+  // gamma = W^T gamma_W ; v = z - C gamma ; (r_W, L v) = (W v, L v)
+  if ((st = transform_synthesis(c.T, gw, nullptr, gam, c.at(w.scal), s))) return st;
+  double* v = c.at(w.v);
+  if ((st = c.pair(c.pts, N, gam, v, nullptr, MLBLUP_FP64, MLBLUP_VALUE))) return st;
+  if ((st = vec_sub_from(z_dev, v, N, s))) return st;
+  double* vw = c.at(w.vw);
+  double* lv = c.at(w.lv);
+  if ((st = transform_analysis(c.T, v, vw, lv, c.at(w.scal), s))) return st;
+  double rw = 0.0;
+  if ((st = c.norm(vw, nw, &rw))) return st;
+  if (interp_res_host) *interp_res_host = rw;
+  // beta in the root frame: (L X_loc) beta_loc = L v with L X_loc = Ms^T
+  std::vector<double> lvh(B.p);
+  MLB_HIP(hipMemcpyAsync(lvh.data(), lv, B.p * sizeof(double), hipMemcpyDeviceToHost, s));
+  MLB_HIP(hipStreamSynchronize(s));
+  std::vector<double> A((size_t)B.p * B.p);
+  for (int i = 0; i < B.p; ++i)
+    for (int j = 0; j < B.p; ++j) A[(size_t)i * B.p + j] = B.root_moments[(size_t)j * B.p + i];
+  std::vector<double> bl = lvh;
+  if (!dense_solve(A, bl, B.p)) return fail(MLBLUP_ERANK, "blup_predict: singular root moment matrix");
+  if (beta_host) {
+    // raw-coordinate coefficients: u = (x - c)/h = s x + b, s = 1/h, b = -c/h
+    std::vector<double> bvec(B.d);
+    for (int kk = 0; kk < B.d; ++kk) bvec[kk] = -B.root_c[kk] / B.root_h;
+    const std::vector<double> S = shift_matrix(B.exps, 1.0 / B.root_h, bvec);
+    for (int g = 0; g < B.p; ++g) {
+      double acc = 0.0;
+      for (int a = 0; a < B.p; ++a) acc += bl[a] * S[(size_t)a * B.p + g];
+      beta_host[g] = acc;
+    }
+  }
+  if (m_t > 0) {
+    double* betad = c.at(w.beta);
+    MLB_HIP(hipMemcpyAsync(betad, bl.data(), B.p * sizeof(double), hipMemcpyHostToDevice, s));
+    if ((st = c.pair(tgt_dev, m_t, gam, zhat_dev, nullptr, predict_precision, MLBLUP_VALUE))) return st;
+    const char* img = (const char*)B.dev_base;
+    const int32_t* ex = (const int32_t*)(img + B.off_exps);
+    const double* rc = (const double*)(img + B.off_exps + (int64_t)B.p * B.d * sizeof(int32_t));
+    if ((st = trend_add(tgt_dev, m_t, B.d, ex, B.p, rc, B.root_h, betad, zhat_dev, s))) return st;
+    MLB_HIP(hipStreamSynchronize(s));  // bl (host) must outlive the copy
+  }
+  if (solve_st) return fail(solve_st, solve_msg);
+  return MLBLUP_OK;
+}
+
+int mlblup_blup_grad(mlblup_basis b, const mlblup_matern* k, const double* z_dev, const double* gamma_dev,
+                     const double* lambda_dev, int32_t precision, double* Q_host, double* dQ_dlogrho_host,
+                     void* work_dev, int64_t work_bytes, void* stream) {
+  clear_error();
+  int st = check_basis_dev(b);
+  if (st) return st;
+  if ((st = check_kernel(k))) return st;
+  if (!gamma_dev) return fail(MLBLUP_EINVAL, "blup_grad: NULL gamma");
+  if (precision < MLBLUP_FP64 || precision > MLBLUP_MFMA_BF16X3) return fail(MLBLUP_EINVAL, "unknown precision");
+  Ws w;
+  if ((st = check_ws(b, 0, work_dev, work_bytes, &w))) return st;
+  const Basis& B = b->b;
+  Ctx c(B, *k, work_dev, w, (hipStream_t)stream);
+  if (Q_host) {
+    if (!z_dev) return fail(MLBLUP_EINVAL, "blup_grad: Q needs z");
+    if ((st = c.dot(z_dev, gamma_dev, B.n, Q_host))) return st;
+  }
+  if (dQ_dlogrho_host) {
+    double* g = c.at(w.b);
+    if ((st = c.pair(c.pts, B.n, gamma_dev, nullptr, g, precision, MLBLUP_DLOGRHO))) return st;
+    double dd = 0.0;
+    if ((st = c.dot(lambda_dev ? lambda_dev : gamma_dev, g, B.n, &dd))) return st;
+    *dQ_dlogrho_host = -dd;
+  }
+  return MLBLUP_OK;
+}
+
+}  // extern "C"

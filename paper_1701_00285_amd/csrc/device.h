@@ -1,0 +1,91 @@
+// Launchers of the device kernels (HIP, gfx950).  All launches go on the
+// caller's stream; none allocates memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace mlb {
+
+// hipError_t -> status with a message naming the call
+int hip_check(hipError_t e, const char* what);
+#define MLB_HIP(call)                                  \
+  do {                                                 \
+    int _st = ::mlb::hip_check((call), #call);         \
+    if (_st != MLBLUP_OK) return _st;                  \
+  } while (0)
+
+// ---- pair kernel -------------------------------------------------------------
+struct PairArgs {
+  const double* rows;
+  int64_t m;
+  const double* cols;
+  int64_t n;
+  int32_t d;
+  int32_t nu2;        // 2 nu: 1, 3 or 5
+  double rho;
+  double sigma2;
+  int32_t precision;  // MLBLUP_FP64 ...
+  int32_t outputs;    // MLBLUP_VALUE | MLBLUP_DLOGRHO
+  const double* x;
+  double* y;
+  double* dy;
+};
+
+// Number of column splits (partial sums per row) used for an m x n product.
+int32_t pair_splits(int64_t m, int64_t n, int32_t d, int32_t precision);
+// Workspace bytes for the partial sums.
+int64_t pair_workspace_bytes(int64_t m, int64_t n, int32_t d, int32_t precision, int32_t outputs);
+// Validates and launches (pair kernel + split reduction).
+int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s);
+
+// ---- multilevel transform ------------------------------------------------------
+struct TransformDev {
+  const NodeDesc* desc;
+  const int32_t* level_nodes;
+  const int32_t* lvl_begin_host;   // host array (levels + 1)
+  int32_t levels;
+  const double* V;
+  const double* Vt;
+};
+// vw = W v, vl = L v (vl may be null).  scal: scaling scratch.
+int transform_analysis(const TransformDev& T, const double* v, double* vw, double* vl, double* scal,
+                       hipStream_t s);
+// v = W^T vw + L^T vl (vl may be null => 0).
+int transform_synthesis(const TransformDev& T, const double* vw, const double* vl, double* v, double* scal,
+                        hipStream_t s);
+
+// ---- vector kernels (deterministic FP64 reductions) -------------------------------
+constexpr int kRedBlocks = 512;   // fixed partial count of every reduction
+
+// scalars kept on the device by the Krylov loop
+enum Scal { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RZNEW, S_FLAG, S_DOT, S_COUNT = 16 };
+
+int vec_dot(const double* a, const double* b, int64_t n, double* part, double* out_dev, hipStream_t s);
+int vec_copy(const double* a, double* b, int64_t n, hipStream_t s);
+int vec_zero(double* a, int64_t n, hipStream_t s);
+// b = a - b  (residual r = z - Cx when b holds Cx); partial |b|^2 into out_dev
+int vec_sub_from(const double* a, double* b, int64_t n, hipStream_t s);
+int vec_axpy(double alpha, const double* x, double* y, int64_t n, hipStream_t s);    // y += alpha x
+// PCG pieces
+int pcg_alpha(const double* p, const double* q, int64_t n, double* part, double* sc, hipStream_t s);
+int pcg_update(double* x, double* r, const double* p, const double* q, const double* diag, double* z,
+               int64_t n, double* part, double* sc, hipStream_t s);
+int pcg_update_p(double* p, const double* z, int64_t n, const double* sc, hipStream_t s);
+// set sc[S_RZ] = r.z (start of an inner solve)
+int pcg_start(const double* r, const double* z, int64_t n, double* part, double* sc, hipStream_t s);
+// z = r / diag
+int vec_div(const double* r, const double* diag, double* z, int64_t n, hipStream_t s);
+
+// trend at targets: out[i] += sum_b beta[b] prod_k ((t_ik - c_k)/h)^e_bk
+int trend_add(const double* tgt, int64_t m, int32_t d, const int32_t* exps, int32_t p, const double* c, double h,
+              const double* beta, double* out, hipStream_t s);
+
+// ---- instrumentation -------------------------------------------------------
+void profile_note(hipEvent_t a, hipEvent_t b, double pairs, int bucket);
+bool profile_on();
+
+}  // namespace mlb

@@ -1,0 +1,86 @@
+// Internal data structures of the multilevel BLUP library (host side).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mlblup.h"
+
+namespace mlb {
+
+// Thread-local last error message; returns the status for `return fail(...)`.
+int fail(int status, const std::string& msg);
+void clear_error();
+
+struct Tree {
+  int64_t n = 0;
+  int32_t d = 0;
+  int32_t leaf_max = 0;
+  std::vector<double> pts;        // input points, row-major n x d
+  std::vector<int64_t> perm;      // tree position -> input index
+  // nodes in preorder
+  std::vector<int64_t> begin, end;
+  std::vector<int32_t> depth, axis, left, right, parent;
+  std::vector<double> threshold;
+  int32_t max_depth = 0;
+  int32_t n_nodes() const { return (int32_t)begin.size(); }
+  bool leaf(int32_t v) const { return left[v] < 0; }
+};
+
+int build_tree(const double* pts, int64_t n, int32_t d, int32_t leaf_max, Tree& t);
+
+// Per-node record of the device transform schedule.  `in_off` is the start
+// of the node's candidate coefficients: for a leaf, its first tree position
+// in the N-vector; for an internal node, the scaling slot of its left child
+// (siblings' slots are contiguous).  `scal_off` is the node's own scaling
+// slot (-1 at the root, whose scaling coefficients are L v).
+struct NodeDesc {
+  int64_t in_off;
+  int64_t scal_off;
+  int64_t w_off;     // first wavelet coefficient in W v
+  int64_t v_off;     // offset (doubles) of the m x m block in the V and V^T arrays
+  int32_t m;
+  int32_t a;
+  int32_t leaf;
+  int32_t pad;
+};
+
+struct Basis {
+  int64_t n = 0;
+  int32_t d = 0;
+  int32_t w = 0;
+  int32_t p = 0;
+  int32_t levels = 0;             // max depth + 1
+  std::vector<std::vector<int32_t>> exps;   // p exponent tuples, graded lex
+  // per node (preorder index)
+  std::vector<NodeDesc> desc;
+  std::vector<double> V;          // row-major m x m blocks, V[i*m + j] = column j (candidate i)
+  std::vector<int64_t> level_counts;   // wavelets per level q
+  // device schedule: node ids grouped by level, level q in [lvl_begin[q], lvl_begin[q+1])
+  std::vector<int32_t> level_nodes;
+  std::vector<int32_t> lvl_begin;
+  int64_t scal_total = 0;         // length of the scaling scratch
+  // tree copy needed later
+  std::vector<double> pts_tree;   // points in tree order, row-major
+  std::vector<int64_t> begin, end;   // node point ranges (tree order)
+  std::vector<int32_t> left, right;  // children (-1 for leaves)
+  // trend: root frame (centre, scale) and L X_loc = Ms^T (p x p) for beta
+  std::vector<double> root_c;
+  double root_h = 1.0;
+  std::vector<double> root_moments;   // Ms (p x p), row-major: Ms[beta][j]
+  // device image
+  void* dev_base = nullptr;
+  int64_t dev_bytes = 0;
+  // offsets inside the device image (bytes)
+  int64_t off_desc = 0, off_V = 0, off_Vt = 0, off_pts = 0, off_levels = 0, off_exps = 0;
+  bool uploaded = false;
+};
+
+int build_basis(const Tree& t, int32_t w, double rank_rtol, Basis& b);
+int64_t basis_device_bytes(const Basis& b);
+
+// exponent tuples of the total-degree set, graded lexicographic
+std::vector<std::vector<int32_t>> td_exponents(int32_t d, int32_t w);
+
+}  // namespace mlb

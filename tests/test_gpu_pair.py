@@ -1,0 +1,108 @@
+"""Pair kernel (dense Matern product) on the GPU against the oracle:
+brute-force fsum sums for n <= 64, row-block FP64 sums at several tiles
+with ragged tails, sampled rows at the full 65,536-point size, special
+cases and determinism."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import dev, host, require_gpu, row_relerr, say
+from oracle import brute
+from oracle.matern import matern, pairwise_dist
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-13      # relative to sum_j |phi_ij x_j|
+FP32_TOL = 2e-6
+
+
+def _scale(rows, cols, x, nu, rho):
+    return np.abs(matern(pairwise_dist(rows, cols), nu, rho)) @ np.abs(x)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 7, 10, 20])
+@pytest.mark.parametrize("nu", [0.5, 1.5, 2.5])
+def test_brute_force_small(d, nu):
+    torch = require_gpu()
+    from paper_1701_00285_amd import DLOGRHO, FP32, FP64, VALUE, cov_matvec
+    m, n = 41, 64
+    rows = synth.uniform_cloud(m, d, 10 + d)
+    cols = synth.uniform_cloud(n, d, 20 + d)
+    x = synth.standard_normal(n, 30 + d)
+    rho, s2 = 0.3 * np.sqrt(d), 1.7
+    say(f"pair brute d={d} nu={nu}")
+    ref = brute.fsum_matvec(rows, cols, x, nu, rho, s2)
+    dref = brute.fsum_matvec(rows, cols, x, nu, rho, s2, deriv=True)
+    sc = s2 * _scale(rows, cols, x, nu, rho)
+    for prec, tol in ((FP64, FP64_TOL), (FP32, FP32_TOL)):
+        y, dy = cov_matvec(dev(rows), dev(cols), dev(x), nu, rho, s2, precision=prec, outputs=VALUE | DLOGRHO)
+        torch.cuda.synchronize()
+        assert row_relerr(host(y), ref, sc) < tol
+        assert row_relerr(host(dy), dref, sc) < tol
+        y1, _ = cov_matvec(dev(rows), dev(cols), dev(x), nu, rho, s2, precision=prec, outputs=VALUE)
+        _, dy2 = cov_matvec(dev(rows), dev(cols), dev(x), nu, rho, s2, precision=prec, outputs=DLOGRHO)
+        assert np.array_equal(host(y1), host(y)) and np.array_equal(host(dy2), host(dy))
+
+
+@pytest.mark.parametrize("m,n,d", [(3000, 2500, 3), (1537, 4099, 2), (2049, 1031, 5), (700, 900, 10), (513, 700, 20)])
+def test_several_tiles_ragged(m, n, d):
+    torch = require_gpu()
+    from paper_1701_00285_amd import FP32, FP64, cov_matvec
+    rows = synth.uniform_cloud(m, d, 1)
+    cols = synth.uniform_cloud(n, d, 2)
+    x = synth.standard_normal(n, 3)
+    for nu in (0.5, 1.5, 2.5):
+        rho = 0.2 * np.sqrt(d)
+        say(f"pair tiles m={m} n={n} d={d} nu={nu}")
+        ref = brute.cov_matvec(rows, cols, x, nu, rho)
+        sc = _scale(rows, cols, x, nu, rho)
+        y, _ = cov_matvec(dev(rows), dev(cols), dev(x), nu, rho, precision=FP64)
+        assert row_relerr(host(y), ref, sc) < FP64_TOL
+        y, _ = cov_matvec(dev(rows), dev(cols), dev(x), nu, rho, precision=FP32)
+        assert row_relerr(host(y), ref, sc) < FP32_TOL
+
+
+def test_self_product_exact_diagonal_and_determinism():
+    torch = require_gpu()
+    from paper_1701_00285_amd import FP32, FP64, cov_matvec
+    pts = synth.uniform_cloud(1000, 3, 5)
+    x = np.zeros(1000)
+    x[17] = 1.0
+    for prec in (FP64, FP32):
+        y, _ = cov_matvec(dev(pts), dev(pts), dev(x), 0.5, 0.1, 2.0, precision=prec)
+        col = host(y)
+        assert col[17] == 2.0                      # sigma2 * phi(0), exactly
+    x = synth.standard_normal(1000, 6)
+    a, _ = cov_matvec(dev(pts), dev(pts), dev(x), 1.5, 0.2)
+    b, _ = cov_matvec(dev(pts), dev(pts), dev(x), 1.5, 0.2)
+    assert np.array_equal(host(a), host(b))
+
+
+def test_empty_inputs():
+    torch = require_gpu()
+    from paper_1701_00285_amd import cov_matvec
+    pts = dev(synth.uniform_cloud(10, 2, 1))
+    y, _ = cov_matvec(pts, pts[:0], dev(np.zeros(0)), 0.5, 0.1)
+    assert np.all(host(y) == 0.0)
+    y, _ = cov_matvec(pts[:0], pts, dev(np.ones(10)), 0.5, 0.1)
+    assert y.numel() == 0
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_full_size_sampled_rows(k):
+    """Full-size square product (the launch the solve uses) checked on 48
+    sampled rows computed one by one by the oracle."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import FP32, FP64, cov_matvec
+    wl = synth.make_config(k, with_z=False, n_targets=1)
+    pts = wl.points
+    x = synth.standard_normal(wl.n, 77)
+    idx = np.random.default_rng(0).choice(wl.n, 48, replace=False)
+    say(f"pair full size cfg{k} n={wl.n}")
+    ref = brute.cov_matvec(pts[idx], pts, x, wl.nu, wl.rho)
+    sc = _scale(pts[idx], pts, x, wl.nu, wl.rho)
+    P, X = dev(pts), dev(x)
+    y, _ = cov_matvec(P, P, X, wl.nu, wl.rho, precision=FP64)
+    assert row_relerr(host(y)[idx], ref, sc) < FP64_TOL
+    y, _ = cov_matvec(P, P, X, wl.nu, wl.rho, precision=FP32)
+    assert row_relerr(host(y)[idx], ref, sc) < FP32_TOL

@@ -1,0 +1,117 @@
+"""Solve, predict and the error paths on the GPU against the oracle's
+dense classic BLUP and its invariants."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import dev, host, require_gpu, say
+from helpers import relerr, workload
+from oracle import blup as OB
+from oracle.design import design_matrix
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(wl, max_targets=0, leaf=None):
+    from paper_1701_00285_amd import Solver
+    return Solver(wl.points, wl.degree_w, leaf or wl.leaf_max, wl.nu, wl.rho, wl.sigma2, max_targets=max_targets)
+
+
+@pytest.mark.parametrize("k,n,nt", [(1, None, None), (2, 3000, 500), (4, 2500, 300), (3, 2000, 200), (5, 1500, 100)])
+def test_predict_matches_classic_oracle_fp64(k, n, nt):
+    torch = require_gpu()
+    from paper_1701_00285_amd import FP64, PcgOptions
+    wl = workload(k, n=n, n_targets=nt)
+    say(f"predict fp64 cfg{k} n={wl.n}")
+    ref = OB.classic_blup(wl.points, wl.z, wl.targets, wl.degree_w, wl.nu, wl.rho)
+    s = _solver(wl, max_targets=wl.targets.shape[0])
+    out = s.predict(dev(wl.z), dev(wl.targets), PcgOptions(rtol=1e-13, max_iter=5000, precision=FP64))
+    assert out["info"]["relres_fp64"] <= 1e-13
+    assert relerr(host(out["zhat"]), ref.zhat) < 1e-10
+    assert relerr(out["beta"], ref.beta) < 1e-9
+    assert relerr(host(out["gamma"]), ref.gamma) < 1e-9
+    # interpolation-residual identity |Zhat(S) - Z| = |r_W| and X^T gamma = 0
+    X = design_matrix(wl.points, wl.degree_w)
+    g = host(out["gamma"])
+    assert np.abs(X.T @ g).max() < 1e-9 * np.abs(X).max() * np.abs(g).sum()
+
+
+def test_predict_relres_1e8_and_interpolation_identity():
+    torch = require_gpu()
+    from paper_1701_00285_amd import PcgOptions
+    wl = workload(1)
+    s = _solver(wl, max_targets=wl.n)
+    out = s.predict(dev(wl.z), dev(wl.points), PcgOptions(rtol=1e-8))
+    info = out["info"]
+    assert info["relres_fp64"] <= 1e-8
+    zs = host(out["zhat"])
+    assert np.linalg.norm(zs - wl.z) == pytest.approx(out["interp_res"], rel=1e-6, abs=1e-12)
+    assert out["interp_res"] <= 1e-8 * info["zw_norm"] * 1.0000001
+
+
+def test_trend_reproduction():
+    torch = require_gpu()
+    from paper_1701_00285_amd import PcgOptions
+    wl = workload(2, n=2000, n_targets=100)
+    X = design_matrix(wl.points, wl.degree_w)
+    beta0 = synth.standard_normal(X.shape[1], 8)
+    z = X @ beta0
+    s = _solver(wl, max_targets=100)
+    out = s.predict(dev(z), dev(wl.targets), PcgOptions())
+    assert out["info"]["inner_iters"] == 0 or out["info"]["relres_fp64"] <= 1e-8
+    assert relerr(out["beta"], beta0) < 1e-10
+    assert np.abs(host(out["gamma"])).max() < 1e-8
+    np.testing.assert_allclose(host(out["zhat"]), design_matrix(wl.targets, wl.degree_w) @ beta0, rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("prec", [1, 2, 3])
+def test_mixed_precision_refinement_reaches_fp64_residual(prec):
+    torch = require_gpu()
+    from paper_1701_00285_amd import FP64, PcgOptions
+    wl = workload(2, n=4000, n_targets=300)
+    s = _solver(wl, max_targets=300)
+    say(f"mixed precision={prec}")
+    a = s.predict(dev(wl.z), dev(wl.targets), PcgOptions(rtol=1e-8, precision=FP64))
+    b = s.predict(dev(wl.z), dev(wl.targets), PcgOptions(rtol=1e-8, precision=prec, inner_rtol=1e-4))
+    assert b["info"]["relres_fp64"] <= 1e-8
+    assert b["info"]["lowp_matvecs"] > 0
+    ref = OB.classic_blup(wl.points, wl.z, wl.targets, wl.degree_w, wl.nu, wl.rho)
+    assert relerr(host(b["zhat"]), ref.zhat) < 1e-6
+    assert relerr(host(b["zhat"]), host(a["zhat"])) < 1e-6
+
+
+def test_error_paths():
+    torch = require_gpu()
+    from paper_1701_00285_amd import MlblupError, PcgOptions
+    from paper_1701_00285_amd import _lib as L
+    wl = workload(1)
+    s = _solver(wl, max_targets=10)
+    out = s.predict(dev(wl.z), dev(wl.targets[:10]), PcgOptions(max_iter=1), allow_noconv=True)
+    assert out["status"] == L.ENOCONV and out["info"]["inner_iters"] == 1
+    z = wl.z.copy()
+    z[5] = np.nan
+    with pytest.raises(MlblupError, match="EINVAL"):
+        s.predict(dev(z), None, PcgOptions())
+    zw = torch.zeros(s.n - s.p, dtype=torch.float64, device="cuda")
+    gw, info, st = s.solve(zw)
+    assert st == 0 and float(torch.abs(gw).max()) == 0.0
+    with pytest.raises(MlblupError, match="EINVAL"):
+        s.solve(zw, PcgOptions(rtol=-1.0))
+    from paper_1701_00285_amd import cov_matvec
+    with pytest.raises(MlblupError, match="EINVAL"):
+        cov_matvec(dev(wl.points), dev(wl.points), dev(wl.z), 1.0, 0.1)
+
+
+def test_basis_independence_of_iterations():
+    """Unpreconditioned CG on C_W is invariant under an orthogonal change of
+    W; leaf 32 and leaf 64 trees give the same iteration count."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import PcgOptions
+    wl = workload(2, n=3000, n_targets=10)
+    it = []
+    for leaf in (32, 64):
+        s = _solver(wl, leaf=leaf)
+        zw, _ = s.apply_W(s.to_tree(dev(wl.z)))
+        _, info, _ = s.solve(zw, PcgOptions(rtol=1e-8))
+        it.append(info["inner_iters"])
+    assert abs(it[0] - it[1]) <= 1
