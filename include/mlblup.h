@@ -59,6 +59,11 @@ extern "C" {
 
 typedef struct mlblup_tree_s* mlblup_tree;
 typedef struct mlblup_basis_s* mlblup_basis;
+typedef struct mlblup_precond_s* mlblup_precond;
+
+/* Preconditioner kinds (preconditioner remark of Sec. 5). */
+#define MLBLUP_PREC_JACOBI 1   /* P_W = diag(C_W) */
+#define MLBLUP_PREC_BLOCK 2    /* P_W = the diagonal blocks of C_W, one per cell (its own wavelets) */
 
 /* Matern covariance sigma2 * phi(r; nu, rho), Definition in Sec. 2.1 with the
  * half-integer closed forms (nu = 1/2, 3/2, 5/2), rho > 0, sigma2 > 0. */
@@ -74,17 +79,20 @@ typedef struct {
  * (MLBLUP_FP64 runs plain PCG with a final FP64 residual check; lower
  * precisions run an FP64 iterative-refinement loop around inner PCG
  * solves).  refine_max: outer refinement steps.  inner_rtol: relative
- * reduction asked of each inner solve (lower precisions).  jacobi_diag_dev:
- * NULL for P_W = I, else diag(C_W) (N - p doubles) as in the preconditioner
- * remark of Sec. 5.  */
+ * reduction asked of each inner solve (lower precisions).  precond: NULL for
+ * P_W = I, else a preconditioner built and uploaded for this basis (the
+ * paper's Jacobi P_W = diag(C_W), or its per-cell block form).
+ * history_host / history_cap: optional per-iteration record of the
+ * recurrence residual. */
 typedef struct {
   double rtol;
   int32_t max_iter;
   int32_t precision;
   int32_t refine_max;
-  int32_t reserved;
+  int32_t history_cap;           /* entries available in history_host (0 = no history) */
   double inner_rtol;
-  const double* jacobi_diag_dev;
+  mlblup_precond precond;        /* NULL: P_W = I; else an uploaded preconditioner of the same basis */
+  double* history_host;          /* optional: |r_k| / |Z_W| after each Krylov iteration k (recurrence residual) */
 } mlblup_pcg_opts;
 
 typedef struct {
@@ -203,6 +211,30 @@ int mlblup_blup_predict(mlblup_basis b, const mlblup_matern* k, const double* z_
 int mlblup_blup_grad(mlblup_basis b, const mlblup_matern* k, const double* z_dev, const double* gamma_dev,
                      const double* lambda_dev, int32_t precision, double* Q_host, double* dQ_dlogrho_host,
                      void* work_dev, int64_t work_bytes, void* stream);
+
+/* ---- preconditioner (remark on P_W = diag(C_W), Sec. 5) -----------------------
+ * Built without forming C_W: the leaf kernel blocks and, for each internal
+ * cell, the Gram of its children's scaling vectors across the two children
+ * are summed on the device (about N^2/2 pairs over all levels, kernel values
+ * with FP32 sqrt/exp), then each cell's wavelet block B_v = Psi_v^T C Psi_v
+ * is assembled bottom-up on the host through the cell's orthogonal block.
+ * JACOBI keeps diag(B_v) (= diag(C_W)); BLOCK keeps every B_v (inverted by
+ * Cholesky).  Needs an uploaded basis with p <= 32.  The kernel parameters
+ * are fixed at build time: rebuild when rho changes.  work_dev: at least
+ * mlblup_precond_workspace_bytes(b).  Synchronises `stream`. */
+int mlblup_precond_workspace_bytes(mlblup_basis b, int64_t* bytes);
+int mlblup_precond_build(mlblup_basis b, const mlblup_matern* k, int32_t kind, void* work_dev, int64_t work_bytes,
+                         void* stream, mlblup_precond* out);
+/* device_bytes: size of the device image; n_blocks: cells with wavelets;
+ * block_entries: sum of squared block sizes. */
+int mlblup_precond_info(mlblup_precond pc, int64_t* device_bytes, int64_t* n_blocks, int64_t* block_entries);
+/* Copies the device image into dev_buf (caller-owned, 256-byte aligned,
+ * must outlive every solve that uses it). */
+int mlblup_precond_upload(mlblup_precond pc, void* dev_buf, int64_t bytes, void* stream);
+/* Host copies for tests: blocks B_v (row-major, concatenated in coefficient
+ * order), each block's first coefficient and size (any pointer may be NULL). */
+int mlblup_precond_blocks(mlblup_precond pc, double* blocks_host, int64_t* w_off_host, int32_t* mw_host);
+void mlblup_precond_free(mlblup_precond pc);
 
 /* ---- instrumentation --------------------------------------------------------
  * When enabled, each pair-kernel launch is bracketed by HIP events on its

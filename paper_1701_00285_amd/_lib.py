@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(_HERE, "libmlblup.so")
 OK, EINVAL, ERANK, ENOCONV, EBREAKDOWN, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32, MFMA_FP32, MFMA_BF16X3 = 0, 1, 2, 3
 VALUE, DLOGRHO = 1, 2
+PREC_JACOBI, PREC_BLOCK = 1, 2
 
 _NAMES = {EINVAL: "EINVAL", ERANK: "ERANK", ENOCONV: "ENOCONV", EBREAKDOWN: "EBREAKDOWN", EHIP: "EHIP",
           ESTATE: "ESTATE"}
@@ -21,8 +22,8 @@ class Matern(C.Structure):
 
 class PcgOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
-                ("refine_max", C.c_int32), ("reserved", C.c_int32), ("inner_rtol", C.c_double),
-                ("jacobi_diag_dev", C.c_void_p)]
+                ("refine_max", C.c_int32), ("history_cap", C.c_int32), ("inner_rtol", C.c_double),
+                ("precond", C.c_void_p), ("history_host", C.c_void_p)]
 
 
 class PcgInfo(C.Structure):
@@ -71,6 +72,12 @@ _SIGS = {
     "mlblup_blup_predict": (C.c_int, [_P, C.POINTER(Matern), _P, _P, _I64, C.POINTER(PcgOpts), _I32, _P, _P, _P,
                                       _P, _P, _P, _I64, C.POINTER(PcgInfo), _P]),
     "mlblup_blup_grad": (C.c_int, [_P, C.POINTER(Matern), _P, _P, _P, _I32, _P, _P, _P, _I64, _P]),
+    "mlblup_precond_workspace_bytes": (C.c_int, [_P, C.POINTER(_I64)]),
+    "mlblup_precond_build": (C.c_int, [_P, C.POINTER(Matern), _I32, _P, _I64, _P, C.POINTER(_P)]),
+    "mlblup_precond_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
+    "mlblup_precond_upload": (C.c_int, [_P, _P, _I64, _P]),
+    "mlblup_precond_blocks": (C.c_int, [_P, _P, _P, _P]),
+    "mlblup_precond_free": (None, [_P]),
     "mlblup_profile_enable": (C.c_int, [_I32]),
     "mlblup_profile_read": (C.c_int, [_P, _P, _P]),
 }

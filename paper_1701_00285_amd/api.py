@@ -17,6 +17,7 @@ from ._lib import check
 
 FP64, FP32, MFMA_FP32, MFMA_BF16X3 = L.FP64, L.FP32, L.MFMA_FP32, L.MFMA_BF16X3
 VALUE, DLOGRHO = L.VALUE, L.DLOGRHO
+PREC_JACOBI, PREC_BLOCK = L.PREC_JACOBI, L.PREC_BLOCK
 
 
 def _torch():
@@ -48,11 +49,55 @@ class PcgOptions:
     precision: int = FP64
     refine_max: int = 8
     inner_rtol: float = 1e-5
-    jacobi_diag: object = None      # device tensor (N - p) or None
+    precond: object = None          # Precond (uploaded) or None for P_W = I
+    history: object = None          # numpy float64 array receiving |r_k|/|Z_W| per iteration, or None
 
     def to_c(self):
-        return L.PcgOpts(self.rtol, self.max_iter, self.precision, self.refine_max, 0, self.inner_rtol,
-                         None if self.jacobi_diag is None else self.jacobi_diag.data_ptr())
+        hist = None if self.history is None else self.history.ctypes.data
+        cap = 0 if self.history is None else int(self.history.size)
+        return L.PcgOpts(self.rtol, self.max_iter, self.precision, self.refine_max, cap, self.inner_rtol,
+                         None if self.precond is None else self.precond.h, hist)
+
+
+class Precond:
+    """Preconditioner P_W (diag(C_W) or its per-cell blocks) for a basis and
+    fixed kernel parameters, built on the device and uploaded."""
+
+    def __init__(self, basis, kern, kind=PREC_BLOCK, device="cuda"):
+        torch = _torch()
+        lib = L.lib()
+        self._lib = lib
+        wb = C.c_int64()
+        check(lib.mlblup_precond_workspace_bytes(basis.h, C.byref(wb)))
+        work = torch.empty(max(wb.value, 256), dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        check(lib.mlblup_precond_build(basis.h, C.byref(kern), int(kind), _ptr(work), work.numel(), _stream(),
+                                       C.byref(h)))
+        self.h = h
+        self.kind = kind
+        db, nb, be = C.c_int64(), C.c_int64(), C.c_int64()
+        check(lib.mlblup_precond_info(h, C.byref(db), C.byref(nb), C.byref(be)))
+        self.n_blocks, self.block_entries = nb.value, be.value
+        self.buf = torch.empty(max(db.value, 256), dtype=torch.uint8, device=device)
+        check(lib.mlblup_precond_upload(h, _ptr(self.buf), self.buf.numel(), _stream()))
+
+    def blocks(self):
+        """(list of B_v as numpy arrays, their first coefficient index)."""
+        vals = np.empty(self.block_entries)
+        woff = np.empty(self.n_blocks, dtype=np.int64)
+        mw = np.empty(self.n_blocks, dtype=np.int32)
+        check(self._lib.mlblup_precond_blocks(self.h, _np_ptr(vals), _np_ptr(woff), _np_ptr(mw)))
+        out, o = [], 0
+        for k in range(self.n_blocks):
+            m = int(mw[k])
+            out.append(vals[o:o + m * m].reshape(m, m))
+            o += m * m
+        return out, woff
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self._lib.mlblup_precond_free(self.h)
+            self.h = None
 
 
 class Tree:
@@ -191,6 +236,9 @@ class Solver:
     def kernel(self, rho=None):
         return matern(self.nu, self.rho if rho is None else rho, self.sigma2)
 
+    def precond(self, kind=PREC_BLOCK, rho=None):
+        return Precond(self.basis, self.kernel(rho), kind, self.device)
+
     # ---- operators ----
     def apply_W(self, v_tree):
         torch = _torch()
@@ -261,9 +309,9 @@ class Solver:
         q, dq = C.c_double(), C.c_double()
         k = self.kernel(rho)
         check(L.lib().mlblup_blup_grad(self.basis.h, C.byref(k), _ptr(z_tree), _ptr(gamma_tree), _ptr(lambda_tree),
-                                       int(precision), C.byref(q), C.byref(dq), _ptr(self.ws), self.ws.numel(),
-                                       _stream()))
-        return q.value, dq.value
+                                       int(precision), C.byref(q) if z_tree is not None else None, C.byref(dq),
+                                       _ptr(self.ws), self.ws.numel(), _stream()))
+        return (q.value if z_tree is not None else None), dq.value
 
 
 def _make_autograd():

@@ -12,13 +12,8 @@
 
 #include "device.h"
 #include "internal.h"
+#include "precond.h"
 
-struct mlblup_tree_s {
-  mlb::Tree t;
-};
-struct mlblup_basis_s {
-  mlb::Basis b;
-};
 
 namespace mlb {
 
@@ -233,7 +228,10 @@ struct Ctx {
 
   // PCG on C_W x = zw with FP64 residual checks and (for reduced precision)
   // iterative refinement.  Stopping rule on the unpreconditioned residual.
-  int solve(const double* zw, double* x, bool use_x0, const mlblup_pcg_opts& o, mlblup_pcg_info& info) {
+  // floor_abs: a right-hand side with |zw| <= floor_abs is treated as zero
+  // (data in the trend space up to rounding: gamma_W = 0).
+  int solve(const double* zw, double* x, bool use_x0, const mlblup_pcg_opts& o, mlblup_pcg_info& info,
+            double floor_abs = 0.0) {
     const int64_t nw = B.n - B.p;
     info = mlblup_pcg_info{};
     double bnorm = 0.0;
@@ -241,7 +239,7 @@ struct Ctx {
     if (st) return st;
     if (!std::isfinite(bnorm)) return fail(MLBLUP_EINVAL, "pcg_solve: non-finite right-hand side");
     info.zw_norm = bnorm;
-    if (bnorm == 0.0) {
+    if (bnorm <= floor_abs) {
       info.relres_fp64 = 0.0;
       return vec_zero(x, nw, s);
     }
@@ -250,7 +248,8 @@ struct Ctx {
       if (st) return st;
     }
     const int prec = o.precision;
-    const double* diag = o.jacobi_diag_dev;
+    const Precond* pc = o.precond ? &o.precond->p : nullptr;
+    if (pc && (!pc->uploaded || pc->nw != nw)) return fail(MLBLUP_ESTATE, "pcg_solve: preconditioner not uploaded or of another basis");
     int iters_left = o.max_iter;
     double* r = at(w.r);
     double* p = at(w.p);
@@ -287,8 +286,8 @@ struct Ctx {
       st = vec_zero(dx, nw, s);
       if (st) return st;
       const double* zz = r;
-      if (diag) {
-        st = vec_div(r, diag, z, nw, s);
+      if (pc) {
+        st = precond_apply(*pc, r, z, s);
         if (st) return st;
         zz = z;
       }
@@ -303,11 +302,19 @@ struct Ctx {
         else info.lowp_matvecs++;
         st = pcg_alpha(p, q, nw, at(w.part), at(w.sc), s);
         if (st) return st;
-        st = pcg_update(dx, r, p, q, diag, z, nw, at(w.part), at(w.sc), s);
+        st = pcg_update_xr(dx, r, p, q, nw, at(w.part), at(w.sc), s);
+        if (st) return st;
+        if (pc) {
+          if ((st = precond_apply(*pc, r, z, s))) return st;
+          if ((st = pcg_rz_partial(r, z, nw, at(w.part), s))) return st;
+        }
+        st = pcg_finish_beta(at(w.part), pc != nullptr, at(w.sc), s);
         if (st) return st;
         st = read_scalars();
         if (st) return st;
         --iters_left;
+        if (o.history_host && info.inner_iters < o.history_cap)
+          o.history_host[info.inner_iters] = std::sqrt(sc_host[S_RR]) / bnorm;
         info.inner_iters++;
         if (sc_host[S_FLAG] != 0.0) {
           // fold what was gained so far into x, then report the breakdown
@@ -345,7 +352,9 @@ mlblup_pcg_opts default_opts() {
   o.precision = MLBLUP_FP64;
   o.refine_max = 8;
   o.inner_rtol = 1e-5;
-  o.jacobi_diag_dev = nullptr;
+  o.precond = nullptr;
+  o.history_cap = 0;
+  o.history_host = nullptr;
   return o;
 }
 
@@ -601,6 +610,7 @@ int mlblup_solve_workspace_bytes(mlblup_basis b, const mlblup_pcg_opts* opts, in
 
 static int check_opts(const mlblup_pcg_opts* opts, mlblup_pcg_opts* o) {
   *o = opts ? *opts : default_opts();
+  if (o->history_cap < 0 || (o->history_cap > 0 && !o->history_host)) return fail(MLBLUP_EINVAL, "pcg options: bad history");
   if (!(o->rtol > 0) || o->max_iter < 0 || o->precision < MLBLUP_FP64 || o->precision > MLBLUP_MFMA_BF16X3)
     return fail(MLBLUP_EINVAL, "pcg options: need rtol > 0, max_iter >= 0, known precision");
   if (o->refine_max <= 0) o->refine_max = 8;
@@ -651,8 +661,12 @@ int mlblup_blup_predict(mlblup_basis b, const mlblup_matern* k, const double* z_
   double* gam = gamma_dev ? gamma_dev : c.at(w.gam);
   // Z_W = W z
   if ((st = transform_analysis(c.T, z_dev, zw, nullptr, c.at(w.scal), s))) return st;
+  // |Z_W| at rounding level of |z| means z lies in the trend space: gamma_W = 0
+  double znorm = 0.0;
+  if ((st = c.norm(z_dev, N, &znorm))) return st;
+  if (!std::isfinite(znorm)) return fail(MLBLUP_EINVAL, "blup_predict: non-finite observations");
   mlblup_pcg_info inf{};
-  const int solve_st = c.solve(zw, gw, false, o, inf);
+  const int solve_st = c.solve(zw, gw, false, o, inf, 1e-13 * znorm);
   if (info) *info = inf;
   if (solve_st != MLBLUP_OK && solve_st != MLBLUP_ENOCONV) return solve_st;
   const std::string solve_msg = solve_st ? std::string(mlblup_last_error()) : std::string();

@@ -72,8 +72,13 @@ int vec_sub_from(const double* a, double* b, int64_t n, hipStream_t s);
 int vec_axpy(double alpha, const double* x, double* y, int64_t n, hipStream_t s);    // y += alpha x
 // PCG pieces
 int pcg_alpha(const double* p, const double* q, int64_t n, double* part, double* sc, hipStream_t s);
-int pcg_update(double* x, double* r, const double* p, const double* q, const double* diag, double* z,
-               int64_t n, double* part, double* sc, hipStream_t s);
+// x += alpha p, r -= alpha q, partial |r|^2 into part[0 .. kRedBlocks)
+int pcg_update_xr(double* x, double* r, const double* p, const double* q, int64_t n, double* part, double* sc,
+                  hipStream_t s);
+// partial r.z into part[kRedBlocks .. 2 kRedBlocks)
+int pcg_rz_partial(const double* r, const double* z, int64_t n, double* part, hipStream_t s);
+// sc[S_RR] = |r|^2, beta = rz_new / rz (rz = |r|^2 without preconditioner)
+int pcg_finish_beta(double* part, bool has_z, double* sc, hipStream_t s);
 int pcg_update_p(double* p, const double* z, int64_t n, const double* sc, hipStream_t s);
 // set sc[S_RZ] = r.z (start of an inner solve)
 int pcg_start(const double* r, const double* z, int64_t n, double* part, double* sc, hipStream_t s);

@@ -84,3 +84,10 @@ int64_t basis_device_bytes(const Basis& b);
 std::vector<std::vector<int32_t>> td_exponents(int32_t d, int32_t w);
 
 }  // namespace mlb
+
+struct mlblup_tree_s {
+  mlb::Tree t;
+};
+struct mlblup_basis_s {
+  mlb::Basis b;
+};

@@ -135,27 +135,17 @@ __global__ __launch_bounds__(kT) void finish_alpha(const double* __restrict__ pa
 
 __global__ __launch_bounds__(kT) void update_xr(double* __restrict__ x, double* __restrict__ r,
                                                 const double* __restrict__ p, const double* __restrict__ q,
-                                                const double* __restrict__ diag, double* __restrict__ z,
                                                 int64_t n, double* __restrict__ part, const double* __restrict__ sc) {
   const double alpha = sc[S_ALPHA];
-  double rr = 0.0, rz = 0.0;
+  double rr = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kT) {
     x[i] = fma(alpha, p[i], x[i]);
     const double ri = fma(-alpha, q[i], r[i]);
     r[i] = ri;
     rr = fma(ri, ri, rr);
-    if (diag) {
-      const double zi = ri / diag[i];
-      z[i] = zi;
-      rz = fma(ri, zi, rz);
-    }
   }
   rr = block_sum(rr);
   if (threadIdx.x == 0) part[blockIdx.x] = rr;
-  if (diag) {
-    rz = block_sum(rz);
-    if (threadIdx.x == 0) part[kRedBlocks + blockIdx.x] = rz;
-  }
 }
 
 __global__ __launch_bounds__(kT) void finish_beta(const double* __restrict__ part, int has_diag,
@@ -307,11 +297,20 @@ int pcg_alpha(const double* p, const double* q, int64_t n, double* part, double*
   return hip_check(hipGetLastError(), "alpha launch");
 }
 
-int pcg_update(double* x, double* r, const double* p, const double* q, const double* diag, double* z, int64_t n,
-               double* part, double* sc, hipStream_t s) {
-  hipLaunchKernelGGL(update_xr, dim3(kRedBlocks), dim3(kT), 0, s, x, r, p, q, diag, z, n, part, sc);
-  hipLaunchKernelGGL(finish_beta, dim3(1), dim3(kT), 0, s, part, diag ? 1 : 0, sc);
+int pcg_update_xr(double* x, double* r, const double* p, const double* q, int64_t n, double* part, double* sc,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(update_xr, dim3(kRedBlocks), dim3(kT), 0, s, x, r, p, q, n, part, sc);
   return hip_check(hipGetLastError(), "update launch");
+}
+
+int pcg_rz_partial(const double* r, const double* z, int64_t n, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(dot_partial, dim3(kRedBlocks), dim3(kT), 0, s, r, z, n, part + kRedBlocks);
+  return hip_check(hipGetLastError(), "rz launch");
+}
+
+int pcg_finish_beta(double* part, bool has_z, double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(finish_beta, dim3(1), dim3(kT), 0, s, part, has_z ? 1 : 0, sc);
+  return hip_check(hipGetLastError(), "beta launch");
 }
 
 int pcg_update_p(double* p, const double* z, int64_t n, const double* sc, hipStream_t s) {

@@ -284,14 +284,15 @@ int64_t pair_workspace_bytes(int64_t m, int64_t n, int32_t d, int32_t precision,
 int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s) {
   if (a.m < 0 || a.n < 0 || a.d < 1 || a.d > 64) return fail(MLBLUP_EINVAL, "cov_matvec: bad m, n or d");
   if (a.outputs < 1 || a.outputs > 3) return fail(MLBLUP_EINVAL, "cov_matvec: outputs must be 1, 2 or 3");
-  if (((a.outputs & 1) && !a.y) || ((a.outputs & 2) && !a.dy))
-    return fail(MLBLUP_EINVAL, "cov_matvec: missing output pointer");
+
   if (!(a.rho > 0) || !(a.sigma2 > 0) || !std::isfinite(a.rho) || !std::isfinite(a.sigma2))
     return fail(MLBLUP_EINVAL, "cov_matvec: rho and sigma2 must be finite and > 0");
   if (a.nu2 != 1 && a.nu2 != 3 && a.nu2 != 5) return fail(MLBLUP_EINVAL, "cov_matvec: nu must be 1/2, 3/2 or 5/2");
   if (a.precision < MLBLUP_FP64 || a.precision > MLBLUP_MFMA_BF16X3)
     return fail(MLBLUP_EINVAL, "cov_matvec: unknown precision");
   if (a.m == 0) return MLBLUP_OK;
+  if (((a.outputs & 1) && !a.y) || ((a.outputs & 2) && !a.dy))
+    return fail(MLBLUP_EINVAL, "cov_matvec: missing output pointer");
   if (a.n == 0) {
     const unsigned g = (unsigned)((a.m + 255) / 256);
     if (a.outputs & 1) hipLaunchKernelGGL(fill_zero, dim3(g), dim3(256), 0, s, a.y, a.m);

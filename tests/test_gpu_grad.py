@@ -52,7 +52,7 @@ def test_autograd_functions():
     Q.backward()
     g_quad = float(lr.grad)
     Q0, dQ0 = OB.quad_form_grad(wl.points, wl.z, wl.degree_w, wl.nu, wl.rho)
-    assert float(Q) == pytest.approx(Q0, rel=1e-8)
+    assert float(Q.detach()) == pytest.approx(Q0, rel=1e-8)
     assert g_quad == pytest.approx(dQ0, rel=1e-8)
     # generic adjoint path: L = Z_W . gamma_W through BlupSolve (one extra solve)
     lr2 = torch.tensor(math.log(wl.rho), dtype=torch.float64, device="cuda", requires_grad=True)
