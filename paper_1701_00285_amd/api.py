@@ -47,8 +47,8 @@ class PcgOptions:
     rtol: float = 1e-8
     max_iter: int = 1000
     precision: int = FP64
-    refine_max: int = 8
-    inner_rtol: float = 1e-5
+    refine_max: int = 200
+    inner_rtol: float = 1e-2
     precond: object = None          # Precond (uploaded) or None for P_W = I
     history: object = None          # numpy float64 array receiving |r_k|/|Z_W| per iteration, or None
 

@@ -120,7 +120,7 @@ void image_layout(Basis& B) {
 
 // Workspace of the solve/predict/grad drivers.
 struct Ws {
-  int64_t r, p, q, z, dx, a, b, scal, part, sc, cov, zw, v, vw, lv, beta, gam, gamw, total;
+  int64_t r, p, q, z, dx, r2, p2, q2, z2, sc2, a, b, scal, part, sc, cov, zw, v, vw, lv, beta, gam, gamw, total;
   int64_t cov_bytes;
 };
 
@@ -138,6 +138,11 @@ Ws ws_layout(const Basis& B, int64_t mt) {
   w.q = take(nw * D);
   w.z = take(nw * D);
   w.dx = take(nw * D);
+  w.r2 = take(nw * D);
+  w.p2 = take(nw * D);
+  w.q2 = take(nw * D);
+  w.z2 = take(nw * D);
+  w.sc2 = take(S_COUNT * D);
   w.a = take(N * D);
   w.b = take(N * D);
   w.scal = take(std::max<int64_t>(B.scal_total, 1) * D);
@@ -201,8 +206,8 @@ struct Ctx {
     return transform_analysis(T, at(w.b), out, nullptr, at(w.scal), s);
   }
 
-  int read_scalars() {
-    MLB_HIP(hipMemcpyAsync(sc_host, at(w.sc), sizeof(sc_host), hipMemcpyDeviceToHost, s));
+  int read_scalars(const double* sc) {
+    MLB_HIP(hipMemcpyAsync(sc_host, sc, sizeof(sc_host), hipMemcpyDeviceToHost, s));
     MLB_HIP(hipStreamSynchronize(s));
     return MLBLUP_OK;
   }
@@ -211,7 +216,7 @@ struct Ctx {
   int norm(const double* a, int64_t n, double* out) {
     int st = vec_dot(a, a, n, at(w.part), at(w.sc) + S_DOT, s);
     if (st) return st;
-    st = read_scalars();
+    st = read_scalars(at(w.sc));
     if (st) return st;
     *out = std::sqrt(sc_host[S_DOT]);
     return MLBLUP_OK;
@@ -220,14 +225,75 @@ struct Ctx {
   int dot(const double* a, const double* b, int64_t n, double* out) {
     int st = vec_dot(a, b, n, at(w.part), at(w.sc) + S_DOT, s);
     if (st) return st;
-    st = read_scalars();
+    st = read_scalars(at(w.sc));
     if (st) return st;
     *out = sc_host[S_DOT];
     return MLBLUP_OK;
   }
 
-  // PCG on C_W x = zw with FP64 residual checks and (for reduced precision)
-  // iterative refinement.  Stopping rule on the unpreconditioned residual.
+  // PCG on C_W d = rhs from d = 0 with the pair kernel in precision `prec`.
+  // Vectors r, p, q, z and scalars sc are this loop's own; stops when the
+  // recurrence residual drops to tol_abs or the iteration budget is spent.
+  // history: record |r_k| / bnorm per iteration (plain FP64 solve only).
+  int inner_pcg(const double* rhs, double* d, double tol_abs, int prec, const Precond* pc, int& iters_left,
+                const mlblup_pcg_opts& o, mlblup_pcg_info& info, double bnorm, bool history) {
+    const int64_t nw = B.n - B.p;
+    double* r = at(w.r);
+    double* p = at(w.p);
+    double* q = at(w.q);
+    double* z = at(w.z);
+    double* sc = at(w.sc);
+    int st;
+    if ((st = vec_copy(rhs, r, nw, s))) return st;
+    if ((st = vec_zero(d, nw, s))) return st;
+    const double* zz = r;
+    if (pc) {
+      if ((st = precond_apply(*pc, r, z, s))) return st;
+      zz = z;
+    }
+    if ((st = vec_copy(zz, p, nw, s))) return st;
+    if ((st = pcg_start(r, zz, nw, at(w.part), sc, s))) return st;
+    while (iters_left > 0) {
+      if ((st = matvec_cw(p, q, prec))) return st;
+      if (prec == MLBLUP_FP64) info.fp64_matvecs++;
+      else info.lowp_matvecs++;
+      if ((st = pcg_alpha(p, q, nw, at(w.part), sc, s))) return st;
+      if ((st = pcg_update_xr(d, r, p, q, nw, at(w.part), sc, s))) return st;
+      if (pc) {
+        if ((st = precond_apply(*pc, r, z, s))) return st;
+        if ((st = pcg_rz_partial(r, z, nw, at(w.part), s))) return st;
+      }
+      if ((st = pcg_finish_beta(at(w.part), pc != nullptr, sc, s))) return st;
+      if ((st = read_scalars(sc))) return st;
+      --iters_left;
+      if (history && o.history_host && info.inner_iters < o.history_cap)
+        o.history_host[info.inner_iters] = std::sqrt(sc_host[S_RR]) / bnorm;
+      info.inner_iters++;
+      if (sc_host[S_FLAG] != 0.0) return fail(MLBLUP_EBREAKDOWN, "pcg_solve: breakdown (p.q <= 0 or non-finite scalar)");
+      if (std::sqrt(sc_host[S_RR]) <= tol_abs) break;
+      if ((st = pcg_update_p(p, zz, nw, sc, s))) return st;
+    }
+    return MLBLUP_OK;
+  }
+
+  // true residual r_out = zw - C_W x (FP64 product); returns |r_out|
+  int true_residual(const double* zw, const double* x, double* r_out, double* rnorm, mlblup_pcg_info& info) {
+    const int64_t nw = B.n - B.p;
+    int st;
+    if ((st = matvec_cw(x, r_out, MLBLUP_FP64))) return st;
+    info.fp64_matvecs++;
+    if ((st = vec_sub_from(zw, r_out, nw, s))) return st;
+    return norm(r_out, nw, rnorm);
+  }
+
+  // Solve C_W x = zw to |zw - C_W x| <= rtol |zw| (FP64 product, unpreconditioned
+  // residual).  FP64: PCG, then the true residual; if rounding drift left it
+  // above rtol, PCG restarts from x on the true residual.  Reduced
+  // precision: flexible CG in FP64 (FP64 products, vectors and dots) whose
+  // preconditioner is an inner PCG solve with the reduced-precision pair
+  // kernel to relative tolerance inner_rtol -- a Krylov-accelerated
+  // iterative refinement; the FP64 recurrence residual is confirmed by a
+  // true residual at the end.
   // floor_abs: a right-hand side with |zw| <= floor_abs is treated as zero
   // (data in the trend space up to rounding: gamma_W = 0).
   int solve(const double* zw, double* x, bool use_x0, const mlblup_pcg_opts& o, mlblup_pcg_info& info,
@@ -243,90 +309,75 @@ struct Ctx {
       info.relres_fp64 = 0.0;
       return vec_zero(x, nw, s);
     }
-    if (!use_x0) {
-      st = vec_zero(x, nw, s);
-      if (st) return st;
-    }
+    if (!use_x0 && (st = vec_zero(x, nw, s))) return st;
     const int prec = o.precision;
     const Precond* pc = o.precond ? &o.precond->p : nullptr;
-    if (pc && (!pc->uploaded || pc->nw != nw)) return fail(MLBLUP_ESTATE, "pcg_solve: preconditioner not uploaded or of another basis");
+    if (pc && (!pc->uploaded || pc->nw != nw))
+      return fail(MLBLUP_ESTATE, "pcg_solve: preconditioner not uploaded or of another basis");
     int iters_left = o.max_iter;
-    double* r = at(w.r);
-    double* p = at(w.p);
-    double* q = at(w.q);
-    double* z = at(w.z);
-    double* dx = at(w.dx);
-    for (int outer = 0;; ++outer) {
-      double rnorm;
-      if (outer == 0 && !use_x0) {
-        st = vec_copy(zw, r, nw, s);
+    double* r2 = at(w.r2);
+    double* p2 = at(w.p2);
+    double* q2 = at(w.q2);
+    double* z2 = at(w.z2);
+    double* sc2 = at(w.sc2);
+    double rnorm = bnorm;
+    if (use_x0) {
+      if ((st = true_residual(zw, x, r2, &rnorm, info))) return st;
+    } else if ((st = vec_copy(zw, r2, nw, s))) {
+      return st;
+    }
+    auto noconv = [&](double rel) {
+      return fail(MLBLUP_ENOCONV, "pcg_solve: tolerance not reached (relres " + std::to_string(rel) + ")");
+    };
+    if (prec == MLBLUP_FP64) {
+      for (int outer = 0;; ++outer) {
+        const double relres = rnorm / bnorm;
+        info.relres_fp64 = relres;
+        if (!std::isfinite(relres)) return fail(MLBLUP_EBREAKDOWN, "pcg_solve: non-finite residual");
+        if (relres <= o.rtol) return MLBLUP_OK;
+        if (outer >= std::max(o.refine_max, 1) || iters_left <= 0) return noconv(relres);
+        info.outer_iters++;
+        st = inner_pcg(r2, z2, 0.7 * o.rtol * bnorm, MLBLUP_FP64, pc, iters_left, o, info, bnorm, true);
+        const int st2 = vec_axpy(1.0, z2, x, nw, s);  // keep the progress even on breakdown
         if (st) return st;
-        rnorm = bnorm;
-      } else {
-        st = matvec_cw(x, q, MLBLUP_FP64);
-        if (st) return st;
-        info.fp64_matvecs++;
-        st = vec_sub_from(zw, q, nw, s);  // q = zw - C_W x
-        if (st) return st;
-        st = vec_copy(q, r, nw, s);
-        if (st) return st;
-        st = norm(r, nw, &rnorm);
-        if (st) return st;
+        if (st2) return st2;
+        if ((st = true_residual(zw, x, r2, &rnorm, info))) return st;
       }
-      const double relres = rnorm / bnorm;
+    }
+    // flexible CG outer loop (FP64), reduced-precision inner solves
+    const double inner = o.inner_rtol > 0 ? o.inner_rtol : 1e-2;
+    const int max_outer = std::max(o.refine_max, 1);
+    for (int k = 0;; ++k) {
+      double relres = rnorm / bnorm;
       info.relres_fp64 = relres;
       if (!std::isfinite(relres)) return fail(MLBLUP_EBREAKDOWN, "pcg_solve: non-finite residual");
-      if (relres <= o.rtol) return MLBLUP_OK;
-      if (outer >= std::max(o.refine_max, 1) || iters_left <= 0)
-        return fail(MLBLUP_ENOCONV, "pcg_solve: tolerance not reached (relres " + std::to_string(relres) + ")");
+      if (relres <= o.rtol) {
+        // confirm with the true FP64 residual; on drift restart the directions
+        if ((st = true_residual(zw, x, r2, &rnorm, info))) return st;
+        relres = rnorm / bnorm;
+        info.relres_fp64 = relres;
+        if (relres <= o.rtol) return MLBLUP_OK;
+        k = 0;
+      }
+      if (info.outer_iters >= max_outer || iters_left <= 0) return noconv(relres);
       info.outer_iters++;
-      // inner PCG on the correction, from 0
-      double target = 0.7 * o.rtol * bnorm / rnorm;
-      if (prec != MLBLUP_FP64) target = std::max(target, o.inner_rtol > 0 ? o.inner_rtol : 1e-5);
-      st = vec_zero(dx, nw, s);
-      if (st) return st;
-      const double* zz = r;
-      if (pc) {
-        st = precond_apply(*pc, r, z, s);
-        if (st) return st;
-        zz = z;
+      if ((st = inner_pcg(r2, z2, inner * rnorm, prec, pc, iters_left, o, info, bnorm, false))) return st;
+      if (o.history_host && info.outer_iters - 1 < o.history_cap) o.history_host[info.outer_iters - 1] = relres;
+      if (k == 0) {
+        if ((st = vec_copy(z2, p2, nw, s))) return st;
+      } else {
+        if ((st = vec_dot(z2, q2, nw, at(w.part), sc2 + S_DOT, s))) return st;  // q2 = C_W p_prev
+        if ((st = fcg_update_p(p2, z2, nw, sc2, s))) return st;
       }
-      st = vec_copy(zz, p, nw, s);
-      if (st) return st;
-      st = pcg_start(r, zz, nw, at(w.part), at(w.sc), s);
-      if (st) return st;
-      while (iters_left > 0) {
-        st = matvec_cw(p, q, prec);
-        if (st) return st;
-        if (prec == MLBLUP_FP64) info.fp64_matvecs++;
-        else info.lowp_matvecs++;
-        st = pcg_alpha(p, q, nw, at(w.part), at(w.sc), s);
-        if (st) return st;
-        st = pcg_update_xr(dx, r, p, q, nw, at(w.part), at(w.sc), s);
-        if (st) return st;
-        if (pc) {
-          if ((st = precond_apply(*pc, r, z, s))) return st;
-          if ((st = pcg_rz_partial(r, z, nw, at(w.part), s))) return st;
-        }
-        st = pcg_finish_beta(at(w.part), pc != nullptr, at(w.sc), s);
-        if (st) return st;
-        st = read_scalars();
-        if (st) return st;
-        --iters_left;
-        if (o.history_host && info.inner_iters < o.history_cap)
-          o.history_host[info.inner_iters] = std::sqrt(sc_host[S_RR]) / bnorm;
-        info.inner_iters++;
-        if (sc_host[S_FLAG] != 0.0) {
-          // fold what was gained so far into x, then report the breakdown
-          (void)vec_axpy(1.0, dx, x, nw, s);
-          return fail(MLBLUP_EBREAKDOWN, "pcg_solve: breakdown (p.q <= 0 or non-finite scalar)");
-        }
-        if (std::sqrt(sc_host[S_RR]) <= target * rnorm) break;
-        st = pcg_update_p(p, zz, nw, at(w.sc), s);
-        if (st) return st;
-      }
-      st = vec_axpy(1.0, dx, x, nw, s);
-      if (st) return st;
+      if ((st = matvec_cw(p2, q2, MLBLUP_FP64))) return st;
+      info.fp64_matvecs++;
+      if ((st = pcg_start(r2, p2, nw, at(w.part), sc2, s))) return st;  // sc2[RZ] = r . p
+      if ((st = pcg_alpha(p2, q2, nw, at(w.part), sc2, s))) return st;
+      if ((st = pcg_update_xr(x, r2, p2, q2, nw, at(w.part), sc2, s))) return st;
+      if ((st = pcg_finish_beta(at(w.part), false, sc2, s))) return st;
+      if ((st = read_scalars(sc2))) return st;
+      if (sc_host[S_FLAG] != 0.0) return fail(MLBLUP_EBREAKDOWN, "pcg_solve: breakdown in the outer iteration");
+      rnorm = std::sqrt(sc_host[S_RR]);
     }
   }
 };
@@ -350,8 +401,8 @@ mlblup_pcg_opts default_opts() {
   o.rtol = 1e-8;
   o.max_iter = 1000;
   o.precision = MLBLUP_FP64;
-  o.refine_max = 8;
-  o.inner_rtol = 1e-5;
+  o.refine_max = 200;
+  o.inner_rtol = 1e-2;
   o.precond = nullptr;
   o.history_cap = 0;
   o.history_host = nullptr;
@@ -613,7 +664,7 @@ static int check_opts(const mlblup_pcg_opts* opts, mlblup_pcg_opts* o) {
   if (o->history_cap < 0 || (o->history_cap > 0 && !o->history_host)) return fail(MLBLUP_EINVAL, "pcg options: bad history");
   if (!(o->rtol > 0) || o->max_iter < 0 || o->precision < MLBLUP_FP64 || o->precision > MLBLUP_MFMA_BF16X3)
     return fail(MLBLUP_EINVAL, "pcg options: need rtol > 0, max_iter >= 0, known precision");
-  if (o->refine_max <= 0) o->refine_max = 8;
+  if (o->refine_max <= 0) o->refine_max = 200;
   return MLBLUP_OK;
 }
 

@@ -39,6 +39,11 @@ struct PairArgs {
 int32_t pair_splits(int64_t m, int64_t n, int32_t d, int32_t precision);
 // Workspace bytes for the partial sums.
 int64_t pair_workspace_bytes(int64_t m, int64_t n, int32_t d, int32_t precision, int32_t outputs);
+// Symmetric square product (pair_sym.hip): each unordered pair once.
+bool sym_supported(int d);
+bool sym_worthwhile(int64_t n);
+int64_t sym_workspace_bytes(int64_t n, int outputs);
+int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s);
 // Validates and launches (pair kernel + split reduction).
 int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s);
 
@@ -80,6 +85,8 @@ int pcg_rz_partial(const double* r, const double* z, int64_t n, double* part, hi
 // sc[S_RR] = |r|^2, beta = rz_new / rz (rz = |r|^2 without preconditioner)
 int pcg_finish_beta(double* part, bool has_z, double* sc, hipStream_t s);
 int pcg_update_p(double* p, const double* z, int64_t n, const double* sc, hipStream_t s);
+// flexible-CG direction: p = z - (z.q_prev / p_prev.q_prev) p  (sc[S_DOT] = z.q_prev, sc[S_PQ])
+int fcg_update_p(double* p, const double* z, int64_t n, const double* sc, hipStream_t s);
 // set sc[S_RZ] = r.z (start of an inner solve)
 int pcg_start(const double* r, const double* z, int64_t n, double* part, double* sc, hipStream_t s);
 // z = r / diag

@@ -180,6 +180,13 @@ __global__ __launch_bounds__(kT) void update_p(double* __restrict__ p, const dou
     p[i] = fma(beta, p[i], z[i]);
 }
 
+__global__ __launch_bounds__(kT) void fcg_p(double* __restrict__ p, const double* __restrict__ z, int64_t n,
+                                            const double* __restrict__ sc) {
+  const double beta = -sc[S_DOT] / sc[S_PQ];
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    p[i] = fma(beta, p[i], z[i]);
+}
+
 __global__ __launch_bounds__(kT) void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) b[i] = a[i];
 }
@@ -316,6 +323,11 @@ int pcg_finish_beta(double* part, bool has_z, double* sc, hipStream_t s) {
 int pcg_update_p(double* p, const double* z, int64_t n, const double* sc, hipStream_t s) {
   hipLaunchKernelGGL(update_p, dim3(grid_for(n)), dim3(kT), 0, s, p, z, n, sc);
   return hip_check(hipGetLastError(), "update_p launch");
+}
+
+int fcg_update_p(double* p, const double* z, int64_t n, const double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(fcg_p, dim3(grid_for(n)), dim3(kT), 0, s, p, z, n, sc);
+  return hip_check(hipGetLastError(), "fcg_p launch");
 }
 
 int pcg_start(const double* r, const double* z, int64_t n, double* part, double* sc, hipStream_t s) {

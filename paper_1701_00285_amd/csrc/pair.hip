@@ -23,40 +23,17 @@
 // with FP32 per-tile sums folded into FP64 accumulators.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "device.h"
+#include "pairmath.h"
 
 namespace mlb {
 namespace {
 
 constexpr int kThreads = 256;
 constexpr int kTile = 128;
-
-template <int NU2>
-__device__ __forceinline__ double pval(double z) {
-  if constexpr (NU2 == 1) return 1.0;
-  else if constexpr (NU2 == 3) return 1.0 + z;
-  else return fma(z, fma(z, 1.0 / 3.0, 1.0), 1.0);
-}
-template <int NU2>
-__device__ __forceinline__ double pder(double z) {
-  if constexpr (NU2 == 1) return z;
-  else if constexpr (NU2 == 3) return z * z;
-  else return (z * z) * fma(z, 1.0 / 3.0, 1.0 / 3.0);
-}
-template <int NU2>
-__device__ __forceinline__ float pvalf(float z) {
-  if constexpr (NU2 == 1) return 1.0f;
-  else if constexpr (NU2 == 3) return 1.0f + z;
-  else return fmaf(z, fmaf(z, 1.0f / 3.0f, 1.0f), 1.0f);
-}
-template <int NU2>
-__device__ __forceinline__ float pderf(float z) {
-  if constexpr (NU2 == 1) return z;
-  else if constexpr (NU2 == 3) return z * z;
-  else return (z * z) * fmaf(z, 1.0f / 3.0f, 1.0f / 3.0f);
-}
 
 // D > 0: compile-time dimension.  FP32T: FP32 transcendentals.
 template <int D, int NU2, int OUT, int R, bool FP32T>
@@ -66,6 +43,8 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const double* __restrict
                                                         double* __restrict__ pdy, double zs, int64_t cps) {
   constexpr int SD = D + 1;
   __shared__ double tile[kTile * SD];
+  __shared__ double tab[kExpTab];
+  exp_table_fill(tab);
   const int tid = threadIdx.x;
   const int64_t rbase = (int64_t)blockIdx.x * (kThreads * R);
   double xr[R][D];
@@ -91,55 +70,24 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const double* __restrict
     }
     for (int j = tid; j < kTile; j += kThreads) tile[j * SD + D] = (j < cnt) ? x[j0 + j] : 0.0;
     __syncthreads();
-    if constexpr (!FP32T) {
 #pragma unroll 2
-      for (int j = 0; j < kTile; ++j) {
-        double cj[D];
+    for (int j = 0; j < kTile; ++j) {
+      double cj[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) cj[k] = tile[j * SD + k];
-        const double aj = tile[j * SD + D];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          double s = 0.0;
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            const double t = xr[r][k] - cj[k];
-            s = fma(t, t, s);
-          }
-          const double z = sqrt(s);
-          const double e = exp(-z);
-          if constexpr (OUT & 1) acc[r] = fma(pval<NU2>(z) * e, aj, acc[r]);
-          if constexpr (OUT & 2) dacc[r] = fma(pder<NU2>(z) * e, aj, dacc[r]);
-        }
-      }
-    } else {
-      float facc[R], fdacc[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) facc[r] = fdacc[r] = 0.0f;
-#pragma unroll 2
-      for (int j = 0; j < kTile; ++j) {
-        double cj[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) cj[k] = tile[j * SD + k];
-        const float aj = (float)tile[j * SD + D];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          double s = 0.0;
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            const double t = xr[r][k] - cj[k];
-            s = fma(t, t, s);
-          }
-          const float z = __builtin_amdgcn_sqrtf((float)s);
-          const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
-          if constexpr (OUT & 1) facc[r] = fmaf(pvalf<NU2>(z) * e, aj, facc[r]);
-          if constexpr (OUT & 2) fdacc[r] = fmaf(pderf<NU2>(z) * e, aj, fdacc[r]);
-        }
-      }
+      for (int k = 0; k < D; ++k) cj[k] = tile[j * SD + k];
+      const double aj = tile[j * SD + D];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        acc[r] += (double)facc[r];
-        dacc[r] += (double)fdacc[r];
+        double s = 1e-300;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          const double t = xr[r][k] - cj[k];
+          s = fma(t, t, s);
+        }
+        double f = 0.0, g = 0.0;
+        pair_value<NU2, OUT, FP32T>(s, tab, f, g);
+        if constexpr (OUT & 1) acc[r] = fma(f, aj, acc[r]);
+        if constexpr (OUT & 2) dacc[r] = fma(g, aj, dacc[r]);
       }
     }
   }
@@ -160,28 +108,24 @@ __global__ __launch_bounds__(kThreads) void pair_kernel_any(const double* __rest
                                                             const double* __restrict__ cols, int64_t n, int d,
                                                             const double* __restrict__ x, double* __restrict__ py,
                                                             double* __restrict__ pdy, double zs, int64_t cps) {
+  __shared__ double tab[kExpTab];
+  exp_table_fill(tab);
+  __syncthreads();
   const int64_t i0 = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t i = i0 < m ? i0 : m - 1;
   const int64_t c0 = (int64_t)blockIdx.y * cps;
   const int64_t c1 = (c0 + cps < n) ? c0 + cps : n;
   double acc = 0.0, dacc = 0.0;
   for (int64_t j = c0; j < c1; ++j) {
-    double s = 0.0;
+    double s = 1e-300;
     for (int k = 0; k < d; ++k) {
       const double t = (rows[i * d + k] - cols[j * d + k]) * zs;
       s = fma(t, t, s);
     }
-    double z, e;
-    if constexpr (FP32T) {
-      const float zf = __builtin_amdgcn_sqrtf((float)s);
-      z = zf;
-      e = __builtin_amdgcn_exp2f(-1.4426950408889634f * zf);
-    } else {
-      z = sqrt(s);
-      e = exp(-z);
-    }
-    if constexpr (OUT & 1) acc = fma(pval<NU2>(z) * e, x[j], acc);
-    if constexpr (OUT & 2) dacc = fma(pder<NU2>(z) * e, x[j], dacc);
+    double f = 0.0, g = 0.0;
+    pair_value<NU2, OUT, FP32T>(s, tab, f, g);
+    if constexpr (OUT & 1) acc = fma(f, x[j], acc);
+    if constexpr (OUT & 2) dacc = fma(g, x[j], dacc);
   }
   if (i0 < m) {
     if constexpr (OUT & 1) py[(int64_t)blockIdx.y * m + i0] = acc;
@@ -278,7 +222,9 @@ int64_t pair_workspace_bytes(int64_t m, int64_t n, int32_t d, int32_t precision,
   const int64_t S = pair_splits(m, n, d, precision);
   const int64_t per = S * m * (int64_t)sizeof(double);
   const int64_t aligned = (per + 255) / 256 * 256;
-  return aligned * (((outputs & 1) ? 1 : 0) + ((outputs & 2) ? 1 : 0));
+  int64_t b = aligned * (((outputs & 1) ? 1 : 0) + ((outputs & 2) ? 1 : 0));
+  if (m == n && sym_supported(d) && sym_worthwhile(n)) b = std::max(b, sym_workspace_bytes(n, outputs));
+  return b;
 }
 
 int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s) {
@@ -303,13 +249,28 @@ int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s
   const int64_t need = pair_workspace_bytes(a.m, a.n, a.d, a.precision, a.outputs);
   if (!work || work_bytes < need)
     return fail(MLBLUP_EINVAL, "cov_matvec: workspace too small (need " + std::to_string(need) + " bytes)");
+  const double zs = std::sqrt((double)a.nu2) / a.rho;  // sqrt(2 nu) / rho
+  if (a.rows == a.cols && a.m == a.n && sym_supported(a.d) && sym_worthwhile(a.n)) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (profile_on()) {
+      MLB_HIP(hipEventCreate(&e0));
+      MLB_HIP(hipEventCreate(&e1));
+      MLB_HIP(hipEventRecord(e0, s));
+    }
+    const int st = sym_launch(a, zs, work, s);
+    if (st) return st;
+    if (profile_on()) {
+      MLB_HIP(hipEventRecord(e1, s));
+      profile_note(e0, e1, (double)a.m * (double)a.n, a.precision * 4 + a.outputs);
+    }
+    return MLBLUP_OK;
+  }
   const int S = pair_splits(a.m, a.n, a.d, a.precision);
   int64_t cps = (a.n + S - 1) / S;
   cps = (cps + kTile - 1) / kTile * kTile;  // splits start on tile boundaries
   const int64_t per = ((S * a.m * (int64_t)sizeof(double)) + 255) / 256 * 256;
   double* py = (a.outputs & 1) ? (double*)work : nullptr;
   double* pdy = (a.outputs & 2) ? (double*)((char*)work + ((a.outputs & 1) ? per : 0)) : nullptr;
-  const double zs = std::sqrt((double)a.nu2) / a.rho;  // sqrt(2 nu) / rho
   // reduced precisions: the FP32-transcendental kernel (MFMA variants share it
   // until their specialised kernels apply)
   const bool f32 = a.precision != MLBLUP_FP64;

@@ -1,0 +1,251 @@
+// Symmetric square product y = C x (C_ij = C_ji): every unordered pair is
+// evaluated once and feeds both row sums.
+//
+// Blocks of 512 points (tree order).  A workgroup (4 waves x 64 lanes x 2
+// rows) owns a row block S and one column block S'.  Column points stream
+// through LDS in chunks of 128; a wave walks each group of 64 columns in 64
+// steps in which lane l evaluates column (l + k*delta) mod 64 of the group
+// (a lane-varying LDS read) for its two rows.  Row sums stay in the lane;
+// the column sum of the lane's current column travels with it: a register
+// is rotated by one lane (DPP wave rotate) after every step, so after 64
+// steps lane l holds the wave's whole contribution to column l.  The four
+// waves' column sums are added in fixed order through LDS.
+//
+// Schedule without atomics: diagonal tiles (S, S) are computed as full
+// squares (row sums only).  Off-diagonal tiles follow a round-robin
+// tournament: in round r = 1..T/2, block S pairs with (S + r) mod T (for
+// even T the last round keeps S < T/2 only), so in one round every block
+// is a row block at most once and a column block at most once; each round
+// writes one row-partial and one column-partial vector, and the rounds are
+// summed in fixed order.  Results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device.h"
+#include "pairmath.h"
+
+namespace mlb {
+namespace {
+
+constexpr int kT = 256;
+constexpr int kBlk = 512;   // points per block
+constexpr int kChunk = 128; // columns staged per LDS fill
+
+template <int D, int NU2, int OUT, bool F>
+__global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts, const double* __restrict__ x,
+                                                 int64_t n, int T, int round0, int diag, double zs,
+                                                 double* __restrict__ prow, double* __restrict__ pcol,
+                                                 double* __restrict__ pdrow, double* __restrict__ pdcol) {
+  constexpr int SD = D + 1;
+  __shared__ double cp[kChunk * SD];
+  __shared__ double cred[4][kChunk];
+  __shared__ double cdred[4][kChunk];
+  __shared__ double tab[kExpTab];
+  const int S = blockIdx.x;
+  const int r = round0 + blockIdx.y;
+  int Sp = S;
+  if (!diag) {
+    Sp = (S + r) % T;
+    if ((T % 2 == 0) && (2 * r == T) && S >= T / 2) return;  // whole block exits
+  }
+  exp_table_fill(tab);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // lane rotation direction: after one rotation lane l holds lane (l + delta)'s value
+  const int delta = (wave_rotate1_i(lane) - lane) & 63;
+
+  double xr[2][D], ar[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int64_t i = (int64_t)S * kBlk + wave * 128 + q * 64 + lane;
+    const int64_t ii = i < n ? i : n - 1;
+#pragma unroll
+    for (int k = 0; k < D; ++k) xr[q][k] = pts[ii * D + k] * zs;
+    ar[q] = i < n ? x[i] : 0.0;
+  }
+  double racc[2] = {0.0, 0.0}, rdacc[2] = {0.0, 0.0};
+  const int64_t cbase = (int64_t)Sp * kBlk;
+  for (int c0 = 0; c0 < kBlk; c0 += kChunk) {
+    __syncthreads();
+    for (int e = tid; e < kChunk * D; e += kT) {
+      const int j = e / D, k = e - j * D;
+      const int64_t gj = cbase + c0 + j;
+      cp[j * SD + k] = gj < n ? pts[gj * D + k] * zs : 0.0;
+    }
+    for (int j = tid; j < kChunk; j += kT) {
+      const int64_t gj = cbase + c0 + j;
+      cp[j * SD + D] = gj < n ? x[gj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int sub = 0; sub < kChunk; sub += 64) {
+      double cacc = 0.0, cdacc = 0.0;
+      int c = lane;
+#pragma unroll 2
+      for (int k = 0; k < 64; ++k) {
+        const double* cj = &cp[(sub + c) * SD];
+        double cv[D];
+#pragma unroll
+        for (int t = 0; t < D; ++t) cv[t] = cj[t];
+        const double aj = cj[D];
+        double cpart = 0.0, cdpart = 0.0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          double s = 1e-300;
+#pragma unroll
+          for (int t = 0; t < D; ++t) {
+            const double u = xr[q][t] - cv[t];
+            s = fma(u, u, s);
+          }
+          double f = 0.0, g = 0.0;
+          pair_value<NU2, OUT, F>(s, tab, f, g);
+          if constexpr (OUT & 1) {
+            racc[q] = fma(f, aj, racc[q]);
+            cpart = fma(f, ar[q], cpart);
+          }
+          if constexpr (OUT & 2) {
+            rdacc[q] = fma(g, aj, rdacc[q]);
+            cdpart = fma(g, ar[q], cdpart);
+          }
+        }
+        if constexpr (OUT & 1) cacc = wave_rotate1(cacc + cpart);
+        if constexpr (OUT & 2) cdacc = wave_rotate1(cdacc + cdpart);
+        c = (c + delta) & 63;
+      }
+      if constexpr (OUT & 1) cred[wave][sub + lane] = cacc;
+      if constexpr (OUT & 2) cdred[wave][sub + lane] = cdacc;
+    }
+    __syncthreads();
+    if (!diag && tid < kChunk) {
+      const int64_t gj = cbase + c0 + tid;
+      if (gj < n) {
+        const int64_t slot = (int64_t)blockIdx.y * n + gj;
+        if constexpr (OUT & 1) pcol[slot] = ((cred[0][tid] + cred[1][tid]) + cred[2][tid]) + cred[3][tid];
+        if constexpr (OUT & 2) pdcol[slot] = ((cdred[0][tid] + cdred[1][tid]) + cdred[2][tid]) + cdred[3][tid];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int64_t i = (int64_t)S * kBlk + wave * 128 + q * 64 + lane;
+    if (i < n) {
+      const int64_t slot = (int64_t)blockIdx.y * n + i;
+      if constexpr (OUT & 1) prow[slot] = racc[q];
+      if constexpr (OUT & 2) pdrow[slot] = rdacc[q];
+    }
+  }
+}
+
+// acc += sum over this launch's rounds of row and column partials (fixed
+// order); on the last launch y = scale * acc.  acc starts as the diagonal
+// partial.
+__global__ __launch_bounds__(kT) void sym_reduce(const double* __restrict__ prow, const double* __restrict__ pcol,
+                                                 int nr, int64_t n, int T, int round0, int last, double scale,
+                                                 double* __restrict__ acc, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  const int blk = (int)(i / kBlk);
+  double s = acc[i];
+  for (int q = 0; q < nr; ++q) {
+    const int r = round0 + q;
+    const bool half = (T % 2 == 0) && (2 * r == T);
+    // as a row of block blk: absent in the half round for blk >= T/2
+    if (!(half && blk >= T / 2)) s += prow[(int64_t)q * n + i];
+    // as a column: written by block (blk - r) mod T; absent in the half round when that block >= T/2
+    const int src = ((blk - r) % T + T) % T;
+    if (!(half && src >= T / 2)) s += pcol[(int64_t)q * n + i];
+  }
+  if (last) y[i] = scale * s;
+  else acc[i] = s;
+}
+
+template <int D, int NU2, int OUT, bool F>
+void launch(const double* pts, const double* x, int64_t n, int T, int round0, int nr, int diag, double zs,
+            double* prow, double* pcol, double* pdrow, double* pdcol, hipStream_t s) {
+  hipLaunchKernelGGL((sym_kernel<D, NU2, OUT, F>), dim3(T, nr), dim3(kT), 0, s, pts, x, n, T, round0, diag, zs, prow,
+                     pcol, pdrow, pdcol);
+}
+
+using LaunchFn = void (*)(const double*, const double*, int64_t, int, int, int, int, double, double*, double*, double*,
+                          double*, hipStream_t);
+
+template <int NU2, int OUT, bool F>
+LaunchFn pick_d(int d) {
+  switch (d) {
+    case 1: return launch<1, NU2, OUT, F>;
+    case 2: return launch<2, NU2, OUT, F>;
+    case 3: return launch<3, NU2, OUT, F>;
+    case 4: return launch<4, NU2, OUT, F>;
+    case 5: return launch<5, NU2, OUT, F>;
+    case 6: return launch<6, NU2, OUT, F>;
+    case 8: return launch<8, NU2, OUT, F>;
+    case 10: return launch<10, NU2, OUT, F>;
+    case 16: return launch<16, NU2, OUT, F>;
+    case 20: return launch<20, NU2, OUT, F>;
+    default: return nullptr;
+  }
+}
+template <int NU2, bool F>
+LaunchFn pick_out(int out, int d) {
+  if (out == 1) return pick_d<NU2, 1, F>(d);
+  if (out == 2) return pick_d<NU2, 2, F>(d);
+  return pick_d<NU2, 3, F>(d);
+}
+template <bool F>
+LaunchFn pick_nu(int nu2, int out, int d) {
+  if (nu2 == 1) return pick_out<1, F>(out, d);
+  if (nu2 == 3) return pick_out<3, F>(out, d);
+  return pick_out<5, F>(out, d);
+}
+
+constexpr int kRoundsPerLaunch = 16;
+
+}  // namespace
+
+bool sym_supported(int d) { return pick_nu<false>(1, 1, d) != nullptr; }
+
+// below this size the tiled row kernel wins (too few blocks to fill the chip)
+bool sym_worthwhile(int64_t n) { return n >= 16384; }
+
+int64_t sym_workspace_bytes(int64_t n, int outputs) {
+  const int64_t per = (int64_t)(2 * kRoundsPerLaunch + 1) * n * 8;
+  const int64_t a = (per + 255) / 256 * 256;
+  return a * ((outputs & 1 ? 1 : 0) + (outputs & 2 ? 1 : 0));
+}
+
+int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s) {
+  const int64_t n = a.n;
+  const int T = (int)((n + kBlk - 1) / kBlk);
+  const bool f32 = a.precision != MLBLUP_FP64;
+  LaunchFn fn = f32 ? pick_nu<true>(a.nu2, a.outputs, a.d) : pick_nu<false>(a.nu2, a.outputs, a.d);
+  if (!fn) return fail(MLBLUP_EINVAL, "symmetric pair kernel: dimension not compiled");
+  const int64_t per = ((int64_t)(2 * kRoundsPerLaunch + 1) * n * 8 + 255) / 256 * 256;
+  double* base_v = (a.outputs & 1) ? (double*)work : nullptr;
+  double* base_d = (a.outputs & 2) ? (double*)((char*)work + ((a.outputs & 1) ? per : 0)) : nullptr;
+  auto parts = [&](double* b, double*& pdiag, double*& prow, double*& pcol) {
+    pdiag = b;
+    prow = b ? b + n : nullptr;
+    pcol = b ? b + n + (int64_t)kRoundsPerLaunch * n : nullptr;
+  };
+  double *vd, *vr, *vc, *dd, *dr, *dc;
+  parts(base_v, vd, vr, vc);
+  parts(base_d, dd, dr, dc);
+  const unsigned g = (unsigned)((n + kT - 1) / kT);
+  // diagonal tiles
+  fn(a.cols, a.x, n, T, 0, 1, 1, zs, vd, nullptr, dd, nullptr, s);
+  const int rounds = T / 2;
+  int r0 = 1;
+  do {
+    const int nr = std::max(0, std::min(kRoundsPerLaunch, rounds - r0 + 1));
+    if (nr > 0) fn(a.cols, a.x, n, T, r0, nr, 0, zs, vr, vc, dr, dc, s);
+    const int last = (r0 + nr > rounds) ? 1 : 0;
+    if (a.outputs & 1)
+      hipLaunchKernelGGL(sym_reduce, dim3(g), dim3(kT), 0, s, vr, vc, nr, n, T, r0, last, a.sigma2, vd, a.y);
+    if (a.outputs & 2)
+      hipLaunchKernelGGL(sym_reduce, dim3(g), dim3(kT), 0, s, dr, dc, nr, n, T, r0, last, a.sigma2, dd, a.dy);
+    r0 += kRoundsPerLaunch;
+  } while (r0 <= rounds);
+  return hip_check(hipGetLastError(), "symmetric pair kernel launch");
+}
+
+}  // namespace mlb

@@ -106,3 +106,32 @@ def test_full_size_sampled_rows(k):
     assert row_relerr(host(y)[idx], ref, sc) < FP64_TOL
     y, _ = cov_matvec(P, P, X, wl.nu, wl.rho, precision=FP32)
     assert row_relerr(host(y)[idx], ref, sc) < FP32_TOL
+
+
+@pytest.mark.parametrize("n", [16384, 16385, 16897, 17408])
+def test_symmetric_square_product(n):
+    """Square products (rows and cols the same array, n >= 16,384) take the
+    symmetric path; ragged last block, odd and even numbers of blocks.  The
+    oracle checks 96 sampled rows (full rows of the product)."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import DLOGRHO, FP32, FP64, VALUE, cov_matvec
+    d = 3 if n % 2 else 5
+    pts = synth.uniform_cloud(n, d, 40 + n)
+    x = synth.standard_normal(n, 41 + n)
+    say(f"symmetric n={n} d={d}")
+    idx = np.unique(np.concatenate([np.arange(0, n, max(1, n // 64)), np.arange(n - 32, n)]))
+    for nu in (0.5, 1.5, 2.5):
+        rho = 0.25
+        ref = brute.cov_matvec(pts[idx], pts, x, nu, rho, 1.3)
+        dref = brute.cov_matvec(pts[idx], pts, x, nu, rho, 1.3, deriv=True)
+        sc = 1.3 * _scale(pts[idx], pts, x, nu, rho)
+        P, X = dev(pts), dev(x)
+        for prec, tol in ((FP64, FP64_TOL), (FP32, FP32_TOL)):
+            y, dy = cov_matvec(P, P, X, nu, rho, 1.3, precision=prec, outputs=VALUE | DLOGRHO)
+            assert row_relerr(host(y)[idx], ref, sc) < tol
+            assert row_relerr(host(dy)[idx], dref, sc) < tol
+            y1, _ = cov_matvec(P, P, X, nu, rho, 1.3, precision=prec, outputs=VALUE)
+            assert np.array_equal(host(y1), host(y))
+            # the row-tiled path on a copy of the same points agrees everywhere
+            yr, _ = cov_matvec(P, P.clone(), X, nu, rho, 1.3, precision=prec)
+            assert np.max(np.abs(host(yr) - host(y1)) / (np.abs(host(yr)) + 1e-3)) < tol
