@@ -2,10 +2,12 @@
 """Benchmark of the multilevel BLUP solve on one MI355X.
 
 One step = one pass of the whole hot path over one synthetic workload:
-kd-tree and multilevel basis (host C++), basis upload, W Z, the FP64 PCG
-solve of C_W gamma_W = Z_W to relres 1e-8, the mixed-precision solve of
-the same system to the same FP64 relres (iterative refinement), beta-hat,
-predictions at the targets, Q and dQ/dlog rho.  Inputs (points, Z,
+kd-tree and multilevel basis (host C++), basis upload, the block
+preconditioner, W Z, the FP64 PCG solve of C_W gamma_W = Z_W to relres
+1e-8, the mixed-precision solve of the same system to the same FP64 relres
+(flexible-CG iterative refinement, FP32 kernel values), the predictor
+(warm-started from the FP64 solution: true FP64 residual, gamma, beta-hat,
+predictions at the targets) and Q, dQ/dlog rho.  Inputs (points, Z,
 targets) are resident in HBM when the timed region starts.
 
 The default workload is 65,536 uniform points in [0,1]^3, Matern nu=3/2,
@@ -32,13 +34,14 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_VALU_TFLOPS = 78.6      # 256 CU x 2.4 GHz x 64 lanes x 2 flop (FMA)
 
 
-def flops_per_pair(d: int, nu: float) -> int:
-    """Algorithmic flops of one pair (FMA = 2): d differences + d squared
-    accumulations (3d), sqrt (1), exp (1), the Matern polynomial (nu=1/2: 0,
-    3/2: 1+z and the product with e^-z = 2, 5/2: 1+z+z^2/3 (two FMA) and the
-    product = 5) and the accumulation FMA (2)."""
+def flops_per_unordered_pair(d: int, nu: float) -> int:
+    """Algorithmic flops of one distinct pair {i, j} of a symmetric product
+    (FMA = 2): d differences + d squared accumulations (3d), sqrt (1), exp (1),
+    the Matern polynomial (nu=1/2: 0; 3/2: 1+z and the product with e^-z = 2;
+    5/2: two FMA and the product = 5) and two accumulation FMAs (4), one for
+    y_i and one for y_j."""
     poly = {0.5: 0, 1.5: 2, 2.5: 5}[nu]
-    return 3 * d + 4 + poly
+    return 3 * d + 6 + poly
 
 
 def cpu_baseline(wl, rows: int):
@@ -61,7 +64,7 @@ def cpu_baseline(wl, rows: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--mixed", type=int, default=-1, help="precision of the mixed solve (default: FP32 for d<8, "
@@ -78,7 +81,7 @@ def main():
     import torch
 
     import synth
-    from paper_1701_00285_amd import (DLOGRHO, FP32, FP64, MFMA_FP32, VALUE, PcgOptions, Solver, profile_enable,
+    from paper_1701_00285_amd import (FP32, FP64, MFMA_FP32, PREC_BLOCK, VALUE, PcgOptions, Solver, profile_enable,
                                       profile_read)
 
     torch.cuda.set_device(0)
@@ -92,22 +95,28 @@ def main():
         t = [time.perf_counter()]
         pts_host = P.cpu().numpy()
         s = Solver(pts_host, wl.degree_w, wl.leaf_max, wl.nu, wl.rho, wl.sigma2, max_targets=T.shape[0])
-        torch.cuda.synchronize()
-        t.append(time.perf_counter())
-        out = s.predict(Z, T, PcgOptions(rtol=1e-8, precision=FP64))
-        torch.cuda.synchronize()
-        t.append(time.perf_counter())
+        pc = s.precond(PREC_BLOCK)
         zt = s.to_tree(Z)
         zw, _ = s.apply_W(zt)
-        gw_m, info_m, _ = s.solve(zw, PcgOptions(rtol=1e-8, precision=mixed, inner_rtol=1e-4))
+        torch.cuda.synchronize()
+        t.append(time.perf_counter())
+        gw64, info64, _ = s.solve(zw, PcgOptions(rtol=1e-8, max_iter=40000, precision=FP64, precond=pc))
+        torch.cuda.synchronize()
+        t.append(time.perf_counter())
+        gwm, infom, _ = s.solve(zw, PcgOptions(rtol=1e-8, max_iter=40000, precision=mixed, inner_rtol=0.1,
+                                               precond=pc))
+        torch.cuda.synchronize()
+        t.append(time.perf_counter())
+        out = s.predict(Z, T, PcgOptions(rtol=1e-8, max_iter=40000, precision=FP64, precond=pc), gamma_w0=gw64)
         torch.cuda.synchronize()
         t.append(time.perf_counter())
         q, dq = s.quad_grad(zt, out["gamma_tree"])
         torch.cuda.synchronize()
         t.append(time.perf_counter())
-        rec.append(dict(setup=t[1] - t[0], predict_fp64=t[2] - t[1], solve_mixed=t[3] - t[2], grad=t[4] - t[3],
-                        total=t[4] - t[0], info64=out["info"], infom=info_m, q=q, dq=dq,
-                        gamma_w64=out["gamma_w"], gamma_wm=gw_m, solver=s))
+        rd = float(torch.linalg.norm(gwm - gw64) / torch.linalg.norm(gw64))
+        rec.append(dict(setup=t[1] - t[0], solve_fp64=t[2] - t[1], solve_mixed=t[3] - t[2], predict=t[4] - t[3],
+                        grad=t[5] - t[4], total=t[5] - t[0], info64=info64, infom=infom, infop=out["info"], q=q,
+                        dq=dq, reldiff=rd, p=s.p))
 
     warm = []
     for _ in range(a.warmup):
@@ -125,28 +134,17 @@ def main():
     prof = profile_read()
     profile_enable(False)
 
-    # FP64-only solve time (separately timed, same system): the predict phase
-    # contains extra products (beta, targets)
-    s = recs[-1]["solver"]
-    zw, _ = s.apply_W(s.to_tree(Z))
-    torch.cuda.synchronize()
-    ts = time.perf_counter()
-    gw64, info64s, _ = s.solve(zw, PcgOptions(rtol=1e-8, precision=FP64))
-    torch.cuda.synchronize()
-    solve64 = time.perf_counter() - ts
-    ts = time.perf_counter()
-    gwm, infoms, _ = s.solve(zw, PcgOptions(rtol=1e-8, precision=mixed, inner_rtol=1e-4))
-    torch.cuda.synchronize()
-    solvem = time.perf_counter() - ts
-    rel_diff = float(torch.linalg.norm(gwm - gw64) / torch.linalg.norm(gw64))
-
     total_pairs = sum(v[2] for v in prof.values())
     value = total_pairs / elapsed / 1e9
+    n = wl.n
     ms64, n64, pairs64 = prof.get((FP64, VALUE), (0.0, 0, 0.0))
     msm, nm, pairsm = prof.get((mixed, VALUE), (0.0, 0, 0.0))
-    fpp = flops_per_pair(wl.d, wl.nu)
-    achieved = pairs64 * fpp / (ms64 * 1e-3) / 1e12 if ms64 > 0 else 0.0
+    # the square launches of the FP64 product (the dominant kernel): logical
+    # pairs n^2 each; the target launches (m x n) are counted apart
+    sq64 = int(round((pairs64 - a.steps * T.shape[0] * n) / (n * n))) if n64 else 0
+    fpp = flops_per_unordered_pair(wl.d, wl.nu)
     last = recs[-1]
+    i64, im, ip = last["info64"], last["infom"], last["infop"]
     out = {
         "metric": "Matern C.x Gpairs/s (whole step); BLUP solve time to relres 1e-8, FP64 vs mixed",
         "value": round(value, 3),
@@ -160,28 +158,39 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded)",
-        "config": {"workload": wl.name, "n": wl.n, "d": wl.d, "nu": wl.nu, "rho": wl.rho, "trend_p": s.p,
-                   "leaf": wl.leaf_max, "targets": int(T.shape[0]), "rtol": 1e-8, "mixed_precision": mixed},
-        "phases_s": {k: round(last[k], 4) for k in ("setup", "predict_fp64", "solve_mixed", "grad", "total")},
-        "solve_s": {"fp64": round(solve64, 4), "mixed": round(solvem, 4), "speedup": round(solve64 / solvem, 3),
-                    "fp64_iters": info64s["inner_iters"], "fp64_matvecs": info64s["fp64_matvecs"],
-                    "mixed_inner_iters": infoms["inner_iters"], "mixed_outer": infoms["outer_iters"],
-                    "mixed_fp64_matvecs": infoms["fp64_matvecs"], "mixed_lowp_matvecs": infoms["lowp_matvecs"],
-                    "relres_fp64": info64s["relres_fp64"],
-                    "relres_mixed": infoms["relres_fp64"], "gamma_w_reldiff_mixed_vs_fp64": rel_diff},
+        "config": {"workload": wl.name, "n": n, "d": wl.d, "nu": wl.nu, "rho": wl.rho, "trend_p": last["p"],
+                   "leaf": wl.leaf_max, "targets": int(T.shape[0]), "rtol": 1e-8, "preconditioner": "cell blocks of C_W",
+                   "mixed_precision": mixed},
+        "phases_s": {k: round(last[k], 4) for k in ("setup", "solve_fp64", "solve_mixed", "predict", "grad", "total")},
+        "solve": {"fp64_s": round(last["solve_fp64"], 3), "mixed_s": round(last["solve_mixed"], 3),
+                  "speedup": round(last["solve_fp64"] / last["solve_mixed"], 3),
+                  "fp64_iters": i64["inner_iters"], "fp64_relres": i64["relres_fp64"],
+                  "mixed_outer": im["outer_iters"], "mixed_inner": im["inner_iters"],
+                  "mixed_fp64_matvecs": im["fp64_matvecs"], "mixed_lowp_matvecs": im["lowp_matvecs"],
+                  "mixed_relres_fp64": im["relres_fp64"], "gamma_w_reldiff_mixed_vs_fp64": last["reldiff"],
+                  "predict_warm_iters": ip["inner_iters"], "predict_relres": ip["relres_fp64"]},
         "pair_kernel": {
-            "fp64_gpairs_s": round(pairs64 / (ms64 * 1e-3) / 1e9, 2) if ms64 else None,
+            "fp64_logical_gpairs_s": round(pairs64 / (ms64 * 1e-3) / 1e9, 2) if ms64 else None,
             "fp64_launches": n64, "fp64_avg_launch_ms": round(ms64 / n64, 4) if n64 else None,
-            "mixed_gpairs_s": round(pairsm / (msm * 1e-3) / 1e9, 2) if msm else None,
+            "mixed_logical_gpairs_s": round(pairsm / (msm * 1e-3) / 1e9, 2) if msm else None,
             "mixed_launches": nm, "mixed_avg_launch_ms": round(msm / nm, 4) if nm else None,
             "pairs_per_step": total_pairs / a.steps,
-            "flops_per_pair": fpp,
         },
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4), "traffic": None,
-                     "kernel": "pair_kernel FP64 VALUE (square + target products)"},
-        "grad": {"Q": last["q"], "dQ_dlogrho": last["dq"]},
     }
+    # roofline of the dominant kernel: the FP64 square product (symmetric
+    # kernel).  Algorithmic flops per launch = n(n+1)/2 distinct pairs x
+    # flops_per_unordered_pair; the event time of those launches is the
+    # bucket time minus the target launches' share (estimated at the same
+    # per-pair rate as the bucket, which overstates their cost: conservative).
+    if n64 and sq64 > 0:
+        frac_sq = sq64 * n * n / pairs64
+        t_sq = ms64 * 1e-3 * frac_sq
+        achieved = sq64 * (n * (n + 1) / 2) * fpp / t_sq / 1e12
+        out["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4), "traffic": None,
+                           "kernel": "sym_kernel FP64 value (square C x)", "launches": sq64,
+                           "avg_launch_ms": round(t_sq / sq64 * 1e3, 4), "flops_per_unordered_pair": fpp}
+    out["grad"] = {"Q": last["q"], "dQ_dlogrho": last["dq"]}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_rows)
     print(json.dumps(out), flush=True)

@@ -5,12 +5,12 @@
  * a computational mathematics approach for high dimensional massive
  * datasets", arXiv:1701.00285.  Observations Z = X beta + eps at N sites in
  * d dimensions, eps ~ N(0, C(theta)) with a Matern covariance C, X the
- * total-degree monomial design (Sec. 1).  A kd-tree (Sec. 2.1, algorithms
+ * total-degree monomial design (Sec. 2).  A kd-tree (Sec. 3.1, algorithms
  * Rule / InitialTree / MakeTree) and a multilevel basis W orthogonal to
- * col(X) (Sec. 2.1 construction) turn the kriging system into the
- * well-conditioned C_W gamma_W = W Z with C_W = W C W^T (Sec. 5,
+ * col(X) (Sec. 3.1 construction) turn the kriging system into the
+ * well-conditioned C_W gamma_W = W Z with C_W = W C W^T (Sec. 5.2,
  * eqs. Spatial:eqn1-3), solved by a Krylov (PCG) iteration whose product is
- * the three-step W^T -> C -> W chain (Sec. 4.2).
+ * the three-step W^T -> C -> W chain (Sec. 6.2).
  *
  * Conventions for every entry point:
  *   - Return value is a status code (MLBLUP_OK = 0, negative on error); the
@@ -61,11 +61,11 @@ typedef struct mlblup_tree_s* mlblup_tree;
 typedef struct mlblup_basis_s* mlblup_basis;
 typedef struct mlblup_precond_s* mlblup_precond;
 
-/* Preconditioner kinds (preconditioner remark of Sec. 5). */
+/* Preconditioner kinds (preconditioner remark of Sec. 5.2). */
 #define MLBLUP_PREC_JACOBI 1   /* P_W = diag(C_W) */
 #define MLBLUP_PREC_BLOCK 2    /* P_W = the diagonal blocks of C_W, one per cell (its own wavelets) */
 
-/* Matern covariance sigma2 * phi(r; nu, rho), Definition in Sec. 2.1 with the
+/* Matern covariance sigma2 * phi(r; nu, rho), Definition in Sec. 3.1 with the
  * half-integer closed forms (nu = 1/2, 3/2, 5/2), rho > 0, sigma2 > 0. */
 typedef struct {
   double nu;
@@ -75,7 +75,7 @@ typedef struct {
 
 /* Krylov solve options.  rtol: stop when |Z_W - C_W gamma_W|_2 <= rtol |Z_W|_2
  * on the UNPRECONDITIONED system, measured with the FP64 product (remark on
- * the stopping rule, Sec. 4.2).  precision: arithmetic of the inner product
+ * the stopping rule, Sec. 6.2).  precision: arithmetic of the inner product
  * (MLBLUP_FP64 runs plain PCG with a final FP64 residual check; lower
  * precisions run an FP64 iterative-refinement loop around inner PCG
  * solves).  refine_max: outer refinement steps.  inner_rtol: relative
@@ -107,7 +107,7 @@ typedef struct {
 const char* mlblup_last_error(void);
 int32_t mlblup_version(void);
 
-/* ---- kd-tree (Sec. 2.1, algorithms Rule / InitialTree / MakeTree) ----------
+/* ---- kd-tree (Sec. 3.1, algorithms Rule / InitialTree / MakeTree) ----------
  * Splits each cell on the coordinate axis of maximal variance of its points
  * at the median: points ordered by (coordinate, input index), the first
  * ceil(m/2) go left.  A cell with <= leaf_max points is a leaf.  Nodes are
@@ -125,7 +125,7 @@ int mlblup_tree_nodes(mlblup_tree t, int64_t* begin, int64_t* end, int32_t* dept
                       int32_t* left, int32_t* right, double* threshold);
 void mlblup_tree_free(mlblup_tree t);
 
-/* ---- multilevel basis (Sec. 2.1 construction; operators W, L, P) ---------
+/* ---- multilevel basis (Sec. 3.1 construction; operators W, L, P) ---------
  * Bottom-up over the tree: for each cell the candidate vectors (leaf: unit
  * vectors of its points; internal: the children's scaling vectors) are
  * split by an orthogonal V into a scaling part spanning the range of
@@ -156,7 +156,7 @@ int mlblup_basis_upload(mlblup_basis b, void* dev_buf, int64_t bytes, void* stre
 int mlblup_basis_points_dev(mlblup_basis b, const double** pts_dev);
 void mlblup_basis_free(mlblup_basis b);
 
-/* ---- dense covariance product (Sec. 4.2, step (2) of the chain) ----------
+/* ---- dense covariance product (Sec. 6.2, step (2) of the chain) ----------
  * y_i = sum_j sigma2 phi(|r_i - c_j|) x_j over all m x n pairs (rows_dev:
  * m x d, cols_dev: n x d, row-major float64), and/or dy = (rho dC/drho) x.
  * The same pointer for rows and cols is allowed (square product).  Sums
@@ -168,7 +168,7 @@ int mlblup_cov_matvec(const mlblup_matern* k, const double* rows_dev, int64_t m,
                       int32_t d, int32_t precision, int32_t outputs, const double* x_dev, double* y_dev,
                       double* dy_dev, void* work_dev, int64_t work_bytes, void* stream);
 
-/* ---- multilevel transform (operators W and W^T, Sec. 2.1 and Sec. 4.2) -----
+/* ---- multilevel transform (operators W and W^T, Sec. 3.1 and Sec. 6.2) -----
  * apply_W:  vw = W v (N - p), vl = L v (p; NULL to skip).
  * apply_Wt: v = W^T vw + L^T vl (vl NULL = 0).
  * work_dev: at least mlblup_transform_workspace_bytes(b). */
@@ -178,7 +178,7 @@ int mlblup_apply_W(mlblup_basis b, const double* v_dev, double* vw_dev, double* 
 int mlblup_apply_Wt(mlblup_basis b, const double* vw_dev, const double* vl_dev, double* v_dev, void* work_dev,
                     int64_t work_bytes, void* stream);
 
-/* ---- solve, predict, gradient (Sec. 4.2 predictor; Sec. 5 eqs. Spatial:eqn2-3)
+/* ---- solve, predict, gradient (Sec. 6.2 predictor; Sec. 5.2 eqs. Spatial:eqn2-3)
  * Workspace for every call below: mlblup_solve_workspace_bytes(b, opts,
  * m_targets) (m_targets = largest target count used with it, 0 if none). */
 int mlblup_solve_workspace_bytes(mlblup_basis b, const mlblup_pcg_opts* opts, int64_t m_targets, int64_t* bytes);
@@ -197,14 +197,18 @@ int mlblup_pcg_solve(mlblup_basis b, const mlblup_matern* k, const double* zw_de
  * order (1, x1, .., xd, x1^2, x1 x2, ..).  gamma_dev (N, tree order) and
  * gamma_w_dev (N - p) receive the solution; interp_res_host (may be NULL)
  * receives |W (z - C gamma)|_2, which equals |Zhat(S) - z|_2.  The final
- * products run in FP64 unless predict_precision says otherwise. */
+ * products run in FP64 unless predict_precision says otherwise.
+ * warm_start != 0: gamma_w_dev holds an initial guess on entry (e.g. the
+ * solution of an earlier pcg_solve of the same system); the solve then
+ * starts from it (one FP64 residual product when it already meets rtol). */
 int mlblup_blup_predict(mlblup_basis b, const mlblup_matern* k, const double* z_dev, const double* tgt_dev,
-                        int64_t m_t, const mlblup_pcg_opts* opts, int32_t predict_precision, double* zhat_dev,
-                        double* beta_host, double* gamma_dev, double* gamma_w_dev, double* interp_res_host,
-                        void* work_dev, int64_t work_bytes, mlblup_pcg_info* info, void* stream);
+                        int64_t m_t, const mlblup_pcg_opts* opts, int32_t predict_precision, int32_t warm_start,
+                        double* zhat_dev, double* beta_host, double* gamma_dev, double* gamma_w_dev,
+                        double* interp_res_host, void* work_dev, int64_t work_bytes, mlblup_pcg_info* info,
+                        void* stream);
 
 /* Quadratic form and its log-rho derivative (data term of the multilevel
- * likelihood, Sec. 2): Q = z . gamma (= Z_W . gamma_W) and
+ * likelihood, Sec. 3): Q = z . gamma (= Z_W . gamma_W) and
  * dQ/dlog rho = -lambda^T (rho dC/drho) gamma, lambda = gamma when
  * lambda_dev is NULL (the adjoint of Q is gamma itself), else the W^T image
  * of an adjoint solve.  One fused value/derivative pass over the pairs. */
@@ -212,7 +216,7 @@ int mlblup_blup_grad(mlblup_basis b, const mlblup_matern* k, const double* z_dev
                      const double* lambda_dev, int32_t precision, double* Q_host, double* dQ_dlogrho_host,
                      void* work_dev, int64_t work_bytes, void* stream);
 
-/* ---- preconditioner (remark on P_W = diag(C_W), Sec. 5) -----------------------
+/* ---- preconditioner (remark on P_W = diag(C_W), Sec. 5.2) -----------------------
  * Built without forming C_W: the leaf kernel blocks and, for each internal
  * cell, the Gram of its children's scaling vectors across the two children
  * are summed on the device (about N^2/2 pairs over all levels, kernel values

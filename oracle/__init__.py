@@ -9,14 +9,14 @@ unbiased prediction: a computational mathematics approach for high
 dimensional massive datasets", arXiv:1701.00285) and cites the section,
 equation or algorithm it restates:
 
-  matern   Matern covariance (Definition in Sec. 2.1 and the half-integer
+  matern   Matern covariance (Definition in Sec. 3.1 and the half-integer
            remark after it), its rho-derivative, dense covariance blocks
-  design   total-degree monomial design matrix X (Sec. 1, TD index set)
+  design   total-degree monomial design matrix X (Sec. 2, TD index set)
   kdtree   kd-tree with the max-variance / median split (Algorithms
-           "Rule", "InitialTree", "MakeTree", Sec. 2.1)
-  basis    multilevel basis W, L by per-cell SVD (Sec. 2.1 construction)
+           "Rule", "InitialTree", "MakeTree", Sec. 3.1)
+  basis    multilevel basis W, L by per-cell SVD (Sec. 3.1 construction)
   blup     classic GLS / kriging (eqs. GLSbeta, KrigBLUP), the multilevel
-           predictor (Sec. 5, eqs. Spatial:eqn1-3), quadratic form and its
+           predictor (Sec. 5.2, eqs. Spatial:eqn1-3), quadratic form and its
            log-rho gradient
   brute    brute-force covariance sums (math.fsum double loop, row blocks)
 

@@ -1,6 +1,6 @@
 """Multilevel basis W, L built explicitly, by per-cell SVD.  TEST INFRASTRUCTURE.
 
-Paper, Sec. 2.1 (multilevel basis construction), followed step by step
+Paper, Sec. 3.1 (multilevel basis construction), followed step by step
 with dense N-vectors:
 
   * start at the deepest level; a leaf cell with s points carries the s
@@ -27,7 +27,7 @@ Pins (tests/test_oracle_basis.py): P P^T = I, W X = 0, the direct-sum
 dimension count, the per-level counts of the paper's sparsity table
 (fixture tests/golden/tabsparse_size.txt, reproduced by `level_sizes`),
 support of every wavelet inside its cell, and the condition-number
-inequality kappa(W C W^T) <= kappa(C) (Proposition in Sec. 2).
+inequality kappa(W C W^T) <= kappa(C) (Proposition in Sec. 3).
 """
 from __future__ import annotations
 

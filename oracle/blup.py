@@ -1,6 +1,6 @@
 """Dense FP64 BLUP: classic formulae and the multilevel predictor.  TEST INFRASTRUCTURE.
 
-Classic route (Sec. 1, eqs. GLSbeta and KrigBLUP):
+Classic route (Sec. 2, eqs. GLSbeta and KrigBLUP):
     beta  = (X^T C^-1 X)^-1 X^T C^-1 Z
     gamma = C^-1 (Z - X beta)
     Zhat(x0) = k(x0)^T beta + c(x0)^T gamma
@@ -8,7 +8,7 @@ computed with the Cholesky factor G of C (A = G^-1 X, b = G^-1 Z, beta
 from the least-squares problem min |A beta - b|, which has the same
 normal equations as GLSbeta).
 
-Multilevel route (Sec. 5, eqs. Spatial:problem and Spatial:eqn1-3): gamma
+Multilevel route (Sec. 5.2, eqs. Spatial:problem and Spatial:eqn1-3): gamma
 lies in the orthogonal complement of col(X), so gamma = W^T gamma_W with
     (W C W^T) gamma_W = W Z,
     beta = (X^T X)^-1 X^T (Z - C gamma)    (least squares on X),
@@ -16,7 +16,7 @@ which solves the saddle-point system exactly.  Here C_W is formed densely
 from the explicit W of oracle.basis and factored by Cholesky.
 
 Quadratic form and gradient (data term of the multilevel likelihood,
-Sec. 2, l_W):  Q(rho) = Z_W^T C_W^-1 Z_W = Z^T gamma, and
+Sec. 3, l_W):  Q(rho) = Z_W^T C_W^-1 Z_W = Z^T gamma, and
     dQ / dlog rho = -gamma^T (rho dC/drho) gamma
 (derivative of an inverse; W does not depend on rho).
 

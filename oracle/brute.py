@@ -1,7 +1,7 @@
 """Brute-force covariance sums y_i = sum_j phi(|x_i - y_j|) a_j.  TEST INFRASTRUCTURE.
 
 The dense product C(theta) x is the dominant step of every iteration of
-the predictor's Krylov solve (Sec. 4.2, three-step product W^T -> C -> W).
+the predictor's Krylov solve (Sec. 6.2, three-step product W^T -> C -> W).
 Two plain forms:
 
   fsum_matvec  pure-Python double loop, distances by math.sqrt of summed

@@ -1,6 +1,6 @@
 """Total-degree design matrix X.  TEST INFRASTRUCTURE.
 
-Paper, Sec. 1 (problem setup): the columns of X are the monomials
+Paper, Sec. 2 (problem setup): the columns of X are the monomials
 x_1^a_1 ... x_d^a_d with |a| <= w (the total-degree set Q^d_w), so
 p(d, w) = binomial(d + w, w).  The paper fixes neither the column order
 nor the coordinates; this oracle uses raw coordinates and graded

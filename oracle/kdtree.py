@@ -1,6 +1,6 @@
 """kd-tree domain decomposition.  TEST INFRASTRUCTURE.
 
-Paper, Sec. 2.1: the cell-split rule (algorithm "Rule for cell-split")
+Paper, Sec. 3.1: the cell-split rule (algorithm "Rule for cell-split")
 picks the coordinate axis along which the cell's points have maximal
 variance, projects the points on it and splits at the median;
 "InitialTree" starts at node 0 / depth 0 and "MakeTree" numbers the

@@ -1,6 +1,6 @@
 """Matern covariance for half-integer smoothness, FP64.  TEST INFRASTRUCTURE.
 
-Paper: Definition (Sec. 2.1, "Binary multilevel basis") gives
+Paper: Definition (Sec. 3.1, "Binary multilevel basis") gives
     phi(r) = (sqrt(2 nu) r / rho)^nu K_nu(sqrt(2 nu) r / rho) / (Gamma(nu) 2^(nu-1)),
 and the remark after it states that for nu = n + 1/2 the function is an
 exponential times a finite sum.  The printed sum is garbled (index starts
@@ -47,7 +47,7 @@ def _prefactor(n: int) -> float:
 
 
 def matern(r, nu: float, rho: float, sigma2: float = 1.0):
-    """phi(r) for nu = n + 1/2 (Definition + half-integer remark, Sec. 2.1)."""
+    """phi(r) for nu = n + 1/2 (Definition + half-integer remark, Sec. 3.1)."""
     n = _halfint_n(nu)
     r = np.asarray(r, dtype=np.float64)
     z = math.sqrt(2.0 * nu) * r / rho
@@ -96,7 +96,7 @@ def pairwise_dist(a: np.ndarray, b: np.ndarray) -> np.ndarray:
 
 
 def cov_matrix(a, b, nu, rho, sigma2=1.0):
-    """Dense block {phi(|a_i - b_j|)} (Sec. 2.1, item ii of the notation)."""
+    """Dense block {phi(|a_i - b_j|)} (Sec. 3.1, item ii of the notation)."""
     return matern(pairwise_dist(a, b), nu, rho, sigma2)
 
 

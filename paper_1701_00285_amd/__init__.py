@@ -1,7 +1,7 @@
 """Multilevel spatial BLUP on AMD MI355X (gfx950).
 
 The solve of the kriging system in a multilevel basis W orthogonal to the
-polynomial trend (arXiv:1701.00285, Sec. 5): C_W gamma_W = W Z with
+polynomial trend (arXiv:1701.00285, Sec. 5.2): C_W gamma_W = W Z with
 C_W = W C W^T, C the dense Matern covariance.  Everything runs in the
 native library libmlblup.so (HIP kernels + host C++); this package only
 binds it.

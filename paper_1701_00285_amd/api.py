@@ -277,7 +277,7 @@ class Solver:
         return gw, info.as_dict(), st
 
     def predict(self, z, targets=None, opts: PcgOptions | None = None, predict_precision=FP64, rho=None,
-                allow_noconv=False):
+                allow_noconv=False, gamma_w0=None):
         """z: (N,) device tensor in input order; targets: (m, d) device tensor.
         Returns dict(zhat, beta (numpy, raw monomials, graded lex), gamma (input
         order), gamma_w, interp_res, info, status)."""
@@ -289,7 +289,8 @@ class Solver:
             raise ValueError(f"{m} targets > max_targets={self.max_targets} given at construction")
         zhat = torch.empty(m, dtype=torch.float64, device=self.device) if m else None
         gamma = torch.empty(self.n, dtype=torch.float64, device=self.device)
-        gw = torch.empty(self.n - self.p, dtype=torch.float64, device=self.device)
+        gw = gamma_w0.clone() if gamma_w0 is not None else torch.empty(self.n - self.p, dtype=torch.float64,
+                                                                       device=self.device)
         beta = np.empty(self.p)
         ires = C.c_double()
         info = L.PcgInfo()
@@ -297,7 +298,8 @@ class Solver:
         co = opts.to_c()
         st = L.lib().mlblup_blup_predict(self.basis.h, C.byref(k), _ptr(z_tree),
                                          _ptr(targets.contiguous()) if m else None, m, C.byref(co),
-                                         int(predict_precision), _ptr(zhat), _np_ptr(beta), _ptr(gamma), _ptr(gw),
+                                         int(predict_precision), 1 if gamma_w0 is not None else 0, _ptr(zhat),
+                                         _np_ptr(beta), _ptr(gamma), _ptr(gw),
                                          C.byref(ires), _ptr(self.ws), self.ws.numel(), C.byref(info), _stream())
         if not (allow_noconv and st == L.ENOCONV):
             check(st)

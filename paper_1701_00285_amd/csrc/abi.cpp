@@ -1,5 +1,5 @@
-// C ABI entry points and the host drivers of the solve (Sec. 4.2 predictor
-// iteration; Sec. 5 eqs. Spatial:eqn2-3).
+// C ABI entry points and the host drivers of the solve (Sec. 6.2 predictor
+// iteration; Sec. 5.2 eqs. Spatial:eqn2-3).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -688,9 +688,10 @@ int mlblup_pcg_solve(mlblup_basis b, const mlblup_matern* k, const double* zw_de
 }
 
 int mlblup_blup_predict(mlblup_basis b, const mlblup_matern* k, const double* z_dev, const double* tgt_dev,
-                        int64_t m_t, const mlblup_pcg_opts* opts, int32_t predict_precision, double* zhat_dev,
-                        double* beta_host, double* gamma_dev, double* gamma_w_dev, double* interp_res_host,
-                        void* work_dev, int64_t work_bytes, mlblup_pcg_info* info, void* stream) {
+                        int64_t m_t, const mlblup_pcg_opts* opts, int32_t predict_precision, int32_t warm_start,
+                        double* zhat_dev, double* beta_host, double* gamma_dev, double* gamma_w_dev,
+                        double* interp_res_host, void* work_dev, int64_t work_bytes, mlblup_pcg_info* info,
+                        void* stream) {
   clear_error();
   int st = check_basis_dev(b);
   if (st) return st;
@@ -717,7 +718,8 @@ int mlblup_blup_predict(mlblup_basis b, const mlblup_matern* k, const double* z_
   if ((st = c.norm(z_dev, N, &znorm))) return st;
   if (!std::isfinite(znorm)) return fail(MLBLUP_EINVAL, "blup_predict: non-finite observations");
   mlblup_pcg_info inf{};
-  const int solve_st = c.solve(zw, gw, false, o, inf, 1e-13 * znorm);
+  if (warm_start && !gamma_w_dev) return fail(MLBLUP_EINVAL, "blup_predict: warm start needs gamma_w_dev");
+  const int solve_st = c.solve(zw, gw, warm_start != 0, o, inf, 1e-13 * znorm);
   if (info) *info = inf;
   if (solve_st != MLBLUP_OK && solve_st != MLBLUP_ENOCONV) return solve_st;
   const std::string solve_msg = solve_st ? std::string(mlblup_last_error()) : std::string();

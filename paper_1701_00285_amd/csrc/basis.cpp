@@ -1,4 +1,4 @@
-// Multilevel basis construction (Sec. 2.1: construction of W and L from the
+// Multilevel basis construction (Sec. 3.1: construction of W and L from the
 // kd-tree; operators W, L, P).
 //
 // For every cell, bottom-up, the candidate vectors (a leaf: the unit vectors

@@ -1,5 +1,5 @@
-// Multilevel transform kernels (operators W and W^T, Sec. 2.1; steps (1)
-// and (3) of the product chain, Sec. 4.2) and the Krylov vector kernels.
+// Multilevel transform kernels (operators W and W^T, Sec. 3.1; steps (1)
+// and (3) of the product chain, Sec. 6.2) and the Krylov vector kernels.
 //
 // Transform: one launch per tree level.  Analysis (v -> W v, L v) runs from
 // the finest level to the root: a cell multiplies its candidate

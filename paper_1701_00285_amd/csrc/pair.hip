@@ -1,9 +1,9 @@
 // Dense Matern covariance product y_i = sum_j sigma2 phi(|r_i - c_j|) x_j
-// (step (2) of the three-step product of the predictor iteration, Sec. 4.2),
+// (step (2) of the three-step product of the predictor iteration, Sec. 6.2),
 // plus the fused rho-derivative dy_i = sum_j rho dphi/drho x_j.
 //
 // Kernel form with z = sqrt(2 nu) r / rho (half-integer closed forms of the
-// Matern family, Sec. 2.1 remark, written in z):
+// Matern family, Sec. 3.1 remark, written in z):
 //   nu = 1/2:  phi = e^-z                   rho dphi/drho = z e^-z
 //   nu = 3/2:  phi = (1 + z) e^-z           rho dphi/drho = z^2 e^-z
 //   nu = 5/2:  phi = (1 + z + z^2/3) e^-z   rho dphi/drho = z^2 (1 + z)/3 e^-z

@@ -1,4 +1,4 @@
-// Preconditioner of the Krylov solve (preconditioner remark of Sec. 5):
+// Preconditioner of the Krylov solve (preconditioner remark of Sec. 5.2):
 // P_W = diag(C_W) (Jacobi), or the block form that keeps, for every cell,
 // the whole block of C_W between that cell's own wavelets.
 //

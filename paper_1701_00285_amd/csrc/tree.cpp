@@ -1,4 +1,4 @@
-// kd-tree domain decomposition (Sec. 2.1: cell-split rule, InitialTree,
+// kd-tree domain decomposition (Sec. 3.1: cell-split rule, InitialTree,
 // MakeTree).  Each cell is split on the coordinate axis along which its own
 // points have the largest variance, at the median of that coordinate.  The
 // median split is taken by rank: points ordered by (coordinate, input

@@ -56,7 +56,7 @@ def test_paper_sparsity_table_sizes():
 
 
 def test_level_bound_lemma():
-    """Lemma (Sec. 2.1): with n0 < 2p, level q holds at most p 2^q vectors."""
+    """Lemma (Sec. 3.1): with n0 < 2p, level q holds at most p 2^q vectors."""
     pts, tree, bas = _setup(600, 2, 2, 10)     # p = 6, n0 = 10 < 12
     for q, c in bas.level_rows.items():
         assert c <= bas.p * 2 ** q
