@@ -44,6 +44,10 @@ bool sym_supported(int d);
 bool sym_worthwhile(int64_t n);
 int64_t sym_workspace_bytes(int64_t n, int outputs);
 int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s);
+// Matrix-core distance Gram (pair_mfma.hip): MFMA precisions, value only, 8 <= d <= 32.
+bool mfma_applies(const PairArgs& a);
+int32_t mfma_splits(int64_t m, int64_t n);
+int mfma_launch(const PairArgs& a, double zs, double* part, hipStream_t s);
 // Validates and launches (pair kernel + split reduction).
 int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s);
 

@@ -34,21 +34,18 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kWavesPerBlock = 4;
+constexpr int kMaxTopLevels = 24;
+constexpr int kTopCells = 16;    // levels with at most this many cells go into the fused launch
 
-__global__ __launch_bounds__(kT) void analysis_level(const NodeDesc* __restrict__ desc,
-                                                     const int32_t* __restrict__ lnodes, int32_t cnt,
-                                                     const double* __restrict__ V, const double* __restrict__ v,
-                                                     double* __restrict__ scal, double* __restrict__ vw,
-                                                     double* __restrict__ vl) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int32_t s = blockIdx.x * kWavesPerBlock + wave;
-  if (s >= cnt) return;
-  const NodeDesc D = desc[lnodes[s]];
+__device__ __forceinline__ void analysis_node(const NodeDesc& D, int lane, const double* __restrict__ V,
+                                              const double* __restrict__ v, double* __restrict__ scal,
+                                              double* __restrict__ vw, double* __restrict__ vl) {
   const double* cin = D.leaf ? v + D.in_off : scal + D.in_off;
   const double* B = V + D.v_off;
   const int m = D.m;
   for (int j = lane; j < m; j += 64) {
     double acc = 0.0;
+#pragma unroll 8
     for (int i = 0; i < m; ++i) acc = fma(B[(int64_t)i * m + j], cin[i], acc);
     if (j < D.a) {
       if (D.scal_off >= 0) scal[D.scal_off + j] = acc;
@@ -59,6 +56,37 @@ __global__ __launch_bounds__(kT) void analysis_level(const NodeDesc* __restrict_
   }
 }
 
+__device__ __forceinline__ void synthesis_node(const NodeDesc& D, int lane, const double* __restrict__ Vt,
+                                               const double* __restrict__ vw, const double* __restrict__ vl,
+                                               double* __restrict__ scal, double* __restrict__ v) {
+  const double* B = Vt + D.v_off;
+  const int m = D.m, a = D.a;
+  const double* cs = D.scal_off >= 0 ? scal + D.scal_off : vl;  // may be null at the root
+  const double* cw = vw + D.w_off - a;
+  double* out = D.leaf ? v + D.in_off : scal + D.in_off;
+  for (int i = lane; i < m; i += 64) {
+    double acc = 0.0;
+    if (cs) {
+#pragma unroll 8
+      for (int j = 0; j < a; ++j) acc = fma(B[(int64_t)j * m + i], cs[j], acc);
+    }
+#pragma unroll 8
+    for (int j = a; j < m; ++j) acc = fma(B[(int64_t)j * m + i], cw[j], acc);
+    out[i] = acc;
+  }
+}
+
+__global__ __launch_bounds__(kT) void analysis_level(const NodeDesc* __restrict__ desc,
+                                                     const int32_t* __restrict__ lnodes, int32_t cnt,
+                                                     const double* __restrict__ V, const double* __restrict__ v,
+                                                     double* __restrict__ scal, double* __restrict__ vw,
+                                                     double* __restrict__ vl) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t s = blockIdx.x * kWavesPerBlock + wave;
+  if (s >= cnt) return;
+  analysis_node(desc[lnodes[s]], lane, V, v, scal, vw, vl);
+}
+
 __global__ __launch_bounds__(kT) void synthesis_level(const NodeDesc* __restrict__ desc,
                                                       const int32_t* __restrict__ lnodes, int32_t cnt,
                                                       const double* __restrict__ Vt, const double* __restrict__ vw,
@@ -67,18 +95,40 @@ __global__ __launch_bounds__(kT) void synthesis_level(const NodeDesc* __restrict
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int32_t s = blockIdx.x * kWavesPerBlock + wave;
   if (s >= cnt) return;
-  const NodeDesc D = desc[lnodes[s]];
-  const double* B = Vt + D.v_off;
-  const int m = D.m, a = D.a;
-  const double* cs = D.scal_off >= 0 ? scal + D.scal_off : vl;  // may be null at the root
-  const double* cw = vw + D.w_off - a;
-  double* out = D.leaf ? v + D.in_off : scal + D.in_off;
-  for (int i = lane; i < m; i += 64) {
-    double acc = 0.0;
-    if (cs)
-      for (int j = 0; j < a; ++j) acc = fma(B[(int64_t)j * m + i], cs[j], acc);
-    for (int j = a; j < m; ++j) acc = fma(B[(int64_t)j * m + i], cw[j], acc);
-    out[i] = acc;
+  synthesis_node(desc[lnodes[s]], lane, Vt, vw, vl, scal, v);
+}
+
+// The small top levels (few cells each) in one launch of one workgroup:
+// levels run in order with a workgroup barrier between them (the barrier
+// orders this workgroup's global writes and reads).
+struct TopLevels {
+  int32_t begin[kMaxTopLevels + 1];  // level q occupies [begin[q], begin[q+1]) of level_nodes, q = 0..nlev-1
+  int32_t nlev;
+};
+
+__global__ __launch_bounds__(kT) void analysis_top(const NodeDesc* __restrict__ desc,
+                                                   const int32_t* __restrict__ lnodes, TopLevels L,
+                                                   const double* __restrict__ V, const double* __restrict__ v,
+                                                   double* __restrict__ scal, double* __restrict__ vw,
+                                                   double* __restrict__ vl) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int q = L.nlev - 1; q >= 0; --q) {
+    for (int32_t s = L.begin[q] + wave; s < L.begin[q + 1]; s += kWavesPerBlock)
+      analysis_node(desc[lnodes[s]], lane, V, v, scal, vw, vl);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kT) void synthesis_top(const NodeDesc* __restrict__ desc,
+                                                    const int32_t* __restrict__ lnodes, TopLevels L,
+                                                    const double* __restrict__ Vt, const double* __restrict__ vw,
+                                                    const double* __restrict__ vl, double* __restrict__ scal,
+                                                    double* __restrict__ v) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int q = 0; q < L.nlev; ++q) {
+    for (int32_t s = L.begin[q] + wave; s < L.begin[q + 1]; s += kWavesPerBlock)
+      synthesis_node(desc[lnodes[s]], lane, Vt, vw, vl, scal, v);
+    __syncthreads();
   }
 }
 
@@ -246,29 +296,51 @@ Prof& prof() {
   return p;
 }
 
+// number of leading (shallow) levels small enough for the fused launch
+int top_levels(const TransformDev& T) {
+  int q = 0;
+  while (q < T.levels && q < kMaxTopLevels && T.lvl_begin_host[q + 1] - T.lvl_begin_host[q] <= kTopCells) ++q;
+  return q;
+}
+
+TopLevels make_top(const TransformDev& T, int nt) {
+  TopLevels L{};
+  for (int q = 0; q <= nt; ++q) L.begin[q] = T.lvl_begin_host[q];
+  L.nlev = nt;
+  return L;
+}
+
 }  // namespace
 
 int transform_analysis(const TransformDev& T, const double* v, double* vw, double* vl, double* scal, hipStream_t s) {
-  for (int q = T.levels - 1; q >= 0; --q) {
+  const int nt = top_levels(T);
+  for (int q = T.levels - 1; q >= nt; --q) {
     const int32_t lb = T.lvl_begin_host[q], cnt = T.lvl_begin_host[q + 1] - lb;
     if (cnt <= 0) continue;
     const unsigned g = (unsigned)((cnt + kWavesPerBlock - 1) / kWavesPerBlock);
     hipLaunchKernelGGL(analysis_level, dim3(g), dim3(kT), 0, s, T.desc, T.level_nodes + lb, cnt, T.V, v, scal, vw,
                        vl);
   }
-  return hip_check(hipGetLastError(), "analysis_level launch");
+  if (nt > 0)
+    hipLaunchKernelGGL(analysis_top, dim3(1), dim3(kT), 0, s, T.desc, T.level_nodes, make_top(T, nt), T.V, v, scal, vw,
+                       vl);
+  return hip_check(hipGetLastError(), "analysis launch");
 }
 
 int transform_synthesis(const TransformDev& T, const double* vw, const double* vl, double* v, double* scal,
                         hipStream_t s) {
-  for (int q = 0; q < T.levels; ++q) {
+  const int nt = top_levels(T);
+  if (nt > 0)
+    hipLaunchKernelGGL(synthesis_top, dim3(1), dim3(kT), 0, s, T.desc, T.level_nodes, make_top(T, nt), T.Vt, vw, vl,
+                       scal, v);
+  for (int q = nt; q < T.levels; ++q) {
     const int32_t lb = T.lvl_begin_host[q], cnt = T.lvl_begin_host[q + 1] - lb;
     if (cnt <= 0) continue;
     const unsigned g = (unsigned)((cnt + kWavesPerBlock - 1) / kWavesPerBlock);
     hipLaunchKernelGGL(synthesis_level, dim3(g), dim3(kT), 0, s, T.desc, T.level_nodes + lb, cnt, T.Vt, vw, vl,
                        scal, v);
   }
-  return hip_check(hipGetLastError(), "synthesis_level launch");
+  return hip_check(hipGetLastError(), "synthesis launch");
 }
 
 int vec_dot(const double* a, const double* b, int64_t n, double* part, double* out_dev, hipStream_t s) {

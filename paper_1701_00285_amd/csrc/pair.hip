@@ -223,6 +223,8 @@ int64_t pair_workspace_bytes(int64_t m, int64_t n, int32_t d, int32_t precision,
   const int64_t per = S * m * (int64_t)sizeof(double);
   const int64_t aligned = (per + 255) / 256 * 256;
   int64_t b = aligned * (((outputs & 1) ? 1 : 0) + ((outputs & 2) ? 1 : 0));
+  if ((precision == MLBLUP_MFMA_FP32 || precision == MLBLUP_MFMA_BF16X3) && outputs == MLBLUP_VALUE)
+    b = std::max(b, ((int64_t)mfma_splits(m, n) * m * (int64_t)sizeof(double) + 255) / 256 * 256);
   if (m == n && sym_supported(d) && sym_worthwhile(n)) b = std::max(b, sym_workspace_bytes(n, outputs));
   return b;
 }
@@ -250,6 +252,24 @@ int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s
   if (!work || work_bytes < need)
     return fail(MLBLUP_EINVAL, "cov_matvec: workspace too small (need " + std::to_string(need) + " bytes)");
   const double zs = std::sqrt((double)a.nu2) / a.rho;  // sqrt(2 nu) / rho
+  if (mfma_applies(a)) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (profile_on()) {
+      MLB_HIP(hipEventCreate(&e0));
+      MLB_HIP(hipEventCreate(&e1));
+      MLB_HIP(hipEventRecord(e0, s));
+    }
+    const int st = mfma_launch(a, zs, (double*)work, s);
+    if (st) return st;
+    if (profile_on()) {
+      MLB_HIP(hipEventRecord(e1, s));
+      profile_note(e0, e1, (double)a.m * (double)a.n, a.precision * 4 + a.outputs);
+    }
+    const unsigned g = (unsigned)((a.m + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(reduce_splits, dim3(g), dim3(kThreads), 0, s, (const double*)work, mfma_splits(a.m, a.n), a.m,
+                       a.sigma2, a.y);
+    return hip_check(hipGetLastError(), "reduce_splits launch");
+  }
   if (a.rows == a.cols && a.m == a.n && sym_supported(a.d) && sym_worthwhile(a.n)) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (profile_on()) {
@@ -271,8 +291,9 @@ int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s
   const int64_t per = ((S * a.m * (int64_t)sizeof(double)) + 255) / 256 * 256;
   double* py = (a.outputs & 1) ? (double*)work : nullptr;
   double* pdy = (a.outputs & 2) ? (double*)((char*)work + ((a.outputs & 1) ? per : 0)) : nullptr;
-  // reduced precisions: the FP32-transcendental kernel (MFMA variants share it
-  // until their specialised kernels apply)
+  // reduced precisions: the FP32-transcendental kernel (also for the
+  // matrix-core precisions when their form does not apply: d < 8 or d > 32,
+  // derivative outputs)
   const bool f32 = a.precision != MLBLUP_FP64;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (profile_on()) {

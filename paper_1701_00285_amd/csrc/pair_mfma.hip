@@ -1,0 +1,273 @@
+// Covariance product with the squared distances from a Gram matrix on the
+// matrix cores: r^2 = |a|^2 + |b|^2 - 2 a.b (intended for d >= 8, where the
+// d differences per pair dominate the direct form).
+//
+// A workgroup owns 64 rows (4 waves x one 16-row tile) and one column range.
+// All coordinates are scaled by sqrt(2 nu)/rho and centred on one row of the
+// block in FP64, then rounded: FP32 for v_mfma_f32_16x16x4_f32, or a BF16
+// hi + lo split for v_mfma_f32_16x16x16_bf16 with three products
+// (hi.hi + hi.lo + lo.hi).  Centring keeps |a|, |b| small for the near pairs
+// that the cancellation in |a|^2 + |b|^2 - 2 a.b would otherwise hurt; the
+// 16-column tiles that overlap the workgroup's own rows of a square product
+// (self pairs and the nearest neighbours, since points are in tree order)
+// take exact FP64 differences instead.  The squared distance is clamped at
+// 0, the kernel value uses FP32 sqrt/exp2, sums are FP64.
+//
+// Fragment layouts of the 16x16 MFMA forms: for 16x16x4 (FP32), lane l
+// supplies A[l%16][l/16] and B[l/16][l%16]; for 16x16x16 (BF16) lane l
+// supplies A[l%16][4(l/16)+e] and B[4(l/16)+e][l%16], e = 0..3; in both the
+// result D[4(l/16)+r][l%16], r = 0..3, sits in the lane's 4 accumulators.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "device.h"
+#include "pairmath.h"
+
+namespace mlb {
+namespace {
+
+constexpr int kT = 256;
+constexpr int kRows = 64;    // rows per workgroup
+constexpr int kChunk = 64;   // columns per LDS fill
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
+
+template <int NU2>
+__device__ __forceinline__ double value32(double s) {
+  s = s > 0.0 ? s : 0.0;
+  const float z = __builtin_amdgcn_sqrtf((float)s);
+  const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
+  return (double)(matern_polyf<NU2>(z) * e);
+}
+
+// KP: padded dimension (multiple of 4 for FP32, of 16 for BF16)
+template <int KP, int NU2, bool BF>
+__global__ __launch_bounds__(kT) void mfma_kernel(const double* __restrict__ rows, int64_t m,
+                                                  const double* __restrict__ cols, int64_t n, int d,
+                                                  const double* __restrict__ x, double* __restrict__ py, double zs,
+                                                  int64_t cps, int self) {
+  __shared__ float cf[kChunk * KP];               // FP32 centred coordinates (FP32 mode)
+  __shared__ unsigned short chi[kChunk * KP];     // BF16 hi (BF16 mode)
+  __shared__ unsigned short clo[kChunk * KP];     // BF16 lo
+  __shared__ double cn[kChunk];                   // column squared norms (of the rounded coordinates)
+  __shared__ double cx[kChunk];
+  __shared__ double ctr[64];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t rb = (int64_t)blockIdx.x * kRows;
+  // centre: the block's middle row (scaled)
+  {
+    int64_t ci = rb + 32;
+    if (ci >= m) ci = m - 1;
+    if (tid < d) ctr[tid] = rows[ci * d + tid] * zs;
+  }
+  __syncthreads();
+  // row fragment: row rb + 16 wave + lr, k indices owned by this lane
+  const int64_t irow = rb + 16 * wave + lr;
+  const int64_t irc = irow < m ? irow : m - 1;
+  float ra[BF ? 1 : KP / 4];
+  s4 rhi[BF ? KP / 16 : 1], rlo[BF ? KP / 16 : 1];
+  if constexpr (!BF) {
+#pragma unroll
+    for (int t = 0; t < KP / 4; ++t) {
+      const int k = 4 * t + lg;
+      ra[t] = k < d ? (float)(rows[irc * d + k] * zs - ctr[k]) : 0.0f;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < KP / 16; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = 16 * t + 4 * lg + e;
+        const float v = k < d ? (float)(rows[irc * d + k] * zs - ctr[k]) : 0.0f;
+        const unsigned short h = bf16_rne(v);
+        const unsigned short l = bf16_rne(v - bf16_to_f(h));
+        rhi[t][e] = (short)h;
+        rlo[t][e] = (short)l;
+      }
+  }
+  // squared norms of the 4 rows whose results this lane holds (rows 4 lg + r of the tile)
+  double rn[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int64_t i = rb + 16 * wave + 4 * lg + r;
+    if (i >= m) i = m - 1;
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const float v = (float)(rows[i * d + k] * zs - ctr[k]);
+      double vv;
+      if constexpr (BF) {
+        const unsigned short h = bf16_rne(v);
+        vv = (double)bf16_to_f(h) + (double)bf16_to_f(bf16_rne(v - bf16_to_f(h)));
+      } else {
+        vv = (double)v;
+      }
+      s = fma(vv, vv, s);
+    }
+    rn[r] = s;
+  }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t c0 = (int64_t)blockIdx.y * cps;
+  const int64_t c1 = (c0 + cps < n) ? c0 + cps : n;
+  for (int64_t j0 = c0; j0 < c1; j0 += kChunk) {
+    const int cnt = (int)((c1 - j0) < kChunk ? (c1 - j0) : kChunk);
+    __syncthreads();
+    for (int e = tid; e < kChunk * KP; e += kT) {
+      const int j = e / KP, k = e - j * KP;
+      const float v = (j < cnt && k < d) ? (float)(cols[(j0 + j) * d + k] * zs - ctr[k]) : 0.0f;
+      if constexpr (BF) {
+        const unsigned short h = bf16_rne(v);
+        chi[e] = h;
+        clo[e] = bf16_rne(v - bf16_to_f(h));
+      } else {
+        cf[e] = v;
+      }
+    }
+    for (int j = tid; j < kChunk; j += kT) cx[j] = j < cnt ? x[j0 + j] : 0.0;
+    __syncthreads();
+    for (int j = tid; j < kChunk; j += kT) {
+      double s = 0.0;
+      for (int k = 0; k < d; ++k) {
+        double vv;
+        if constexpr (BF) vv = (double)bf16_to_f(chi[j * KP + k]) + (double)bf16_to_f(clo[j * KP + k]);
+        else vv = (double)cf[j * KP + k];
+        s = fma(vv, vv, s);
+      }
+      cn[j] = s;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int tile = 0; tile < kChunk / 16; ++tile) {
+      const int jc = tile * 16 + lr;          // this lane's column in the chunk
+      const int64_t jt = j0 + tile * 16;      // first column of the tile
+      const bool near = self && (jt < rb + kRows) && (jt + 16 > rb);
+      if (near) {
+        // exact FP64 differences
+        const int64_t j = j0 + jc;
+        const int64_t jj = (jc < cnt) ? j : j0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int64_t i = rb + 16 * wave + 4 * lg + r;
+          if (i >= m) i = m - 1;
+          double s = 0.0;
+          for (int k = 0; k < d; ++k) {
+            const double t = (rows[i * d + k] - cols[jj * d + k]) * zs;
+            s = fma(t, t, s);
+          }
+          acc[r] = fma(value32<NU2>(s), cx[jc], acc[r]);
+        }
+        continue;
+      }
+      f4 g = {0.0f, 0.0f, 0.0f, 0.0f};
+      if constexpr (!BF) {
+#pragma unroll
+        for (int t = 0; t < KP / 4; ++t) {
+          const float b = cf[jc * KP + 4 * t + lg];
+          g = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[t], b, g, 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < KP / 16; ++t) {
+          s4 bh, bl;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            bh[e] = (short)chi[jc * KP + 16 * t + 4 * lg + e];
+            bl[e] = (short)clo[jc * KP + 16 * t + 4 * lg + e];
+          }
+          g = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rhi[t], bh, g, 0, 0, 0);
+          g = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rhi[t], bl, g, 0, 0, 0);
+          g = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(rlo[t], bh, g, 0, 0, 0);
+        }
+      }
+      const double nc = cn[jc], xc = cx[jc];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double s = fma(-2.0, (double)g[r], rn[r] + nc);
+        acc[r] = fma(value32<NU2>(s), xc, acc[r]);
+      }
+    }
+  }
+  // rows 4 lg + r: reduce over the 16 lanes of the group (the 16 columns)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    double v = acc[r];
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 8, 64);
+    acc[r] = v;
+  }
+  if (lr == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = rb + 16 * wave + 4 * lg + r;
+      if (i < m) py[(int64_t)blockIdx.y * m + i] = acc[r];
+    }
+  }
+}
+
+template <int KP, int NU2, bool BF>
+void launch(const PairArgs& a, double zs, int S, int64_t cps, double* py, hipStream_t s) {
+  dim3 grid((unsigned)((a.m + kRows - 1) / kRows), (unsigned)S);
+  const int self = (a.rows == a.cols) ? 1 : 0;
+  hipLaunchKernelGGL((mfma_kernel<KP, NU2, BF>), grid, dim3(kT), 0, s, a.rows, a.m, a.cols, a.n, a.d, a.x, py, zs, cps,
+                     self);
+}
+
+template <int NU2, bool BF>
+bool dispatch_kp(const PairArgs& a, double zs, int S, int64_t cps, double* py, hipStream_t s) {
+  if constexpr (BF) {
+    if (a.d <= 16) launch<16, NU2, true>(a, zs, S, cps, py, s);
+    else if (a.d <= 32) launch<32, NU2, true>(a, zs, S, cps, py, s);
+    else return false;
+  } else {
+    if (a.d <= 8) launch<8, NU2, false>(a, zs, S, cps, py, s);
+    else if (a.d <= 12) launch<12, NU2, false>(a, zs, S, cps, py, s);
+    else if (a.d <= 16) launch<16, NU2, false>(a, zs, S, cps, py, s);
+    else if (a.d <= 20) launch<20, NU2, false>(a, zs, S, cps, py, s);
+    else if (a.d <= 24) launch<24, NU2, false>(a, zs, S, cps, py, s);
+    else if (a.d <= 32) launch<32, NU2, false>(a, zs, S, cps, py, s);
+    else return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+int32_t mfma_splits(int64_t m, int64_t n) {
+  const int64_t rb = (m + kRows - 1) / kRows;
+  int64_t S = (4096 + rb - 1) / rb;
+  const int64_t max_by_cols = (n + kChunk - 1) / kChunk;
+  S = std::max<int64_t>(1, std::min<int64_t>({S, max_by_cols, 64}));
+  return (int32_t)S;
+}
+
+bool mfma_applies(const PairArgs& a) {
+  return (a.precision == MLBLUP_MFMA_FP32 || a.precision == MLBLUP_MFMA_BF16X3) && a.outputs == MLBLUP_VALUE &&
+         a.d >= 8 && a.d <= 32;
+}
+
+int mfma_launch(const PairArgs& a, double zs, double* part, hipStream_t s) {
+  const int S = mfma_splits(a.m, a.n);
+  int64_t cps = (a.n + S - 1) / S;
+  cps = (cps + kChunk - 1) / kChunk * kChunk;
+  const bool bf = a.precision == MLBLUP_MFMA_BF16X3;
+  bool ok;
+  if (a.nu2 == 1) ok = bf ? dispatch_kp<1, true>(a, zs, S, cps, part, s) : dispatch_kp<1, false>(a, zs, S, cps, part, s);
+  else if (a.nu2 == 3) ok = bf ? dispatch_kp<3, true>(a, zs, S, cps, part, s) : dispatch_kp<3, false>(a, zs, S, cps, part, s);
+  else ok = bf ? dispatch_kp<5, true>(a, zs, S, cps, part, s) : dispatch_kp<5, false>(a, zs, S, cps, part, s);
+  if (!ok) return fail(MLBLUP_EINVAL, "matrix-core pair kernel: d > 32");
+  return hip_check(hipGetLastError(), "mfma pair kernel launch");
+}
+
+}  // namespace mlb

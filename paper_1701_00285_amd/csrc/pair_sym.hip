@@ -1,11 +1,12 @@
 // Symmetric square product y = C x (C_ij = C_ji): every unordered pair is
 // evaluated once and feeds both row sums.
 //
-// Blocks of 512 points (tree order).  A workgroup (4 waves x 64 lanes x 2
-// rows) owns a row block S and one column block S'.  Column points stream
+// Blocks of 256 RL points (tree order; RL = 4 rows per lane for d <= 6,
+// else 2).  A workgroup (4 waves x 64 lanes x RL rows) owns a row block S
+// and one column block S'.  Column points stream
 // through LDS in chunks of 128; a wave walks each group of 64 columns in 64
 // steps in which lane l evaluates column (l + k*delta) mod 64 of the group
-// (a lane-varying LDS read) for its two rows.  Row sums stay in the lane;
+// (a lane-varying LDS read) for its RL rows.  Row sums stay in the lane;
 // the column sum of the lane's current column travels with it: a register
 // is rotated by one lane (DPP wave rotate) after every step, so after 64
 // steps lane l holds the wave's whole contribution to column l.  The four
@@ -29,8 +30,11 @@ namespace mlb {
 namespace {
 
 constexpr int kT = 256;
-constexpr int kBlk = 512;   // points per block
 constexpr int kChunk = 128; // columns staged per LDS fill
+
+// rows per lane: 4 for small d (amortises the LDS read and the rotation over
+// more pairs), 2 otherwise; a block holds 256 * RL points
+constexpr int rows_per_lane(int D) { return D <= 6 ? 4 : 2; }
 
 template <int D, int NU2, int OUT, bool F>
 __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts, const double* __restrict__ x,
@@ -38,12 +42,14 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
                                                  double* __restrict__ prow, double* __restrict__ pcol,
                                                  double* __restrict__ pdrow, double* __restrict__ pdcol) {
   constexpr int SD = D + 1;
+  constexpr int RL = rows_per_lane(D);
+  constexpr int kBlk = 256 * RL;
   __shared__ double cp[kChunk * SD];
   __shared__ double cred[4][kChunk];
   __shared__ double cdred[4][kChunk];
   __shared__ double tab[kExpTab];
   const int S = blockIdx.x;
-  const int r = round0 + blockIdx.y;
+  const int r = round0 + (diag ? 0 : (int)blockIdx.y);
   int Sp = S;
   if (!diag) {
     Sp = (S + r) % T;
@@ -54,18 +60,23 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
   // lane rotation direction: after one rotation lane l holds lane (l + delta)'s value
   const int delta = (wave_rotate1_i(lane) - lane) & 63;
 
-  double xr[2][D], ar[2];
+  double xr[RL][D], ar[RL];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int64_t i = (int64_t)S * kBlk + wave * 128 + q * 64 + lane;
+  for (int q = 0; q < RL; ++q) {
+    const int64_t i = (int64_t)S * kBlk + wave * (64 * RL) + q * 64 + lane;
     const int64_t ii = i < n ? i : n - 1;
 #pragma unroll
     for (int k = 0; k < D; ++k) xr[q][k] = pts[ii * D + k] * zs;
     ar[q] = i < n ? x[i] : 0.0;
   }
-  double racc[2] = {0.0, 0.0}, rdacc[2] = {0.0, 0.0};
+  double racc[RL], rdacc[RL];
+#pragma unroll
+  for (int q = 0; q < RL; ++q) racc[q] = rdacc[q] = 0.0;
   const int64_t cbase = (int64_t)Sp * kBlk;
-  for (int c0 = 0; c0 < kBlk; c0 += kChunk) {
+  // a diagonal tile is split over gridDim.y column ranges (one partial slot each)
+  const int cfirst = diag ? (int)blockIdx.y * (kBlk / (int)gridDim.y) : 0;
+  const int clast = diag ? cfirst + kBlk / (int)gridDim.y : kBlk;
+  for (int c0 = cfirst; c0 < clast; c0 += kChunk) {
     __syncthreads();
     for (int e = tid; e < kChunk * D; e += kT) {
       const int j = e / D, k = e - j * D;
@@ -90,7 +101,7 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
         const double aj = cj[D];
         double cpart = 0.0, cdpart = 0.0;
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < RL; ++q) {
           double s = 1e-300;
 #pragma unroll
           for (int t = 0; t < D; ++t) {
@@ -126,8 +137,8 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
     }
   }
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int64_t i = (int64_t)S * kBlk + wave * 128 + q * 64 + lane;
+  for (int q = 0; q < RL; ++q) {
+    const int64_t i = (int64_t)S * kBlk + wave * (64 * RL) + q * 64 + lane;
     if (i < n) {
       const int64_t slot = (int64_t)blockIdx.y * n + i;
       if constexpr (OUT & 1) prow[slot] = racc[q];
@@ -141,10 +152,10 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
 // partial.
 __global__ __launch_bounds__(kT) void sym_reduce(const double* __restrict__ prow, const double* __restrict__ pcol,
                                                  int nr, int64_t n, int T, int round0, int last, double scale,
-                                                 double* __restrict__ acc, double* __restrict__ y) {
+                                                 double* __restrict__ acc, double* __restrict__ y, int blk_pts) {
   const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
   if (i >= n) return;
-  const int blk = (int)(i / kBlk);
+  const int blk = (int)(i / blk_pts);
   double s = acc[i];
   for (int q = 0; q < nr; ++q) {
     const int r = round0 + q;
@@ -199,6 +210,16 @@ LaunchFn pick_nu(int nu2, int out, int d) {
 }
 
 constexpr int kRoundsPerLaunch = 16;
+constexpr int kDiagSplit = 4;
+
+__global__ __launch_bounds__(kT) void sum_slots(const double* __restrict__ slots, int k, int64_t n,
+                                                double* __restrict__ acc) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int q = 0; q < k; ++q) s += slots[(int64_t)q * n + i];
+  acc[i] = s;
+}
 
 }  // namespace
 
@@ -208,31 +229,36 @@ bool sym_supported(int d) { return pick_nu<false>(1, 1, d) != nullptr; }
 bool sym_worthwhile(int64_t n) { return n >= 16384; }
 
 int64_t sym_workspace_bytes(int64_t n, int outputs) {
-  const int64_t per = (int64_t)(2 * kRoundsPerLaunch + 1) * n * 8;
+  const int64_t per = (int64_t)(2 * kRoundsPerLaunch + 1 + kDiagSplit) * n * 8;
   const int64_t a = (per + 255) / 256 * 256;
   return a * ((outputs & 1 ? 1 : 0) + (outputs & 2 ? 1 : 0));
 }
 
 int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s) {
   const int64_t n = a.n;
+  const int kBlk = 256 * rows_per_lane(a.d);
   const int T = (int)((n + kBlk - 1) / kBlk);
   const bool f32 = a.precision != MLBLUP_FP64;
   LaunchFn fn = f32 ? pick_nu<true>(a.nu2, a.outputs, a.d) : pick_nu<false>(a.nu2, a.outputs, a.d);
   if (!fn) return fail(MLBLUP_EINVAL, "symmetric pair kernel: dimension not compiled");
-  const int64_t per = ((int64_t)(2 * kRoundsPerLaunch + 1) * n * 8 + 255) / 256 * 256;
+  const int64_t per = ((int64_t)(2 * kRoundsPerLaunch + 1 + kDiagSplit) * n * 8 + 255) / 256 * 256;
   double* base_v = (a.outputs & 1) ? (double*)work : nullptr;
   double* base_d = (a.outputs & 2) ? (double*)((char*)work + ((a.outputs & 1) ? per : 0)) : nullptr;
-  auto parts = [&](double* b, double*& pdiag, double*& prow, double*& pcol) {
-    pdiag = b;
-    prow = b ? b + n : nullptr;
-    pcol = b ? b + n + (int64_t)kRoundsPerLaunch * n : nullptr;
+  // per output: [kDiagSplit diagonal slots | accumulator | row partials | column partials]
+  auto parts = [&](double* b, double*& pslots, double*& pacc, double*& prow, double*& pcol) {
+    pslots = b;
+    pacc = b ? b + (int64_t)kDiagSplit * n : nullptr;
+    prow = b ? b + (int64_t)(kDiagSplit + 1) * n : nullptr;
+    pcol = b ? b + (int64_t)(kDiagSplit + 1 + kRoundsPerLaunch) * n : nullptr;
   };
-  double *vd, *vr, *vc, *dd, *dr, *dc;
-  parts(base_v, vd, vr, vc);
-  parts(base_d, dd, dr, dc);
+  double *vs, *vd, *vr, *vc, *ds, *dd, *dr, *dc;
+  parts(base_v, vs, vd, vr, vc);
+  parts(base_d, ds, dd, dr, dc);
   const unsigned g = (unsigned)((n + kT - 1) / kT);
-  // diagonal tiles
-  fn(a.cols, a.x, n, T, 0, 1, 1, zs, vd, nullptr, dd, nullptr, s);
+  // diagonal tiles, each split over kDiagSplit column ranges
+  fn(a.cols, a.x, n, T, 0, kDiagSplit, 1, zs, vs, nullptr, ds, nullptr, s);
+  if (a.outputs & 1) hipLaunchKernelGGL(sum_slots, dim3(g), dim3(kT), 0, s, vs, kDiagSplit, n, vd);
+  if (a.outputs & 2) hipLaunchKernelGGL(sum_slots, dim3(g), dim3(kT), 0, s, ds, kDiagSplit, n, dd);
   const int rounds = T / 2;
   int r0 = 1;
   do {
@@ -240,9 +266,9 @@ int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s) {
     if (nr > 0) fn(a.cols, a.x, n, T, r0, nr, 0, zs, vr, vc, dr, dc, s);
     const int last = (r0 + nr > rounds) ? 1 : 0;
     if (a.outputs & 1)
-      hipLaunchKernelGGL(sym_reduce, dim3(g), dim3(kT), 0, s, vr, vc, nr, n, T, r0, last, a.sigma2, vd, a.y);
+      hipLaunchKernelGGL(sym_reduce, dim3(g), dim3(kT), 0, s, vr, vc, nr, n, T, r0, last, a.sigma2, vd, a.y, kBlk);
     if (a.outputs & 2)
-      hipLaunchKernelGGL(sym_reduce, dim3(g), dim3(kT), 0, s, dr, dc, nr, n, T, r0, last, a.sigma2, dd, a.dy);
+      hipLaunchKernelGGL(sym_reduce, dim3(g), dim3(kT), 0, s, dr, dc, nr, n, T, r0, last, a.sigma2, dd, a.dy, kBlk);
     r0 += kRoundsPerLaunch;
   } while (r0 <= rounds);
   return hip_check(hipGetLastError(), "symmetric pair kernel launch");

@@ -35,10 +35,14 @@ __device__ __forceinline__ void exp_table_fill(double* tab) {
 
 __device__ __forceinline__ double exp_neg_f64(double z, const double* __restrict__ tab) {
   z = fmin(z, 708.0);
-  const double n = __builtin_rint(z * kExpInvL);
+  // n = nearest integer to z 32/ln2: adding 1.5 * 2^52 leaves n in the low
+  // mantissa bits (exact rounding by the FMA); subtracting it back gives n
+  constexpr double kShift = 6755399441055744.0;  // 1.5 * 2^52
+  const double t = fma(z, kExpInvL, kShift);
+  const int ni = __double2loint(t);
+  const double n = t - kShift;
   double r = fma(-n, kExpLHi, z);
   r = fma(-n, kExpLLo, r);
-  const int ni = (int)n;
   const double u = -r;
   double p = fma(u, 1.0 / 720.0, 1.0 / 120.0);
   p = fma(u, p, 1.0 / 24.0);
@@ -46,7 +50,11 @@ __device__ __forceinline__ double exp_neg_f64(double z, const double* __restrict
   p = fma(u, p, 0.5);
   p = fma(u, p, 1.0);
   p = fma(u, p, 1.0);
-  return __builtin_ldexp(p * tab[ni & (kExpTab - 1)], -(ni >> 5));
+  // 2^{-m} 2^{-j/32}: subtract m = n >> 5 from the exponent field of the
+  // table value (m <= 1021 keeps the result a normal number)
+  const double tj = tab[ni & (kExpTab - 1)];
+  const double sc = __hiloint2double(__double2hiint(tj) - ((ni >> 5) << 20), __double2loint(tj));
+  return p * sc;
 }
 
 // sqrt(s) for s > 0 (callers keep s away from 0 by a 1e-300 offset): the

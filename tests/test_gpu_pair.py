@@ -108,20 +108,19 @@ def test_full_size_sampled_rows(k):
     assert row_relerr(host(y)[idx], ref, sc) < FP32_TOL
 
 
-@pytest.mark.parametrize("n", [16384, 16385, 16897, 17408])
-def test_symmetric_square_product(n):
+@pytest.mark.parametrize("n,d", [(16384, 3), (16385, 5), (16897, 3), (17408, 5), (16385, 10), (16896, 20)])
+def test_symmetric_square_product(n, d):
     """Square products (rows and cols the same array, n >= 16,384) take the
     symmetric path; ragged last block, odd and even numbers of blocks.  The
     oracle checks 96 sampled rows (full rows of the product)."""
     torch = require_gpu()
     from paper_1701_00285_amd import DLOGRHO, FP32, FP64, VALUE, cov_matvec
-    d = 3 if n % 2 else 5
     pts = synth.uniform_cloud(n, d, 40 + n)
     x = synth.standard_normal(n, 41 + n)
     say(f"symmetric n={n} d={d}")
     idx = np.unique(np.concatenate([np.arange(0, n, max(1, n // 64)), np.arange(n - 32, n)]))
     for nu in (0.5, 1.5, 2.5):
-        rho = 0.25
+        rho = 0.25 * np.sqrt(d / 3)
         ref = brute.cov_matvec(pts[idx], pts, x, nu, rho, 1.3)
         dref = brute.cov_matvec(pts[idx], pts, x, nu, rho, 1.3, deriv=True)
         sc = 1.3 * _scale(pts[idx], pts, x, nu, rho)
@@ -136,3 +135,34 @@ def test_symmetric_square_product(n):
             yr, _ = cov_matvec(P, P.clone(), X, nu, rho, 1.3, precision=prec)
             full_scale, _ = cov_matvec(P, P.clone(), torch.abs(X), nu, rho, 1.3, precision=FP64)
             assert row_relerr(host(yr), host(y1), host(full_scale)) < 2 * tol
+
+
+@pytest.mark.parametrize("d", [8, 10, 16, 20, 25])
+@pytest.mark.parametrize("square", [False, True])
+def test_matrix_core_gram(d, square):
+    """Distance Gram on the matrix cores (FP32 and BF16 x3), rectangular and
+    square (the square case takes exact differences on the near tiles),
+    against the oracle; the self pair stays exact."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import MFMA_BF16X3, MFMA_FP32, cov_matvec
+    n = 3001
+    cols = synth.uniform_cloud(n, d, 60 + d)
+    rows = cols if square else synth.uniform_cloud(777, d, 61 + d)
+    x = synth.standard_normal(n, 62 + d)
+    idx = np.arange(0, rows.shape[0], 7)
+    say(f"mfma d={d} square={square}")
+    for nu in (0.5, 1.5, 2.5):
+        rho = 0.35 * np.sqrt(d)
+        ref = brute.cov_matvec(rows[idx], cols, x, nu, rho)
+        sc = _scale(rows[idx], cols, x, nu, rho)
+        R = dev(rows)
+        C = R if square else dev(cols)
+        for prec, tol in ((MFMA_FP32, 2e-5), (MFMA_BF16X3, 3e-4)):
+            y, _ = cov_matvec(R, C, dev(x), nu, rho, precision=prec)
+            assert row_relerr(host(y)[idx], ref, sc) < tol, (prec, nu)
+    if square:
+        e = np.zeros(n)
+        e[1234] = 1.0
+        for prec in (MFMA_FP32, MFMA_BF16X3):
+            y, _ = cov_matvec(R, R, dev(e), 0.5, 1.0, 1.0, precision=prec)
+            assert host(y)[1234] == 1.0

@@ -122,3 +122,22 @@ def test_basis_independence_of_iterations():
     # over hundreds of iterations rounding (loss of orthogonality) lets the
     # two finite-precision runs drift apart slightly
     assert abs(it[0] - it[1]) <= 0.03 * max(it) + 2
+
+
+@pytest.mark.parametrize("k,prec", [(5, 2), (5, 3), (3, 2)])
+def test_mixed_matrix_core_solve(k, prec):
+    """Mixed solves whose inner products use the matrix-core distance Gram
+    (d = 20 and d = 10 workloads, subsampled) reach the FP64 residual and
+    the oracle's predictions."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import PREC_BLOCK, PcgOptions
+    wl = workload(k, n=3000, n_targets=200)
+    say(f"mixed matrix-core cfg{k} precision={prec}")
+    s = _solver(wl, max_targets=200)
+    pc = s.precond(PREC_BLOCK)
+    out = s.predict(dev(wl.z), dev(wl.targets), PcgOptions(rtol=1e-10, precision=prec, inner_rtol=1e-2,
+                                                           precond=pc, max_iter=5000))
+    assert out["info"]["relres_fp64"] <= 1e-10
+    assert out["info"]["lowp_matvecs"] > 0
+    ref = OB.classic_blup(wl.points, wl.z, wl.targets, wl.degree_w, wl.nu, wl.rho)
+    assert relerr(host(out["zhat"]), ref.zhat) < 1e-8
