@@ -44,6 +44,32 @@ def flops_per_unordered_pair(d: int, nu: float) -> int:
     return 3 * d + 6 + poly
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sym_kernel_fp64_cfg2_n65536_d3.txt")
+
+
+def measured_traffic():
+    """HBM bytes per FP64 symmetric product from the calibrated rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs recorded under profiles/, or None when the
+    kernel sources changed since they were taken (hash mismatch)."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for src in kv.get("sources", "").split():
+        p = os.path.join(ROOT, src)
+        if not os.path.exists(p):
+            return None
+        h.update(open(p, "rb").read())
+    if h.hexdigest() != kv.get("source_sha256"):
+        return None
+    return int(float(kv["hbm_bytes_per_product"]))
+
+
 def cpu_baseline(wl, rows: int):
     """The oracle's row-block FP64 product on a bounded sample of rows."""
     import numpy as np
@@ -71,6 +97,10 @@ def main():
                                                           "MFMA FP32 for d>=8)")
     ap.add_argument("--cpu-rows", type=int, default=3072)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=40000,
+                    help="Krylov iteration cap (lower it only for short profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 512 MiB three times with a plain device copy (reference for HBM counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {a.gpus} is not supported (run with --gpus 1)",
@@ -79,6 +109,15 @@ def main():
 
     import numpy as np
     import torch
+
+    if a.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": src.numel() * 8, "launches": 3}), flush=True)
+        return
 
     import synth
     from paper_1701_00285_amd import (FP32, FP64, MFMA_FP32, PREC_BLOCK, VALUE, PcgOptions, Solver, profile_enable,
@@ -100,14 +139,16 @@ def main():
         zw, _ = s.apply_W(zt)
         torch.cuda.synchronize()
         t.append(time.perf_counter())
-        gw64, info64, _ = s.solve(zw, PcgOptions(rtol=1e-8, max_iter=40000, precision=FP64, precond=pc))
+        gw64, info64, st64 = s.solve(zw, PcgOptions(rtol=1e-8, max_iter=a.max_iter, precision=FP64, precond=pc),
+                                     allow_noconv=True)
         torch.cuda.synchronize()
         t.append(time.perf_counter())
-        gwm, infom, _ = s.solve(zw, PcgOptions(rtol=1e-8, max_iter=40000, precision=mixed, inner_rtol=0.1,
-                                               precond=pc))
+        gwm, infom, stm = s.solve(zw, PcgOptions(rtol=1e-8, max_iter=a.max_iter, precision=mixed, inner_rtol=0.1,
+                                                 precond=pc), allow_noconv=True)
         torch.cuda.synchronize()
         t.append(time.perf_counter())
-        out = s.predict(Z, T, PcgOptions(rtol=1e-8, max_iter=40000, precision=FP64, precond=pc), gamma_w0=gw64)
+        out = s.predict(Z, T, PcgOptions(rtol=1e-8, max_iter=a.max_iter, precision=FP64, precond=pc), gamma_w0=gw64,
+                        allow_noconv=True)
         torch.cuda.synchronize()
         t.append(time.perf_counter())
         q, dq = s.quad_grad(zt, out["gamma_tree"])
@@ -116,7 +157,7 @@ def main():
         rd = float(torch.linalg.norm(gwm - gw64) / torch.linalg.norm(gw64))
         rec.append(dict(setup=t[1] - t[0], solve_fp64=t[2] - t[1], solve_mixed=t[3] - t[2], predict=t[4] - t[3],
                         grad=t[5] - t[4], total=t[5] - t[0], info64=info64, infom=infom, infop=out["info"], q=q,
-                        dq=dq, reldiff=rd, p=s.p))
+                        dq=dq, reldiff=rd, p=s.p, converged=(st64 == 0 and stm == 0 and out["status"] == 0)))
 
     warm = []
     for _ in range(a.warmup):
@@ -162,7 +203,8 @@ def main():
                    "leaf": wl.leaf_max, "targets": int(T.shape[0]), "rtol": 1e-8, "preconditioner": "cell blocks of C_W",
                    "mixed_precision": mixed},
         "phases_s": {k: round(last[k], 4) for k in ("setup", "solve_fp64", "solve_mixed", "predict", "grad", "total")},
-        "solve": {"fp64_s": round(last["solve_fp64"], 3), "mixed_s": round(last["solve_mixed"], 3),
+        "solve": {"converged": last["converged"],
+                  "fp64_s": round(last["solve_fp64"], 3), "mixed_s": round(last["solve_mixed"], 3),
                   "speedup": round(last["solve_fp64"] / last["solve_mixed"], 3),
                   "fp64_iters": i64["inner_iters"], "fp64_relres": i64["relres_fp64"],
                   "mixed_outer": im["outer_iters"], "mixed_inner": im["inner_iters"],
@@ -186,8 +228,10 @@ def main():
         frac_sq = sq64 * n * n / pairs64
         t_sq = ms64 * 1e-3 * frac_sq
         achieved = sq64 * (n * (n + 1) / 2) * fpp / t_sq / 1e12
+        traffic = measured_traffic() if (wl.n == 65536 and wl.d == 3) else None
         out["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU_TFLOPS,
-                           "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4), "traffic": None,
+                           "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4),
+                           "traffic": traffic,
                            "kernel": "sym_kernel FP64 value (square C x)", "launches": sq64,
                            "avg_launch_ms": round(t_sq / sq64 * 1e3, 4), "flops_per_unordered_pair": fpp}
     out["grad"] = {"Q": last["q"], "dQ_dlogrho": last["dq"]}
