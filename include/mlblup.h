@@ -29,6 +29,8 @@
  *   - Handles (tree, basis) are immutable after construction and may be
  *     used from several streams at once; a workspace must not be shared by
  *     calls in flight at the same time.
+ *   - Environment: MLBLUP_LOG_EVERY=k (k > 0) makes the Krylov solves print
+ *     the recurrence residual every k iterations to stderr.
  */
 #ifndef MLBLUP_H
 #define MLBLUP_H

@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -31,6 +33,15 @@ namespace {
 
 constexpr int64_t kAlign = 256;
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// progress log of long solves: MLBLUP_LOG_EVERY=k prints the residual every k iterations to stderr
+int log_every() {
+  static const int k = [] {
+    const char* e = std::getenv("MLBLUP_LOG_EVERY");
+    return e ? std::atoi(e) : 0;
+  }();
+  return k;
+}
 
 int nu2_of(const mlblup_matern* k) {
   if (!k) return -1;
@@ -269,6 +280,11 @@ struct Ctx {
       if (history && o.history_host && info.inner_iters < o.history_cap)
         o.history_host[info.inner_iters] = std::sqrt(sc_host[S_RR]) / bnorm;
       info.inner_iters++;
+      if (log_every() > 0 && info.inner_iters % log_every() == 0) {
+        std::fprintf(stderr, "mlblup: iteration %d (precision %d) relres %.3e\n", info.inner_iters, prec,
+                     std::sqrt(sc_host[S_RR]) / bnorm);
+        std::fflush(stderr);
+      }
       if (sc_host[S_FLAG] != 0.0) return fail(MLBLUP_EBREAKDOWN, "pcg_solve: breakdown (p.q <= 0 or non-finite scalar)");
       if (std::sqrt(sc_host[S_RR]) <= tol_abs) break;
       if ((st = pcg_update_p(p, zz, nw, sc, s))) return st;

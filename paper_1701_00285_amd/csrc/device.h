@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 
 #include "internal.h"
 
@@ -40,6 +41,10 @@ int32_t pair_splits(int64_t m, int64_t n, int32_t d, int32_t precision);
 // Workspace bytes for the partial sums.
 int64_t pair_workspace_bytes(int64_t m, int64_t n, int32_t d, int32_t precision, int32_t outputs);
 // Symmetric square product (pair_sym.hip): each unordered pair once.
+// tile launcher of a symmetric schedule: (T blocks, first round, rounds, diagonal?, partial buffers)
+using SymTileLaunch = std::function<void(int, int, int, int, double*, double*, double*, double*)>;
+// deterministic tournament schedule over blocks of blk_pts points (pair_sym.hip)
+int sym_schedule(const PairArgs& a, int blk_pts, void* work, hipStream_t s, const SymTileLaunch& fn);
 bool sym_supported(int d);
 bool sym_worthwhile(int64_t n);
 int64_t sym_workspace_bytes(int64_t n, int outputs);
@@ -48,6 +53,8 @@ int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s);
 bool mfma_applies(const PairArgs& a);
 int32_t mfma_splits(int64_t m, int64_t n);
 int mfma_launch(const PairArgs& a, double zs, double* part, hipStream_t s);
+// square products (n >= 16,384): each unordered pair once, tournament schedule
+int mfma_sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s);
 // Validates and launches (pair kernel + split reduction).
 int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s);
 

@@ -225,7 +225,7 @@ int64_t pair_workspace_bytes(int64_t m, int64_t n, int32_t d, int32_t precision,
   int64_t b = aligned * (((outputs & 1) ? 1 : 0) + ((outputs & 2) ? 1 : 0));
   if ((precision == MLBLUP_MFMA_FP32 || precision == MLBLUP_MFMA_BF16X3) && outputs == MLBLUP_VALUE)
     b = std::max(b, ((int64_t)mfma_splits(m, n) * m * (int64_t)sizeof(double) + 255) / 256 * 256);
-  if (m == n && sym_supported(d) && sym_worthwhile(n)) b = std::max(b, sym_workspace_bytes(n, outputs));
+  if (m == n && sym_worthwhile(n)) b = std::max(b, sym_workspace_bytes(n, outputs));
   return b;
 }
 
@@ -259,16 +259,19 @@ int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s
       MLB_HIP(hipEventCreate(&e1));
       MLB_HIP(hipEventRecord(e0, s));
     }
-    const int st = mfma_launch(a, zs, (double*)work, s);
+    const bool square = a.rows == a.cols && a.m == a.n && sym_worthwhile(a.n);
+    const int st = square ? mfma_sym_launch(a, zs, work, s) : mfma_launch(a, zs, (double*)work, s);
     if (st) return st;
+    if (!square) {
+      const unsigned g = (unsigned)((a.m + kThreads - 1) / kThreads);
+      hipLaunchKernelGGL(reduce_splits, dim3(g), dim3(kThreads), 0, s, (const double*)work, mfma_splits(a.m, a.n),
+                         a.m, a.sigma2, a.y);
+    }
     if (profile_on()) {
       MLB_HIP(hipEventRecord(e1, s));
       profile_note(e0, e1, (double)a.m * (double)a.n, a.precision * 4 + a.outputs);
     }
-    const unsigned g = (unsigned)((a.m + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(reduce_splits, dim3(g), dim3(kThreads), 0, s, (const double*)work, mfma_splits(a.m, a.n), a.m,
-                       a.sigma2, a.y);
-    return hip_check(hipGetLastError(), "reduce_splits launch");
+    return hip_check(hipGetLastError(), "matrix-core pair kernel launch");
   }
   if (a.rows == a.cols && a.m == a.n && sym_supported(a.d) && sym_worthwhile(a.n)) {
     hipEvent_t e0 = nullptr, e1 = nullptr;

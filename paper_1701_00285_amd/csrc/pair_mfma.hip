@@ -216,6 +216,262 @@ __global__ __launch_bounds__(kT) void mfma_kernel(const double* __restrict__ row
   }
 }
 
+// Symmetric square product on the matrix cores: blocks of 256 points
+// (4 waves x 4 row tiles of 16), the tournament schedule of the direct
+// symmetric kernel (diagonal tiles split over column ranges, each block a
+// row block and a column block at most once per round).  Row sums stay in
+// the lanes (16 column lanes per row, reduced at the end); a column's sum
+// over the wave's 64 rows is the lane sum over the 4 row groups (two
+// cross-lane steps) and is then added over the 4 waves through LDS.  On
+// diagonal tiles the 16x16 sub-tiles whose rows and columns are the same
+// points (self pairs and their nearest neighbours) take exact FP64
+// differences from LDS; every other pair uses the Gram.
+constexpr int kSymRT = 4;
+constexpr int kSymBlk = 4 * 16 * kSymRT;
+constexpr int kMaxDExact = 33;
+
+// exact squared distance of two staged chunk points from their FP64 scaled coordinates
+template <int KP>
+__device__ __forceinline__ float exact_sq(const double* cexact, int a, int b, int d) {
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    if (k >= d) break;
+    const double t = cexact[a * kMaxDExact + k] - cexact[b * kMaxDExact + k];
+    s = fma(t, t, s);
+  }
+  return (float)s;
+}
+
+template <int KP, int NU2, bool BF>
+__global__ __launch_bounds__(kT) void mfma_sym_kernel(const double* __restrict__ pts, const double* __restrict__ x,
+                                                      int64_t n, int d, int T, int round0, int diag, double zs,
+                                                      double* __restrict__ prow, double* __restrict__ pcol) {
+  __shared__ float cf[kChunk * KP];
+  __shared__ unsigned short chi[kChunk * KP];
+  __shared__ unsigned short clo[kChunk * KP];
+  __shared__ float cn[kChunk];
+  __shared__ double cx[kChunk];
+  __shared__ double cexact[kChunk * kMaxDExact];
+  __shared__ float csum[4][kChunk];
+  __shared__ double ctr[32];
+  const int S = blockIdx.x;
+  const int rr = round0 + (diag ? 0 : (int)blockIdx.y);
+  int Sp = S;
+  if (!diag) {
+    Sp = (S + rr) % T;
+    if ((T % 2 == 0) && (2 * rr == T) && S >= T / 2) return;  // whole block exits
+  }
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t rb = (int64_t)S * kSymBlk, cb = (int64_t)Sp * kSymBlk;
+  {
+    int64_t ci = rb + kSymBlk / 2;
+    if (ci >= n) ci = n - 1;
+    if (tid < d) ctr[tid] = pts[ci * d + tid] * zs;
+  }
+  __syncthreads();
+  float af[BF ? 1 : kSymRT][BF ? 1 : KP / 4];
+  s4 ahi[BF ? kSymRT : 1][BF ? KP / 16 : 1], alo[BF ? kSymRT : 1][BF ? KP / 16 : 1];
+  float rn[kSymRT][4], xr[kSymRT][4];
+  double racc[kSymRT][4];
+#pragma unroll
+  for (int rt = 0; rt < kSymRT; ++rt) {
+    const int64_t i0 = rb + wave * 64 + rt * 16 + lr;  // the row whose A fragment this lane holds
+    const int64_t ia = i0 < n ? i0 : n - 1;
+    float part = 0.0f;  // this lane's share of |a|^2 for row lr
+    if constexpr (!BF) {
+#pragma unroll
+      for (int t = 0; t < KP / 4; ++t) {
+        const int k = 4 * t + lg;
+        af[rt][t] = k < d ? (float)(pts[ia * d + k] * zs - ctr[k]) : 0.0f;
+        part = fmaf(af[rt][t], af[rt][t], part);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < KP / 16; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = 16 * t + 4 * lg + e;
+          const float v = k < d ? (float)(pts[ia * d + k] * zs - ctr[k]) : 0.0f;
+          const unsigned short h = bf16_rne(v);
+          const unsigned short l = bf16_rne(v - bf16_to_f(h));
+          ahi[rt][t][e] = (short)h;
+          alo[rt][t][e] = (short)l;
+          const float vv = bf16_to_f(h) + bf16_to_f(l);
+          part = fmaf(vv, vv, part);
+        }
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);  // every lane: |a|^2 of row lr
+    const float xa = i0 < n ? (float)x[i0] : 0.0f;
+    // the result rows of this lane are 4 lg + r: fetch their norm and x from lane 4 lg + r
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      rn[rt][r] = __shfl(part, 4 * lg + r, 64);
+      xr[rt][r] = __shfl(xa, 4 * lg + r, 64);
+      racc[rt][r] = 0.0;
+    }
+  }
+  const int cfirst = diag ? (int)blockIdx.y * (kSymBlk / (int)gridDim.y) : 0;
+  const int clast = diag ? cfirst + kSymBlk / (int)gridDim.y : kSymBlk;
+  for (int c0 = cfirst; c0 < clast; c0 += kChunk) {
+    __syncthreads();
+#pragma unroll
+    for (int e = tid; e < kChunk * KP; e += kT) {
+      const int j = e / KP, k = e - j * KP;
+      const int64_t gj = cb + c0 + j;
+      const bool ok = gj < n && k < d;
+      const double xs = ok ? pts[gj * d + k] * zs : 0.0;
+      const float v = ok ? (float)(xs - ctr[k]) : 0.0f;
+      if constexpr (BF) {
+        const unsigned short h = bf16_rne(v);
+        chi[e] = h;
+        clo[e] = bf16_rne(v - bf16_to_f(h));
+      } else {
+        cf[e] = v;
+      }
+      if (diag && k < kMaxDExact) cexact[j * kMaxDExact + k] = xs;
+    }
+    for (int j = tid; j < kChunk; j += kT) {
+      const int64_t gj = cb + c0 + j;
+      cx[j] = gj < n ? x[gj] : 0.0;
+    }
+    __syncthreads();
+    for (int j = tid; j < kChunk; j += kT) {
+      float s = 0.0f;
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        float vv;
+        if constexpr (BF) vv = bf16_to_f(chi[j * KP + k]) + bf16_to_f(clo[j * KP + k]);
+        else vv = cf[j * KP + k];
+        s = fmaf(vv, vv, s);
+      }
+      cn[j] = s;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int tile = 0; tile < kChunk / 16; ++tile) {
+      const int jc = tile * 16 + lr;
+      const double xc = cx[jc];
+      const float ncol = cn[jc];
+      float cpart = 0.0f;
+      if constexpr (!BF) {
+        float bf[KP / 4];
+#pragma unroll
+        for (int t = 0; t < KP / 4; ++t) bf[t] = cf[jc * KP + 4 * t + lg];
+        f4 gg[kSymRT];
+#pragma unroll
+        for (int rt = 0; rt < kSymRT; ++rt) gg[rt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < KP / 4; ++t)
+#pragma unroll
+          for (int rt = 0; rt < kSymRT; ++rt) gg[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[rt][t], bf[t], gg[rt], 0, 0, 0);
+#pragma unroll
+        for (int rt = 0; rt < kSymRT; ++rt) {
+          const f4 g = gg[rt];
+          const bool same = diag && (wave * 64 + rt * 16 == c0 + tile * 16);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            float sv = fmaxf(fmaf(-2.0f, g[r], rn[rt][r] + ncol), 0.0f);
+            if (same) sv = exact_sq<KP>(cexact, tile * 16 + 4 * lg + r, jc, d);
+            const float z = __builtin_amdgcn_sqrtf(sv);
+            const float ph = matern_polyf<NU2>(z) * __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
+            racc[rt][r] = fma((double)ph, xc, racc[rt][r]);
+            cpart = fmaf(ph, xr[rt][r], cpart);
+          }
+        }
+      } else {
+        s4 bh[KP / 16], bl[KP / 16];
+#pragma unroll
+        for (int t = 0; t < KP / 16; ++t)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            bh[t][e] = (short)chi[jc * KP + 16 * t + 4 * lg + e];
+            bl[t][e] = (short)clo[jc * KP + 16 * t + 4 * lg + e];
+          }
+        f4 gg[kSymRT];
+#pragma unroll
+        for (int rt = 0; rt < kSymRT; ++rt) gg[rt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < KP / 16; ++t)
+#pragma unroll
+          for (int rt = 0; rt < kSymRT; ++rt) {
+            gg[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[rt][t], bh[t], gg[rt], 0, 0, 0);
+            gg[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[rt][t], bl[t], gg[rt], 0, 0, 0);
+            gg[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo[rt][t], bh[t], gg[rt], 0, 0, 0);
+          }
+#pragma unroll
+        for (int rt = 0; rt < kSymRT; ++rt) {
+          const f4 g = gg[rt];
+          const bool same = diag && (wave * 64 + rt * 16 == c0 + tile * 16);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            float sv = fmaxf(fmaf(-2.0f, g[r], rn[rt][r] + ncol), 0.0f);
+            if (same) sv = exact_sq<KP>(cexact, tile * 16 + 4 * lg + r, jc, d);
+            const float z = __builtin_amdgcn_sqrtf(sv);
+            const float ph = matern_polyf<NU2>(z) * __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
+            racc[rt][r] = fma((double)ph, xc, racc[rt][r]);
+            cpart = fmaf(ph, xr[rt][r], cpart);
+          }
+        }
+      }
+      // column jc: sum over the four row groups of this wave
+      if (!diag) {
+        cpart += __shfl_xor(cpart, 16, 64);
+        cpart += __shfl_xor(cpart, 32, 64);
+        if (lg == 0) csum[wave][jc] = cpart;
+      }
+    }
+    __syncthreads();
+    if (!diag && tid < kChunk) {
+      const int64_t gj = cb + c0 + tid;
+      if (gj < n)
+        pcol[(int64_t)blockIdx.y * n + gj] =
+            (((double)csum[0][tid] + (double)csum[1][tid]) + (double)csum[2][tid]) + (double)csum[3][tid];
+    }
+  }
+  // row sums: reduce over the 16 column lanes of each row group
+#pragma unroll
+  for (int rt = 0; rt < kSymRT; ++rt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double v = racc[rt][r];
+      v += __shfl_xor(v, 1, 64);
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 8, 64);
+      const int64_t i = rb + wave * 64 + rt * 16 + 4 * lg + r;
+      if (lr == 0 && i < n) prow[(int64_t)blockIdx.y * n + i] = v;
+    }
+}
+
+template <int KP, int NU2, bool BF>
+void launch_sym(const PairArgs& a, double zs, void* work, int T, int r0, int nr, int diag, double* prow, double* pcol,
+                hipStream_t s) {
+  (void)work;
+  hipLaunchKernelGGL((mfma_sym_kernel<KP, NU2, BF>), dim3(T, nr), dim3(kT), 0, s, a.cols, a.x, a.n, a.d, T, r0, diag,
+                     zs, prow, pcol);
+}
+
+using SymFn = void (*)(const PairArgs&, double, void*, int, int, int, int, double*, double*, hipStream_t);
+
+template <int NU2, bool BF>
+SymFn pick_sym_kp(int d) {
+  if constexpr (BF) {
+    if (d <= 16) return launch_sym<16, NU2, true>;
+    if (d <= 32) return launch_sym<32, NU2, true>;
+  } else {
+    if (d <= 8) return launch_sym<8, NU2, false>;
+    if (d <= 12) return launch_sym<12, NU2, false>;
+    if (d <= 16) return launch_sym<16, NU2, false>;
+    if (d <= 20) return launch_sym<20, NU2, false>;
+    if (d <= 24) return launch_sym<24, NU2, false>;
+    if (d <= 32) return launch_sym<32, NU2, false>;
+  }
+  return nullptr;
+}
+
 template <int KP, int NU2, bool BF>
 void launch(const PairArgs& a, double zs, int S, int64_t cps, double* py, hipStream_t s) {
   dim3 grid((unsigned)((a.m + kRows - 1) / kRows), (unsigned)S);
@@ -255,6 +511,19 @@ int32_t mfma_splits(int64_t m, int64_t n) {
 bool mfma_applies(const PairArgs& a) {
   return (a.precision == MLBLUP_MFMA_FP32 || a.precision == MLBLUP_MFMA_BF16X3) && a.outputs == MLBLUP_VALUE &&
          a.d >= 8 && a.d <= 32;
+}
+
+int mfma_sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s) {
+  const bool bf = a.precision == MLBLUP_MFMA_BF16X3;
+  SymFn fn = nullptr;
+  if (a.nu2 == 1) fn = bf ? pick_sym_kp<1, true>(a.d) : pick_sym_kp<1, false>(a.d);
+  else if (a.nu2 == 3) fn = bf ? pick_sym_kp<3, true>(a.d) : pick_sym_kp<3, false>(a.d);
+  else fn = bf ? pick_sym_kp<5, true>(a.d) : pick_sym_kp<5, false>(a.d);
+  if (!fn) return fail(MLBLUP_EINVAL, "matrix-core pair kernel: d > 32");
+  return sym_schedule(a, kSymBlk, work, s,
+                      [&](int T, int r0, int nr, int diag, double* prow, double* pcol, double*, double*) {
+                        fn(a, zs, work, T, r0, nr, diag, prow, pcol, s);
+                      });
 }
 
 int mfma_launch(const PairArgs& a, double zs, double* part, hipStream_t s) {

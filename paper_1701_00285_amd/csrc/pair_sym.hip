@@ -234,13 +234,9 @@ int64_t sym_workspace_bytes(int64_t n, int outputs) {
   return a * ((outputs & 1 ? 1 : 0) + (outputs & 2 ? 1 : 0));
 }
 
-int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s) {
+int sym_schedule(const PairArgs& a, int blk_pts, void* work, hipStream_t s, const SymTileLaunch& fn) {
   const int64_t n = a.n;
-  const int kBlk = 256 * rows_per_lane(a.d);
-  const int T = (int)((n + kBlk - 1) / kBlk);
-  const bool f32 = a.precision != MLBLUP_FP64;
-  LaunchFn fn = f32 ? pick_nu<true>(a.nu2, a.outputs, a.d) : pick_nu<false>(a.nu2, a.outputs, a.d);
-  if (!fn) return fail(MLBLUP_EINVAL, "symmetric pair kernel: dimension not compiled");
+  const int T = (int)((n + blk_pts - 1) / blk_pts);
   const int64_t per = ((int64_t)(2 * kRoundsPerLaunch + 1 + kDiagSplit) * n * 8 + 255) / 256 * 256;
   double* base_v = (a.outputs & 1) ? (double*)work : nullptr;
   double* base_d = (a.outputs & 2) ? (double*)((char*)work + ((a.outputs & 1) ? per : 0)) : nullptr;
@@ -256,22 +252,34 @@ int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s) {
   parts(base_d, ds, dd, dr, dc);
   const unsigned g = (unsigned)((n + kT - 1) / kT);
   // diagonal tiles, each split over kDiagSplit column ranges
-  fn(a.cols, a.x, n, T, 0, kDiagSplit, 1, zs, vs, nullptr, ds, nullptr, s);
+  fn(T, 0, kDiagSplit, 1, vs, nullptr, ds, nullptr);
   if (a.outputs & 1) hipLaunchKernelGGL(sum_slots, dim3(g), dim3(kT), 0, s, vs, kDiagSplit, n, vd);
   if (a.outputs & 2) hipLaunchKernelGGL(sum_slots, dim3(g), dim3(kT), 0, s, ds, kDiagSplit, n, dd);
   const int rounds = T / 2;
   int r0 = 1;
   do {
     const int nr = std::max(0, std::min(kRoundsPerLaunch, rounds - r0 + 1));
-    if (nr > 0) fn(a.cols, a.x, n, T, r0, nr, 0, zs, vr, vc, dr, dc, s);
+    if (nr > 0) fn(T, r0, nr, 0, vr, vc, dr, dc);
     const int last = (r0 + nr > rounds) ? 1 : 0;
     if (a.outputs & 1)
-      hipLaunchKernelGGL(sym_reduce, dim3(g), dim3(kT), 0, s, vr, vc, nr, n, T, r0, last, a.sigma2, vd, a.y, kBlk);
+      hipLaunchKernelGGL(sym_reduce, dim3(g), dim3(kT), 0, s, vr, vc, nr, n, T, r0, last, a.sigma2, vd, a.y, blk_pts);
     if (a.outputs & 2)
-      hipLaunchKernelGGL(sym_reduce, dim3(g), dim3(kT), 0, s, dr, dc, nr, n, T, r0, last, a.sigma2, dd, a.dy, kBlk);
+      hipLaunchKernelGGL(sym_reduce, dim3(g), dim3(kT), 0, s, dr, dc, nr, n, T, r0, last, a.sigma2, dd, a.dy,
+                         blk_pts);
     r0 += kRoundsPerLaunch;
   } while (r0 <= rounds);
   return hip_check(hipGetLastError(), "symmetric pair kernel launch");
+}
+
+int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s) {
+  const bool f32 = a.precision != MLBLUP_FP64;
+  LaunchFn fn = f32 ? pick_nu<true>(a.nu2, a.outputs, a.d) : pick_nu<false>(a.nu2, a.outputs, a.d);
+  if (!fn) return fail(MLBLUP_EINVAL, "symmetric pair kernel: dimension not compiled");
+  const int blk = 256 * rows_per_lane(a.d);
+  return sym_schedule(a, blk, work, s,
+                      [&](int T, int r0, int nr, int diag, double* prow, double* pcol, double* pdrow, double* pdcol) {
+                        fn(a.cols, a.x, a.n, T, r0, nr, diag, zs, prow, pcol, pdrow, pdcol, s);
+                      });
 }
 
 }  // namespace mlb

@@ -166,3 +166,31 @@ def test_matrix_core_gram(d, square):
         for prec in (MFMA_FP32, MFMA_BF16X3):
             y, _ = cov_matvec(R, R, dev(e), 0.5, 1.0, 1.0, precision=prec)
             assert host(y)[1234] == 1.0
+
+
+@pytest.mark.parametrize("n,d", [(16385, 10), (17000, 20), (16384, 8)])
+def test_matrix_core_symmetric(n, d):
+    """Square products in the matrix-core precisions at n >= 16,384 take the
+    symmetric matrix-core kernel (tournament schedule, exact diagonal
+    tiles); sampled rows against the oracle, self pair exact."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import MFMA_BF16X3, MFMA_FP32, cov_matvec
+    pts = synth.uniform_cloud(n, d, 70 + d)
+    x = synth.standard_normal(n, 71 + d)
+    idx = np.unique(np.concatenate([np.arange(0, n, max(1, n // 48)), np.arange(n - 16, n)]))
+    say(f"mfma symmetric n={n} d={d}")
+    P, X = dev(pts), dev(x)
+    for nu in (0.5, 2.5):
+        rho = 0.35 * np.sqrt(d)
+        ref = brute.cov_matvec(pts[idx], pts, x, nu, rho)
+        sc = _scale(pts[idx], pts, x, nu, rho)
+        for prec, tol in ((MFMA_FP32, 2e-5), (MFMA_BF16X3, 3e-4)):
+            y, _ = cov_matvec(P, P, X, nu, rho, precision=prec)
+            assert row_relerr(host(y)[idx], ref, sc) < tol, (prec, nu)
+            y2, _ = cov_matvec(P, P, X, nu, rho, precision=prec)
+            assert np.array_equal(host(y), host(y2))
+    e = np.zeros(n)
+    e[n // 3] = 1.0
+    for prec in (MFMA_FP32, MFMA_BF16X3):
+        y, _ = cov_matvec(P, P, dev(e), 0.5, 1.0, 1.0, precision=prec)
+        assert host(y)[n // 3] == 1.0
