@@ -2,13 +2,15 @@
 """Benchmark of the multilevel BLUP solve on one MI355X.
 
 One step = one pass of the whole hot path over one synthetic workload:
-kd-tree and multilevel basis (host C++), basis upload, the block
-preconditioner, W Z, the FP64 PCG solve of C_W gamma_W = Z_W to relres
-1e-8, the mixed-precision solve of the same system to the same FP64 relres
-(flexible-CG iterative refinement, FP32 kernel values), the predictor
-(warm-started from the FP64 solution: true FP64 residual, gamma, beta-hat,
-predictions at the targets) and Q, dQ/dlog rho.  Inputs (points, Z,
-targets) are resident in HBM when the timed region starts.
+kd-tree and multilevel basis (host C++), basis upload, the preconditioner
+(cell blocks of C_W by default), W Z, the FP64 PCG solve of
+C_W gamma_W = Z_W to relres 1e-8, the mixed-precision solve of the same
+system to the same FP64 relres (flexible-CG iterative refinement, FP32
+kernel values), the predictor of each path (warm-started from its own
+solution: true FP64 residual, gamma, beta-hat, predictions at the targets;
+the mixed path's target products in its low precision) and Q, dQ/dlog rho
+of each.  Inputs (points, Z, targets) are resident in HBM when the timed
+region starts.
 
 The default workload is 65,536 uniform points in [0,1]^3, Matern nu=3/2,
 rho=0.2, quadratic trend (p=10), leaf 64, 4,096 targets.
@@ -95,6 +97,8 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--mixed", type=int, default=-1, help="precision of the mixed solve (default: FP32 for d<8, "
                                                           "MFMA FP32 for d>=8)")
+    ap.add_argument("--precond", choices=("block", "jacobi", "none"), default="block",
+                    help="preconditioner of both solves (cell blocks of C_W, its diagonal, or none)")
     ap.add_argument("--cpu-rows", type=int, default=3072)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-iter", type=int, default=40000,
@@ -120,8 +124,8 @@ def main():
         return
 
     import synth
-    from paper_1701_00285_amd import (FP32, FP64, MFMA_FP32, PREC_BLOCK, VALUE, PcgOptions, Solver, profile_enable,
-                                      profile_read)
+    from paper_1701_00285_amd import (FP32, FP64, MFMA_FP32, PREC_BLOCK, PREC_JACOBI, VALUE, PcgOptions, Solver,
+                                      profile_enable, profile_read)
 
     torch.cuda.set_device(0)
     wl = synth.make_config(a.config)
@@ -134,7 +138,8 @@ def main():
         t = [time.perf_counter()]
         pts_host = P.cpu().numpy()
         s = Solver(pts_host, wl.degree_w, wl.leaf_max, wl.nu, wl.rho, wl.sigma2, max_targets=T.shape[0])
-        pc = s.precond(PREC_BLOCK)
+        pc = {"block": PREC_BLOCK, "jacobi": PREC_JACOBI}.get(a.precond)
+        pc = s.precond(pc) if pc is not None else None
         zt = s.to_tree(Z)
         zw, _ = s.apply_W(zt)
         torch.cuda.synchronize()
@@ -151,13 +156,23 @@ def main():
                         allow_noconv=True)
         torch.cuda.synchronize()
         t.append(time.perf_counter())
+        # the mixed path's predictor: FP64 residual check of its gamma_W, the
+        # target products with low-precision kernel values
+        outm = s.predict(Z, T, PcgOptions(rtol=1e-8, max_iter=a.max_iter, precision=mixed, inner_rtol=0.1, precond=pc),
+                         predict_precision=mixed, gamma_w0=gwm, allow_noconv=True)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter())
         q, dq = s.quad_grad(zt, out["gamma_tree"])
+        qm, dqm = s.quad_grad(zt, outm["gamma_tree"], precision=mixed)
         torch.cuda.synchronize()
         t.append(time.perf_counter())
         rd = float(torch.linalg.norm(gwm - gw64) / torch.linalg.norm(gw64))
+        pe = float(torch.max(torch.abs(outm["zhat"] - out["zhat"])) / torch.max(torch.abs(out["zhat"])))
+        be = float(np.max(np.abs(outm["beta"] - out["beta"])) / np.max(np.abs(out["beta"])))
         rec.append(dict(setup=t[1] - t[0], solve_fp64=t[2] - t[1], solve_mixed=t[3] - t[2], predict=t[4] - t[3],
-                        grad=t[5] - t[4], total=t[5] - t[0], info64=info64, infom=infom, infop=out["info"], q=q,
-                        dq=dq, reldiff=rd, p=s.p, converged=(st64 == 0 and stm == 0 and out["status"] == 0)))
+                        predict_mixed=t[5] - t[4], grad=t[6] - t[5], total=t[6] - t[0], info64=info64, infom=infom,
+                        infop=out["info"], q=q, dq=dq, qm=qm, dqm=dqm, reldiff=rd, pred_err=pe, beta_err=be, p=s.p,
+                        converged=(st64 == 0 and stm == 0 and out["status"] == 0 and outm["status"] == 0)))
 
     warm = []
     for _ in range(a.warmup):
@@ -200,9 +215,11 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded)",
         "config": {"workload": wl.name, "n": n, "d": wl.d, "nu": wl.nu, "rho": wl.rho, "trend_p": last["p"],
-                   "leaf": wl.leaf_max, "targets": int(T.shape[0]), "rtol": 1e-8, "preconditioner": "cell blocks of C_W",
+                   "leaf": wl.leaf_max, "targets": int(T.shape[0]), "rtol": 1e-8,
+                   "preconditioner": {"block": "cell blocks of C_W", "jacobi": "diag(C_W)", "none": "none"}[a.precond],
                    "mixed_precision": mixed},
-        "phases_s": {k: round(last[k], 4) for k in ("setup", "solve_fp64", "solve_mixed", "predict", "grad", "total")},
+        "phases_s": {k: round(last[k], 4) for k in ("setup", "solve_fp64", "solve_mixed", "predict", "predict_mixed",
+                                                     "grad", "total")},
         "solve": {"converged": last["converged"],
                   "fp64_s": round(last["solve_fp64"], 3), "mixed_s": round(last["solve_mixed"], 3),
                   "speedup": round(last["solve_fp64"] / last["solve_mixed"], 3),
@@ -210,6 +227,7 @@ def main():
                   "mixed_outer": im["outer_iters"], "mixed_inner": im["inner_iters"],
                   "mixed_fp64_matvecs": im["fp64_matvecs"], "mixed_lowp_matvecs": im["lowp_matvecs"],
                   "mixed_relres_fp64": im["relres_fp64"], "gamma_w_reldiff_mixed_vs_fp64": last["reldiff"],
+                  "zhat_maxrelerr_mixed_vs_fp64": last["pred_err"], "beta_maxrelerr_mixed_vs_fp64": last["beta_err"],
                   "predict_warm_iters": ip["inner_iters"], "predict_relres": ip["relres_fp64"]},
         "pair_kernel": {
             "fp64_logical_gpairs_s": round(pairs64 / (ms64 * 1e-3) / 1e9, 2) if ms64 else None,
@@ -234,7 +252,8 @@ def main():
                            "traffic": traffic,
                            "kernel": "sym_kernel FP64 value (square C x)", "launches": sq64,
                            "avg_launch_ms": round(t_sq / sq64 * 1e3, 4), "flops_per_unordered_pair": fpp}
-    out["grad"] = {"Q": last["q"], "dQ_dlogrho": last["dq"]}
+    out["grad"] = {"Q": last["q"], "dQ_dlogrho": last["dq"], "Q_mixed": last["qm"], "dQ_dlogrho_mixed": last["dqm"],
+                   "dQ_relerr_mixed_vs_fp64": abs(last["dqm"] - last["dq"]) / abs(last["dq"])}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_rows)
     print(json.dumps(out), flush=True)

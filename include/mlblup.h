@@ -67,6 +67,10 @@ typedef struct mlblup_precond_s* mlblup_precond;
 #define MLBLUP_PREC_JACOBI 1   /* P_W = diag(C_W) */
 #define MLBLUP_PREC_BLOCK 2    /* P_W = the diagonal blocks of C_W, one per cell (its own wavelets) */
 
+/* mixed-precision schemes (mlblup_pcg_opts.mixed_scheme) */
+#define MLBLUP_MIXED_FLEXIBLE 0
+#define MLBLUP_MIXED_RELIABLE 1
+
 /* Matern covariance sigma2 * phi(r; nu, rho), Definition in Sec. 3.1 with the
  * half-integer closed forms (nu = 1/2, 3/2, 5/2), rho > 0, sigma2 > 0. */
 typedef struct {
@@ -78,13 +82,23 @@ typedef struct {
 /* Krylov solve options.  rtol: stop when |Z_W - C_W gamma_W|_2 <= rtol |Z_W|_2
  * on the UNPRECONDITIONED system, measured with the FP64 product (remark on
  * the stopping rule, Sec. 6.2).  precision: arithmetic of the inner product
- * (MLBLUP_FP64 runs plain PCG with a final FP64 residual check; lower
- * precisions run an FP64 iterative-refinement loop around inner PCG
- * solves).  refine_max: outer refinement steps.  inner_rtol: relative
- * reduction asked of each inner solve (lower precisions).  precond: NULL for
- * P_W = I, else a preconditioner built and uploaded for this basis (the
- * paper's Jacobi P_W = diag(C_W), or its per-cell block form).
- * history_host / history_cap: optional per-iteration record of the
+ * (MLBLUP_FP64 runs plain PCG with a final FP64 residual check).  Lower
+ * precisions keep vectors, dots and gamma_W in FP64 and use the
+ * reduced-precision product inside the Krylov recurrence, in one of two
+ * schemes (mixed_scheme):
+ *   MLBLUP_MIXED_FLEXIBLE: flexible CG in FP64 (FP64 products) whose
+ *     preconditioner is an inner PCG solve with the reduced-precision
+ *     product to relative tolerance inner_rtol; refine_max bounds the outer
+ *     steps.  Robust when cond(C_W) times the reduced precision's rounding
+ *     unit exceeds 1.
+ *   MLBLUP_MIXED_RELIABLE: one PCG recurrence with reduced-precision
+ *     products; whenever its residual has fallen by the factor inner_rtol
+ *     since the last check, the true FP64 residual replaces it and the
+ *     search direction is kept (reliable updates); refine_max bounds the
+ *     replacements.  Keeps the Krylov convergence of a single recurrence.
+ * precond: NULL for P_W = I, else a preconditioner built and uploaded for
+ * this basis (the paper's Jacobi P_W = diag(C_W), or its per-cell block
+ * form).  history_host / history_cap: optional per-iteration record of the
  * recurrence residual. */
 typedef struct {
   double rtol;
@@ -95,6 +109,7 @@ typedef struct {
   double inner_rtol;
   mlblup_precond precond;        /* NULL: P_W = I; else an uploaded preconditioner of the same basis */
   double* history_host;          /* optional: |r_k| / |Z_W| after each Krylov iteration k (recurrence residual) */
+  int32_t mixed_scheme;          /* MLBLUP_MIXED_FLEXIBLE or MLBLUP_MIXED_RELIABLE (ignored for MLBLUP_FP64) */
 } mlblup_pcg_opts;
 
 typedef struct {

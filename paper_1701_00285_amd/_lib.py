@@ -11,6 +11,7 @@ OK, EINVAL, ERANK, ENOCONV, EBREAKDOWN, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32, MFMA_FP32, MFMA_BF16X3 = 0, 1, 2, 3
 VALUE, DLOGRHO = 1, 2
 PREC_JACOBI, PREC_BLOCK = 1, 2
+MIXED_FLEXIBLE, MIXED_RELIABLE = 0, 1
 
 _NAMES = {EINVAL: "EINVAL", ERANK: "ERANK", ENOCONV: "ENOCONV", EBREAKDOWN: "EBREAKDOWN", EHIP: "EHIP",
           ESTATE: "ESTATE"}
@@ -23,7 +24,7 @@ class Matern(C.Structure):
 class PcgOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
                 ("refine_max", C.c_int32), ("history_cap", C.c_int32), ("inner_rtol", C.c_double),
-                ("precond", C.c_void_p), ("history_host", C.c_void_p)]
+                ("precond", C.c_void_p), ("history_host", C.c_void_p), ("mixed_scheme", C.c_int32)]
 
 
 class PcgInfo(C.Structure):

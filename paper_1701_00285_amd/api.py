@@ -18,6 +18,7 @@ from ._lib import check
 FP64, FP32, MFMA_FP32, MFMA_BF16X3 = L.FP64, L.FP32, L.MFMA_FP32, L.MFMA_BF16X3
 VALUE, DLOGRHO = L.VALUE, L.DLOGRHO
 PREC_JACOBI, PREC_BLOCK = L.PREC_JACOBI, L.PREC_BLOCK
+MIXED_FLEXIBLE, MIXED_RELIABLE = L.MIXED_FLEXIBLE, L.MIXED_RELIABLE
 
 
 def _torch():
@@ -51,12 +52,13 @@ class PcgOptions:
     inner_rtol: float = 1e-2
     precond: object = None          # Precond (uploaded) or None for P_W = I
     history: object = None          # numpy float64 array receiving |r_k|/|Z_W| per iteration, or None
+    mixed_scheme: int = 0           # MIXED_FLEXIBLE or MIXED_RELIABLE (reduced precisions)
 
     def to_c(self):
         hist = None if self.history is None else self.history.ctypes.data
         cap = 0 if self.history is None else int(self.history.size)
         return L.PcgOpts(self.rtol, self.max_iter, self.precision, self.refine_max, cap, self.inner_rtol,
-                         None if self.precond is None else self.precond.h, hist)
+                         None if self.precond is None else self.precond.h, hist, self.mixed_scheme)
 
 
 class Precond:

@@ -292,6 +292,86 @@ struct Ctx {
     return MLBLUP_OK;
   }
 
+  // Reduced precision, reliable updates (G. L. G. Sleijpen and H. A. van der
+  // Vorst, "Reliable updated residuals in hybrid Bi-CG methods", Computing
+  // 56, 1996): one PCG recurrence whose products use the reduced-precision
+  // pair kernel, with x, r, p and every dot in FP64.  When the recurred
+  // residual has fallen by the factor delta since the last true residual,
+  // or below the target, zw - C_W x is formed with the FP64 product and
+  // replaces it; the search direction is kept and beta is taken from the
+  // replaced residual, so the recurrence is never restarted.  On entry r2
+  // holds the true residual of x, of norm rnorm.
+  int reliable_pcg(const double* zw, double* x, double rnorm, double bnorm, const Precond* pc, int iters_left,
+                   const mlblup_pcg_opts& o, mlblup_pcg_info& info) {
+    const int64_t nw = B.n - B.p;
+    const int prec = o.precision;
+    const double delta = o.inner_rtol > 0 ? o.inner_rtol : 1e-2;
+    const double tol = o.rtol * bnorm;
+    double* r = at(w.r2);
+    double* p = at(w.p);
+    double* q = at(w.q);
+    double* z = at(w.z);
+    double* sc = at(w.sc);
+    double* part = at(w.part);
+    int st;
+    const double* zz = r;
+    if (pc) {
+      if ((st = precond_apply(*pc, r, z, s))) return st;
+      zz = z;
+    }
+    if ((st = vec_copy(zz, p, nw, s))) return st;
+    if ((st = pcg_start(r, zz, nw, part, sc, s))) return st;
+    if ((st = read_scalars(sc))) return st;
+    double rz_prev = sc_host[S_RZ];
+    double rcheck = rnorm;  // norm of the last true residual
+    info.relres_fp64 = rnorm / bnorm;
+    for (;;) {
+      if (iters_left <= 0) return fail(MLBLUP_ENOCONV, "pcg_solve: tolerance not reached (relres " +
+                                                           std::to_string(info.relres_fp64) + ")");
+      if ((st = matvec_cw(p, q, prec))) return st;
+      info.lowp_matvecs++;
+      if ((st = pcg_alpha(p, q, nw, part, sc, s))) return st;
+      if ((st = pcg_update_xr(x, r, p, q, nw, part, sc, s))) return st;
+      if (pc) {
+        if ((st = precond_apply(*pc, r, z, s))) return st;
+        if ((st = pcg_rz_partial(r, z, nw, part, s))) return st;
+      }
+      if ((st = pcg_finish_beta(part, pc != nullptr, sc, s))) return st;
+      if ((st = read_scalars(sc))) return st;
+      --iters_left;
+      const double rr = std::sqrt(sc_host[S_RR]);
+      if (o.history_host && info.inner_iters < o.history_cap) o.history_host[info.inner_iters] = rr / bnorm;
+      info.inner_iters++;
+      if (log_every() > 0 && info.inner_iters % log_every() == 0) {
+        std::fprintf(stderr, "mlblup: iteration %d (precision %d, reliable) relres %.3e\n", info.inner_iters, prec,
+                     rr / bnorm);
+        std::fflush(stderr);
+      }
+      if (sc_host[S_FLAG] != 0.0) return fail(MLBLUP_EBREAKDOWN, "pcg_solve: breakdown (p.q <= 0 or non-finite scalar)");
+      if (rr <= tol || rr <= delta * rcheck) {
+        // replace the recurred residual by the true one
+        if ((st = true_residual(zw, x, r, &rnorm, info))) return st;
+        info.outer_iters++;
+        info.relres_fp64 = rnorm / bnorm;
+        if (!std::isfinite(rnorm)) return fail(MLBLUP_EBREAKDOWN, "pcg_solve: non-finite residual");
+        if (rnorm <= tol) return MLBLUP_OK;
+        if (info.outer_iters >= o.refine_max)
+          return fail(MLBLUP_ENOCONV, "pcg_solve: tolerance not reached after " + std::to_string(o.refine_max) +
+                                          " residual replacements (relres " + std::to_string(info.relres_fp64) + ")");
+        rcheck = rnorm;
+        if ((st = pcg_rr_partial(r, nw, part, s))) return st;
+        if (pc) {
+          if ((st = precond_apply(*pc, r, z, s))) return st;
+          if ((st = pcg_rz_partial(r, z, nw, part, s))) return st;
+        }
+        if ((st = pcg_finish_beta_from(part, pc != nullptr, rz_prev, sc, s))) return st;
+        if ((st = read_scalars(sc))) return st;
+      }
+      rz_prev = sc_host[S_RZ];
+      if ((st = pcg_update_p(p, zz, nw, sc, s))) return st;
+    }
+  }
+
   // true residual r_out = zw - C_W x (FP64 product); returns |r_out|
   int true_residual(const double* zw, const double* x, double* r_out, double* rnorm, mlblup_pcg_info& info) {
     const int64_t nw = B.n - B.p;
@@ -360,6 +440,11 @@ struct Ctx {
         if ((st = true_residual(zw, x, r2, &rnorm, info))) return st;
       }
     }
+    if (o.mixed_scheme == MLBLUP_MIXED_RELIABLE) {
+      info.relres_fp64 = rnorm / bnorm;
+      if (rnorm <= o.rtol * bnorm) return MLBLUP_OK;
+      return reliable_pcg(zw, x, rnorm, bnorm, pc, iters_left, o, info);
+    }
     // flexible CG outer loop (FP64), reduced-precision inner solves
     const double inner = o.inner_rtol > 0 ? o.inner_rtol : 1e-2;
     const int max_outer = std::max(o.refine_max, 1);
@@ -422,6 +507,7 @@ mlblup_pcg_opts default_opts() {
   o.precond = nullptr;
   o.history_cap = 0;
   o.history_host = nullptr;
+  o.mixed_scheme = MLBLUP_MIXED_FLEXIBLE;
   return o;
 }
 
@@ -680,6 +766,8 @@ static int check_opts(const mlblup_pcg_opts* opts, mlblup_pcg_opts* o) {
   if (o->history_cap < 0 || (o->history_cap > 0 && !o->history_host)) return fail(MLBLUP_EINVAL, "pcg options: bad history");
   if (!(o->rtol > 0) || o->max_iter < 0 || o->precision < MLBLUP_FP64 || o->precision > MLBLUP_MFMA_BF16X3)
     return fail(MLBLUP_EINVAL, "pcg options: need rtol > 0, max_iter >= 0, known precision");
+  if (o->mixed_scheme != MLBLUP_MIXED_FLEXIBLE && o->mixed_scheme != MLBLUP_MIXED_RELIABLE)
+    return fail(MLBLUP_EINVAL, "pcg options: unknown mixed_scheme");
   if (o->refine_max <= 0) o->refine_max = 200;
   return MLBLUP_OK;
 }

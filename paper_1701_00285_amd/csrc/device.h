@@ -95,6 +95,10 @@ int pcg_update_xr(double* x, double* r, const double* p, const double* q, int64_
 int pcg_rz_partial(const double* r, const double* z, int64_t n, double* part, hipStream_t s);
 // sc[S_RR] = |r|^2, beta = rz_new / rz (rz = |r|^2 without preconditioner)
 int pcg_finish_beta(double* part, bool has_z, double* sc, hipStream_t s);
+// part[0..) = partial sums of r.r (the layout pcg_update_xr leaves)
+int pcg_rr_partial(const double* r, int64_t n, double* part, hipStream_t s);
+// as pcg_finish_beta, with beta = r.z / rz_prev for a given previous r.z
+int pcg_finish_beta_from(double* part, bool has_z, double rz_prev, double* sc, hipStream_t s);
 int pcg_update_p(double* p, const double* z, int64_t n, const double* sc, hipStream_t s);
 // flexible-CG direction: p = z - (z.q_prev / p_prev.q_prev) p  (sc[S_DOT] = z.q_prev, sc[S_PQ])
 int fcg_update_p(double* p, const double* z, int64_t n, const double* sc, hipStream_t s);

@@ -198,7 +198,8 @@ __global__ __launch_bounds__(kT) void update_xr(double* __restrict__ x, double* 
   if (threadIdx.x == 0) part[blockIdx.x] = rr;
 }
 
-__global__ __launch_bounds__(kT) void finish_beta(const double* __restrict__ part, int has_diag,
+// rz_prev < 0: the previous r.z is sc[S_RZ]; else the one given
+__global__ __launch_bounds__(kT) void finish_beta(const double* __restrict__ part, int has_diag, double rz_prev,
                                                   double* __restrict__ sc) {
   const double rr = sum_partials(part);
   double rz = rr;
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(kT) void finish_beta(const double* __restrict__ par
   }
   if (threadIdx.x == 0) {
     sc[S_RR] = rr;
-    const double beta = rz / sc[S_RZ];
+    const double beta = rz / (rz_prev < 0.0 ? sc[S_RZ] : rz_prev);
     sc[S_BETA] = beta;
     sc[S_RZ] = rz;
     if (!isfinite(rr) || !isfinite(rz)) sc[S_FLAG] = 1.0;
@@ -388,7 +389,17 @@ int pcg_rz_partial(const double* r, const double* z, int64_t n, double* part, hi
 }
 
 int pcg_finish_beta(double* part, bool has_z, double* sc, hipStream_t s) {
-  hipLaunchKernelGGL(finish_beta, dim3(1), dim3(kT), 0, s, part, has_z ? 1 : 0, sc);
+  hipLaunchKernelGGL(finish_beta, dim3(1), dim3(kT), 0, s, part, has_z ? 1 : 0, -1.0, sc);
+  return hip_check(hipGetLastError(), "beta launch");
+}
+
+int pcg_rr_partial(const double* r, int64_t n, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(dot_partial, dim3(kRedBlocks), dim3(kT), 0, s, r, r, n, part);
+  return hip_check(hipGetLastError(), "rr launch");
+}
+
+int pcg_finish_beta_from(double* part, bool has_z, double rz_prev, double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(finish_beta, dim3(1), dim3(kT), 0, s, part, has_z ? 1 : 0, rz_prev, sc);
   return hip_check(hipGetLastError(), "beta launch");
 }
 

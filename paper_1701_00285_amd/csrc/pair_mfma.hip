@@ -216,16 +216,16 @@ __global__ __launch_bounds__(kT) void mfma_kernel(const double* __restrict__ row
   }
 }
 
-// Symmetric square product on the matrix cores: blocks of 256 points
-// (4 waves x 4 row tiles of 16), the tournament schedule of the direct
-// symmetric kernel (diagonal tiles split over column ranges, each block a
-// row block and a column block at most once per round).  Row sums stay in
-// the lanes (16 column lanes per row, reduced at the end); a column's sum
-// over the wave's 64 rows is the lane sum over the 4 row groups (two
-// cross-lane steps) and is then added over the 4 waves through LDS.  On
-// diagonal tiles the 16x16 sub-tiles whose rows and columns are the same
-// points (self pairs and their nearest neighbours) take exact FP64
-// differences from LDS; every other pair uses the Gram.
+// Symmetric square product on the matrix cores: blocks of 4 waves x kSymRT
+// row tiles of 16 points, the tournament schedule of the direct symmetric
+// kernel (diagonal tiles split over column ranges, each block a row block
+// and a column block at most once per round).  Row sums stay in the lanes
+// (FP32 within a chunk, FP64 across chunks; 16 column lanes per row,
+// reduced at the end); each lane's column partial over its rows goes to
+// LDS, and the 16 partials of a column (4 row groups x 4 waves) are added
+// after the chunk.  On diagonal tiles the 16x16 sub-tiles whose rows and
+// columns are the same points (self pairs and their nearest neighbours)
+// take exact FP64 differences from LDS; every other pair uses the Gram.
 constexpr int kSymRT = 4;
 constexpr int kSymBlk = 4 * 16 * kSymRT;
 constexpr int kMaxDExact = 33;
@@ -250,10 +250,10 @@ __global__ __launch_bounds__(kT) void mfma_sym_kernel(const double* __restrict__
   __shared__ float cf[kChunk * KP];
   __shared__ unsigned short chi[kChunk * KP];
   __shared__ unsigned short clo[kChunk * KP];
-  __shared__ float cn[kChunk];
+  __shared__ float cnp[2][kChunk];  // column squared norms, two halves of the coordinates
   __shared__ double cx[kChunk];
   __shared__ double cexact[kChunk * kMaxDExact];
-  __shared__ float csum[4][kChunk];
+  __shared__ float csum[4][4][kChunk];  // column partials per (wave, row group of 4 lanes x 4 rows)
   __shared__ double ctr[32];
   const int S = blockIdx.x;
   const int rr = round0 + (diag ? 0 : (int)blockIdx.y);
@@ -262,7 +262,8 @@ __global__ __launch_bounds__(kT) void mfma_sym_kernel(const double* __restrict__
     Sp = (S + rr) % T;
     if ((T % 2 == 0) && (2 * rr == T) && S >= T / 2) return;  // whole block exits
   }
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // wave index in a scalar register: branches on it stay wave-uniform
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int lr = lane & 15, lg = lane >> 4;
   const int64_t rb = (int64_t)S * kSymBlk, cb = (int64_t)Sp * kSymBlk;
   {
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(kT) void mfma_sym_kernel(const double* __restrict__
   double racc[kSymRT][4];
 #pragma unroll
   for (int rt = 0; rt < kSymRT; ++rt) {
-    const int64_t i0 = rb + wave * 64 + rt * 16 + lr;  // the row whose A fragment this lane holds
+    const int64_t i0 = rb + wave * (16 * kSymRT) + rt * 16 + lr;  // the row whose A fragment this lane holds
     const int64_t ia = i0 < n ? i0 : n - 1;
     float part = 0.0f;  // this lane's share of |a|^2 for row lr
     if constexpr (!BF) {
@@ -315,72 +316,73 @@ __global__ __launch_bounds__(kT) void mfma_sym_kernel(const double* __restrict__
   }
   const int cfirst = diag ? (int)blockIdx.y * (kSymBlk / (int)gridDim.y) : 0;
   const int clast = diag ? cfirst + kSymBlk / (int)gridDim.y : kSymBlk;
+  // column staging: thread t stages column t mod 128 of a chunk, coordinates
+  // [h KH, (h+1) KH) with h = t / 128; the next chunk's loads are issued
+  // before the current chunk's tiles so that they overlap with them
+  constexpr int KH = KP / 2;
+  const int sj = tid & (kChunk - 1), sh = tid >> 7;
+  double pre[KH];
+  double prex = 0.0;
+  auto fetch = [&](int cc) {
+    const int64_t gj = cb + cc + sj;
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int kk = sh * KH + k;
+      pre[k] = (gj < n && kk < d) ? pts[gj * d + kk] : 0.0;
+    }
+    prex = (gj < n && sh == 0) ? x[gj] : 0.0;
+  };
+  fetch(cfirst);
   for (int c0 = cfirst; c0 < clast; c0 += kChunk) {
     __syncthreads();
+    {
+      const bool okj = cb + c0 + sj < n;
+      float part = 0.0f;
 #pragma unroll
-    for (int e = tid; e < kChunk * KP; e += kT) {
-      const int j = e / KP, k = e - j * KP;
-      const int64_t gj = cb + c0 + j;
-      const bool ok = gj < n && k < d;
-      const double xs = ok ? pts[gj * d + k] * zs : 0.0;
-      const float v = ok ? (float)(xs - ctr[k]) : 0.0f;
-      if constexpr (BF) {
-        const unsigned short h = bf16_rne(v);
-        chi[e] = h;
-        clo[e] = bf16_rne(v - bf16_to_f(h));
-      } else {
-        cf[e] = v;
-      }
-      if (diag && k < kMaxDExact) cexact[j * kMaxDExact + k] = xs;
-    }
-    for (int j = tid; j < kChunk; j += kT) {
-      const int64_t gj = cb + c0 + j;
-      cx[j] = gj < n ? x[gj] : 0.0;
-    }
-    __syncthreads();
-    for (int j = tid; j < kChunk; j += kT) {
-      float s = 0.0f;
-#pragma unroll
-      for (int k = 0; k < KP; ++k) {
+      for (int k = 0; k < KH; ++k) {
+        const int kk = sh * KH + k;
+        const bool ok = okj && kk < d;
+        const double xs = pre[k] * zs;
+        const float v = ok ? (float)(xs - ctr[kk]) : 0.0f;
         float vv;
-        if constexpr (BF) vv = bf16_to_f(chi[j * KP + k]) + bf16_to_f(clo[j * KP + k]);
-        else vv = cf[j * KP + k];
-        s = fmaf(vv, vv, s);
+        if constexpr (BF) {
+          const unsigned short h = bf16_rne(v);
+          const unsigned short l = bf16_rne(v - bf16_to_f(h));
+          chi[sj * KP + kk] = h;
+          clo[sj * KP + kk] = l;
+          vv = bf16_to_f(h) + bf16_to_f(l);
+        } else {
+          cf[sj * KP + kk] = v;
+          vv = v;
+        }
+        part = fmaf(vv, vv, part);
+        if (diag && kk < kMaxDExact) cexact[sj * kMaxDExact + kk] = xs;
       }
-      cn[j] = s;
+      cnp[sh][sj] = part;
+      if (sh == 0) cx[sj] = prex;
     }
     __syncthreads();
-#pragma unroll 1
-    for (int tile = 0; tile < kChunk / 16; ++tile) {
+    if (c0 + kChunk < clast) fetch(c0 + kChunk);
+    float rs[kSymRT][4];  // this chunk's row sums (FP32, 8 terms per lane)
+#pragma unroll
+    for (int rt = 0; rt < kSymRT; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rs[rt][r] = 0.0f;
+    // tiles of this chunk inside the column range (a diagonal split can be narrower than a chunk)
+    const int ntile = (clast - c0 < kChunk ? clast - c0 : kChunk) / 16;
+    // Gram of the 16 columns of a tile with the wave's kSymRT row tiles
+    auto gram = [&](int tile, f4 (&gg)[kSymRT]) {
       const int jc = tile * 16 + lr;
-      const double xc = cx[jc];
-      const float ncol = cn[jc];
-      float cpart = 0.0f;
+#pragma unroll
+      for (int rt = 0; rt < kSymRT; ++rt) gg[rt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
       if constexpr (!BF) {
         float bf[KP / 4];
 #pragma unroll
         for (int t = 0; t < KP / 4; ++t) bf[t] = cf[jc * KP + 4 * t + lg];
-        f4 gg[kSymRT];
-#pragma unroll
-        for (int rt = 0; rt < kSymRT; ++rt) gg[rt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int t = 0; t < KP / 4; ++t)
 #pragma unroll
           for (int rt = 0; rt < kSymRT; ++rt) gg[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[rt][t], bf[t], gg[rt], 0, 0, 0);
-#pragma unroll
-        for (int rt = 0; rt < kSymRT; ++rt) {
-          const f4 g = gg[rt];
-          const bool same = diag && (wave * 64 + rt * 16 == c0 + tile * 16);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            float sv = fmaxf(fmaf(-2.0f, g[r], rn[rt][r] + ncol), 0.0f);
-            if (same) sv = exact_sq<KP>(cexact, tile * 16 + 4 * lg + r, jc, d);
-            const float z = __builtin_amdgcn_sqrtf(sv);
-            const float ph = matern_polyf<NU2>(z) * __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
-            racc[rt][r] = fma((double)ph, xc, racc[rt][r]);
-            cpart = fmaf(ph, xr[rt][r], cpart);
-          }
-        }
       } else {
         s4 bh[KP / 16], bl[KP / 16];
 #pragma unroll
@@ -390,9 +392,6 @@ __global__ __launch_bounds__(kT) void mfma_sym_kernel(const double* __restrict__
             bh[t][e] = (short)chi[jc * KP + 16 * t + 4 * lg + e];
             bl[t][e] = (short)clo[jc * KP + 16 * t + 4 * lg + e];
           }
-        f4 gg[kSymRT];
-#pragma unroll
-        for (int rt = 0; rt < kSymRT; ++rt) gg[rt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int t = 0; t < KP / 16; ++t)
 #pragma unroll
@@ -401,34 +400,58 @@ __global__ __launch_bounds__(kT) void mfma_sym_kernel(const double* __restrict__
             gg[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[rt][t], bl[t], gg[rt], 0, 0, 0);
             gg[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo[rt][t], bh[t], gg[rt], 0, 0, 0);
           }
+      }
+    };
+    // kernel values of a tile from its Gram: row sums in the lanes, the
+    // lane's column partial to LDS
+    auto values = [&](int tile, const f4 (&gg)[kSymRT]) {
+      const int jc = tile * 16 + lr;
+      const float xc = (float)cx[jc];
+      const float ncol = cnp[0][jc] + cnp[1][jc];
+      float cpart = 0.0f;
 #pragma unroll
-        for (int rt = 0; rt < kSymRT; ++rt) {
-          const f4 g = gg[rt];
-          const bool same = diag && (wave * 64 + rt * 16 == c0 + tile * 16);
+      for (int rt = 0; rt < kSymRT; ++rt) {
+        const f4 g = gg[rt];
+        const bool same = diag && (wave * (16 * kSymRT) + rt * 16 == c0 + tile * 16);
+        float sv[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            float sv = fmaxf(fmaf(-2.0f, g[r], rn[rt][r] + ncol), 0.0f);
-            if (same) sv = exact_sq<KP>(cexact, tile * 16 + 4 * lg + r, jc, d);
-            const float z = __builtin_amdgcn_sqrtf(sv);
-            const float ph = matern_polyf<NU2>(z) * __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
-            racc[rt][r] = fma((double)ph, xc, racc[rt][r]);
-            cpart = fmaf(ph, xr[rt][r], cpart);
-          }
+        for (int r = 0; r < 4; ++r) sv[r] = fmaxf(fmaf(-2.0f, g[r], rn[rt][r] + ncol), 0.0f);
+        if (same) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sv[r] = exact_sq<KP>(cexact, tile * 16 + 4 * lg + r, jc, d);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float ph, unused;
+          pair_value_w<NU2, 1>(__builtin_amdgcn_sqrtf(sv[r]), ph, unused);
+          rs[rt][r] = fmaf(ph, xc, rs[rt][r]);
+          cpart = fmaf(ph, xr[rt][r], cpart);
         }
       }
-      // column jc: sum over the four row groups of this wave
-      if (!diag) {
-        cpart += __shfl_xor(cpart, 16, 64);
-        cpart += __shfl_xor(cpart, 32, 64);
-        if (lg == 0) csum[wave][jc] = cpart;
-      }
+      // column jc: this lane's rows; the row groups and waves are added after the chunk
+      if (!diag) csum[wave][lg][jc] = cpart;
+    };
+#pragma unroll 1
+    for (int tile = 0; tile < ntile; ++tile) {
+      f4 gg[kSymRT];
+      gram(tile, gg);
+      values(tile, gg);
     }
+#pragma unroll
+    for (int rt = 0; rt < kSymRT; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) racc[rt][r] += (double)rs[rt][r];
     __syncthreads();
     if (!diag && tid < kChunk) {
       const int64_t gj = cb + c0 + tid;
-      if (gj < n)
-        pcol[(int64_t)blockIdx.y * n + gj] =
-            (((double)csum[0][tid] + (double)csum[1][tid]) + (double)csum[2][tid]) + (double)csum[3][tid];
+      if (gj < n) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+#pragma unroll
+          for (int g = 0; g < 4; ++g) t += (double)csum[w][g][tid];
+        pcol[(int64_t)blockIdx.y * n + gj] = t;
+      }
     }
   }
   // row sums: reduce over the 16 column lanes of each row group
@@ -441,7 +464,7 @@ __global__ __launch_bounds__(kT) void mfma_sym_kernel(const double* __restrict__
       v += __shfl_xor(v, 2, 64);
       v += __shfl_xor(v, 4, 64);
       v += __shfl_xor(v, 8, 64);
-      const int64_t i = rb + wave * 64 + rt * 16 + 4 * lg + r;
+      const int64_t i = rb + wave * (16 * kSymRT) + rt * 16 + 4 * lg + r;
       if (lr == 0 && i < n) prow[(int64_t)blockIdx.y * n + i] = v;
     }
 }
@@ -450,8 +473,9 @@ template <int KP, int NU2, bool BF>
 void launch_sym(const PairArgs& a, double zs, void* work, int T, int r0, int nr, int diag, double* prow, double* pcol,
                 hipStream_t s) {
   (void)work;
+  // coordinates scaled by sqrt(2 nu)/rho log2(e): the kernel's distances are w = log2(e) z
   hipLaunchKernelGGL((mfma_sym_kernel<KP, NU2, BF>), dim3(T, nr), dim3(kT), 0, s, a.cols, a.x, a.n, a.d, T, r0, diag,
-                     zs, prow, pcol);
+                     zs * 1.4426950408889634, prow, pcol);
 }
 
 using SymFn = void (*)(const PairArgs&, double, void*, int, int, int, int, double*, double*, hipStream_t);

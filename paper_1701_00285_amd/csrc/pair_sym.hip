@@ -35,8 +35,9 @@ constexpr int kChunk = 128; // columns staged per LDS fill
 // rows per lane: 4 for small d (amortises the LDS read and the rotation over
 // more pairs), 2 otherwise; a block holds 256 * RL points
 constexpr int rows_per_lane(int D) { return D <= 6 ? 4 : 2; }
+constexpr int rows_per_lane_lp(int D) { return D <= 6 ? 4 : 2; }
 
-template <int D, int NU2, int OUT, bool F>
+template <int D, int NU2, int OUT>
 __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts, const double* __restrict__ x,
                                                  int64_t n, int T, int round0, int diag, double zs,
                                                  double* __restrict__ prow, double* __restrict__ pcol,
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
             s = fma(u, u, s);
           }
           double f = 0.0, g = 0.0;
-          pair_value<NU2, OUT, F>(s, tab, f, g);
+          pair_value<NU2, OUT, false>(s, tab, f, g);
           if constexpr (OUT & 1) {
             racc[q] = fma(f, aj, racc[q]);
             cpart = fma(f, ar[q], cpart);
@@ -147,6 +148,134 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
   }
 }
 
+// FP32 variant.  Coordinates are taken relative to the first point of the
+// row block (kd-tree blocks are compact, so row coordinates stay small),
+// scaled by sqrt(2 nu)/rho log2(e) in FP64 and rounded to FP32; the pair
+// value comes from pair_value_w.  Row sums accumulate in FP32 over 16
+// columns and then in FP64; the travelling column sums are FP64.
+template <int D, int NU2, int OUT>
+__global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ pts, const double* __restrict__ x,
+                                                    int64_t n, int T, int round0, int diag, double ws,
+                                                    double* __restrict__ prow, double* __restrict__ pcol,
+                                                    double* __restrict__ pdrow, double* __restrict__ pdcol) {
+  constexpr int SP = (D + 1 + 3) / 4 * 4;  // floats per staged column (coordinates, x), 16-byte rows
+  constexpr int RL = rows_per_lane_lp(D);
+  constexpr int kBlk = 256 * RL;
+  constexpr int kSeg = 16;  // columns per FP32 row-sum segment
+  __shared__ __align__(16) float cp[kChunk * SP];
+  __shared__ double cred[4][kChunk];
+  __shared__ double cdred[4][kChunk];
+  const int S = blockIdx.x;
+  const int r = round0 + (diag ? 0 : (int)blockIdx.y);
+  int Sp = S;
+  if (!diag) {
+    Sp = (S + r) % T;
+    if ((T % 2 == 0) && (2 * r == T) && S >= T / 2) return;  // whole block exits
+  }
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int delta = (wave_rotate1_i(lane) - lane) & 63;
+
+  const int64_t o = (int64_t)S * kBlk;  // first point of the row block (o < n)
+  double org[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) org[k] = pts[o * D + k];
+  float xr[RL][D], ar[RL];
+#pragma unroll
+  for (int q = 0; q < RL; ++q) {
+    const int64_t i = o + wave * (64 * RL) + q * 64 + lane;
+    const int64_t ii = i < n ? i : n - 1;
+#pragma unroll
+    for (int k = 0; k < D; ++k) xr[q][k] = (float)((pts[ii * D + k] - org[k]) * ws);
+    ar[q] = i < n ? (float)x[i] : 0.0f;
+  }
+  double racc[RL], rdacc[RL];
+#pragma unroll
+  for (int q = 0; q < RL; ++q) racc[q] = rdacc[q] = 0.0;
+  const int64_t cbase = (int64_t)Sp * kBlk;
+  const int cfirst = diag ? (int)blockIdx.y * (kBlk / (int)gridDim.y) : 0;
+  const int clast = diag ? cfirst + kBlk / (int)gridDim.y : kBlk;
+  for (int c0 = cfirst; c0 < clast; c0 += kChunk) {
+    __syncthreads();
+    for (int e = tid; e < kChunk * D; e += kT) {
+      const int j = e / D, k = e - j * D;
+      const int64_t gj = cbase + c0 + j;
+      cp[j * SP + k] = gj < n ? (float)((pts[gj * D + k] - org[k]) * ws) : 0.0f;
+    }
+    for (int j = tid; j < kChunk; j += kT) {
+      const int64_t gj = cbase + c0 + j;
+      cp[j * SP + D] = gj < n ? (float)x[gj] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int sub = 0; sub < kChunk; sub += 64) {
+      double cacc = 0.0, cdacc = 0.0;
+      int c = lane;
+#pragma unroll 1
+      for (int seg = 0; seg < 64; seg += kSeg) {
+        float rs[RL], rds[RL];
+#pragma unroll
+        for (int q = 0; q < RL; ++q) rs[q] = rds[q] = 0.0f;
+#pragma unroll 4
+        for (int k = 0; k < kSeg; ++k) {
+          const float* cj = &cp[(sub + c) * SP];
+          float cv[D];
+#pragma unroll
+          for (int t = 0; t < D; ++t) cv[t] = cj[t];
+          const float aj = cj[D];
+          float cpart = 0.0f, cdpart = 0.0f;
+#pragma unroll
+          for (int q = 0; q < RL; ++q) {
+            float s = 0.0f;
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+              const float u = xr[q][t] - cv[t];
+              s = fmaf(u, u, s);
+            }
+            float f = 0.0f, g = 0.0f;
+            pair_value_w<NU2, OUT>(__builtin_amdgcn_sqrtf(s), f, g);
+            if constexpr (OUT & 1) {
+              rs[q] = fmaf(f, aj, rs[q]);
+              cpart = fmaf(f, ar[q], cpart);
+            }
+            if constexpr (OUT & 2) {
+              rds[q] = fmaf(g, aj, rds[q]);
+              cdpart = fmaf(g, ar[q], cdpart);
+            }
+          }
+          if constexpr (OUT & 1) cacc = wave_rotate1(cacc + (double)cpart);
+          if constexpr (OUT & 2) cdacc = wave_rotate1(cdacc + (double)cdpart);
+          c = (c + delta) & 63;
+        }
+#pragma unroll
+        for (int q = 0; q < RL; ++q) {
+          if constexpr (OUT & 1) racc[q] += (double)rs[q];
+          if constexpr (OUT & 2) rdacc[q] += (double)rds[q];
+        }
+      }
+      if constexpr (OUT & 1) cred[wave][sub + lane] = cacc;
+      if constexpr (OUT & 2) cdred[wave][sub + lane] = cdacc;
+    }
+    __syncthreads();
+    if (!diag && tid < kChunk) {
+      const int64_t gj = cbase + c0 + tid;
+      if (gj < n) {
+        const int64_t slot = (int64_t)blockIdx.y * n + gj;
+        if constexpr (OUT & 1) pcol[slot] = ((cred[0][tid] + cred[1][tid]) + cred[2][tid]) + cred[3][tid];
+        if constexpr (OUT & 2) pdcol[slot] = ((cdred[0][tid] + cdred[1][tid]) + cdred[2][tid]) + cdred[3][tid];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RL; ++q) {
+    const int64_t i = o + wave * (64 * RL) + q * 64 + lane;
+    if (i < n) {
+      const int64_t slot = (int64_t)blockIdx.y * n + i;
+      if constexpr (OUT & 1) prow[slot] = racc[q];
+      if constexpr (OUT & 2) pdrow[slot] = rdacc[q];
+    }
+  }
+}
+
 // acc += sum over this launch's rounds of row and column partials (fixed
 // order); on the last launch y = scale * acc.  acc starts as the diagonal
 // partial.
@@ -173,8 +302,12 @@ __global__ __launch_bounds__(kT) void sym_reduce(const double* __restrict__ prow
 template <int D, int NU2, int OUT, bool F>
 void launch(const double* pts, const double* x, int64_t n, int T, int round0, int nr, int diag, double zs,
             double* prow, double* pcol, double* pdrow, double* pdcol, hipStream_t s) {
-  hipLaunchKernelGGL((sym_kernel<D, NU2, OUT, F>), dim3(T, nr), dim3(kT), 0, s, pts, x, n, T, round0, diag, zs, prow,
-                     pcol, pdrow, pdcol);
+  if constexpr (F)
+    hipLaunchKernelGGL((sym_kernel_lp<D, NU2, OUT>), dim3(T, nr), dim3(kT), 0, s, pts, x, n, T, round0, diag,
+                       zs * 1.4426950408889634, prow, pcol, pdrow, pdcol);
+  else
+    hipLaunchKernelGGL((sym_kernel<D, NU2, OUT>), dim3(T, nr), dim3(kT), 0, s, pts, x, n, T, round0, diag, zs, prow,
+                       pcol, pdrow, pdcol);
 }
 
 using LaunchFn = void (*)(const double*, const double*, int64_t, int, int, int, int, double, double*, double*, double*,
@@ -275,7 +408,7 @@ int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s) {
   const bool f32 = a.precision != MLBLUP_FP64;
   LaunchFn fn = f32 ? pick_nu<true>(a.nu2, a.outputs, a.d) : pick_nu<false>(a.nu2, a.outputs, a.d);
   if (!fn) return fail(MLBLUP_EINVAL, "symmetric pair kernel: dimension not compiled");
-  const int blk = 256 * rows_per_lane(a.d);
+  const int blk = 256 * (f32 ? rows_per_lane_lp(a.d) : rows_per_lane(a.d));
   return sym_schedule(a, blk, work, s,
                       [&](int T, int r0, int nr, int diag, double* prow, double* pcol, double* pdrow, double* pdcol) {
                         fn(a.cols, a.x, a.n, T, r0, nr, diag, zs, prow, pcol, pdrow, pdcol, s);

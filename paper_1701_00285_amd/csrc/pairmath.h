@@ -8,53 +8,72 @@ namespace mlb {
 
 // e^{-z} for 0 <= z, FP64, by the table-driven method of P. T. P. Tang
 // ("Table-driven implementation of the exponential function in IEEE
-// floating-point arithmetic", ACM TOMS 15(2), 1989): z = (32 m + j) ln2/32 + r,
-// |r| <= ln2/64, e^{-z} = 2^{-m} 2^{-j/32} e^{-r}, with e^{-r} from its
-// degree-6 Taylor polynomial (truncation < 4e-18 relative) and the 32
-// values 2^{-j/32} from a table in LDS.  ln2/32 is split in two parts
-// (Cody-Waite) so that n * L_HI is exact for n < 2^16; z is clamped to 708
-// (e^{-708} is still a normal number), so m stays in range.  About 2 ulp.
-constexpr double kExpInvL = 46.16624130844683;        // 32 / ln 2
-constexpr double kExpLHi = 0.021660849392446835;      // ln 2 / 32, low 16 bits cleared
-constexpr double kExpLLo = 5.145609244655338e-14;     // ln 2 / 32 - L_HI
-constexpr int kExpTab = 32;
+// floating-point arithmetic", ACM TOMS 15(2), 1989): with k the integer
+// nearest to -z 64/ln2, -z = k ln2/64 + r, |r| <= ln2/128, and
+// e^{-z} = 2^{k >> 6} 2^{(k & 63)/64} e^r.  e^r comes from its degree-5
+// Taylor polynomial (truncation < 4e-17 relative), the 64 values
+// 2^{j/64} from a table in LDS, and the power of two is added to the exponent
+// field.  ln2/64 is
+// split in two parts (Cody-Waite; the high part has 36 significant bits, so
+// k L_HI is exact for |k| < 2^17); z is clamped to 700, which bounds |k|
+// and keeps every scaled result a normal number.  About 2 ulp.
+constexpr double kExpInvL = 92.33248261689366;         // 64 / ln 2
+constexpr double kExpLHi = 0.010830424696223417;       // ln 2 / 64 to 36 bits
+constexpr double kExpLLo = 2.572804622327669e-14;      // ln 2 / 64 - L_HI
+constexpr int kExpTab = 64;
 
 __device__ __forceinline__ void exp_table_fill(double* tab) {
-  // 2^{-j/32}, j = 0..31, correctly rounded
+  // 2^{j/64}, j = 0..63, correctly rounded
   constexpr double t[kExpTab] = {
-      1.0, 0.9785720620877001, 0.9576032806985737, 0.93708381705515, 0.9170040432046712,
-      0.8973545375015536, 0.8781260801866497, 0.859309649061239, 0.8408964152537145,
-      0.8228777390769825, 0.8052451659746271, 0.7879904225539432, 0.7711054127039704,
-      0.7545822137967114, 0.7384130729697497, 0.7225904034885233, 0.7071067811865476,
-      0.691954940981916, 0.6771277734684463, 0.6626183215798707, 0.6484197773255048,
-      0.6345254785958666, 0.620928906036742, 0.6076236799902345, 0.5946035575013605,
-      0.5818624293887887, 0.5693943173783458, 0.5571933712979462, 0.5452538663326288,
-      0.5335702003384118, 0.5221368912137069, 0.5109485743270583};
+      1.0, 1.0108892860517005, 1.0218971486541166, 1.0330248790212284,
+      1.0442737824274138, 1.0556451783605572, 1.0671404006768237, 1.0787607977571199,
+      1.0905077326652577, 1.102382583307841, 1.1143867425958924, 1.1265216186082418,
+      1.1387886347566916, 1.1511892299529827, 1.1637248587775775, 1.1763969916502812,
+      1.189207115002721, 1.202156731452703, 1.215247359980469, 1.22848053610687,
+      1.241857812073484, 1.255380757024691, 1.2690509571917332, 1.2828700160787783,
+      1.2968395546510096, 1.3109612115247644, 1.3252366431597413, 1.339667524053303,
+      1.3542555469368927, 1.3690024229745905, 1.383909881963832, 1.3989796725383112,
+      1.4142135623730951, 1.42961333839197, 1.4451808069770467, 1.460917794180647,
+      1.4768261459394993, 1.4929077282912648, 1.5091644275934228, 1.5255981507445384,
+      1.5422108254079407, 1.559004400237837, 1.5759808451078865, 1.593142151342267,
+      1.6104903319492543, 1.6280274218573478, 1.645755478153965, 1.6636765803267364,
+      1.681792830507429, 1.7001063537185235, 1.718619298122478, 1.7373338352737062,
+      1.7562521603732995, 1.7753764925265212, 1.7947090750031072, 1.8142521755003989,
+      1.8340080864093424, 1.8539791250833855, 1.8741676341103, 1.8945759815869656,
+      1.9152065613971474, 1.9360617934922943, 1.9571441241754002, 1.978456026387951};
   for (int j = threadIdx.x; j < kExpTab; j += blockDim.x) tab[j] = t[j];
 }
 
-__device__ __forceinline__ double exp_neg_f64(double z, const double* __restrict__ tab) {
-  z = fmin(z, 708.0);
-  // n = nearest integer to z 32/ln2: adding 1.5 * 2^52 leaves n in the low
-  // mantissa bits (exact rounding by the FMA); subtracting it back gives n
+// e^{-z} = v 2^m: the mantissa part v in [~0.99, 2) and the exponent m, so
+// that callers can multiply v by the Matern polynomial before scaling.
+struct ExpParts {
+  double v;
+  int m;
+};
+__device__ __forceinline__ ExpParts exp_neg_parts(double z, const double* __restrict__ tab) {
+  z = fmin(z, 700.0);
+  // k = nearest integer to -z 64/ln2: adding 1.5 * 2^52 leaves k in the low
+  // mantissa bits (exact rounding by the FMA); subtracting it back gives k
   constexpr double kShift = 6755399441055744.0;  // 1.5 * 2^52
-  const double t = fma(z, kExpInvL, kShift);
-  const int ni = __double2loint(t);
-  const double n = t - kShift;
-  double r = fma(-n, kExpLHi, z);
-  r = fma(-n, kExpLLo, r);
-  const double u = -r;
-  double p = fma(u, 1.0 / 720.0, 1.0 / 120.0);
-  p = fma(u, p, 1.0 / 24.0);
-  p = fma(u, p, 1.0 / 6.0);
-  p = fma(u, p, 0.5);
-  p = fma(u, p, 1.0);
-  p = fma(u, p, 1.0);
-  // 2^{-m} 2^{-j/32}: subtract m = n >> 5 from the exponent field of the
-  // table value (m <= 1021 keeps the result a normal number)
-  const double tj = tab[ni & (kExpTab - 1)];
-  const double sc = __hiloint2double(__double2hiint(tj) - ((ni >> 5) << 20), __double2loint(tj));
-  return p * sc;
+  const double t = fma(-z, kExpInvL, kShift);
+  const int k = __double2loint(t);
+  const double kn = t - kShift;
+  double r = fma(-kn, kExpLHi, -z);
+  r = fma(-kn, kExpLLo, r);
+  double p = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+  p = fma(r, p, 1.0 / 6.0);
+  p = fma(r, p, 0.5);
+  p = fma(r, p, 1.0);
+  p = fma(r, p, 1.0);
+  return {p * tab[k & (kExpTab - 1)], k >> 6};
+}
+// v 2^m for a normal v and a normal result: m added to the exponent field
+__device__ __forceinline__ double scale_pow2(double v, int m) {
+  return __hiloint2double(__double2hiint(v) + (m << 20), __double2loint(v));
+}
+__device__ __forceinline__ double exp_neg_f64(double z, const double* __restrict__ tab) {
+  const ExpParts e = exp_neg_parts(z, tab);
+  return scale_pow2(e.v, e.m);
 }
 
 // sqrt(s) for s > 0 (callers keep s away from 0 by a 1e-300 offset): the
@@ -99,6 +118,8 @@ __device__ __forceinline__ float matern_dpolyf(float z) {
 
 // Kernel value (and rho-derivative) of one pair from its squared scaled
 // distance s (FP64).  FP32T: FP32 sqrt and exp2 after rounding s to FP32.
+// FP64: the polynomial multiplies the mantissa part of e^{-z} (for nu=3/2,
+// (1+z) v is one FMA) before the power of two is applied.
 template <int NU2, int OUT, bool FP32T>
 __device__ __forceinline__ void pair_value(double s, const double* __restrict__ tab, double& f, double& g) {
   if constexpr (FP32T) {
@@ -108,20 +129,50 @@ __device__ __forceinline__ void pair_value(double s, const double* __restrict__ 
     if constexpr (OUT & 2) g = (double)(matern_dpolyf<NU2>(zf) * ef);
   } else {
     const double z = sqrt_pos_f64(s);
-    const double e = exp_neg_f64(z, tab);
-    if constexpr (OUT & 1) f = matern_poly<NU2>(z) * e;
-    if constexpr (OUT & 2) g = matern_dpoly<NU2>(z) * e;
+    const ExpParts e = exp_neg_parts(z, tab);
+    if constexpr (OUT & 1) {
+      double fv;
+      if constexpr (NU2 == 1) fv = e.v;
+      else if constexpr (NU2 == 3) fv = fma(z, e.v, e.v);
+      else fv = fma(z * fma(z, 1.0 / 3.0, 1.0), e.v, e.v);
+      f = scale_pow2(fv, e.m);
+    }
+    if constexpr (OUT & 2) g = scale_pow2(matern_dpoly<NU2>(z) * e.v, e.m);
+  }
+}
+
+// FP32 kernel value (and rho-derivative) from w = log2(e) z, the distance
+// scaled so that e^{-z} = 2^{-w}: FP32 exp2 and the Matern polynomial with
+// its coefficients rescaled to w.
+template <int NU2, int OUT>
+__device__ __forceinline__ void pair_value_w(float w, float& f, float& g) {
+  constexpr float l1 = 0.6931471805599453f;               // ln 2
+  constexpr float l2 = 0.4804530139182014f;               // ln^2 2
+  const float e = __builtin_amdgcn_exp2f(-w);
+  if constexpr (OUT & 1) {
+    if constexpr (NU2 == 1) f = e;
+    else if constexpr (NU2 == 3) f = fmaf(w, l1, 1.0f) * e;
+    else f = fmaf(w, fmaf(w, l2 / 3.0f, l1), 1.0f) * e;
+  }
+  if constexpr (OUT & 2) {
+    // rho dphi/drho: z e^{-z}, z^2 e^{-z}, z^2 (1 + z) e^{-z} / 3
+    if constexpr (NU2 == 1) g = (w * l1) * e;
+    else if constexpr (NU2 == 3) g = (w * (w * l2)) * e;
+    else g = (w * (w * (l2 / 3.0f))) * (fmaf(w, l1, 1.0f) * e);
   }
 }
 
 // 64-lane rotation by one lane (DPP wave rotate); 64-bit value in two halves.
 __device__ __forceinline__ double wave_rotate1(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x134, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x134, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x134, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x134, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ float wave_rotate1_f(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xF, 0xF, false));
+}
 __device__ __forceinline__ int wave_rotate1_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x134, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, 0x134, 0xF, 0xF, false);
 }
 
 }  // namespace mlb

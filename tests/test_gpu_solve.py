@@ -64,21 +64,49 @@ def test_trend_reproduction():
     np.testing.assert_allclose(host(out["zhat"]), design_matrix(wl.targets, wl.degree_w) @ beta0, rtol=1e-9, atol=1e-9)
 
 
+@pytest.mark.parametrize("scheme", [0, 1])
 @pytest.mark.parametrize("prec", [1, 2, 3])
-def test_mixed_precision_refinement_reaches_fp64_residual(prec):
+def test_mixed_precision_refinement_reaches_fp64_residual(prec, scheme):
+    """Both mixed schemes (flexible CG around inner solves; one recurrence
+    with reliable updates) reach the FP64 residual and the oracle."""
     torch = require_gpu()
     from paper_1701_00285_amd import FP64, PcgOptions
     wl = workload(4, n=3000, n_targets=300)
     s = _solver(wl, max_targets=300)
-    say(f"mixed precision={prec}")
+    say(f"mixed precision={prec} scheme={scheme}")
     a = s.predict(dev(wl.z), dev(wl.targets), PcgOptions(rtol=1e-8, precision=FP64, max_iter=5000))
     b = s.predict(dev(wl.z), dev(wl.targets), PcgOptions(rtol=1e-8, precision=prec, inner_rtol=1e-4,
-                                                         max_iter=5000))
+                                                         max_iter=5000, mixed_scheme=scheme))
     assert b["info"]["relres_fp64"] <= 1e-8
     assert b["info"]["lowp_matvecs"] > 0
     ref = OB.classic_blup(wl.points, wl.z, wl.targets, wl.degree_w, wl.nu, wl.rho)
     assert relerr(host(b["zhat"]), ref.zhat) < 1e-6
     assert relerr(host(b["zhat"]), host(a["zhat"])) < 1e-6
+    if scheme == 1:
+        # one recurrence: a residual replacement per factor inner_rtol, not a restart
+        assert b["info"]["fp64_matvecs"] <= b["info"]["outer_iters"] + 3
+
+
+def test_reliable_update_keeps_the_recurrence():
+    """Reliable updates replace the residual without restarting: the
+    low-precision recurrence needs about as many iterations as FP64 PCG,
+    and a cap on replacements ends the solve with ENOCONV."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import FP32, FP64, MIXED_RELIABLE, PcgOptions
+    from paper_1701_00285_amd import _lib as L
+    wl = workload(3, n=4000, n_targets=10)
+    s = _solver(wl)
+    zw, _ = s.apply_W(s.to_tree(dev(wl.z)))
+    g64, i64, _ = s.solve(zw, PcgOptions(rtol=1e-9, max_iter=5000))
+    gr, ir, _ = s.solve(zw, PcgOptions(rtol=1e-9, max_iter=5000, precision=FP32, inner_rtol=1e-2,
+                                       mixed_scheme=MIXED_RELIABLE))
+    say(f"fp64 {i64} reliable {ir}")
+    assert ir["relres_fp64"] <= 1e-9 and ir["outer_iters"] >= 3
+    assert ir["inner_iters"] <= 1.25 * i64["inner_iters"] + 10
+    assert relerr(host(gr), host(g64)) < 1e-6
+    _, ic, st = s.solve(zw, PcgOptions(rtol=1e-9, max_iter=5000, precision=FP32, inner_rtol=1e-2, refine_max=2,
+                                       mixed_scheme=MIXED_RELIABLE), allow_noconv=True)
+    assert st == L.ENOCONV and ic["outer_iters"] == 2
 
 
 def test_error_paths():
@@ -98,6 +126,8 @@ def test_error_paths():
     assert st == 0 and float(torch.abs(gw).max()) == 0.0
     with pytest.raises(MlblupError, match="EINVAL"):
         s.solve(zw, PcgOptions(rtol=-1.0))
+    with pytest.raises(MlblupError, match="EINVAL"):
+        s.solve(zw, PcgOptions(precision=1, mixed_scheme=7))
     from paper_1701_00285_amd import cov_matvec
     with pytest.raises(MlblupError, match="EINVAL"):
         cov_matvec(dev(wl.points), dev(wl.points), dev(wl.z), 1.0, 0.1)
@@ -124,19 +154,19 @@ def test_basis_independence_of_iterations():
     assert abs(it[0] - it[1]) <= 0.03 * max(it) + 2
 
 
-@pytest.mark.parametrize("k,prec", [(5, 2), (5, 3), (3, 2)])
-def test_mixed_matrix_core_solve(k, prec):
+@pytest.mark.parametrize("k,prec,scheme", [(5, 2, 0), (5, 3, 0), (3, 2, 0), (5, 2, 1), (3, 3, 1)])
+def test_mixed_matrix_core_solve(k, prec, scheme):
     """Mixed solves whose inner products use the matrix-core distance Gram
     (d = 20 and d = 10 workloads, subsampled) reach the FP64 residual and
     the oracle's predictions."""
     torch = require_gpu()
     from paper_1701_00285_amd import PREC_BLOCK, PcgOptions
     wl = workload(k, n=3000, n_targets=200)
-    say(f"mixed matrix-core cfg{k} precision={prec}")
+    say(f"mixed matrix-core cfg{k} precision={prec} scheme={scheme}")
     s = _solver(wl, max_targets=200)
     pc = s.precond(PREC_BLOCK)
     out = s.predict(dev(wl.z), dev(wl.targets), PcgOptions(rtol=1e-10, precision=prec, inner_rtol=1e-2,
-                                                           precond=pc, max_iter=5000))
+                                                           precond=pc, max_iter=5000, mixed_scheme=scheme))
     assert out["info"]["relres_fp64"] <= 1e-10
     assert out["info"]["lowp_matvecs"] > 0
     ref = OB.classic_blup(wl.points, wl.z, wl.targets, wl.degree_w, wl.nu, wl.rho)
