@@ -5,11 +5,13 @@ One step = one pass of the whole hot path over one synthetic workload:
 kd-tree and multilevel basis (host C++), basis upload, the preconditioner
 (cell blocks of C_W by default), W Z, the FP64 PCG solve of
 C_W gamma_W = Z_W to relres 1e-8, the mixed-precision solve of the same
-system to the same FP64 relres (flexible-CG iterative refinement, FP32
-kernel values), the predictor of each path (warm-started from its own
-solution: true FP64 residual, gamma, beta-hat, predictions at the targets;
-the mixed path's target products in its low precision) and Q, dQ/dlog rho
-of each.  Inputs (points, Z, targets) are resident in HBM when the timed
+system to the same FP64 relres (FP32 kernel values inside the Krylov
+recurrence; flexible CG around inner solves by default), the predictor of
+each path (warm-started from its own solution: true FP64 residual, gamma,
+beta-hat, predictions at the targets with FP64 products) and Q, dQ/dlog rho
+of each.  The errors of the mixed path against the FP64 path are reported,
+and for the record also those of low-precision target and gradient
+products.  Inputs (points, Z, targets) are resident in HBM when the timed
 region starts.
 
 The default workload is 65,536 uniform points in [0,1]^3, Matern nu=3/2,
@@ -95,8 +97,19 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--mixed", type=int, default=-1, help="precision of the mixed solve (default: FP32 for d<8, "
-                                                          "MFMA FP32 for d>=8)")
+    ap.add_argument("--n", type=int, default=0, help="number of points drawn from the workload generator (0: its full size)")
+    ap.add_argument("--targets", type=int, default=0, help="number of targets (0: the workload's)")
+    ap.add_argument("--mixed", type=int, default=-1, help="precision of the mixed solve (default: FP32 for d<16, "
+                                                          "MFMA FP32 for d>=16)")
+    ap.add_argument("--scheme", choices=("flexible", "reliable"), default="flexible",
+                    help="mixed-precision scheme: flexible CG around inner solves, or one recurrence with reliable "
+                         "updates")
+    ap.add_argument("--inner-rtol", type=float, default=0.1,
+                    help="inner tolerance (flexible) or residual-replacement factor (reliable)")
+    ap.add_argument("--fp64-solve", choices=("full", "refine", "skip"), default="full",
+                    help="full: independent FP64 solve (timed against the mixed one); refine: FP64 PCG from the mixed "
+                         "solution to relres 1e-10 as the error reference (for workloads where a full FP64 solve "
+                         "does not fit the time budget); skip: none")
     ap.add_argument("--precond", choices=("block", "jacobi", "none"), default="block",
                     help="preconditioner of both solves (cell blocks of C_W, its diagonal, or none)")
     ap.add_argument("--cpu-rows", type=int, default=3072)
@@ -124,12 +137,14 @@ def main():
         return
 
     import synth
-    from paper_1701_00285_amd import (FP32, FP64, MFMA_FP32, PREC_BLOCK, PREC_JACOBI, VALUE, PcgOptions, Solver,
-                                      profile_enable, profile_read)
+    from paper_1701_00285_amd import (FP32, FP64, MFMA_FP32, MIXED_FLEXIBLE, MIXED_RELIABLE, PREC_BLOCK, PREC_JACOBI,
+                                      VALUE, PcgOptions, Solver, profile_enable, profile_read)
 
     torch.cuda.set_device(0)
-    wl = synth.make_config(a.config)
-    mixed = a.mixed if a.mixed >= 0 else (FP32 if wl.d < 8 else MFMA_FP32)
+    wl = synth.make_config(a.config, n=a.n or None, n_targets=a.targets or None)
+    wname = wl.name if not a.n else f"{wl.name}, generator at n={wl.n}"
+    mixed = a.mixed if a.mixed >= 0 else (FP32 if wl.d < 16 else MFMA_FP32)
+    scheme = {"flexible": MIXED_FLEXIBLE, "reliable": MIXED_RELIABLE}[a.scheme]
     dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda")
     P, Z, T = dev(wl.points), dev(wl.z), dev(wl.targets)
     torch.cuda.synchronize()
@@ -144,35 +159,61 @@ def main():
         zw, _ = s.apply_W(zt)
         torch.cuda.synchronize()
         t.append(time.perf_counter())
-        gw64, info64, st64 = s.solve(zw, PcgOptions(rtol=1e-8, max_iter=a.max_iter, precision=FP64, precond=pc),
-                                     allow_noconv=True)
+        o64 = PcgOptions(rtol=1e-8, max_iter=a.max_iter, precision=FP64, precond=pc)
+        om = PcgOptions(rtol=1e-8, max_iter=a.max_iter, precision=mixed, inner_rtol=a.inner_rtol, precond=pc,
+                        mixed_scheme=scheme)
+        r = dict(solve_fp64=None, reference_fp64=None)
+        if a.fp64_solve == "full":
+            gw64, info64, st64 = s.solve(zw, o64, allow_noconv=True)
+            torch.cuda.synchronize()
+            t.append(time.perf_counter())
+            r["solve_fp64"] = t[-1] - t[-2]
+        gwm, infom, stm = s.solve(zw, om, allow_noconv=True)
         torch.cuda.synchronize()
         t.append(time.perf_counter())
-        gwm, infom, stm = s.solve(zw, PcgOptions(rtol=1e-8, max_iter=a.max_iter, precision=mixed, inner_rtol=0.1,
-                                                 precond=pc), allow_noconv=True)
+        r["solve_mixed"] = t[-1] - t[-2]
+        if a.fp64_solve == "refine":
+            o_ref = PcgOptions(rtol=1e-10, max_iter=a.max_iter, precision=FP64, precond=pc)
+            gw64, info64, st64 = s.solve(zw, o_ref, x0=gwm, allow_noconv=True)
+            torch.cuda.synchronize()
+            t.append(time.perf_counter())
+            r["reference_fp64"] = t[-1] - t[-2]
+        have64 = a.fp64_solve != "skip"
+        # predictor of each path: FP64 residual check of its gamma_W, gamma,
+        # beta-hat and the target products in FP64
+        out = s.predict(Z, T, o64, gamma_w0=gw64, allow_noconv=True) if have64 else None
         torch.cuda.synchronize()
         t.append(time.perf_counter())
-        out = s.predict(Z, T, PcgOptions(rtol=1e-8, max_iter=a.max_iter, precision=FP64, precond=pc), gamma_w0=gw64,
-                        allow_noconv=True)
+        r["predict"] = t[-1] - t[-2]
+        outm = s.predict(Z, T, om, gamma_w0=gwm, allow_noconv=True)
         torch.cuda.synchronize()
         t.append(time.perf_counter())
-        # the mixed path's predictor: FP64 residual check of its gamma_W, the
-        # target products with low-precision kernel values
-        outm = s.predict(Z, T, PcgOptions(rtol=1e-8, max_iter=a.max_iter, precision=mixed, inner_rtol=0.1, precond=pc),
-                         predict_precision=mixed, gamma_w0=gwm, allow_noconv=True)
+        r["predict_mixed"] = t[-1] - t[-2]
+        q, dq = s.quad_grad(zt, out["gamma_tree"]) if have64 else (None, None)
+        qm, dqm = s.quad_grad(zt, outm["gamma_tree"])
         torch.cuda.synchronize()
         t.append(time.perf_counter())
-        q, dq = s.quad_grad(zt, out["gamma_tree"])
-        qm, dqm = s.quad_grad(zt, outm["gamma_tree"], precision=mixed)
-        torch.cuda.synchronize()
-        t.append(time.perf_counter())
-        rd = float(torch.linalg.norm(gwm - gw64) / torch.linalg.norm(gw64))
-        pe = float(torch.max(torch.abs(outm["zhat"] - out["zhat"])) / torch.max(torch.abs(out["zhat"])))
-        be = float(np.max(np.abs(outm["beta"] - out["beta"])) / np.max(np.abs(out["beta"])))
-        rec.append(dict(setup=t[1] - t[0], solve_fp64=t[2] - t[1], solve_mixed=t[3] - t[2], predict=t[4] - t[3],
-                        predict_mixed=t[5] - t[4], grad=t[6] - t[5], total=t[6] - t[0], info64=info64, infom=infom,
-                        infop=out["info"], q=q, dq=dq, qm=qm, dqm=dqm, reldiff=rd, pred_err=pe, beta_err=be, p=s.p,
-                        converged=(st64 == 0 and stm == 0 and out["status"] == 0 and outm["status"] == 0)))
+        r["grad"] = t[-1] - t[-2]
+        r["total"] = t[-1] - t[0]
+        # for the record: the same results with low-precision kernel values in
+        # the target products and in the gradient product (outside the timed
+        # phases above)
+        outl = s.predict(Z, T, om, predict_precision=mixed, gamma_w0=gwm, allow_noconv=True)
+        _, dql = s.quad_grad(zt, outm["gamma_tree"], precision=mixed)
+        mx = lambda u, v: float(torch.max(torch.abs(u - v)) / torch.max(torch.abs(v)))
+        err = {}
+        if have64:
+            err = {"gamma_w_reldiff_mixed_vs_fp64": float(torch.linalg.norm(gwm - gw64) / torch.linalg.norm(gw64)),
+                   "zhat_maxrelerr_mixed_vs_fp64": mx(outm["zhat"], out["zhat"]),
+                   "beta_maxrelerr_mixed_vs_fp64": float(np.max(np.abs(outm["beta"] - out["beta"])) /
+                                                         np.max(np.abs(out["beta"]))),
+                   "dQ_relerr_mixed_vs_fp64": abs(dqm - dq) / abs(dq),
+                   "zhat_maxrelerr_lowp_target_products": mx(outl["zhat"], out["zhat"]),
+                   "dQ_relerr_lowp_grad_product": abs(dql - dq) / abs(dq)}
+        rec.append(dict(r, setup=t[1] - t[0], info64=info64 if have64 else None, infom=infom,
+                        infop=out["info"] if have64 else None, q=q, dq=dq, qm=qm, dqm=dqm, err=err, p=s.p,
+                        converged=(stm == 0 and outm["status"] == 0 and
+                                   (not have64 or (st64 == 0 and out["status"] == 0)))))
 
     warm = []
     for _ in range(a.warmup):
@@ -195,12 +236,16 @@ def main():
     n = wl.n
     ms64, n64, pairs64 = prof.get((FP64, VALUE), (0.0, 0, 0.0))
     msm, nm, pairsm = prof.get((mixed, VALUE), (0.0, 0, 0.0))
-    # the square launches of the FP64 product (the dominant kernel): logical
-    # pairs n^2 each; the target launches (m x n) are counted apart
-    sq64 = int(round((pairs64 - a.steps * T.shape[0] * n) / (n * n))) if n64 else 0
-    fpp = flops_per_unordered_pair(wl.d, wl.nu)
     last = recs[-1]
+    have64 = a.fp64_solve != "skip"
+    # the square launches of the FP64 product (the dominant kernel): logical
+    # pairs n^2 each; the FP64 target launches (m x n: one per predictor that
+    # runs, i.e. FP64 and mixed paths) are counted apart
+    rect64 = a.steps * (2 if have64 else 1) * T.shape[0] * n
+    sq64 = int(round((pairs64 - rect64) / (n * n))) if n64 else 0
+    fpp = flops_per_unordered_pair(wl.d, wl.nu)
     i64, im, ip = last["info64"], last["infom"], last["infop"]
+    rnd = lambda v, k=4: None if v is None else round(v, k)
     out = {
         "metric": "Matern C.x Gpairs/s (whole step); BLUP solve time to relres 1e-8, FP64 vs mixed",
         "value": round(value, 3),
@@ -214,21 +259,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded)",
-        "config": {"workload": wl.name, "n": n, "d": wl.d, "nu": wl.nu, "rho": wl.rho, "trend_p": last["p"],
+        "config": {"workload": wname, "n": n, "d": wl.d, "nu": wl.nu, "rho": wl.rho, "trend_p": last["p"],
                    "leaf": wl.leaf_max, "targets": int(T.shape[0]), "rtol": 1e-8,
                    "preconditioner": {"block": "cell blocks of C_W", "jacobi": "diag(C_W)", "none": "none"}[a.precond],
-                   "mixed_precision": mixed},
-        "phases_s": {k: round(last[k], 4) for k in ("setup", "solve_fp64", "solve_mixed", "predict", "predict_mixed",
-                                                     "grad", "total")},
-        "solve": {"converged": last["converged"],
-                  "fp64_s": round(last["solve_fp64"], 3), "mixed_s": round(last["solve_mixed"], 3),
-                  "speedup": round(last["solve_fp64"] / last["solve_mixed"], 3),
-                  "fp64_iters": i64["inner_iters"], "fp64_relres": i64["relres_fp64"],
-                  "mixed_outer": im["outer_iters"], "mixed_inner": im["inner_iters"],
-                  "mixed_fp64_matvecs": im["fp64_matvecs"], "mixed_lowp_matvecs": im["lowp_matvecs"],
-                  "mixed_relres_fp64": im["relres_fp64"], "gamma_w_reldiff_mixed_vs_fp64": last["reldiff"],
-                  "zhat_maxrelerr_mixed_vs_fp64": last["pred_err"], "beta_maxrelerr_mixed_vs_fp64": last["beta_err"],
-                  "predict_warm_iters": ip["inner_iters"], "predict_relres": ip["relres_fp64"]},
+                   "mixed_precision": mixed, "mixed_scheme": a.scheme, "inner_rtol": a.inner_rtol,
+                   "fp64_solve": a.fp64_solve},
+        "phases_s": {k: rnd(last[k]) for k in ("setup", "solve_fp64", "solve_mixed", "reference_fp64", "predict",
+                                                "predict_mixed", "grad", "total")},
+        "solve": dict({"converged": last["converged"],
+                       "fp64_s": rnd(last["solve_fp64"], 3), "mixed_s": round(last["solve_mixed"], 3),
+                       "speedup": (round(last["solve_fp64"] / last["solve_mixed"], 3)
+                                   if last["solve_fp64"] is not None else None),
+                       "fp64_iters": i64["inner_iters"] if i64 else None,
+                       "fp64_relres": i64["relres_fp64"] if i64 else None,
+                       "mixed_outer": im["outer_iters"], "mixed_inner": im["inner_iters"],
+                       "mixed_fp64_matvecs": im["fp64_matvecs"], "mixed_lowp_matvecs": im["lowp_matvecs"],
+                       "mixed_relres_fp64": im["relres_fp64"],
+                       "predict_warm_iters": ip["inner_iters"] if ip else None,
+                       "predict_relres": ip["relres_fp64"] if ip else None}, **last["err"]),
         "pair_kernel": {
             "fp64_logical_gpairs_s": round(pairs64 / (ms64 * 1e-3) / 1e9, 2) if ms64 else None,
             "fp64_launches": n64, "fp64_avg_launch_ms": round(ms64 / n64, 4) if n64 else None,
@@ -252,8 +300,7 @@ def main():
                            "traffic": traffic,
                            "kernel": "sym_kernel FP64 value (square C x)", "launches": sq64,
                            "avg_launch_ms": round(t_sq / sq64 * 1e3, 4), "flops_per_unordered_pair": fpp}
-    out["grad"] = {"Q": last["q"], "dQ_dlogrho": last["dq"], "Q_mixed": last["qm"], "dQ_dlogrho_mixed": last["dqm"],
-                   "dQ_relerr_mixed_vs_fp64": abs(last["dqm"] - last["dq"]) / abs(last["dq"])}
+    out["grad"] = {"Q": last["q"], "dQ_dlogrho": last["dq"], "Q_mixed": last["qm"], "dQ_dlogrho_mixed": last["dqm"]}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_rows)
     print(json.dumps(out), flush=True)
