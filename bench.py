@@ -49,17 +49,18 @@ def flops_per_unordered_pair(d: int, nu: float) -> int:
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sym_kernel_fp64_cfg2_n65536_d3.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_per_pair_sym_kernel.txt")
+VALU_LANE_RATE = 256 * 4 * 16 * 2.4e9   # VALU lane-instructions per second (CUs x SIMDs x lanes x clock)
 
 
-def measured_traffic():
-    """HBM bytes per FP64 symmetric product from the calibrated rocprofv3
-    FETCH_SIZE / WRITE_SIZE runs recorded under profiles/, or None when the
-    kernel sources changed since they were taken (hash mismatch)."""
+def _hashed_file(path):
+    """key = value lines of a recorded measurement whose source hash still
+    matches the sources it names, else None."""
     import hashlib
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
@@ -69,9 +70,25 @@ def measured_traffic():
         if not os.path.exists(p):
             return None
         h.update(open(p, "rb").read())
-    if h.hexdigest() != kv.get("source_sha256"):
+    return kv if h.hexdigest() == kv.get("source_sha256") else None
+
+
+def valu_per_pair(kind: str, d: int, nu: float):
+    """VALU instructions per evaluated pair of the symmetric kernel (from the
+    gfx950 assembly, recorded by paper_1701_00285_amd.isa_stats), or None."""
+    kv = _hashed_file(VALU_FILE)
+    if kv is None:
         return None
-    return int(float(kv["hbm_bytes_per_product"]))
+    v = kv.get(f"{kind}_d{d}_nu2{int(round(2 * nu))}")
+    return float(v) if v is not None else None
+
+
+def measured_traffic():
+    """HBM bytes per FP64 symmetric product from the calibrated rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs recorded under profiles/, or None when the
+    kernel sources changed since they were taken (hash mismatch)."""
+    kv = _hashed_file(TRAFFIC_FILE)
+    return int(float(kv["hbm_bytes_per_product"])) if kv else None
 
 
 def cpu_baseline(wl, rows: int):
@@ -300,6 +317,15 @@ def main():
                            "traffic": traffic,
                            "kernel": "sym_kernel FP64 value (square C x)", "launches": sq64,
                            "avg_launch_ms": round(t_sq / sq64 * 1e3, 4), "flops_per_unordered_pair": fpp}
+        # the same launches against the VALU instruction-issue ceiling of the
+        # kernel's own instruction mix (one lane evaluates one pair)
+        vpp = valu_per_pair("fp64", wl.d, wl.nu)
+        if vpp:
+            ceil = 2 * VALU_LANE_RATE / vpp / 1e9   # logical (ordered) pairs per second
+            got = sq64 * n * n / t_sq / 1e9
+            out["roofline"]["issue_ceiling"] = {"valu_instr_per_pair": vpp, "ceiling_logical_gpairs_s": round(ceil, 1),
+                                                "achieved_logical_gpairs_s": round(got, 1),
+                                                "frac": round(got / ceil, 4)}
     out["grad"] = {"Q": last["q"], "dQ_dlogrho": last["dq"], "Q_mixed": last["qm"], "dQ_dlogrho_mixed": last["dqm"]}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_rows)

@@ -1,0 +1,19 @@
+"""The VALU-per-pair counter reads the gfx950 assembly of the symmetric
+kernels built from this repository (host-side compile, no GPU)."""
+import shutil
+
+import pytest
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None and not __import__("os").path.exists("/opt/rocm/bin/hipcc"),
+                    reason="hipcc not available")
+def test_valu_counts_are_sane():
+    from paper_1701_00285_amd import isa_stats
+    c = isa_stats.counts()
+    for (kind, d, nu2), v in c.items():
+        assert 5 < v < 200, (kind, d, nu2, v)
+    for d, nu2 in isa_stats.SHAPES:
+        # the FP32 kernel issues fewer instructions per pair than the FP64 one
+        assert c[("fp32", d, nu2)] < c[("fp64", d, nu2)]
+        # at least the 2d distance operations (d subtractions + d multiply-adds)
+        assert c[("fp64", d, nu2)] >= 2 * d
