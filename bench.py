@@ -108,6 +108,85 @@ def cpu_baseline(wl, rows: int):
                       f"{dt:.1f} s, one thread)"}
 
 
+def sweep(configs, reps: int = 10, warm: int = 3):
+    """Per workload: the square product in every precision that applies
+    (median of `reps` HIP-event timings after `warm` untimed launches), the
+    FP64 target product, and W / W^T against their algorithmic bytes.  Errors:
+    each precision against the FP64 GPU product, and the FP64 product against
+    the oracle on 16 sampled rows.  One JSON line per workload."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import brute
+    from paper_1701_00285_amd import (FP32, FP64, MFMA_BF16X3, MFMA_FP32, VALUE, Solver, cov_matvec,
+                                      cov_workspace_bytes, profile_enable, profile_read)
+    torch.cuda.set_device(0)
+    names = {FP64: "fp64", FP32: "fp32", MFMA_FP32: "mfma_fp32", MFMA_BF16X3: "mfma_bf16x3"}
+    for k in configs:
+        wl = synth.make_config(k, with_z=False)
+        n, d = wl.n, wl.d
+        s = Solver(wl.points, wl.degree_w, wl.leaf_max, wl.nu, wl.rho, wl.sigma2, max_targets=wl.targets.shape[0])
+        P = s.basis.points_dev
+        x_host = synth.standard_normal(n, 7)
+        x = torch.as_tensor(x_host, dtype=torch.float64, device="cuda")
+        pts_tree = P.cpu().numpy()
+        idx = np.random.default_rng(k).choice(n, 16, replace=False)
+        ref = brute.cov_matvec(pts_tree[idx], pts_tree, x_host, wl.nu, wl.rho, wl.sigma2)
+        scale = brute.cov_matvec(pts_tree[idx], pts_tree, np.abs(x_host), wl.nu, wl.rho, wl.sigma2)
+
+        def timed(fn, prec):
+            times = []
+            out = None
+            for i in range(warm + reps):
+                profile_enable(True)
+                profile_read()
+                out = fn()
+                torch.cuda.synchronize()
+                ms, nl, _ = profile_read()[(prec, VALUE)]
+                if i >= warm:
+                    times.append(ms / nl)
+            profile_enable(False)
+            return float(np.median(times)), out
+
+        precs = [FP64, FP32] + ([MFMA_FP32, MFMA_BF16X3] if 8 <= d <= 32 else [])
+        prods, y64 = {}, None
+        for prec in precs:
+            work = torch.empty(max(cov_workspace_bytes(n, n, d, prec, VALUE), 256), dtype=torch.uint8, device="cuda")
+            ms, (y, _) = timed(lambda: cov_matvec(P, P, x, wl.nu, wl.rho, wl.sigma2, precision=prec, work=work), prec)
+            if prec == FP64:
+                y64 = y
+            e = {"ms": round(ms, 4), "logical_gpairs_s": round(n * n / (ms * 1e-3) / 1e9, 1),
+                 "maxerr_vs_fp64_product": float(torch.max(torch.abs(y - y64)) / torch.max(torch.abs(y64)))}
+            if prec == FP64:
+                e["rowerr_vs_oracle"] = float(np.max(np.abs(y.cpu().numpy()[idx] - ref) / scale))
+            prods[names[prec]] = e
+            del work
+        T = torch.as_tensor(wl.targets, dtype=torch.float64, device="cuda")
+        m = T.shape[0]
+        work = torch.empty(max(cov_workspace_bytes(m, n, d, FP64, VALUE), 256), dtype=torch.uint8, device="cuda")
+        ms, _ = timed(lambda: cov_matvec(T, P, x, wl.nu, wl.rho, wl.sigma2, precision=FP64, work=work), FP64)
+        targets = {"m": m, "ms": round(ms, 4), "logical_gpairs_s": round(m * n / (ms * 1e-3) / 1e9, 1)}
+        # W and W^T: torch events on the current stream (the library launches on it)
+        tb = s.basis.transform_bytes()
+        res = {}
+        for name, fn in (("apply_W", lambda: s.apply_W(x)), ("apply_Wt", lambda: s.apply_Wt(x[: n - s.p]))):
+            ts = []
+            for i in range(warm + reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                torch.cuda.synchronize()
+                if i >= warm:
+                    ts.append(e0.elapsed_time(e1))
+            med = float(np.median(ts))
+            res[name] = {"ms": round(med, 4), "algorithmic_bytes": tb, "gb_s": round(tb / (med * 1e-3) / 1e9, 1)}
+        print(json.dumps({"workload": wl.name, "n": n, "d": d, "nu": wl.nu, "rho": wl.rho, "reps": reps,
+                          "warmup": warm, "square_product": prods, "target_product_fp64": targets,
+                          "transform": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +212,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-iter", type=int, default=40000,
                     help="Krylov iteration cap (lower it only for short profiling runs)")
+    ap.add_argument("--sweep", default="",
+                    help="comma-separated workloads: time every precision's product, the target product and W / W^T "
+                         "(one JSON line each) instead of the step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 512 MiB three times with a plain device copy (reference for HBM counters)")
     a = ap.parse_args()
@@ -143,6 +225,10 @@ def main():
 
     import numpy as np
     import torch
+
+    if a.sweep:
+        sweep([int(v) for v in a.sweep.split(",")])
+        return
 
     if a.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")

@@ -151,6 +151,12 @@ class Basis:
         self.d = tree.d
         self.buf = None
 
+    def transform_bytes(self):
+        """Algorithmic bytes of one apply_W / apply_Wt (blocks + vectors)."""
+        b = C.c_int64()
+        check(self._lib.mlblup_basis_transform_bytes(self.h, C.byref(b)))
+        return b.value
+
     def level_counts(self):
         out = np.empty(self.levels, dtype=np.int64)
         check(self._lib.mlblup_basis_level_counts(self.h, _np_ptr(out)))

@@ -591,6 +591,15 @@ int mlblup_basis_info(mlblup_basis b, int32_t* p, int32_t* levels, int64_t* n_mi
   return MLBLUP_OK;
 }
 
+int mlblup_basis_transform_bytes(mlblup_basis b, int64_t* bytes) {
+  clear_error();
+  if (!b || !bytes) return fail(MLBLUP_EINVAL, "NULL argument");
+  int64_t s = 0;
+  for (const auto& nd : b->b.desc) s += (int64_t)nd.m * nd.m;
+  *bytes = 8 * s + 16 * b->b.n;
+  return MLBLUP_OK;
+}
+
 int mlblup_basis_level_counts(mlblup_basis b, int64_t* counts_host) {
   clear_error();
   if (!b || !counts_host) return fail(MLBLUP_EINVAL, "NULL argument");

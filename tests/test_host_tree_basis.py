@@ -84,6 +84,29 @@ def test_basis_level_counts_complete_tree():
     assert list(b.level_counts()) == level_sizes(4096, t.max_depth, b.p)
 
 
+def test_transform_bytes_count_every_block_once():
+    """Algorithmic bytes of one transform: 8 sum m^2 over the cells (a leaf's
+    m is its point count, an internal cell's the sum of its children's
+    scaling counts, a = min(m, p) for generic points) + 16 N."""
+    pts = synth.uniform_cloud(3000, 3, seed=10)
+    t = Tree(pts, 40)
+    b = Basis(t, 2)
+    nd = t.nodes()
+    begin, end, left, right = nd["begin"], nd["end"], nd["left"], nd["right"]
+
+    def walk(v):
+        if left[v] < 0:
+            m = int(end[v] - begin[v])
+            return min(m, b.p), m * m
+        al, sl = walk(left[v])
+        ar, sr = walk(right[v])
+        m = al + ar
+        return min(m, b.p), m * m + sl + sr
+
+    _, s = walk(0)
+    assert b.transform_bytes() == 8 * s + 16 * 3000
+
+
 def test_rank_error_collinear_quadratic():
     pts = np.zeros((40, 2))
     pts[:, 0] = np.linspace(0, 1, 40)
