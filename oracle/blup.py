@@ -61,6 +61,26 @@ def classic_blup(S, Z, T, w, nu, rho, sigma2=1.0) -> BlupResult:
     return BlupResult(beta=beta, gamma=gamma, zhat=zhat)
 
 
+def classic_blup_direct(S, Z, T, w, nu, rho, sigma2=1.0) -> BlupResult:
+    """The classic formulae taken literally in FP64 (eqs. GLSbeta and
+    KrigBLUP): C^-1 X and C^-1 Z by an LU solve with partial pivoting, then
+    beta = (X^T C^-1 X)^-1 X^T C^-1 Z and gamma = C^-1 (Z - X beta).  This is
+    the "traditional formulae in double precision" of the accuracy
+    experiment (Sec. 8): unlike classic_blup it does not stop when C is not
+    numerically positive definite."""
+    S = np.asarray(S, dtype=np.float64)
+    X = design_matrix(S, w)
+    C = cov_matrix(S, S, nu, rho, sigma2)
+    CiX = np.linalg.solve(C, X)
+    CiZ = np.linalg.solve(C, Z)
+    beta = np.linalg.solve(X.T @ CiX, X.T @ CiZ)
+    gamma = np.linalg.solve(C, Z - X @ beta)
+    zhat = None
+    if T is not None:
+        zhat = design_matrix(T, w) @ beta + cov_matrix(T, S, nu, rho, sigma2) @ gamma
+    return BlupResult(beta=beta, gamma=gamma, zhat=zhat)
+
+
 def multilevel_blup(S, Z, T, w, nu, rho, basis: Basis, sigma2=1.0) -> BlupResult:
     S = np.asarray(S, dtype=np.float64)
     X = design_matrix(S, w)

@@ -18,9 +18,15 @@ Derivative used by the gradient: rho d phi / d rho = -u m'(u) with u = r/rho
 and m the sigma2 = 1 shape; with P(z) the finite sum above,
     rho d phi/d rho = sigma2 * c_n * z e^{-z} (P(z) - P'(z)).
 
+nu = +inf: the Definition's limit as nu grows without bound, in this
+parametrisation, is the Gaussian kernel
+    phi(r) = sigma2 exp(-r^2 / (2 rho^2)),   rho d phi/d rho = (r/rho)^2 phi,
+the kernel of the accuracy experiment in Sec. 8 (there with theta = rho).
+
 Pins (tests/test_oracle_matern.py): scipy.special.kv through the
 Definition; nu = 1/2 reduces to exp(-r/rho); phi(0) = sigma2; derivative
-against central differences of the kv form.
+against central differences of the kv form; the Gaussian against the kv
+form at large nu.
 """
 from __future__ import annotations
 
@@ -47,7 +53,11 @@ def _prefactor(n: int) -> float:
 
 
 def matern(r, nu: float, rho: float, sigma2: float = 1.0):
-    """phi(r) for nu = n + 1/2 (Definition + half-integer remark, Sec. 3.1)."""
+    """phi(r) for nu = n + 1/2 (Definition + half-integer remark, Sec. 3.1),
+    or the Gaussian limit for nu = +inf."""
+    if math.isinf(nu) and nu > 0:
+        r = np.asarray(r, dtype=np.float64)
+        return sigma2 * np.exp(-(r / rho) ** 2 / 2.0)
     n = _halfint_n(nu)
     r = np.asarray(r, dtype=np.float64)
     z = math.sqrt(2.0 * nu) * r / rho
@@ -59,6 +69,10 @@ def matern(r, nu: float, rho: float, sigma2: float = 1.0):
 
 def matern_rho_drho(r, nu: float, rho: float, sigma2: float = 1.0):
     """rho * d phi / d rho at fixed r (used for the log-rho gradient)."""
+    if math.isinf(nu) and nu > 0:
+        r = np.asarray(r, dtype=np.float64)
+        u2 = (r / rho) ** 2
+        return sigma2 * u2 * np.exp(-u2 / 2.0)
     n = _halfint_n(nu)
     r = np.asarray(r, dtype=np.float64)
     z = math.sqrt(2.0 * nu) * r / rho

@@ -34,6 +34,18 @@ namespace {
 constexpr int64_t kAlign = 256;
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+}  // namespace
+
+int nu2_of_nu(double nu) {
+  if (std::isinf(nu) && nu > 0) return 0;
+  const double n2 = 2.0 * nu;
+  for (int c : {1, 3, 5})
+    if (std::fabs(n2 - c) < 1e-12) return c;
+  return -1;
+}
+
+namespace {
+
 // progress log of long solves: MLBLUP_LOG_EVERY=k prints the residual every k iterations to stderr
 int log_every() {
   static const int k = [] {
@@ -43,17 +55,11 @@ int log_every() {
   return k;
 }
 
-int nu2_of(const mlblup_matern* k) {
-  if (!k) return -1;
-  const double n2 = 2.0 * k->nu;
-  for (int c : {1, 3, 5})
-    if (std::fabs(n2 - c) < 1e-12) return c;
-  return -1;
-}
+int nu2_of(const mlblup_matern* k) { return k ? nu2_of_nu(k->nu) : -1; }
 
 int check_kernel(const mlblup_matern* k) {
   if (!k) return fail(MLBLUP_EINVAL, "NULL covariance parameters");
-  if (nu2_of(k) < 0) return fail(MLBLUP_EINVAL, "nu must be 0.5, 1.5 or 2.5");
+  if (nu2_of(k) < 0) return fail(MLBLUP_EINVAL, "nu must be 0.5, 1.5, 2.5 or +inf (Gaussian)");
   if (!(k->rho > 0) || !std::isfinite(k->rho)) return fail(MLBLUP_EINVAL, "rho must be finite and > 0");
   if (!(k->sigma2 > 0) || !std::isfinite(k->sigma2)) return fail(MLBLUP_EINVAL, "sigma2 must be finite and > 0");
   return MLBLUP_OK;

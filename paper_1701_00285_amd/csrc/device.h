@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include <cstdint>
 #include <functional>
 
@@ -51,6 +53,12 @@ int64_t sym_workspace_bytes(int64_t n, int outputs);
 int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s);
 // Matrix-core distance Gram (pair_mfma.hip): MFMA precisions, value only, 8 <= d <= 32.
 bool mfma_applies(const PairArgs& a);
+// 2 nu of a covariance: 1, 3, 5 (half-integer Matern) or 0 for nu = +inf, the
+// Gaussian exp(-r^2 / (2 rho^2)) (the Matern limit in the sqrt(2 nu) r / rho
+// parametrisation); -1 for anything else
+int nu2_of_nu(double nu);
+// scale applied to the coordinates: sqrt(2 nu) / rho, or 1 / rho for the Gaussian
+inline double kernel_scale(int nu2, double rho) { return (nu2 == 0 ? 1.0 : std::sqrt((double)nu2)) / rho; }
 int32_t mfma_splits(int64_t m, int64_t n);
 int mfma_launch(const PairArgs& a, double zs, double* part, hipStream_t s);
 // square products (n >= 16,384): each unordered pair once, tournament schedule

@@ -193,6 +193,7 @@ void dispatch_out(const PairArgs& a, double zs, int S, int64_t cps, double* py, 
 template <bool F>
 void dispatch_nu(const PairArgs& a, double zs, int S, int64_t cps, double* py, double* pdy, hipStream_t s) {
   switch (a.nu2) {
+    case 0: dispatch_out<0, F>(a, zs, S, cps, py, pdy, s); break;
     case 1: dispatch_out<1, F>(a, zs, S, cps, py, pdy, s); break;
     case 3: dispatch_out<3, F>(a, zs, S, cps, py, pdy, s); break;
     default: dispatch_out<5, F>(a, zs, S, cps, py, pdy, s); break;
@@ -235,7 +236,8 @@ int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s
 
   if (!(a.rho > 0) || !(a.sigma2 > 0) || !std::isfinite(a.rho) || !std::isfinite(a.sigma2))
     return fail(MLBLUP_EINVAL, "cov_matvec: rho and sigma2 must be finite and > 0");
-  if (a.nu2 != 1 && a.nu2 != 3 && a.nu2 != 5) return fail(MLBLUP_EINVAL, "cov_matvec: nu must be 1/2, 3/2 or 5/2");
+  if (a.nu2 != 0 && a.nu2 != 1 && a.nu2 != 3 && a.nu2 != 5)
+    return fail(MLBLUP_EINVAL, "cov_matvec: nu must be 1/2, 3/2, 5/2 or +inf (Gaussian)");
   if (a.precision < MLBLUP_FP64 || a.precision > MLBLUP_MFMA_BF16X3)
     return fail(MLBLUP_EINVAL, "cov_matvec: unknown precision");
   if (a.m == 0) return MLBLUP_OK;
@@ -251,7 +253,7 @@ int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s
   const int64_t need = pair_workspace_bytes(a.m, a.n, a.d, a.precision, a.outputs);
   if (!work || work_bytes < need)
     return fail(MLBLUP_EINVAL, "cov_matvec: workspace too small (need " + std::to_string(need) + " bytes)");
-  const double zs = std::sqrt((double)a.nu2) / a.rho;  // sqrt(2 nu) / rho
+  const double zs = kernel_scale(a.nu2, a.rho);  // sqrt(2 nu) / rho (Gaussian: 1 / rho)
   if (mfma_applies(a)) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (profile_on()) {

@@ -150,8 +150,8 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
 
 // FP32 variant.  Coordinates are taken relative to the first point of the
 // row block (kd-tree blocks are compact, so row coordinates stay small),
-// scaled by sqrt(2 nu)/rho log2(e) in FP64 and rounded to FP32; the pair
-// value comes from pair_value_w.  Row sums accumulate in FP32 over 16
+// scaled by the kernel's coordinate scale times lp_scale in FP64 and rounded
+// to FP32; the pair value comes from pair_value_lp.  Row sums accumulate in FP32 over 16
 // columns and then in FP64; the travelling column sums are FP64.
 template <int D, int NU2, int OUT>
 __global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ pts, const double* __restrict__ x,
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ p
               s = fmaf(u, u, s);
             }
             float f = 0.0f, g = 0.0f;
-            pair_value_w<NU2, OUT>(__builtin_amdgcn_sqrtf(s), f, g);
+            pair_value_lp<NU2, OUT>(s, f, g);
             if constexpr (OUT & 1) {
               rs[q] = fmaf(f, aj, rs[q]);
               cpart = fmaf(f, ar[q], cpart);
@@ -304,7 +304,7 @@ void launch(const double* pts, const double* x, int64_t n, int T, int round0, in
             double* prow, double* pcol, double* pdrow, double* pdcol, hipStream_t s) {
   if constexpr (F)
     hipLaunchKernelGGL((sym_kernel_lp<D, NU2, OUT>), dim3(T, nr), dim3(kT), 0, s, pts, x, n, T, round0, diag,
-                       zs * 1.4426950408889634, prow, pcol, pdrow, pdcol);
+                       zs * lp_scale<NU2>(), prow, pcol, pdrow, pdcol);
   else
     hipLaunchKernelGGL((sym_kernel<D, NU2, OUT>), dim3(T, nr), dim3(kT), 0, s, pts, x, n, T, round0, diag, zs, prow,
                        pcol, pdrow, pdcol);
@@ -337,6 +337,7 @@ LaunchFn pick_out(int out, int d) {
 }
 template <bool F>
 LaunchFn pick_nu(int nu2, int out, int d) {
+  if (nu2 == 0) return pick_out<0, F>(out, d);
   if (nu2 == 1) return pick_out<1, F>(out, d);
   if (nu2 == 3) return pick_out<3, F>(out, d);
   return pick_out<5, F>(out, d);

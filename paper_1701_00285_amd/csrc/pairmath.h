@@ -122,7 +122,18 @@ __device__ __forceinline__ float matern_dpolyf(float z) {
 // (1+z) v is one FMA) before the power of two is applied.
 template <int NU2, int OUT, bool FP32T>
 __device__ __forceinline__ void pair_value(double s, const double* __restrict__ tab, double& f, double& g) {
-  if constexpr (FP32T) {
+  if constexpr (NU2 == 0) {
+    // Gaussian: s = r^2 / rho^2, phi = e^{-s/2}, rho dphi/drho = s e^{-s/2}
+    if constexpr (FP32T) {
+      const float e = __builtin_amdgcn_exp2f(-0.72134752044448170f * (float)s);
+      if constexpr (OUT & 1) f = (double)e;
+      if constexpr (OUT & 2) g = (double)((float)s * e);
+    } else {
+      const ExpParts e = exp_neg_parts(0.5 * s, tab);
+      if constexpr (OUT & 1) f = scale_pow2(e.v, e.m);
+      if constexpr (OUT & 2) g = scale_pow2(s * e.v, e.m);
+    }
+  } else if constexpr (FP32T) {
     const float zf = __builtin_amdgcn_sqrtf((float)s);
     const float ef = __builtin_amdgcn_exp2f(-1.4426950408889634f * zf);
     if constexpr (OUT & 1) f = (double)(matern_polyf<NU2>(zf) * ef);
@@ -159,6 +170,26 @@ __device__ __forceinline__ void pair_value_w(float w, float& f, float& g) {
     if constexpr (NU2 == 1) g = (w * l1) * e;
     else if constexpr (NU2 == 3) g = (w * (w * l2)) * e;
     else g = (w * (w * (l2 / 3.0f))) * (fmaf(w, l1, 1.0f) * e);
+  }
+}
+
+// FP32 kernels take coordinates scaled by the kernel scale times lp_scale:
+// log2(e) for the Matern forms (the distance is then w = log2(e) z), and
+// sqrt(log2(e)/2) for the Gaussian (the squared distance is then
+// s' = log2(e) r^2 / (2 rho^2), so that phi = 2^{-s'})
+template <int NU2>
+constexpr double lp_scale() {
+  return NU2 == 0 ? 0.84932180028801907 : 1.4426950408889634;
+}
+// FP32 kernel value (and rho-derivative) from the squared scaled distance
+template <int NU2, int OUT>
+__device__ __forceinline__ void pair_value_lp(float s, float& f, float& g) {
+  if constexpr (NU2 == 0) {
+    const float e = __builtin_amdgcn_exp2f(-s);
+    if constexpr (OUT & 1) f = e;
+    if constexpr (OUT & 2) g = (s * 1.3862943611198906f) * e;  // r^2/rho^2 = 2 ln2 s'
+  } else {
+    pair_value_w<NU2, OUT>(__builtin_amdgcn_sqrtf(s), f, g);
   }
 }
 

@@ -30,6 +30,7 @@ constexpr int kT = 256;
 constexpr int kMaxD = 64;
 
 __device__ __forceinline__ double phi32(double s, int nu2) {
+  if (nu2 == 0) return (double)__builtin_amdgcn_exp2f(-0.72134752044448170f * (float)s);  // Gaussian e^{-s/2}
   const float z = __builtin_amdgcn_sqrtf((float)s);
   const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
   float p = 1.0f;

@@ -163,3 +163,26 @@ def uniform_cloud(n: int, d: int, seed: int) -> np.ndarray:
 
 def standard_normal(n: int, seed: int) -> np.ndarray:
     return np.random.Generator(np.random.PCG64(seed)).standard_normal(n)
+
+
+# The cases of the accuracy experiment (Sec. 8, "Prediction numerical
+# accuracy under ill-conditioning"): (alpha, theta) of each row of its table.
+ACCURACY_CASES = [(1.0, 10.0), (0.5, 10.0), (2.0, 10.0), (2.0, 3.0), (0.5, 3.0)]
+
+
+def unit_disk(n: int, g: np.random.Generator) -> np.ndarray:
+    """n points uniform on the unit disk (radius sqrt(U), angle 2 pi U)."""
+    r = np.sqrt(g.random(n))
+    a = 2.0 * np.pi * g.random(n)
+    return np.stack([r * np.cos(a), r * np.sin(a)], axis=1)
+
+
+def accuracy_experiment(alpha: float, n: int = 200, n_targets: int = 200):
+    """Inputs of the accuracy experiment: n observation sites and n_targets
+    targets uniform on the unit disk, Z_i = 1 + sin(alpha x_i1) sin(alpha x_i2).
+    The sites and targets do not depend on alpha."""
+    g = np.random.default_rng(np.random.SeedSequence(BASE_SEED + 100))
+    pts = unit_disk(n, g)
+    tgt = unit_disk(n_targets, g)
+    z = 1.0 + np.sin(alpha * pts[:, 0]) * np.sin(alpha * pts[:, 1])
+    return pts, tgt, z

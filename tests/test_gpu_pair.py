@@ -21,7 +21,7 @@ def _scale(rows, cols, x, nu, rho):
 
 
 @pytest.mark.parametrize("d", [1, 2, 3, 5, 7, 10, 20])
-@pytest.mark.parametrize("nu", [0.5, 1.5, 2.5])
+@pytest.mark.parametrize("nu", [0.5, 1.5, 2.5, np.inf])
 def test_brute_force_small(d, nu):
     torch = require_gpu()
     from paper_1701_00285_amd import DLOGRHO, FP32, FP64, VALUE, cov_matvec
@@ -51,7 +51,7 @@ def test_several_tiles_ragged(m, n, d):
     rows = synth.uniform_cloud(m, d, 1)
     cols = synth.uniform_cloud(n, d, 2)
     x = synth.standard_normal(n, 3)
-    for nu in (0.5, 1.5, 2.5):
+    for nu in (0.5, 1.5, 2.5, np.inf):
         rho = 0.2 * np.sqrt(d)
         say(f"pair tiles m={m} n={n} d={d} nu={nu}")
         ref = brute.cov_matvec(rows, cols, x, nu, rho)
@@ -119,7 +119,7 @@ def test_symmetric_square_product(n, d):
     x = synth.standard_normal(n, 41 + n)
     say(f"symmetric n={n} d={d}")
     idx = np.unique(np.concatenate([np.arange(0, n, max(1, n // 64)), np.arange(n - 32, n)]))
-    for nu in (0.5, 1.5, 2.5):
+    for nu in (0.5, 1.5, 2.5, np.inf):
         rho = 0.25 * np.sqrt(d / 3)
         ref = brute.cov_matvec(pts[idx], pts, x, nu, rho, 1.3)
         dref = brute.cov_matvec(pts[idx], pts, x, nu, rho, 1.3, deriv=True)
@@ -196,3 +196,21 @@ def test_matrix_core_symmetric(n, d):
     for prec in (MFMA_FP32, MFMA_BF16X3):
         y, _ = cov_matvec(P, P, dev(e), 0.5, 1.0, 1.0, precision=prec)
         assert host(y)[n // 3] == 1.0
+
+
+def test_gaussian_in_matrix_core_precisions_uses_the_fp32_kernels():
+    """The matrix cores take the half-integer forms only; a Gaussian product
+    asked in a matrix-core precision runs the FP32 kernels (FP32 tolerance)."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import MFMA_BF16X3, MFMA_FP32, cov_matvec
+    for n in (3001, 16385):
+        pts = synth.uniform_cloud(n, 10, 90 + n)
+        x = synth.standard_normal(n, 91)
+        idx = np.arange(0, n, max(1, n // 40))
+        rho = 0.4 * np.sqrt(10)
+        ref = brute.cov_matvec(pts[idx], pts, x, np.inf, rho)
+        sc = _scale(pts[idx], pts, x, np.inf, rho)
+        P = dev(pts)
+        for prec in (MFMA_FP32, MFMA_BF16X3):
+            y, _ = cov_matvec(P, P, dev(x), np.inf, rho, precision=prec)
+            assert row_relerr(host(y)[idx], ref, sc) < FP32_TOL

@@ -64,3 +64,26 @@ def test_planted_mistake_printed_sum_is_rejected(monkeypatch):
     a = M.matern(R[1:], 1.5, 0.3)
     b = M.matern_bessel(R[1:], 1.5, 0.3)
     assert not np.allclose(a, b, rtol=1e-3)
+
+
+def test_gaussian_is_the_large_nu_limit_of_the_definition():
+    """nu = +inf (Gaussian, Sec. 8 accuracy experiment) against the kv form
+    of the Definition at large nu: the gap shrinks like 1/nu."""
+    r = np.linspace(0.0, 3.0, 31)
+    g = M.matern(r, np.inf, 0.7, 1.3)
+    assert g[0] == 1.3
+    gaps = []
+    for nu in (25.0, 50.0, 100.0):          # the kv form overflows Gamma(nu) beyond nu ~ 170
+        b = M.matern_bessel(r, nu, 0.7, 1.3)
+        gaps.append(np.max(np.abs(b - g)))
+    assert gaps[2] < 4e-3
+    for a, b in zip(gaps, gaps[1:]):        # O(1/nu): the gap halves when nu doubles
+        assert 1.8 < a / b < 2.2
+    np.testing.assert_allclose(g, 1.3 * np.exp(-r ** 2 / (2 * 0.49)), rtol=4e-15)
+
+
+def test_gaussian_rho_derivative_central_difference():
+    r = np.linspace(0.01, 2.5, 40)
+    rho, h = 0.6, 1e-6
+    fd = rho * (M.matern(r, np.inf, rho * (1 + h)) - M.matern(r, np.inf, rho * (1 - h))) / (2 * rho * h)
+    np.testing.assert_allclose(M.matern_rho_drho(r, np.inf, rho), fd, rtol=1e-7, atol=1e-10)
