@@ -108,7 +108,7 @@ def cpu_baseline(wl, rows: int):
                       f"{dt:.1f} s, one thread)"}
 
 
-def sweep(configs, reps: int = 10, warm: int = 3):
+def sweep(configs, reps: int = 10, warm: int = 3, nu=None):
     """Per workload: the square product in every precision that applies
     (median of `reps` HIP-event timings after `warm` untimed launches), the
     FP64 target product, and W / W^T against their algorithmic bytes.  Errors:
@@ -125,7 +125,10 @@ def sweep(configs, reps: int = 10, warm: int = 3):
     names = {FP64: "fp64", FP32: "fp32", MFMA_FP32: "mfma_fp32", MFMA_BF16X3: "mfma_bf16x3"}
     for k in configs:
         wl = synth.make_config(k, with_z=False)
+        if nu is not None:
+            wl.nu = nu
         n, d = wl.n, wl.d
+        closed = wl.nu in (0.5, 1.5, 2.5) or math.isinf(wl.nu)
         s = Solver(wl.points, wl.degree_w, wl.leaf_max, wl.nu, wl.rho, wl.sigma2, max_targets=wl.targets.shape[0])
         P = s.basis.points_dev
         x_host = synth.standard_normal(n, 7)
@@ -149,7 +152,7 @@ def sweep(configs, reps: int = 10, warm: int = 3):
             profile_enable(False)
             return float(np.median(times)), out
 
-        precs = [FP64, FP32] + ([MFMA_FP32, MFMA_BF16X3] if 8 <= d <= 32 else [])
+        precs = ([FP64, FP32] + ([MFMA_FP32, MFMA_BF16X3] if 8 <= d <= 32 else [])) if closed else [FP64]
         prods, y64 = {}, None
         for prec in precs:
             work = torch.empty(max(cov_workspace_bytes(n, n, d, prec, VALUE), 256), dtype=torch.uint8, device="cuda")
@@ -195,6 +198,9 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--n", type=int, default=0, help="number of points drawn from the workload generator (0: its full size)")
     ap.add_argument("--targets", type=int, default=0, help="number of targets (0: the workload's)")
+    ap.add_argument("--nu", type=float, default=0.0,
+                    help="smoothness in place of the workload's (sweep: products only; a nu other than 1/2, 3/2, "
+                         "5/2 or +inf has FP64 values only)")
     ap.add_argument("--mixed", type=int, default=-1, help="precision of the mixed solve (default: FP32 for d<16, "
                                                           "MFMA FP32 for d>=16)")
     ap.add_argument("--scheme", choices=("flexible", "reliable"), default="flexible",
@@ -227,7 +233,7 @@ def main():
     import torch
 
     if a.sweep:
-        sweep([int(v) for v in a.sweep.split(",")])
+        sweep([int(v) for v in a.sweep.split(",")], nu=a.nu or None)
         return
 
     if a.copy_calibration:

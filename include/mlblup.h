@@ -177,6 +177,12 @@ int mlblup_basis_upload(mlblup_basis b, void* dev_buf, int64_t bytes, void* stre
 int mlblup_basis_points_dev(mlblup_basis b, const double** pts_dev);
 void mlblup_basis_free(mlblup_basis b);
 
+/* Host evaluation of sigma2 phi(r) for n distances r_host[i] >= 0 into
+ * phi_host (host pointers): the same arithmetic as the FP64 pair kernels for
+ * a general nu (table of genu.h), the closed forms otherwise.  For checking
+ * and plotting; the products run on the device. */
+int mlblup_matern_host(const mlblup_matern* k, const double* r_host, int64_t n, double* phi_host);
+
 /* ---- dense covariance product (Sec. 6.2, step (2) of the chain) ----------
  * y_i = sum_j sigma2 phi(|r_i - c_j|) x_j over all m x n pairs (rows_dev:
  * m x d, cols_dev: n x d, row-major float64), and/or dy = (rho dC/drho) x.

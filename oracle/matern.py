@@ -54,10 +54,13 @@ def _prefactor(n: int) -> float:
 
 def matern(r, nu: float, rho: float, sigma2: float = 1.0):
     """phi(r) for nu = n + 1/2 (Definition + half-integer remark, Sec. 3.1),
-    or the Gaussian limit for nu = +inf."""
+    the Gaussian limit for nu = +inf, and the Definition itself (scipy's
+    K_nu, `matern_bessel`) for any other nu > 0."""
     if math.isinf(nu) and nu > 0:
         r = np.asarray(r, dtype=np.float64)
         return sigma2 * np.exp(-(r / rho) ** 2 / 2.0)
+    if abs(nu - 0.5 - round(nu - 0.5)) > 1e-12:
+        return matern_bessel(r, nu, rho, sigma2)
     n = _halfint_n(nu)
     r = np.asarray(r, dtype=np.float64)
     z = math.sqrt(2.0 * nu) * r / rho

@@ -58,6 +58,7 @@ _SIGS = {
     "mlblup_basis_info": (C.c_int, [_P, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I64), C.POINTER(_I64)]),
     "mlblup_basis_level_counts": (C.c_int, [_P, _P]),
     "mlblup_basis_transform_bytes": (C.c_int, [_P, _P]),
+    "mlblup_matern_host": (C.c_int, [_P, _P, C.c_int64, _P]),
     "mlblup_basis_dense": (C.c_int, [_P, _P, _P]),
     "mlblup_basis_upload": (C.c_int, [_P, _P, _I64, _P]),
     "mlblup_basis_points_dev": (C.c_int, [_P, C.POINTER(_P)]),

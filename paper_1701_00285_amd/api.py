@@ -194,6 +194,15 @@ def cov_workspace_bytes(m, n, d, precision=FP64, outputs=VALUE):
     return b.value
 
 
+def matern_host(r, nu, rho, sigma2=1.0):
+    """sigma2 phi(r) evaluated on the host by the library (numpy in, numpy out)."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    out = np.empty_like(r)
+    k = matern(nu, rho, sigma2)
+    check(L.lib().mlblup_matern_host(C.byref(k), _np_ptr(r), r.size, _np_ptr(out)))
+    return out
+
+
 def cov_matvec(rows, cols, x, nu, rho, sigma2=1.0, precision=FP64, outputs=VALUE, work=None):
     """y = C(rows, cols) x and/or dy = (rho dC/drho) x on the GPU.  rows (m, d),
     cols (n, d), x (n,) are float64 device tensors."""

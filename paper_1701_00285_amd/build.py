@@ -20,7 +20,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmlblup.so")
-SOURCES = ["tree.cpp", "basis.cpp", "abi.cpp", "precond_host.cpp", "ops.hip", "pair.hip", "pair_sym.hip", "precond.hip",
+SOURCES = ["tree.cpp", "basis.cpp", "abi.cpp", "precond_host.cpp", "genu.cpp", "ops.hip", "pair.hip", "pair_sym.hip", "precond.hip",
            "pair_mfma.hip"]
 
 

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "device.h"
+#include "genu.h"
 #include "internal.h"
 #include "precond.h"
 
@@ -41,6 +42,7 @@ int nu2_of_nu(double nu) {
   const double n2 = 2.0 * nu;
   for (int c : {1, 3, 5})
     if (std::fabs(n2 - c) < 1e-12) return c;
+  if (nu > 0.0 && nu <= 8.0) return kNuGeneral;
   return -1;
 }
 
@@ -59,7 +61,7 @@ int nu2_of(const mlblup_matern* k) { return k ? nu2_of_nu(k->nu) : -1; }
 
 int check_kernel(const mlblup_matern* k) {
   if (!k) return fail(MLBLUP_EINVAL, "NULL covariance parameters");
-  if (nu2_of(k) < 0) return fail(MLBLUP_EINVAL, "nu must be 0.5, 1.5, 2.5 or +inf (Gaussian)");
+  if (nu2_of(k) == -1) return fail(MLBLUP_EINVAL, "nu must be in (0, 8] or +inf (Gaussian)");
   if (!(k->rho > 0) || !std::isfinite(k->rho)) return fail(MLBLUP_EINVAL, "rho must be finite and > 0");
   if (!(k->sigma2 > 0) || !std::isfinite(k->sigma2)) return fail(MLBLUP_EINVAL, "sigma2 must be finite and > 0");
   return MLBLUP_OK;
@@ -210,7 +212,7 @@ struct Ctx {
   }
 
   int pair(const double* rows, int64_t m, const double* x, double* y, double* dy, int prec, int outputs) {
-    PairArgs a{rows, m, pts, B.n, B.d, nu2, k.rho, k.sigma2, prec, outputs, x, y, dy};
+    PairArgs a{rows, m, pts, B.n, B.d, nu2, k.rho, k.sigma2, prec, outputs, x, y, dy, k.nu, nullptr};
     return pair_launch(a, at(w.cov), w.cov_bytes, s);
   }
 
@@ -715,13 +717,36 @@ int mlblup_cov_workspace_bytes(int64_t m, int64_t n, int32_t d, int32_t precisio
   return MLBLUP_OK;
 }
 
+int mlblup_matern_host(const mlblup_matern* k, const double* r_host, int64_t n, double* phi_host) {
+  clear_error();
+  int st = check_kernel(k);
+  if (st) return st;
+  if (n < 0 || (n > 0 && (!r_host || !phi_host))) return fail(MLBLUP_EINVAL, "matern_host: bad arguments");
+  const int nu2 = nu2_of(k);
+  const double* tab = nu2 == kNuGeneral ? genu_table_cached(k->nu) : nullptr;
+  if (nu2 == kNuGeneral && !tab) return fail(MLBLUP_EINVAL, "matern_host: nu out of range");
+  const double zs = kernel_scale(nu2, k->nu, k->rho);
+  for (int64_t i = 0; i < n; ++i) {
+    const double z = r_host[i] * zs;
+    double f;
+    if (nu2 == kNuGeneral) f = genu_f(z * z + 1e-300, tab);
+    else if (nu2 == 0) f = std::exp(-0.5 * z * z);
+    else if (nu2 == 1) f = std::exp(-z);
+    else if (nu2 == 3) f = (1.0 + z) * std::exp(-z);
+    else f = (1.0 + z + z * z / 3.0) * std::exp(-z);
+    phi_host[i] = k->sigma2 * f;
+  }
+  return MLBLUP_OK;
+}
+
 int mlblup_cov_matvec(const mlblup_matern* k, const double* rows_dev, int64_t m, const double* cols_dev, int64_t n,
                       int32_t d, int32_t precision, int32_t outputs, const double* x_dev, double* y_dev,
                       double* dy_dev, void* work_dev, int64_t work_bytes, void* stream) {
   clear_error();
   int st = check_kernel(k);
   if (st) return st;
-  PairArgs a{rows_dev, m, cols_dev, n, d, nu2_of(k), k->rho, k->sigma2, precision, outputs, x_dev, y_dev, dy_dev};
+  PairArgs a{rows_dev, m, cols_dev, n, d, nu2_of(k), k->rho, k->sigma2, precision, outputs, x_dev, y_dev, dy_dev,
+             k->nu, nullptr};
   return pair_launch(a, work_dev, work_bytes, (hipStream_t)stream);
 }
 

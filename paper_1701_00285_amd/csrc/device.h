@@ -36,7 +36,15 @@ struct PairArgs {
   const double* x;
   double* y;
   double* dy;
+  double nu = 0.0;                // the smoothness itself (general nu)
+  const double* gtab = nullptr;   // general-nu table on the device (set by pair_launch)
 };
+
+// nu2 code of a general smoothness (0 < nu <= 8, not a half-integer): the
+// FP64 kernels evaluate it from a table (genu.h)
+constexpr int kNuGeneral = -2;
+// host copy of the general-nu table for nu (built once, kept for the process); NULL if nu is out of range
+const double* genu_table_cached(double nu);
 
 // Number of column splits (partial sums per row) used for an m x n product.
 int32_t pair_splits(int64_t m, int64_t n, int32_t d, int32_t precision);
@@ -53,12 +61,16 @@ int64_t sym_workspace_bytes(int64_t n, int outputs);
 int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s);
 // Matrix-core distance Gram (pair_mfma.hip): MFMA precisions, value only, 8 <= d <= 32.
 bool mfma_applies(const PairArgs& a);
-// 2 nu of a covariance: 1, 3, 5 (half-integer Matern) or 0 for nu = +inf, the
+// 2 nu of a covariance: 1, 3, 5 (half-integer Matern), 0 for nu = +inf, the
 // Gaussian exp(-r^2 / (2 rho^2)) (the Matern limit in the sqrt(2 nu) r / rho
-// parametrisation); -1 for anything else
+// parametrisation), kNuGeneral for any other 0 < nu <= 8; -1 otherwise
 int nu2_of_nu(double nu);
 // scale applied to the coordinates: sqrt(2 nu) / rho, or 1 / rho for the Gaussian
-inline double kernel_scale(int nu2, double rho) { return (nu2 == 0 ? 1.0 : std::sqrt((double)nu2)) / rho; }
+inline double kernel_scale(int nu2, double nu, double rho) {
+  if (nu2 == 0) return 1.0 / rho;
+  if (nu2 == kNuGeneral) return std::sqrt(2.0 * nu) / rho;
+  return std::sqrt((double)nu2) / rho;
+}
 int32_t mfma_splits(int64_t m, int64_t n);
 int mfma_launch(const PairArgs& a, double zs, double* part, hipStream_t s);
 // square products (n >= 16,384): each unordered pair once, tournament schedule

@@ -25,6 +25,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <vector>
 
 #include "device.h"
 #include "pairmath.h"
@@ -40,7 +43,8 @@ template <int D, int NU2, int OUT, int R, bool FP32T>
 __global__ __launch_bounds__(kThreads) void pair_kernel(const double* __restrict__ rows, int64_t m,
                                                         const double* __restrict__ cols, int64_t n,
                                                         const double* __restrict__ x, double* __restrict__ py,
-                                                        double* __restrict__ pdy, double zs, int64_t cps) {
+                                                        double* __restrict__ pdy, double zs, int64_t cps,
+                                                        const double* __restrict__ gtab) {
   constexpr int SD = D + 1;
   __shared__ double tile[kTile * SD];
   __shared__ double tab[kExpTab];
@@ -85,7 +89,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const double* __restrict
           s = fma(t, t, s);
         }
         double f = 0.0, g = 0.0;
-        pair_value<NU2, OUT, FP32T>(s, tab, f, g);
+        pair_value<NU2, OUT, FP32T>(s, tab, f, g, gtab);
         if constexpr (OUT & 1) acc[r] = fma(f, aj, acc[r]);
         if constexpr (OUT & 2) dacc[r] = fma(g, aj, dacc[r]);
       }
@@ -107,7 +111,8 @@ template <int NU2, int OUT, bool FP32T>
 __global__ __launch_bounds__(kThreads) void pair_kernel_any(const double* __restrict__ rows, int64_t m,
                                                             const double* __restrict__ cols, int64_t n, int d,
                                                             const double* __restrict__ x, double* __restrict__ py,
-                                                            double* __restrict__ pdy, double zs, int64_t cps) {
+                                                            double* __restrict__ pdy, double zs, int64_t cps,
+                                                            const double* __restrict__ gtab) {
   __shared__ double tab[kExpTab];
   exp_table_fill(tab);
   __syncthreads();
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel_any(const double* __rest
       s = fma(t, t, s);
     }
     double f = 0.0, g = 0.0;
-    pair_value<NU2, OUT, FP32T>(s, tab, f, g);
+    pair_value<NU2, OUT, FP32T>(s, tab, f, g, gtab);
     if constexpr (OUT & 1) acc = fma(f, x[j], acc);
     if constexpr (OUT & 2) dacc = fma(g, x[j], dacc);
   }
@@ -154,14 +159,14 @@ void launch_fixed(const PairArgs& a, double zs, int S, int64_t cps, double* py, 
   constexpr int R = rows_per_thread(D);
   dim3 grid((unsigned)((a.m + kThreads * R - 1) / (kThreads * R)), (unsigned)S);
   hipLaunchKernelGGL((pair_kernel<D, NU2, OUT, R, F>), grid, dim3(kThreads), 0, s, a.rows, a.m, a.cols, a.n, a.x,
-                     py, pdy, zs, cps);
+                     py, pdy, zs, cps, a.gtab);
 }
 
 template <int NU2, int OUT, bool F>
 void launch_any(const PairArgs& a, double zs, int S, int64_t cps, double* py, double* pdy, hipStream_t s) {
   dim3 grid((unsigned)((a.m + kThreads - 1) / kThreads), (unsigned)S);
   hipLaunchKernelGGL((pair_kernel_any<NU2, OUT, F>), grid, dim3(kThreads), 0, s, a.rows, a.m, a.cols, a.n, a.d,
-                     a.x, py, pdy, zs, cps);
+                     a.x, py, pdy, zs, cps, a.gtab);
 }
 
 template <int NU2, int OUT, bool F>
@@ -192,6 +197,12 @@ void dispatch_out(const PairArgs& a, double zs, int S, int64_t cps, double* py, 
 
 template <bool F>
 void dispatch_nu(const PairArgs& a, double zs, int S, int64_t cps, double* py, double* pdy, hipStream_t s) {
+  if constexpr (!F) {
+    if (a.nu2 == kNuGeneral) {  // FP64 values only
+      dispatch_d<kNuGeneralT, 1, false>(a, zs, S, cps, py, pdy, s);
+      return;
+    }
+  }
   switch (a.nu2) {
     case 0: dispatch_out<0, F>(a, zs, S, cps, py, pdy, s); break;
     case 1: dispatch_out<1, F>(a, zs, S, cps, py, pdy, s); break;
@@ -227,7 +238,24 @@ int64_t pair_workspace_bytes(int64_t m, int64_t n, int32_t d, int32_t precision,
   if ((precision == MLBLUP_MFMA_FP32 || precision == MLBLUP_MFMA_BF16X3) && outputs == MLBLUP_VALUE)
     b = std::max(b, ((int64_t)mfma_splits(m, n) * m * (int64_t)sizeof(double) + 255) / 256 * 256);
   if (m == n && sym_worthwhile(n)) b = std::max(b, sym_workspace_bytes(n, outputs));
-  return b;
+  // tail: the general-nu table
+  return (b + 255) / 256 * 256 + kGenuBytes;
+}
+
+int pair_launch_body(const PairArgs& a, double zs, void* work, hipStream_t s);
+
+// general-nu tables, built once per nu on the host and kept for the process
+const double* genu_table_cached(double nu) {
+  static std::mutex mu;
+  static std::map<double, std::vector<double>> cache;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(nu);
+  if (it == cache.end()) {
+    std::vector<double> tab;
+    if (!genu_build(nu, tab)) return nullptr;
+    it = cache.emplace(nu, std::move(tab)).first;
+  }
+  return it->second.data();
 }
 
 int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s) {
@@ -236,8 +264,10 @@ int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s
 
   if (!(a.rho > 0) || !(a.sigma2 > 0) || !std::isfinite(a.rho) || !std::isfinite(a.sigma2))
     return fail(MLBLUP_EINVAL, "cov_matvec: rho and sigma2 must be finite and > 0");
-  if (a.nu2 != 0 && a.nu2 != 1 && a.nu2 != 3 && a.nu2 != 5)
-    return fail(MLBLUP_EINVAL, "cov_matvec: nu must be 1/2, 3/2, 5/2 or +inf (Gaussian)");
+  if (a.nu2 != 0 && a.nu2 != 1 && a.nu2 != 3 && a.nu2 != 5 && a.nu2 != kNuGeneral)
+    return fail(MLBLUP_EINVAL, "cov_matvec: nu must be in (0, 8] or +inf (Gaussian)");
+  if (a.nu2 == kNuGeneral && (a.precision != MLBLUP_FP64 || a.outputs != MLBLUP_VALUE))
+    return fail(MLBLUP_EINVAL, "cov_matvec: a nu other than 1/2, 3/2, 5/2 or +inf has FP64 values only");
   if (a.precision < MLBLUP_FP64 || a.precision > MLBLUP_MFMA_BF16X3)
     return fail(MLBLUP_EINVAL, "cov_matvec: unknown precision");
   if (a.m == 0) return MLBLUP_OK;
@@ -253,7 +283,21 @@ int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s
   const int64_t need = pair_workspace_bytes(a.m, a.n, a.d, a.precision, a.outputs);
   if (!work || work_bytes < need)
     return fail(MLBLUP_EINVAL, "cov_matvec: workspace too small (need " + std::to_string(need) + " bytes)");
-  const double zs = kernel_scale(a.nu2, a.rho);  // sqrt(2 nu) / rho (Gaussian: 1 / rho)
+  const double zs = kernel_scale(a.nu2, a.nu, a.rho);  // sqrt(2 nu) / rho (Gaussian: 1 / rho)
+  if (a.nu2 == kNuGeneral) {
+    // the table goes to the workspace's tail; the host copy lives as long as the process
+    const double* host = genu_table_cached(a.nu);
+    if (!host) return fail(MLBLUP_EINVAL, "cov_matvec: nu out of range for the general-nu table");
+    double* dev = (double*)((char*)work + (need - kGenuBytes));
+    MLB_HIP(hipMemcpyAsync(dev, host, kGenuBytes, hipMemcpyHostToDevice, s));
+    PairArgs b = a;
+    b.gtab = dev;
+    return pair_launch_body(b, zs, work, s);
+  }
+  return pair_launch_body(a, zs, work, s);
+}
+
+int pair_launch_body(const PairArgs& a, double zs, void* work, hipStream_t s) {
   if (mfma_applies(a)) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (profile_on()) {

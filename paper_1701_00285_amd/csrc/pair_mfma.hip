@@ -534,7 +534,7 @@ int32_t mfma_splits(int64_t m, int64_t n) {
 
 bool mfma_applies(const PairArgs& a) {
   return (a.precision == MLBLUP_MFMA_FP32 || a.precision == MLBLUP_MFMA_BF16X3) && a.outputs == MLBLUP_VALUE &&
-         a.d >= 8 && a.d <= 32 && a.nu2 != 0;
+         a.d >= 8 && a.d <= 32 && a.nu2 > 0;
 }
 
 int mfma_sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s) {

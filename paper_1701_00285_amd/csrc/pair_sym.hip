@@ -41,7 +41,8 @@ template <int D, int NU2, int OUT>
 __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts, const double* __restrict__ x,
                                                  int64_t n, int T, int round0, int diag, double zs,
                                                  double* __restrict__ prow, double* __restrict__ pcol,
-                                                 double* __restrict__ pdrow, double* __restrict__ pdcol) {
+                                                 double* __restrict__ pdrow, double* __restrict__ pdcol,
+                                                 const double* __restrict__ gtab) {
   constexpr int SD = D + 1;
   constexpr int RL = rows_per_lane(D);
   constexpr int kBlk = 256 * RL;
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
             s = fma(u, u, s);
           }
           double f = 0.0, g = 0.0;
-          pair_value<NU2, OUT, false>(s, tab, f, g);
+          pair_value<NU2, OUT, false>(s, tab, f, g, gtab);
           if constexpr (OUT & 1) {
             racc[q] = fma(f, aj, racc[q]);
             cpart = fma(f, ar[q], cpart);
@@ -301,17 +302,17 @@ __global__ __launch_bounds__(kT) void sym_reduce(const double* __restrict__ prow
 
 template <int D, int NU2, int OUT, bool F>
 void launch(const double* pts, const double* x, int64_t n, int T, int round0, int nr, int diag, double zs,
-            double* prow, double* pcol, double* pdrow, double* pdcol, hipStream_t s) {
+            double* prow, double* pcol, double* pdrow, double* pdcol, const double* gtab, hipStream_t s) {
   if constexpr (F)
     hipLaunchKernelGGL((sym_kernel_lp<D, NU2, OUT>), dim3(T, nr), dim3(kT), 0, s, pts, x, n, T, round0, diag,
                        zs * lp_scale<NU2>(), prow, pcol, pdrow, pdcol);
   else
     hipLaunchKernelGGL((sym_kernel<D, NU2, OUT>), dim3(T, nr), dim3(kT), 0, s, pts, x, n, T, round0, diag, zs, prow,
-                       pcol, pdrow, pdcol);
+                       pcol, pdrow, pdcol, gtab);
 }
 
 using LaunchFn = void (*)(const double*, const double*, int64_t, int, int, int, int, double, double*, double*, double*,
-                          double*, hipStream_t);
+                          double*, const double*, hipStream_t);
 
 template <int NU2, int OUT, bool F>
 LaunchFn pick_d(int d) {
@@ -337,6 +338,9 @@ LaunchFn pick_out(int out, int d) {
 }
 template <bool F>
 LaunchFn pick_nu(int nu2, int out, int d) {
+  if constexpr (!F) {
+    if (nu2 == kNuGeneral) return out == 1 ? pick_d<kNuGeneralT, 1, false>(d) : nullptr;  // FP64 values only
+  }
   if (nu2 == 0) return pick_out<0, F>(out, d);
   if (nu2 == 1) return pick_out<1, F>(out, d);
   if (nu2 == 3) return pick_out<3, F>(out, d);
@@ -412,7 +416,7 @@ int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s) {
   const int blk = 256 * (f32 ? rows_per_lane_lp(a.d) : rows_per_lane(a.d));
   return sym_schedule(a, blk, work, s,
                       [&](int T, int r0, int nr, int diag, double* prow, double* pcol, double* pdrow, double* pdcol) {
-                        fn(a.cols, a.x, a.n, T, r0, nr, diag, zs, prow, pcol, pdrow, pdcol, s);
+                        fn(a.cols, a.x, a.n, T, r0, nr, diag, zs, prow, pcol, pdrow, pdcol, a.gtab, s);
                       });
 }
 

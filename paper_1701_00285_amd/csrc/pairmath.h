@@ -4,7 +4,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include "genu.h"
+
 namespace mlb {
+
+constexpr int kNuGeneralT = -2;  // template code of a general smoothness (see device.h)
 
 // e^{-z} for 0 <= z, FP64, by the table-driven method of P. T. P. Tang
 // ("Table-driven implementation of the exponential function in IEEE
@@ -170,8 +174,12 @@ __device__ __forceinline__ float matern_dpolyf(float z) {
 // FP64: the polynomial multiplies the mantissa part of e^{-z} (for nu=3/2,
 // (1+z) v is one FMA) before the power of two is applied.
 template <int NU2, int OUT, bool FP32T>
-__device__ __forceinline__ void pair_value(double s, const double* __restrict__ tab, double& f, double& g) {
-  if constexpr (NU2 == 0) {
+__device__ __forceinline__ void pair_value(double s, const double* __restrict__ tab, double& f, double& g,
+                                           const double* __restrict__ gtab = nullptr) {
+  if constexpr (NU2 == kNuGeneralT) {
+    // general nu: FP64 values from the table (genu.h); no derivative
+    if constexpr (OUT & 1) f = genu_f(s, gtab);
+  } else if constexpr (NU2 == 0) {
     // Gaussian: s = r^2 / rho^2, phi = e^{-s/2}, rho dphi/drho = s e^{-s/2}
     if constexpr (FP32T) {
       const float e = __builtin_amdgcn_exp2f(-0.72134752044448170f * (float)s);

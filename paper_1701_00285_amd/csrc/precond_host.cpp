@@ -169,7 +169,7 @@ int precond_build(const Basis& B, double nu2d, double rho, double sigma2, int ki
   if (!work || work_bytes < w.total)
     return fail(MLBLUP_EINVAL, "preconditioner workspace too small (need " + std::to_string(w.total) + ")");
   const int nu2 = (int)std::lround(nu2d);
-  const double zs = kernel_scale(nu2, rho);
+  const double zs = kernel_scale(nu2, 0.5 * nu2d, rho);
   const int32_t nn = (int32_t)B.desc.size();
   char* base = (char*)work;
   const char* img = (const char*)B.dev_base;
@@ -382,7 +382,7 @@ int mlblup_precond_build(mlblup_basis b, const mlblup_matern* k, int32_t kind, v
   if (!b->b.uploaded) return fail(MLBLUP_ESTATE, "basis not uploaded");
   if (kind != MLBLUP_PREC_JACOBI && kind != MLBLUP_PREC_BLOCK) return fail(MLBLUP_EINVAL, "unknown preconditioner kind");
   const int n2 = nu2_of_nu(k->nu);
-  if (n2 < 0) return fail(MLBLUP_EINVAL, "nu must be 0.5, 1.5, 2.5 or +inf (Gaussian)");
+  if (n2 < 0) return fail(MLBLUP_EINVAL, "preconditioner: nu must be 0.5, 1.5, 2.5 or +inf (Gaussian)");
   if (!(k->rho > 0) || !(k->sigma2 > 0) || !std::isfinite(k->rho) || !std::isfinite(k->sigma2))
     return fail(MLBLUP_EINVAL, "rho and sigma2 must be finite and > 0");
   std::unique_ptr<mlblup_precond_s> pc(new (std::nothrow) mlblup_precond_s);

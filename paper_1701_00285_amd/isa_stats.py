@@ -47,8 +47,10 @@ def _assembly() -> list[str]:
             return f.read().split("\n")
 
 
-def _largest_block(lines: list[str], symbol: str) -> list[str]:
-    start = next(i for i, l in enumerate(lines) if l.startswith(symbol + ":"))
+def _largest_block(lines: list[str], prefix: str) -> list[str]:
+    """Largest basic block of the kernel whose mangled name starts with prefix
+    (the template arguments; the parameter list is not matched)."""
+    start = next(i for i, l in enumerate(lines) if l.startswith(prefix) and l.split(";")[0].rstrip().endswith(":"))
     end = start + 1
     while not lines[end].startswith(".Lfunc_end"):
         end += 1
@@ -69,7 +71,7 @@ def counts() -> dict:
     for d, nu2 in SHAPES:
         for kind, marker in (("fp64", "v_rsq_f64"), ("fp32", "v_sqrt_f32")):
             name = "sym_kernel" if kind == "fp64" else "sym_kernel_lp"
-            sym = f"_ZN3mlb12_GLOBAL__N_1{len(name)}{name}ILi{d}ELi{nu2}ELi1EEEvPKdS3_liiidPdS4_S4_S4_"
+            sym = f"_ZN3mlb12_GLOBAL__N_1{len(name)}{name}ILi{d}ELi{nu2}ELi1EEEv"
             blk = Counter(_largest_block(lines, sym))
             pairs = sum(v for k, v in blk.items() if k.startswith(marker))
             valu = sum(v for k, v in blk.items() if k.startswith("v_"))

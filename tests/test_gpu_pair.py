@@ -214,3 +214,49 @@ def test_gaussian_in_matrix_core_precisions_uses_the_fp32_kernels():
         for prec in (MFMA_FP32, MFMA_BF16X3):
             y, _ = cov_matvec(P, P, dev(x), np.inf, rho, precision=prec)
             assert row_relerr(host(y)[idx], ref, sc) < FP32_TOL
+
+
+GENERAL_TOL = 2e-13   # per-entry table error <= 1.5e-13 relative (host test), then FP64 sums
+
+
+@pytest.mark.parametrize("nu", [0.75, 1.0, 1.25, 3.5])
+def test_general_nu_products(nu):
+    """A smoothness outside the closed forms (Definition of Sec. 3.1, the
+    paper's experiments use 0.75, 1 and 1.25): FP64 products from the table
+    on the row-tiled path (brute force and several tiles) and the symmetric
+    path, against the Definition through scipy's K_nu."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import FP64, cov_matvec
+    for (m, n, d) in ((41, 64, 2), (700, 1031, 3), (513, 700, 10)):
+        rows = synth.uniform_cloud(m, d, 100 + d)
+        cols = synth.uniform_cloud(n, d, 101 + d)
+        x = synth.standard_normal(n, 102 + d)
+        rho = 0.3 * np.sqrt(d)
+        say(f"general nu={nu} m={m} n={n} d={d}")
+        ref = brute.cov_matvec(rows, cols, x, nu, rho, 1.4)
+        sc = 1.4 * _scale(rows, cols, x, nu, rho)
+        y, _ = cov_matvec(dev(rows), dev(cols), dev(x), nu, rho, 1.4, precision=FP64)
+        assert row_relerr(host(y), ref, sc) < GENERAL_TOL
+    n = 16385
+    pts = synth.uniform_cloud(n, 3, 103)
+    x = synth.standard_normal(n, 104)
+    idx = np.unique(np.concatenate([np.arange(0, n, n // 40), np.arange(n - 8, n)]))
+    ref = brute.cov_matvec(pts[idx], pts, x, nu, 0.25)
+    sc = _scale(pts[idx], pts, x, nu, 0.25)
+    P = dev(pts)
+    y, _ = cov_matvec(P, P, dev(x), nu, 0.25, precision=FP64)
+    assert row_relerr(host(y)[idx], ref, sc) < GENERAL_TOL
+    yr, _ = cov_matvec(P, P.clone(), dev(x), nu, 0.25, precision=FP64)       # row-tiled on a copy
+    assert row_relerr(host(yr), host(y), host(cov_matvec(P, P.clone(), torch.abs(dev(x)), nu, 0.25)[0])) < GENERAL_TOL
+
+
+def test_general_nu_rejects_what_it_does_not_provide():
+    torch = require_gpu()
+    from paper_1701_00285_amd import DLOGRHO, FP32, MFMA_FP32, MlblupError, VALUE, cov_matvec
+    P = dev(synth.uniform_cloud(300, 3, 5))
+    x = dev(synth.standard_normal(300, 6))
+    for prec, out in ((FP32, VALUE), (MFMA_FP32, VALUE)):
+        with pytest.raises(MlblupError, match="EINVAL"):
+            cov_matvec(P, P, x, 1.25, 0.3, precision=prec, outputs=out)
+    with pytest.raises(MlblupError, match="EINVAL"):
+        cov_matvec(P, P, x, 1.25, 0.3, outputs=VALUE | DLOGRHO)

@@ -12,9 +12,10 @@ from oracle.design import design_matrix
 pytestmark = pytest.mark.gpu
 
 
-def _solver(wl, max_targets=0, leaf=None):
+def _solver(wl, max_targets=0, leaf=None, nu=None):
     from paper_1701_00285_amd import Solver
-    return Solver(wl.points, wl.degree_w, leaf or wl.leaf_max, wl.nu, wl.rho, wl.sigma2, max_targets=max_targets)
+    return Solver(wl.points, wl.degree_w, leaf or wl.leaf_max, wl.nu if nu is None else nu, wl.rho, wl.sigma2,
+                  max_targets=max_targets)
 
 
 @pytest.mark.parametrize("k,n,nt", [(1, None, None), (2, 3000, 500), (4, 2500, 300), (3, 2000, 200), (5, 1500, 100)])
@@ -171,3 +172,18 @@ def test_mixed_matrix_core_solve(k, prec, scheme):
     assert out["info"]["lowp_matvecs"] > 0
     ref = OB.classic_blup(wl.points, wl.z, wl.targets, wl.degree_w, wl.nu, wl.rho)
     assert relerr(host(out["zhat"]), ref.zhat) < 1e-8
+
+
+@pytest.mark.parametrize("nu", [0.75, 1.0, 1.25])
+def test_general_nu_blup_matches_oracle(nu):
+    """The predictor with a general smoothness (FP64 products from the table)
+    against the oracle's classic BLUP with scipy's K_nu."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import PcgOptions
+    wl = workload(4, n=2000, n_targets=150)
+    say(f"general nu={nu} blup")
+    s = _solver(wl, max_targets=150, nu=nu)
+    out = s.predict(dev(wl.z), dev(wl.targets), PcgOptions(rtol=1e-12, max_iter=6000))
+    ref = OB.classic_blup(wl.points, wl.z, wl.targets, wl.degree_w, nu, wl.rho)
+    assert relerr(host(out["zhat"]), ref.zhat) < 1e-9
+    assert relerr(out["beta"], ref.beta) < 1e-8
