@@ -37,7 +37,7 @@
 
 namespace mlb {
 
-constexpr int kGenuSer = 20;        // series terms (w <= 1: terms below 1e-30)
+constexpr int kGenuSer = 14;        // series terms (w <= 1: the next is below 1e-20 of the first)
 constexpr int kGenuDeg = 8;         // polynomial degree per interval
 constexpr int kGenuMaxInt = 256;    // intervals (z up to Z0 + 64)
 constexpr int kGenuLogTab = 65;     // c_j = 1 + j/64, j = 0..64

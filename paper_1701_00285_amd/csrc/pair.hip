@@ -49,6 +49,14 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const double* __restrict
   __shared__ double tile[kTile * SD];
   __shared__ double tab[kExpTab];
   exp_table_fill(tab);
+  // general nu: the table in LDS (read by every pair)
+  const double* gt = gtab;
+  if constexpr (NU2 == kNuGeneralT) {
+    __shared__ double gsh[kGenuDoubles];
+    const int nd = kGenuOffPoly + (int)gtab[5] * (kGenuDeg + 1);
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) gsh[i] = gtab[i];
+    gt = gsh;
+  }
   const int tid = threadIdx.x;
   const int64_t rbase = (int64_t)blockIdx.x * (kThreads * R);
   double xr[R][D];
@@ -89,7 +97,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const double* __restrict
           s = fma(t, t, s);
         }
         double f = 0.0, g = 0.0;
-        pair_value<NU2, OUT, FP32T>(s, tab, f, g, gtab);
+        pair_value<NU2, OUT, FP32T>(s, tab, f, g, gt);
         if constexpr (OUT & 1) acc[r] = fma(f, aj, acc[r]);
         if constexpr (OUT & 2) dacc[r] = fma(g, aj, dacc[r]);
       }
@@ -115,6 +123,14 @@ __global__ __launch_bounds__(kThreads) void pair_kernel_any(const double* __rest
                                                             const double* __restrict__ gtab) {
   __shared__ double tab[kExpTab];
   exp_table_fill(tab);
+  // general nu: the table in LDS (read by every pair)
+  const double* gt = gtab;
+  if constexpr (NU2 == kNuGeneralT) {
+    __shared__ double gsh[kGenuDoubles];
+    const int nd = kGenuOffPoly + (int)gtab[5] * (kGenuDeg + 1);
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) gsh[i] = gtab[i];
+    gt = gsh;
+  }
   __syncthreads();
   const int64_t i0 = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t i = i0 < m ? i0 : m - 1;
@@ -128,7 +144,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel_any(const double* __rest
       s = fma(t, t, s);
     }
     double f = 0.0, g = 0.0;
-    pair_value<NU2, OUT, FP32T>(s, tab, f, g, gtab);
+    pair_value<NU2, OUT, FP32T>(s, tab, f, g, gt);
     if constexpr (OUT & 1) acc = fma(f, x[j], acc);
     if constexpr (OUT & 2) dacc = fma(g, x[j], dacc);
   }

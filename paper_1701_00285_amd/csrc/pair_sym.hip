@@ -58,6 +58,14 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
     if ((T % 2 == 0) && (2 * r == T) && S >= T / 2) return;  // whole block exits
   }
   exp_table_fill(tab);
+  // general nu: the table in LDS (read by every pair)
+  const double* gt = gtab;
+  if constexpr (NU2 == kNuGeneralT) {
+    __shared__ double gsh[kGenuDoubles];
+    const int nd = kGenuOffPoly + (int)gtab[5] * (kGenuDeg + 1);
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) gsh[i] = gtab[i];
+    gt = gsh;
+  }
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   // lane rotation direction: after one rotation lane l holds lane (l + delta)'s value
   const int delta = (wave_rotate1_i(lane) - lane) & 63;
@@ -111,7 +119,7 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
             s = fma(u, u, s);
           }
           double f = 0.0, g = 0.0;
-          pair_value<NU2, OUT, false>(s, tab, f, g, gtab);
+          pair_value<NU2, OUT, false>(s, tab, f, g, gt);
           if constexpr (OUT & 1) {
             racc[q] = fma(f, aj, racc[q]);
             cpart = fma(f, ar[q], cpart);

@@ -131,7 +131,7 @@ def test_error_paths():
         s.solve(zw, PcgOptions(precision=1, mixed_scheme=7))
     from paper_1701_00285_amd import cov_matvec
     with pytest.raises(MlblupError, match="EINVAL"):
-        cov_matvec(dev(wl.points), dev(wl.points), dev(wl.z), 1.0, 0.1)
+        cov_matvec(dev(wl.points), dev(wl.points), dev(wl.z), 9.0, 0.1)   # nu out of (0, 8]
 
 
 def test_basis_independence_of_iterations():
