@@ -42,7 +42,8 @@ extern "C" {
 #endif
 
 #define MLBLUP_OK 0
-#define MLBLUP_EINVAL (-1)     /* bad argument: shape, NULL, nu not in {1/2,3/2,5/2}, NaN input, small workspace */
+#define MLBLUP_EINVAL (-1)     /* bad argument: shape, NULL, nu outside (0, 8] and not +inf, NaN input, small
+                                  workspace, or an option the kernel's nu does not provide */
 #define MLBLUP_ERANK (-2)      /* design matrix rank < p on the point set (e.g. collinear points, duplicates) */
 #define MLBLUP_ENOCONV (-3)    /* iteration limit reached; outputs hold the last iterate, info is filled */
 #define MLBLUP_EBREAKDOWN (-4) /* Krylov breakdown: p.q <= 0 or a non-finite scalar */
@@ -51,9 +52,12 @@ extern "C" {
 
 /* Arithmetic of the pair kernel (the dense covariance product). */
 #define MLBLUP_FP64 0          /* FP64 differences, sqrt, exp, sums */
-#define MLBLUP_FP32 1          /* FP64 differences and squared distance, FP32 sqrt/exp/kernel value, FP64 sums */
-#define MLBLUP_MFMA_FP32 2     /* distance Gram on FP32 matrix cores (d >= 8 intended), exact near tiles */
-#define MLBLUP_MFMA_BF16X3 3   /* distance Gram on BF16 matrix cores with a hi/lo split (3 products) */
+#define MLBLUP_FP32 1          /* FP32 kernel values: square products (N >= 16384) from FP32 coordinates relative
+                                  to a block origin, FP32 sums over 16 columns then FP64; other products from
+                                  FP64 squared distances with FP32 sqrt/exp and FP64 sums */
+#define MLBLUP_MFMA_FP32 2     /* distance Gram on FP32 matrix cores, exact near tiles (8 <= d <= 32, half-integer
+                                  nu, values only; elsewhere the MLBLUP_FP32 kernels) */
+#define MLBLUP_MFMA_BF16X3 3   /* distance Gram on BF16 matrix cores with a hi/lo split (3 products); same scope */
 
 /* Output selection bitmask of mlblup_cov_matvec. */
 #define MLBLUP_VALUE 1         /* y  = C x            */
@@ -71,8 +75,14 @@ typedef struct mlblup_precond_s* mlblup_precond;
 #define MLBLUP_MIXED_FLEXIBLE 0
 #define MLBLUP_MIXED_RELIABLE 1
 
-/* Matern covariance sigma2 * phi(r; nu, rho), Definition in Sec. 3.1 with the
- * half-integer closed forms (nu = 1/2, 3/2, 5/2), rho > 0, sigma2 > 0. */
+/* Matern covariance sigma2 * phi(r; nu, rho), Definition in Sec. 3.1, rho > 0,
+ * sigma2 > 0, z = sqrt(2 nu) r / rho:
+ *   nu = 1/2, 3/2, 5/2: the half-integer closed forms, every precision and output;
+ *   nu = +INFINITY: the Gaussian exp(-r^2 / (2 rho^2)) (the Definition's limit;
+ *     the kernel of the accuracy experiment in Sec. 8), every precision and output;
+ *   any other 0 < nu <= 8: FP64 values from a series at the origin and tables
+ *     (entries below 1e-18 sigma2 dropped); no derivative, no low precision, no
+ *     preconditioner (EINVAL). */
 typedef struct {
   double nu;
   double rho;
