@@ -88,24 +88,36 @@ def test_empty_inputs():
     assert y.numel() == 0
 
 
-@pytest.mark.parametrize("k", [2, 4])
+@pytest.mark.parametrize("k", [2, 3, 4, 5])
 def test_full_size_sampled_rows(k):
-    """Full-size square product (the launch the solve uses) checked on 48
+    """Every workload at full size, in the launches the solve and the bench
+    use: the square product on the tree-ordered points in every precision
+    that applies to the workload, and the FP64 target product, checked on
     sampled rows computed one by one by the oracle."""
     torch = require_gpu()
-    from paper_1701_00285_amd import FP32, FP64, cov_matvec
-    wl = synth.make_config(k, with_z=False, n_targets=1)
-    pts = wl.points
+    from paper_1701_00285_amd import FP32, FP64, MFMA_BF16X3, MFMA_FP32, Tree, cov_matvec
+    wl = synth.make_config(k, with_z=False)
+    pts = wl.points[Tree(wl.points, wl.leaf_max).perm]
     x = synth.standard_normal(wl.n, 77)
-    idx = np.random.default_rng(0).choice(wl.n, 48, replace=False)
-    say(f"pair full size cfg{k} n={wl.n}")
+    nrow = 32 if wl.n <= 600_000 else 12   # the oracle's rows stay within seconds
+    idx = np.random.default_rng(k).choice(wl.n, nrow, replace=False)
+    say(f"pair full size cfg{k} n={wl.n} d={wl.d}")
     ref = brute.cov_matvec(pts[idx], pts, x, wl.nu, wl.rho)
     sc = _scale(pts[idx], pts, x, wl.nu, wl.rho)
     P, X = dev(pts), dev(x)
-    y, _ = cov_matvec(P, P, X, wl.nu, wl.rho, precision=FP64)
-    assert row_relerr(host(y)[idx], ref, sc) < FP64_TOL
-    y, _ = cov_matvec(P, P, X, wl.nu, wl.rho, precision=FP32)
-    assert row_relerr(host(y)[idx], ref, sc) < FP32_TOL
+    precs = [(FP64, FP64_TOL), (FP32, FP32_TOL)]
+    if 8 <= wl.d <= 32:
+        precs += [(MFMA_FP32, 2e-5), (MFMA_BF16X3, 3e-4)]
+    for prec, tol in precs:
+        y, _ = cov_matvec(P, P, X, wl.nu, wl.rho, precision=prec)
+        err = row_relerr(host(y)[idx], ref, sc)
+        say(f"  precision={prec}: max row error {err:.2e}")
+        assert err < tol, prec
+    it = np.random.default_rng(k + 10).choice(wl.targets.shape[0], nrow // 2, replace=False)
+    tref = brute.cov_matvec(wl.targets[it], pts, x, wl.nu, wl.rho)
+    tsc = _scale(wl.targets[it], pts, x, wl.nu, wl.rho)
+    yt, _ = cov_matvec(dev(wl.targets), P, X, wl.nu, wl.rho, precision=FP64)
+    assert row_relerr(host(yt)[it], tref, tsc) < FP64_TOL
 
 
 @pytest.mark.parametrize("n,d", [(16384, 3), (16385, 5), (16897, 3), (17408, 5), (16385, 10), (16896, 20)])
