@@ -53,8 +53,11 @@ int64_t pair_workspace_bytes(int64_t m, int64_t n, int32_t d, int32_t precision,
 // Symmetric square product (pair_sym.hip): each unordered pair once.
 // tile launcher of a symmetric schedule: (T blocks, first round, rounds, diagonal?, partial buffers)
 using SymTileLaunch = std::function<void(int, int, int, int, double*, double*, double*, double*)>;
-// deterministic tournament schedule over blocks of blk_pts points (pair_sym.hip)
-int sym_schedule(const PairArgs& a, int blk_pts, void* work, hipStream_t s, const SymTileLaunch& fn);
+// deterministic tournament schedule over blocks of blk_pts points (pair_sym.hip);
+// rows_summed: the off-diagonal launches write one row partial for all their
+// rounds (slot 0) instead of one per round
+int sym_schedule(const PairArgs& a, int blk_pts, void* work, hipStream_t s, const SymTileLaunch& fn,
+                 bool rows_summed = false);
 bool sym_supported(int d);
 bool sym_worthwhile(int64_t n);
 int64_t sym_workspace_bytes(int64_t n, int outputs);

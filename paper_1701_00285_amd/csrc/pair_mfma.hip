@@ -469,6 +469,330 @@ __global__ __launch_bounds__(kT) void mfma_sym_kernel(const double* __restrict__
     }
 }
 
+// Off-diagonal rounds on the matrix cores.  A workgroup keeps row block S
+// (4 waves x kSymRT row tiles of 16) in registers for all the rounds of a
+// launch and streams the column blocks (S + r) mod T through LDS, kRChunk
+// columns at a time.  The Gram is augmented so that the matrix cores return
+// the squared distance itself: rows carry (a, |a|^2, 1) and columns
+// (-2 b, 1, |b|^2) in the coordinates k < d, k = d and k = d + 1 (so
+// d + 2 <= KP).  The Gram of the next 16-column tile is issued between the
+// kernel values of the current one (scheduling groups of one MFMA and a few
+// VALU instructions), so that one wave keeps the matrix core and the vector
+// ALU busy at the same time.  Row sums: FP32 within a round (16 columns per
+// lane), FP64 across rounds (reduced over the 16 column lanes at the end), one row
+// partial per launch.  Column partials: one per round, as in the other
+// symmetric kernels.  Workgroups are dealt to the 8
+// XCDs in turn; the row blocks are numbered so that each XCD takes a
+// contiguous range of them, whose column blocks overlap (shared L2).
+constexpr int kRChunk = 128;
+constexpr int kRTiles = kRChunk / 16;
+constexpr int kChunksPerRound = kSymBlk / kRChunk;
+
+template <int KP, int NU2, bool BF>
+__global__ __launch_bounds__(kT, 2) void mfma_rounds_kernel(const double* __restrict__ pts,
+                                                            const double* __restrict__ x, int64_t n, int d, int T,
+                                                            int round0, int nr, double zs, double* __restrict__ prow,
+                                                            double* __restrict__ pcol) {
+  constexpr int KT = BF ? KP / 16 : KP / 4;  // k steps of one Gram
+  constexpr int KH = KP / 2;                 // coordinates per staging thread (two threads per column)
+  // column operands by k step: FP32 [KT][kRChunk][4], BF16 hi / lo [KT][kRChunk][16]
+  __shared__ __attribute__((aligned(16))) float cf[BF ? 4 : KT * kRChunk * 4];
+  __shared__ __attribute__((aligned(16))) unsigned short chi[BF ? KT * kRChunk * 16 : 8];
+  __shared__ __attribute__((aligned(16))) unsigned short clo[BF ? KT * kRChunk * 16 : 8];
+  __shared__ double cx[kRChunk];
+  __shared__ float csum[4][4][kRChunk];  // column partials per (wave, row group)
+  __shared__ double ctr[32];
+  int S;
+  {
+    const int b = (int)blockIdx.x, q = T / 8, rem = T % 8, xcd = b % 8;
+    S = xcd * q + (xcd < rem ? xcd : rem) + b / 8;
+  }
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int64_t rb = (int64_t)S * kSymBlk;
+  {
+    int64_t ci = rb + kSymBlk / 2;
+    if (ci >= n) ci = n - 1;
+    if (tid < d) ctr[tid] = pts[ci * d + tid] * zs;
+  }
+  __syncthreads();
+  // row operands (a, |a|^2, 1); lane l holds row l mod 16 of each row tile
+  float af[BF ? 1 : kSymRT][BF ? 1 : KT];
+  s4 ahi[BF ? kSymRT : 1][BF ? KT : 1], alo[BF ? kSymRT : 1][BF ? KT : 1];
+  float xr[kSymRT][4];
+#pragma unroll
+  for (int rt = 0; rt < kSymRT; ++rt) {
+    const int64_t i0 = rb + wave * (16 * kSymRT) + rt * 16 + lr;
+    const int64_t ia = i0 < n ? i0 : n - 1;
+    float part = 0.0f;
+    if constexpr (!BF) {
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        const int k = 4 * t + lg;
+        af[rt][t] = k < d ? (float)(pts[ia * d + k] * zs - ctr[k]) : 0.0f;
+        part = fmaf(af[rt][t], af[rt][t], part);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < KT; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = 16 * t + 4 * lg + e;
+          const float v = k < d ? (float)(pts[ia * d + k] * zs - ctr[k]) : 0.0f;
+          const unsigned short h = bf16_rne(v);
+          const unsigned short l = bf16_rne(v - bf16_to_f(h));
+          ahi[rt][t][e] = (short)h;
+          alo[rt][t][e] = (short)l;
+          const float vv = bf16_to_f(h) + bf16_to_f(l);
+          part = fmaf(vv, vv, part);
+        }
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);  // |a|^2 of row lr
+    if constexpr (!BF) {
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        const int k = 4 * t + lg;
+        if (k == d) af[rt][t] = part;
+        if (k == d + 1) af[rt][t] = 1.0f;
+      }
+    } else {
+      const unsigned short nh = bf16_rne(part), nl = bf16_rne(part - bf16_to_f(nh));
+#pragma unroll
+      for (int t = 0; t < KT; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = 16 * t + 4 * lg + e;
+          if (k == d) {
+            ahi[rt][t][e] = (short)nh;
+            alo[rt][t][e] = (short)nl;
+          }
+          if (k == d + 1) {
+            ahi[rt][t][e] = (short)0x3F80;  // 1.0
+            alo[rt][t][e] = 0;
+          }
+        }
+    }
+    const float xa = i0 < n ? (float)x[i0] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) xr[rt][r] = __shfl(xa, 4 * lg + r, 64);
+  }
+  // rounds this block takes part in: in the half round (2 r = T, the last
+  // round of all) the blocks S >= T/2 have no partner
+  int nq = nr;
+  if ((T % 2 == 0) && (2 * (round0 + nr - 1) == T) && S >= T / 2) --nq;
+  const int nchunks = nq * kChunksPerRound;
+  auto colbase = [&](int u) -> int64_t {
+    const int rr = round0 + u / kChunksPerRound;
+    return (int64_t)((S + rr) % T) * kSymBlk + (int64_t)(u % kChunksPerRound) * kRChunk;
+  };
+  const int sj = tid >> 1, sh = tid & 1;
+  double pre[KH];
+  double prex = 0.0;
+  auto fetch = [&](int u) {
+    const int64_t gj = colbase(u) + sj;
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int kk = sh * KH + k;
+      pre[k] = (gj < n && kk < d) ? pts[gj * d + kk] : 0.0;
+    }
+    prex = (gj < n && sh == 0) ? x[gj] : 0.0;
+  };
+  // (-2 b, 1, |b|^2) of column sj into LDS
+  auto stage = [&]() {
+    float v[KH];
+    float part = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int kk = sh * KH + k;
+      v[k] = kk < d ? (float)(pre[k] * zs - ctr[kk]) : 0.0f;
+      if constexpr (BF) {
+        const unsigned short h = bf16_rne(v[k]);
+        v[k] = bf16_to_f(h) + bf16_to_f(bf16_rne(v[k] - bf16_to_f(h)));
+      }
+      part = fmaf(v[k], v[k], part);
+    }
+    part += __shfl_xor(part, 1, 64);  // the column's two staging threads are adjacent lanes
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int kk = sh * KH + k;
+      if constexpr (!BF) {
+        const float b = kk < d ? -2.0f * v[k] : (kk == d ? 1.0f : (kk == d + 1 ? part : 0.0f));
+        cf[((kk >> 2) * kRChunk + sj) * 4 + (kk & 3)] = b;
+      } else {
+        unsigned short h = 0, l = 0;
+        if (kk < d) {
+          const unsigned short vh = bf16_rne(v[k]);
+          h = bf16_rne(-2.0f * bf16_to_f(vh));  // exact
+          l = bf16_rne(-2.0f * (v[k] - bf16_to_f(vh)));
+        } else if (kk == d) {
+          h = 0x3F80;
+        } else if (kk == d + 1) {
+          h = bf16_rne(part);
+          l = bf16_rne(part - bf16_to_f(h));
+        }
+        const int o = ((kk >> 4) * kRChunk + sj) * 16 + (kk & 15);
+        chi[o] = h;
+        clo[o] = l;
+      }
+    }
+    if (sh == 0) cx[sj] = prex;
+  };
+  auto gram = [&](int tile, f4 (&gg)[kSymRT]) {
+    const int jc = tile * 16 + lr;
+#pragma unroll
+    for (int rt = 0; rt < kSymRT; ++rt) gg[rt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (!BF) {
+      float bf[KT];
+#pragma unroll
+      for (int t = 0; t < KT; ++t) bf[t] = cf[(t * kRChunk + jc) * 4 + lg];
+#pragma unroll
+      for (int t = 0; t < KT; ++t)
+#pragma unroll
+        for (int rt = 0; rt < kSymRT; ++rt) gg[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[rt][t], bf[t], gg[rt], 0, 0, 0);
+    } else {
+      s4 bh[KT], bl[KT];
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        const int o = (t * kRChunk + jc) * 16 + 4 * lg;
+        bh[t] = *reinterpret_cast<const s4*>(&chi[o]);
+        bl[t] = *reinterpret_cast<const s4*>(&clo[o]);
+      }
+#pragma unroll
+      for (int t = 0; t < KT; ++t)
+#pragma unroll
+        for (int rt = 0; rt < kSymRT; ++rt) {
+          gg[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[rt][t], bh[t], gg[rt], 0, 0, 0);
+          gg[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[rt][t], bl[t], gg[rt], 0, 0, 0);
+          gg[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo[rt][t], bh[t], gg[rt], 0, 0, 0);
+        }
+    }
+  };
+  float rs[kSymRT][4];
+#pragma unroll
+  for (int rt = 0; rt < kSymRT; ++rt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rs[rt][r] = 0.0f;
+  auto values = [&](int tile, const f4 (&gg)[kSymRT]) {
+    const int jc = tile * 16 + lr;
+    const float xc = (float)cx[jc];
+    float cp0 = 0.0f, cp1 = 0.0f;
+#pragma unroll
+    for (int rt = 0; rt < kSymRT; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float ph, unused;
+        // |s|: a squared distance below zero is rounding of a near pair (free source modifier)
+        pair_value_w<NU2, 1>(__builtin_amdgcn_sqrtf(fabsf(gg[rt][r])), ph, unused);
+        rs[rt][r] = fmaf(ph, xc, rs[rt][r]);
+        if (r & 1) cp1 = fmaf(ph, xr[rt][r], cp1);
+        else cp0 = fmaf(ph, xr[rt][r], cp0);
+      }
+    csum[wave][lg][jc] = cp0 + cp1;
+  };
+  // one MFMA, then a few VALU instructions, for every MFMA of the next tile's Gram
+  constexpr int kMfma = BF ? 3 * KT * kSymRT : KT * kSymRT;
+  constexpr int kValu = 16 * (NU2 == 1 ? 5 : (NU2 == 3 ? 7 : 8)) + 4;
+  constexpr int kValuPer = (kValu + kMfma - 1) / kMfma;
+  auto interleave = [&]() {
+    __builtin_amdgcn_sched_group_barrier(0x100, BF ? 2 * KT : KT, 0);
+#pragma unroll
+    for (int i = 0; i < kMfma; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, kValuPer, 0);
+    }
+  };
+  double racc[kSymRT][4];
+#pragma unroll
+  for (int rt = 0; rt < kSymRT; ++rt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) racc[rt][r] = 0.0;
+  if (nchunks > 0) fetch(0);
+  for (int u = 0; u < nchunks; ++u) {
+    if (u > 0) __syncthreads();  // the previous chunk's operands and column partials have been read
+    stage();
+    __syncthreads();
+    if (u + 1 < nchunks) fetch(u + 1);
+    f4 ga[kSymRT], gb[kSymRT];
+    gram(0, ga);
+#pragma unroll 1
+    for (int tile = 0; tile < kRTiles - 2; tile += 2) {
+      gram(tile + 1, gb);
+      values(tile, ga);
+      interleave();
+      gram(tile + 2, ga);
+      values(tile + 1, gb);
+      interleave();
+    }
+    gram(kRTiles - 1, gb);
+    values(kRTiles - 2, ga);
+    interleave();
+    values(kRTiles - 1, gb);
+    if (u % kChunksPerRound == kChunksPerRound - 1) {
+      // round done: the FP32 row sums (16 columns per lane) go to FP64
+#pragma unroll
+      for (int rt = 0; rt < kSymRT; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          racc[rt][r] += (double)rs[rt][r];
+          rs[rt][r] = 0.0f;
+        }
+    }
+    __syncthreads();
+    if (tid < kRChunk) {
+      const int64_t gj = colbase(u) + tid;
+      if (gj < n) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+#pragma unroll
+          for (int g = 0; g < 4; ++g) t += (double)csum[w][g][tid];
+        pcol[(int64_t)(u / kChunksPerRound) * n + gj] = t;
+      }
+    }
+  }
+  // row sums: reduce over the 16 column lanes of each row group
+#pragma unroll
+  for (int rt = 0; rt < kSymRT; ++rt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double v = racc[rt][r];
+      v += __shfl_xor(v, 1, 64);
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 8, 64);
+      const int64_t i = rb + wave * (16 * kSymRT) + rt * 16 + 4 * lg + r;
+      if (lr == 0 && i < n) prow[i] = v;
+    }
+}
+
+template <int KP, int NU2, bool BF>
+void launch_rounds(const PairArgs& a, double zs, int T, int r0, int nr, double* prow, double* pcol, hipStream_t s) {
+  hipLaunchKernelGGL((mfma_rounds_kernel<KP, NU2, BF>), dim3(T), dim3(kT), 0, s, a.cols, a.x, a.n, a.d, T, r0, nr,
+                     zs * 1.4426950408889634, prow, pcol);
+}
+
+using RoundsFn = void (*)(const PairArgs&, double, int, int, int, double*, double*, hipStream_t);
+
+// the augmented Gram needs d + 2 <= KP
+template <int NU2, bool BF>
+RoundsFn pick_rounds_kp(int d) {
+  if constexpr (BF) {
+    if (d + 2 <= 16) return launch_rounds<16, NU2, true>;
+    if (d + 2 <= 32) return launch_rounds<32, NU2, true>;
+    if (d + 2 <= 48) return launch_rounds<48, NU2, true>;
+  } else {
+    if (d + 2 <= 12) return launch_rounds<12, NU2, false>;
+    if (d + 2 <= 16) return launch_rounds<16, NU2, false>;
+    if (d + 2 <= 20) return launch_rounds<20, NU2, false>;
+    if (d + 2 <= 24) return launch_rounds<24, NU2, false>;
+    if (d + 2 <= 28) return launch_rounds<28, NU2, false>;
+    if (d + 2 <= 32) return launch_rounds<32, NU2, false>;
+    if (d + 2 <= 36) return launch_rounds<36, NU2, false>;
+  }
+  return nullptr;
+}
+
 template <int KP, int NU2, bool BF>
 void launch_sym(const PairArgs& a, double zs, void* work, int T, int r0, int nr, int diag, double* prow, double* pcol,
                 hipStream_t s) {
@@ -543,11 +867,20 @@ int mfma_sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s) {
   if (a.nu2 == 1) fn = bf ? pick_sym_kp<1, true>(a.d) : pick_sym_kp<1, false>(a.d);
   else if (a.nu2 == 3) fn = bf ? pick_sym_kp<3, true>(a.d) : pick_sym_kp<3, false>(a.d);
   else fn = bf ? pick_sym_kp<5, true>(a.d) : pick_sym_kp<5, false>(a.d);
-  if (!fn) return fail(MLBLUP_EINVAL, "matrix-core pair kernel: d > 32");
-  return sym_schedule(a, kSymBlk, work, s,
-                      [&](int T, int r0, int nr, int diag, double* prow, double* pcol, double*, double*) {
-                        fn(a, zs, work, T, r0, nr, diag, prow, pcol, s);
-                      });
+  RoundsFn rfn = nullptr;
+  if (a.nu2 == 1) rfn = bf ? pick_rounds_kp<1, true>(a.d) : pick_rounds_kp<1, false>(a.d);
+  else if (a.nu2 == 3) rfn = bf ? pick_rounds_kp<3, true>(a.d) : pick_rounds_kp<3, false>(a.d);
+  else rfn = bf ? pick_rounds_kp<5, true>(a.d) : pick_rounds_kp<5, false>(a.d);
+  if (!fn || !rfn) return fail(MLBLUP_EINVAL, "matrix-core pair kernel: d > 32");
+  // diagonal tiles: the tile kernel (exact differences on the self sub-tiles); rounds: one launch of
+  // T workgroups per 16 rounds, one row partial per launch
+  return sym_schedule(
+      a, kSymBlk, work, s,
+      [&](int T, int r0, int nr, int diag, double* prow, double* pcol, double*, double*) {
+        if (diag) fn(a, zs, work, T, r0, nr, 1, prow, pcol, s);
+        else rfn(a, zs, T, r0, nr, prow, pcol, s);
+      },
+      true);
 }
 
 int mfma_launch(const PairArgs& a, double zs, double* part, hipStream_t s) {

@@ -289,17 +289,20 @@ __global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ p
 // order); on the last launch y = scale * acc.  acc starts as the diagonal
 // partial.
 __global__ __launch_bounds__(kT) void sym_reduce(const double* __restrict__ prow, const double* __restrict__ pcol,
-                                                 int nr, int64_t n, int T, int round0, int last, double scale,
-                                                 double* __restrict__ acc, double* __restrict__ y, int blk_pts) {
+                                                 int nr, int rows_summed, int64_t n, int T, int round0, int last,
+                                                 double scale, double* __restrict__ acc, double* __restrict__ y,
+                                                 int blk_pts) {
   const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
   if (i >= n) return;
   const int blk = (int)(i / blk_pts);
   double s = acc[i];
+  // one row partial for all the launch's rounds, or one per round
+  if (rows_summed) s += prow[i];
   for (int q = 0; q < nr; ++q) {
     const int r = round0 + q;
     const bool half = (T % 2 == 0) && (2 * r == T);
     // as a row of block blk: absent in the half round for blk >= T/2
-    if (!(half && blk >= T / 2)) s += prow[(int64_t)q * n + i];
+    if (!rows_summed && !(half && blk >= T / 2)) s += prow[(int64_t)q * n + i];
     // as a column: written by block (blk - r) mod T; absent in the half round when that block >= T/2
     const int src = ((blk - r) % T + T) % T;
     if (!(half && src >= T / 2)) s += pcol[(int64_t)q * n + i];
@@ -380,7 +383,8 @@ int64_t sym_workspace_bytes(int64_t n, int outputs) {
   return a * ((outputs & 1 ? 1 : 0) + (outputs & 2 ? 1 : 0));
 }
 
-int sym_schedule(const PairArgs& a, int blk_pts, void* work, hipStream_t s, const SymTileLaunch& fn) {
+int sym_schedule(const PairArgs& a, int blk_pts, void* work, hipStream_t s, const SymTileLaunch& fn,
+                 bool rows_summed) {
   const int64_t n = a.n;
   const int T = (int)((n + blk_pts - 1) / blk_pts);
   const int64_t per = ((int64_t)(2 * kRoundsPerLaunch + 1 + kDiagSplit) * n * 8 + 255) / 256 * 256;
@@ -408,10 +412,11 @@ int sym_schedule(const PairArgs& a, int blk_pts, void* work, hipStream_t s, cons
     if (nr > 0) fn(T, r0, nr, 0, vr, vc, dr, dc);
     const int last = (r0 + nr > rounds) ? 1 : 0;
     if (a.outputs & 1)
-      hipLaunchKernelGGL(sym_reduce, dim3(g), dim3(kT), 0, s, vr, vc, nr, n, T, r0, last, a.sigma2, vd, a.y, blk_pts);
+      hipLaunchKernelGGL(sym_reduce, dim3(g), dim3(kT), 0, s, vr, vc, nr, (rows_summed && nr > 0) ? 1 : 0, n, T, r0, last,
+                         a.sigma2, vd, a.y, blk_pts);
     if (a.outputs & 2)
-      hipLaunchKernelGGL(sym_reduce, dim3(g), dim3(kT), 0, s, dr, dc, nr, n, T, r0, last, a.sigma2, dd, a.dy,
-                         blk_pts);
+      hipLaunchKernelGGL(sym_reduce, dim3(g), dim3(kT), 0, s, dr, dc, nr, (rows_summed && nr > 0) ? 1 : 0, n, T, r0, last,
+                         a.sigma2, dd, a.dy, blk_pts);
     r0 += kRoundsPerLaunch;
   } while (r0 <= rounds);
   return hip_check(hipGetLastError(), "symmetric pair kernel launch");
