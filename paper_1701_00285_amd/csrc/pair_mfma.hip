@@ -15,12 +15,14 @@
 //
 // Fragment layouts of the 16x16 MFMA forms: for 16x16x4 (FP32), lane l
 // supplies A[l%16][l/16] and B[l/16][l%16]; for 16x16x16 (BF16) lane l
-// supplies A[l%16][4(l/16)+e] and B[4(l/16)+e][l%16], e = 0..3; in both the
+// supplies A[l%16][4(l/16)+e] and B[4(l/16)+e][l%16], e = 0..3; for
+// 16x16x32 (BF16) 8 values of k per lane, the same k for A and B; in all the
 // result D[4(l/16)+r][l%16], r = 0..3, sits in the lane's 4 accumulators.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "device.h"
 #include "pairmath.h"
@@ -34,6 +36,15 @@ constexpr int kChunk = 64;   // columns per LDS fill
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// v_mfma_f32_16x16x32_bf16 on BF16 bit patterns: lane l supplies A[l%16][k]
+// and B[k][l%16] for the 8 k of its lane group; A and B use the same k
+// assignment (k = 8 (l/16) + e here), which is all a dot product needs
+__device__ __forceinline__ f4 mfma_bf16_k32(s8 a, s8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
 
 __device__ __forceinline__ unsigned short bf16_rne(float f) {
   unsigned int u = __float_as_uint(f);
@@ -473,35 +484,51 @@ __global__ __launch_bounds__(kT) void mfma_sym_kernel(const double* __restrict__
 // (4 waves x kSymRT row tiles of 16) in registers for all the rounds of a
 // launch and streams the column blocks (S + r) mod T through LDS, kRChunk
 // columns at a time.  The Gram is augmented so that the matrix cores return
-// the squared distance itself: rows carry (a, |a|^2, 1) and columns
-// (-2 b, 1, |b|^2) in the coordinates k < d, k = d and k = d + 1 (so
-// d + 2 <= KP).  The Gram of the next 16-column tile is issued between the
-// kernel values of the current one (scheduling groups of one MFMA and a few
-// VALU instructions), so that one wave keeps the matrix core and the vector
-// ALU busy at the same time.  Row sums: FP32 within a round (16 columns per
-// lane), FP64 across rounds (reduced over the 16 column lanes at the end), one row
-// partial per launch.  Column partials: one per round, as in the other
-// symmetric kernels.  Workgroups are dealt to the 8
-// XCDs in turn; the row blocks are numbered so that each XCD takes a
-// contiguous range of them, whose column blocks overlap (shared L2).
+// the squared distance itself: rows carry (-2 a, |a|^2, 1) and columns
+// (b, 1, |b|^2) in the coordinates k < d, k = d and k = d + 1 (so
+// d + 2 <= KP; the padding k >= d + 2 is zero, written once).  Row sums:
+// FP32 within a round (16 columns per lane), FP64 across rounds (reduced
+// over the 16 column lanes at the end), one row partial per launch.  Column
+// partials: one per round, as in the other symmetric kernels.
+//
+// BF16 x3 uses v_mfma_f32_16x16x32_bf16 when KP is a multiple of 32, else
+// the 16x16x16 form.  These run beside the VALU, so the Gram of the next
+// 16-column tile is issued between the kernel values of the current one
+// (scheduling groups of one MFMA and a few VALU instructions).  FP32 MFMAs
+// hold the VALU while they run; the same order costs nothing there.
+//
+// Workgroups are dealt to the 8 XCDs in turn; the row blocks are numbered so
+// that each XCD takes a contiguous range of them, whose column blocks
+// overlap (shared L2).
 constexpr int kRChunk = 128;
 constexpr int kRTiles = kRChunk / 16;
 constexpr int kChunksPerRound = kSymBlk / kRChunk;
+
+template <int KP, bool BF>
+struct RoundsShape {
+  static constexpr int KW = BF ? (KP % 32 == 0 ? 32 : 16) : 4;  // k per MFMA
+  static constexpr int KT = KP / KW;                            // k steps of one Gram
+  static constexpr int KE = KW / 4;                             // k per lane and step
+  static constexpr int KH = KP / 2;                             // coordinates per staging thread
+};
 
 template <int KP, int NU2, bool BF>
 __global__ __launch_bounds__(kT, 2) void mfma_rounds_kernel(const double* __restrict__ pts,
                                                             const double* __restrict__ x, int64_t n, int d, int T,
                                                             int round0, int nr, double zs, double* __restrict__ prow,
                                                             double* __restrict__ pcol) {
-  constexpr int KT = BF ? KP / 16 : KP / 4;  // k steps of one Gram
-  constexpr int KH = KP / 2;                 // coordinates per staging thread (two threads per column)
-  // column operands by k step: FP32 [KT][kRChunk][4], BF16 hi / lo [KT][kRChunk][16]
-  __shared__ __attribute__((aligned(16))) float cf[BF ? 4 : KT * kRChunk * 4];
-  __shared__ __attribute__((aligned(16))) unsigned short chi[BF ? KT * kRChunk * 16 : 8];
-  __shared__ __attribute__((aligned(16))) unsigned short clo[BF ? KT * kRChunk * 16 : 8];
+  using Sh = RoundsShape<KP, BF>;
+  constexpr int KW = Sh::KW, KT = Sh::KT, KE = Sh::KE, KH = Sh::KH;
+  using frag = typename std::conditional<KE == 8, s8, s4>::type;
+  // column operands by k step: [KT][kRChunk][KW] (FP32, or BF16 hi and lo)
+  constexpr int kOps = KT * kRChunk * KW;
+  __shared__ __attribute__((aligned(16))) float cf[BF ? 4 : kOps];
+  __shared__ __attribute__((aligned(16))) unsigned short chi[BF ? kOps : 8];
+  __shared__ __attribute__((aligned(16))) unsigned short clo[BF ? kOps : 8];
   __shared__ double cx[kRChunk];
   __shared__ float csum[4][4][kRChunk];  // column partials per (wave, row group)
   __shared__ double ctr[32];
+  auto op_index = [](int kk, int j) { return ((kk / KW) * kRChunk + j) * KW + (kk % KW); };
   int S;
   {
     const int b = (int)blockIdx.x, q = T / 8, rem = T % 8, xcd = b % 8;
@@ -514,65 +541,66 @@ __global__ __launch_bounds__(kT, 2) void mfma_rounds_kernel(const double* __rest
     int64_t ci = rb + kSymBlk / 2;
     if (ci >= n) ci = n - 1;
     if (tid < d) ctr[tid] = pts[ci * d + tid] * zs;
+    for (int i = tid; i < kOps; i += kT) {
+      if constexpr (BF) {
+        chi[i] = 0;
+        clo[i] = 0;
+      } else {
+        cf[i] = 0.0f;
+      }
+    }
   }
   __syncthreads();
-  // row operands (a, |a|^2, 1); lane l holds row l mod 16 of each row tile
+  // row operands (-2 a, |a|^2, 1); lane l holds row l mod 16 of each row
+  // tile and the k = KE (l / 16) + e of each step
   float af[BF ? 1 : kSymRT][BF ? 1 : KT];
-  s4 ahi[BF ? kSymRT : 1][BF ? KT : 1], alo[BF ? kSymRT : 1][BF ? KT : 1];
+  frag ahi[BF ? kSymRT : 1][BF ? KT : 1], alo[BF ? kSymRT : 1][BF ? KT : 1];
   float xr[kSymRT][4];
 #pragma unroll
   for (int rt = 0; rt < kSymRT; ++rt) {
     const int64_t i0 = rb + wave * (16 * kSymRT) + rt * 16 + lr;
     const int64_t ia = i0 < n ? i0 : n - 1;
     float part = 0.0f;
-    if constexpr (!BF) {
 #pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        const int k = 4 * t + lg;
-        af[rt][t] = k < d ? (float)(pts[ia * d + k] * zs - ctr[k]) : 0.0f;
-        part = fmaf(af[rt][t], af[rt][t], part);
-      }
-    } else {
+    for (int t = 0; t < KT; ++t)
 #pragma unroll
-      for (int t = 0; t < KT; ++t)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int k = 16 * t + 4 * lg + e;
-          const float v = k < d ? (float)(pts[ia * d + k] * zs - ctr[k]) : 0.0f;
-          const unsigned short h = bf16_rne(v);
-          const unsigned short l = bf16_rne(v - bf16_to_f(h));
-          ahi[rt][t][e] = (short)h;
-          alo[rt][t][e] = (short)l;
-          const float vv = bf16_to_f(h) + bf16_to_f(l);
+      for (int e = 0; e < KE; ++e) {
+        const int k = KW * t + KE * lg + e;
+        const float v = k < d ? (float)(pts[ia * d + k] * zs - ctr[k]) : 0.0f;
+        if constexpr (!BF) {
+          af[rt][t] = -2.0f * v;
+          part = fmaf(v, v, part);
+        } else {
+          const __bf16 h = (__bf16)v;
+          const __bf16 l = (__bf16)(v - (float)h);
+          ahi[rt][t][e] = __builtin_bit_cast(short, (__bf16)(-2.0f * (float)h));  // exact
+          alo[rt][t][e] = __builtin_bit_cast(short, (__bf16)(-2.0f * (float)l));
+          const float vv = (float)h + (float)l;
           part = fmaf(vv, vv, part);
         }
-    }
+      }
     part += __shfl_xor(part, 16, 64);
     part += __shfl_xor(part, 32, 64);  // |a|^2 of row lr
-    if constexpr (!BF) {
+    const __bf16 nh = (__bf16)part, nl = (__bf16)(part - (float)nh);
 #pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        const int k = 4 * t + lg;
-        if (k == d) af[rt][t] = part;
-        if (k == d + 1) af[rt][t] = 1.0f;
-      }
-    } else {
-      const unsigned short nh = bf16_rne(part), nl = bf16_rne(part - bf16_to_f(nh));
+    for (int t = 0; t < KT; ++t)
 #pragma unroll
-      for (int t = 0; t < KT; ++t)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int k = 16 * t + 4 * lg + e;
+      for (int e = 0; e < KE; ++e) {
+        const int k = KW * t + KE * lg + e;
+        if constexpr (!BF) {
+          if (k == d) af[rt][t] = part;
+          if (k == d + 1) af[rt][t] = 1.0f;
+        } else {
           if (k == d) {
-            ahi[rt][t][e] = (short)nh;
-            alo[rt][t][e] = (short)nl;
+            ahi[rt][t][e] = __builtin_bit_cast(short, nh);
+            alo[rt][t][e] = __builtin_bit_cast(short, nl);
           }
           if (k == d + 1) {
             ahi[rt][t][e] = (short)0x3F80;  // 1.0
             alo[rt][t][e] = 0;
           }
         }
-    }
+      }
     const float xa = i0 < n ? (float)x[i0] : 0.0f;
 #pragma unroll
     for (int r = 0; r < 4; ++r) xr[rt][r] = __shfl(xa, 4 * lg + r, 64);
@@ -586,55 +614,63 @@ __global__ __launch_bounds__(kT, 2) void mfma_rounds_kernel(const double* __rest
     const int rr = round0 + u / kChunksPerRound;
     return (int64_t)((S + rr) % T) * kSymBlk + (int64_t)(u % kChunksPerRound) * kRChunk;
   };
+  // staging: two adjacent threads per column, thread sh takes the
+  // coordinates kk = 2 k + sh
   const int sj = tid >> 1, sh = tid & 1;
   double pre[KH];
   double prex = 0.0;
   auto fetch = [&](int u) {
+    // columns past n read point n - 1 (their x is 0, their partials are not written)
     const int64_t gj = colbase(u) + sj;
+    const double* src = pts + (gj < n ? gj : n - 1) * d;
 #pragma unroll
     for (int k = 0; k < KH; ++k) {
-      const int kk = sh * KH + k;
-      pre[k] = (gj < n && kk < d) ? pts[gj * d + kk] : 0.0;
+      if (2 * k < d) {  // wave-uniform
+        const int kk = 2 * k + sh;
+        pre[k] = src[kk < d ? kk : d - 1];
+      }
     }
     prex = (gj < n && sh == 0) ? x[gj] : 0.0;
   };
-  // (-2 b, 1, |b|^2) of column sj into LDS
+  // (b, 1, |b|^2) of column sj into LDS
   auto stage = [&]() {
-    float v[KH];
     float part = 0.0f;
 #pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      const int kk = sh * KH + k;
-      v[k] = kk < d ? (float)(pre[k] * zs - ctr[kk]) : 0.0f;
-      if constexpr (BF) {
-        const unsigned short h = bf16_rne(v[k]);
-        v[k] = bf16_to_f(h) + bf16_to_f(bf16_rne(v[k] - bf16_to_f(h)));
+    for (int k = 0; k < KH; k += 2) {
+      if (2 * k >= d) break;  // wave-uniform
+      const int kk0 = 2 * k + sh, kk1 = kk0 + 2;
+      const bool ok0 = kk0 < d, ok1 = kk1 < d;
+      const float v0 = ok0 ? (float)(pre[k] * zs - ctr[kk0]) : 0.0f;
+      const float v1 = ok1 ? (float)(pre[k + 1] * zs - ctr[kk1]) : 0.0f;
+      if constexpr (!BF) {
+        if (ok0) cf[op_index(kk0, sj)] = v0;
+        if (ok1) cf[op_index(kk1, sj)] = v1;
+        part = fmaf(v0, v0, fmaf(v1, v1, part));
+      } else {
+        const __bf16 h0 = (__bf16)v0, h1 = (__bf16)v1;
+        const __bf16 l0 = (__bf16)(v0 - (float)h0), l1 = (__bf16)(v1 - (float)h1);
+        if (ok0) {
+          chi[op_index(kk0, sj)] = __builtin_bit_cast(unsigned short, h0);
+          clo[op_index(kk0, sj)] = __builtin_bit_cast(unsigned short, l0);
+        }
+        if (ok1) {
+          chi[op_index(kk1, sj)] = __builtin_bit_cast(unsigned short, h1);
+          clo[op_index(kk1, sj)] = __builtin_bit_cast(unsigned short, l1);
+        }
+        const float w0 = (float)h0 + (float)l0, w1 = (float)h1 + (float)l1;
+        part = fmaf(w0, w0, fmaf(w1, w1, part));
       }
-      part = fmaf(v[k], v[k], part);
     }
     part += __shfl_xor(part, 1, 64);  // the column's two staging threads are adjacent lanes
-#pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      const int kk = sh * KH + k;
-      if constexpr (!BF) {
-        const float b = kk < d ? -2.0f * v[k] : (kk == d ? 1.0f : (kk == d + 1 ? part : 0.0f));
-        cf[((kk >> 2) * kRChunk + sj) * 4 + (kk & 3)] = b;
-      } else {
-        unsigned short h = 0, l = 0;
-        if (kk < d) {
-          const unsigned short vh = bf16_rne(v[k]);
-          h = bf16_rne(-2.0f * bf16_to_f(vh));  // exact
-          l = bf16_rne(-2.0f * (v[k] - bf16_to_f(vh)));
-        } else if (kk == d) {
-          h = 0x3F80;
-        } else if (kk == d + 1) {
-          h = bf16_rne(part);
-          l = bf16_rne(part - bf16_to_f(h));
-        }
-        const int o = ((kk >> 4) * kRChunk + sj) * 16 + (kk & 15);
-        chi[o] = h;
-        clo[o] = l;
-      }
+    // k = d holds 1, k = d + 1 holds |b|^2: one each for the two threads
+    const int kk = (sh == (d & 1)) ? d : d + 1;
+    if constexpr (!BF) {
+      cf[op_index(kk, sj)] = kk == d ? 1.0f : part;
+    } else {
+      const __bf16 h = kk == d ? (__bf16)1.0f : (__bf16)part;
+      const __bf16 l = kk == d ? (__bf16)0.0f : (__bf16)(part - (float)h);
+      chi[op_index(kk, sj)] = __builtin_bit_cast(unsigned short, h);
+      clo[op_index(kk, sj)] = __builtin_bit_cast(unsigned short, l);
     }
     if (sh == 0) cx[sj] = prex;
   };
@@ -651,20 +687,26 @@ __global__ __launch_bounds__(kT, 2) void mfma_rounds_kernel(const double* __rest
 #pragma unroll
         for (int rt = 0; rt < kSymRT; ++rt) gg[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[rt][t], bf[t], gg[rt], 0, 0, 0);
     } else {
-      s4 bh[KT], bl[KT];
+      frag bh[KT], bl[KT];
 #pragma unroll
       for (int t = 0; t < KT; ++t) {
-        const int o = (t * kRChunk + jc) * 16 + 4 * lg;
-        bh[t] = *reinterpret_cast<const s4*>(&chi[o]);
-        bl[t] = *reinterpret_cast<const s4*>(&clo[o]);
+        const int o = (t * kRChunk + jc) * KW + KE * lg;
+        bh[t] = *reinterpret_cast<const frag*>(&chi[o]);
+        bl[t] = *reinterpret_cast<const frag*>(&clo[o]);
       }
 #pragma unroll
       for (int t = 0; t < KT; ++t)
 #pragma unroll
         for (int rt = 0; rt < kSymRT; ++rt) {
-          gg[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[rt][t], bh[t], gg[rt], 0, 0, 0);
-          gg[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[rt][t], bl[t], gg[rt], 0, 0, 0);
-          gg[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo[rt][t], bh[t], gg[rt], 0, 0, 0);
+          if constexpr (KE == 8) {
+            gg[rt] = mfma_bf16_k32(ahi[rt][t], bh[t], gg[rt]);
+            gg[rt] = mfma_bf16_k32(ahi[rt][t], bl[t], gg[rt]);
+            gg[rt] = mfma_bf16_k32(alo[rt][t], bh[t], gg[rt]);
+          } else {
+            gg[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[rt][t], bh[t], gg[rt], 0, 0, 0);
+            gg[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[rt][t], bl[t], gg[rt], 0, 0, 0);
+            gg[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo[rt][t], bh[t], gg[rt], 0, 0, 0);
+          }
         }
     }
   };
@@ -690,7 +732,6 @@ __global__ __launch_bounds__(kT, 2) void mfma_rounds_kernel(const double* __rest
       }
     csum[wave][lg][jc] = cp0 + cp1;
   };
-  // one MFMA, then a few VALU instructions, for every MFMA of the next tile's Gram
   constexpr int kMfma = BF ? 3 * KT * kSymRT : KT * kSymRT;
   constexpr int kValu = 16 * (NU2 == 1 ? 5 : (NU2 == 3 ? 7 : 8)) + 4;
   constexpr int kValuPer = (kValu + kMfma - 1) / kMfma;
@@ -780,7 +821,7 @@ RoundsFn pick_rounds_kp(int d) {
   if constexpr (BF) {
     if (d + 2 <= 16) return launch_rounds<16, NU2, true>;
     if (d + 2 <= 32) return launch_rounds<32, NU2, true>;
-    if (d + 2 <= 48) return launch_rounds<48, NU2, true>;
+    if (d + 2 <= 64) return launch_rounds<64, NU2, true>;
   } else {
     if (d + 2 <= 12) return launch_rounds<12, NU2, false>;
     if (d + 2 <= 16) return launch_rounds<16, NU2, false>;
