@@ -201,8 +201,8 @@ def main():
     ap.add_argument("--nu", type=float, default=0.0,
                     help="smoothness in place of the workload's (sweep: products only; a nu other than 1/2, 3/2, "
                          "5/2 or +inf has FP64 values only)")
-    ap.add_argument("--mixed", type=int, default=-1, help="precision of the mixed solve (default: FP32 for d<16, "
-                                                          "MFMA FP32 for d>=16)")
+    ap.add_argument("--mixed", type=int, default=-1, help="precision of the mixed solve (default: FP32 for d<8, "
+                                                          "matrix-core BF16 x3 for d>=8)")
     ap.add_argument("--scheme", choices=("flexible", "reliable"), default="flexible",
                     help="mixed-precision scheme: flexible CG around inner solves, or one recurrence with reliable "
                          "updates")
@@ -246,13 +246,13 @@ def main():
         return
 
     import synth
-    from paper_1701_00285_amd import (FP32, FP64, MFMA_FP32, MIXED_FLEXIBLE, MIXED_RELIABLE, PREC_BLOCK, PREC_JACOBI,
-                                      VALUE, PcgOptions, Solver, profile_enable, profile_read)
+    from paper_1701_00285_amd import (FP32, FP64, MFMA_BF16X3, MIXED_FLEXIBLE, MIXED_RELIABLE, PREC_BLOCK,
+                                      PREC_JACOBI, VALUE, PcgOptions, Solver, profile_enable, profile_read)
 
     torch.cuda.set_device(0)
     wl = synth.make_config(a.config, n=a.n or None, n_targets=a.targets or None)
     wname = wl.name if not a.n else f"{wl.name}, generator at n={wl.n}"
-    mixed = a.mixed if a.mixed >= 0 else (FP32 if wl.d < 16 else MFMA_FP32)
+    mixed = a.mixed if a.mixed >= 0 else (FP32 if wl.d < 8 else MFMA_BF16X3)
     scheme = {"flexible": MIXED_FLEXIBLE, "reliable": MIXED_RELIABLE}[a.scheme]
     dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda")
     P, Z, T = dev(wl.points), dev(wl.z), dev(wl.targets)
