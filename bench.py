@@ -190,6 +190,46 @@ def sweep(configs, reps: int = 10, warm: int = 3, nu=None):
                           "transform": res}), flush=True)
 
 
+def loglik_bench(k: int, n: int, reps: int = 3):
+    """Estimator path: l_n at the finest levels and at level 0 (each the
+    median of `reps` calls after one untimed call, host clock around a call
+    that synchronises), and one golden-section MLE of rho at level t - 1.
+    Flops of one call: the dense Cholesky N~^3/3, the two batched analyses
+    2 sum_cells m^2 (N + N~) and the covariance N^2 pairs."""
+    import time
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1701_00285_amd import Solver
+    torch.cuda.set_device(0)
+    wl = synth.make_config(k, n=n, n_targets=1)
+    s = Solver(wl.points, wl.degree_w, wl.leaf_max, wl.nu, wl.rho, wl.sigma2)
+    z = torch.as_tensor(wl.z, dtype=torch.float64, device="cuda")
+    t = s.basis.levels - 1
+    res = {"workload": f"cfg{k} generator, n={n}, d={wl.d}, nu={wl.nu}, rho={wl.rho}", "levels": {}}
+    for level in (t, t - 1, t - 2, 0):
+        s.loglik(z, level)
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = s.loglik(z, level)
+            times.append(time.perf_counter() - t0)
+        ms = 1e3 * float(np.median(times))
+        nt = out["rows"]
+        res["levels"][str(level)] = {"rows": nt, "ms": round(ms, 3), "loglik": out["loglik"],
+                                    "logdet": out["logdet"], "quad": out["quad"],
+                                    "cholesky_gflop": round(nt ** 3 / 3 / 1e9, 2)}
+        print(f"loglik level {level}: rows {nt}, {ms:.1f} ms", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    m = s.mle_rho(z, t - 1, wl.rho / 10, wl.rho * 10, 1e-4)
+    res["mle_rho_level_t_minus_1"] = {"rho_hat": m["rho"], "loglik": m["loglik"], "evals": m["evals"],
+                                      "s": round(time.perf_counter() - t0, 3), "rho_workload": wl.rho}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +261,9 @@ def main():
     ap.add_argument("--sweep", default="",
                     help="comma-separated workloads: time every precision's product, the target product and W / W^T "
                          "(one JSON line each) instead of the step")
+    ap.add_argument("--loglik", type=int, default=0,
+                    help="estimator: time the multilevel log-likelihood (dense C^n_W, blocked Cholesky) and the "
+                         "rho MLE on this many points of the workload's generator (one JSON line) instead of the step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 512 MiB three times with a plain device copy (reference for HBM counters)")
     a = ap.parse_args()
@@ -234,6 +277,10 @@ def main():
 
     if a.sweep:
         sweep([int(v) for v in a.sweep.split(",")], nu=a.nu or None)
+        return
+
+    if a.loglik:
+        loglik_bench(a.config, a.loglik)
         return
 
     if a.copy_calibration:

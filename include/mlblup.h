@@ -253,6 +253,36 @@ int mlblup_blup_grad(mlblup_basis b, const mlblup_matern* k, const double* z_dev
                      const double* lambda_dev, int32_t precision, double* Q_host, double* dQ_dlogrho_host,
                      void* work_dev, int64_t work_bytes, void* stream);
 
+/* ---- estimator: multilevel log-likelihood (Sec. 3 reduced likelihoods; Sec. 7) ----
+ * For the levels q >= level of W (rows [W_t; ...; W_level], the first
+ * N~ rows of W, finest level first):
+ *   l = -N~/2 log(2 pi) - 1/2 log det C^n_W - 1/2 (Z^n_W)^T (C^n_W)^-1 Z^n_W,
+ * C^n_W = [W_t; ..; W_level] C [W_t; ..; W_level]^T, Z^n_W = [..] z.
+ * C^n_W is formed densely on the device from the N x N covariance and two
+ * batched multilevel analyses, then factorized by a blocked FP64 Cholesky
+ * G G^T = C^n_W: log det = 2 sum log G_ii, the quadratic form = |G^-1 Z^n_W|^2.
+ * (The paper sparsifies C_W with distance rules and uses a sparse Cholesky;
+ * this is the exact dense value.)  Any kernel of mlblup_matern.
+ * z_dev: N data values in tree order.  level: 0 .. levels - 1 (level 0 takes
+ * all of W, where Z^0_W^T (C_W)^-1 Z^0_W is the Q of mlblup_blup_grad).
+ * work_dev: at least the bytes from mlblup_loglik_workspace_bytes, which also
+ * returns N~ in rows (may be NULL); about 8 (N^2 + N~ N) bytes, so N of a few
+ * 10^4.  out3_host = {l, log det C^n_W, quadratic form}.  Synchronises
+ * `stream`.  MLBLUP_EBREAKDOWN if a Cholesky pivot is not positive (C^n_W not
+ * numerically positive definite, e.g. duplicate points). */
+int mlblup_loglik_workspace_bytes(mlblup_basis b, int32_t level, int64_t* bytes, int64_t* rows);
+int mlblup_loglik(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double* out3_host,
+                  void* work_dev, int64_t work_bytes, void* stream);
+/* Maximum-likelihood rho of l at the given level, nu and sigma2 of k fixed
+ * (k->rho is ignored): golden-section search on log rho over
+ * [rho_lo, rho_hi] until the bracket is below log_rho_tol, each step one
+ * mlblup_loglik evaluation (same workspace).  out4_host = {rho_hat,
+ * l(rho_hat), number of evaluations, final bracket width in log rho}.  A
+ * maximum on the boundary of the bracket is returned as found there. */
+int mlblup_mle_rho(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double rho_lo,
+                   double rho_hi, double log_rho_tol, double* out4_host, void* work_dev, int64_t work_bytes,
+                   void* stream);
+
 /* ---- preconditioner (remark on P_W = diag(C_W), Sec. 5.2) -----------------------
  * Built without forming C_W: the leaf kernel blocks and, for each internal
  * cell, the Gram of its children's scaling vectors across the two children

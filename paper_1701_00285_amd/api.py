@@ -279,6 +279,46 @@ class Solver:
         pts = self.basis.points_dev
         return cov_matvec(pts, pts, x_tree, k.nu, k.rho, k.sigma2, precision, outputs)
 
+    # ---- estimator: multilevel log-likelihood ----
+    def loglik_workspace(self, level):
+        """(bytes, N~) of the log-likelihood at `level` (levels >= level of W)."""
+        b, r = C.c_int64(), C.c_int64()
+        check(L.lib().mlblup_loglik_workspace_bytes(self.basis.h, int(level), C.byref(b), C.byref(r)))
+        return b.value, r.value
+
+    def _loglik_ws(self, level):
+        torch = _torch()
+        need, _ = self.loglik_workspace(level)
+        ws = getattr(self, "_llws", None)
+        if ws is None or ws.numel() < need:
+            self._llws = None
+            ws = self._llws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return ws
+
+    def loglik(self, z, level, rho=None, nu=None):
+        """Multilevel log-likelihood of z (input order) at `level`:
+        dict(loglik, logdet, quad, rows=N~)."""
+        k = self.kernel(rho)
+        if nu is not None:
+            k = matern(nu, k.rho, k.sigma2)
+        ws = self._loglik_ws(level)
+        out = np.zeros(3)
+        zt = self.to_tree(z).contiguous()
+        check(L.lib().mlblup_loglik(self.basis.h, C.byref(k), _ptr(zt), int(level), _np_ptr(out), _ptr(ws),
+                                    ws.numel(), _stream()))
+        return dict(loglik=out[0], logdet=out[1], quad=out[2], rows=self.loglik_workspace(level)[1])
+
+    def mle_rho(self, z, level, rho_lo, rho_hi, log_rho_tol=1e-6, nu=None):
+        """Maximum-likelihood rho of the level's log-likelihood (golden
+        section on log rho): dict(rho, loglik, evals, bracket)."""
+        k = matern(self.nu if nu is None else nu, 1.0, self.sigma2)
+        ws = self._loglik_ws(level)
+        out = np.zeros(4)
+        zt = self.to_tree(z).contiguous()
+        check(L.lib().mlblup_mle_rho(self.basis.h, C.byref(k), _ptr(zt), int(level), float(rho_lo), float(rho_hi),
+                                     float(log_rho_tol), _np_ptr(out), _ptr(ws), ws.numel(), _stream()))
+        return dict(rho=out[0], loglik=out[1], evals=int(out[2]), bracket=out[3])
+
     # ---- solve / predict / grad ----
     def solve(self, zw, opts: PcgOptions | None = None, x0=None, rho=None, allow_noconv=False):
         torch = _torch()

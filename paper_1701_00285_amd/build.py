@@ -23,7 +23,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmlblup.so")
 PROBE = os.path.join(PKG, "issue_rates")
 SOURCES = ["tree.cpp", "basis.cpp", "abi.cpp", "precond_host.cpp", "genu.cpp", "ops.hip", "pair.hip", "pair_sym.hip", "precond.hip",
-           "pair_mfma.hip"]
+           "pair_mfma.hip", "loglik.hip"]
 
 
 def hipcc() -> str:

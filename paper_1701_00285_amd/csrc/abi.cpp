@@ -939,4 +939,104 @@ int mlblup_blup_grad(mlblup_basis b, const mlblup_matern* k, const double* z_dev
   return MLBLUP_OK;
 }
 
+int mlblup_loglik_workspace_bytes(mlblup_basis b, int32_t level, int64_t* bytes, int64_t* rows) {
+  clear_error();
+  if (!b || !bytes) return fail(MLBLUP_EINVAL, "NULL argument");
+  if (level < 0 || level >= b->b.levels)
+    return fail(MLBLUP_EINVAL, "loglik: level must be in [0, " + std::to_string(b->b.levels - 1) + "]");
+  const LoglikLayout L = loglik_layout(b->b, level);
+  *bytes = L.total;
+  if (rows) *rows = L.rows;
+  return MLBLUP_OK;
+}
+
+static int loglik_common(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, void* work_dev,
+                         int64_t work_bytes, TransformDev* T, LoglikLayout* L, PairArgs* a) {
+  int st = check_basis_dev(b);
+  if (st) return st;
+  if ((st = check_kernel(k))) return st;
+  const Basis& B = b->b;
+  if (level < 0 || level >= B.levels)
+    return fail(MLBLUP_EINVAL, "loglik: level must be in [0, " + std::to_string(B.levels - 1) + "]");
+  if (!z_dev) return fail(MLBLUP_EINVAL, "loglik: NULL data vector");
+  *L = loglik_layout(B, level);
+  if (!work_dev || work_bytes < L->total)
+    return fail(MLBLUP_EINVAL, "loglik: workspace too small (need " + std::to_string(L->total) + " bytes)");
+  const char* img = (const char*)B.dev_base;
+  T->desc = (const NodeDesc*)(img + B.off_desc);
+  T->level_nodes = (const int32_t*)(img + B.off_levels);
+  T->lvl_begin_host = B.lvl_begin.data();
+  T->levels = B.levels;
+  T->V = (const double*)(img + B.off_V);
+  T->Vt = (const double*)(img + B.off_Vt);
+  *a = PairArgs{nullptr, 0, nullptr, B.n, B.d, nu2_of(k), k->rho, k->sigma2, MLBLUP_FP64, MLBLUP_VALUE,
+                nullptr, nullptr, nullptr, k->nu, nullptr};
+  return MLBLUP_OK;
+}
+
+int mlblup_loglik(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double* out3_host,
+                  void* work_dev, int64_t work_bytes, void* stream) {
+  clear_error();
+  if (!out3_host) return fail(MLBLUP_EINVAL, "loglik: NULL output");
+  TransformDev T;
+  LoglikLayout L;
+  PairArgs a;
+  int st = loglik_common(b, k, z_dev, level, work_dev, work_bytes, &T, &L, &a);
+  if (st) return st;
+  return loglik_device(b->b, T, a, level, z_dev, work_dev, L, out3_host, (hipStream_t)stream);
+}
+
+int mlblup_mle_rho(mlblup_basis b, const mlblup_matern* k0, const double* z_dev, int32_t level, double rho_lo,
+                   double rho_hi, double log_rho_tol, double* out4_host, void* work_dev, int64_t work_bytes,
+                   void* stream) {
+  clear_error();
+  if (!out4_host) return fail(MLBLUP_EINVAL, "mle_rho: NULL output");
+  if (!(rho_lo > 0) || !(rho_hi > rho_lo) || !std::isfinite(rho_hi))
+    return fail(MLBLUP_EINVAL, "mle_rho: need 0 < rho_lo < rho_hi < inf");
+  if (!(log_rho_tol > 0)) return fail(MLBLUP_EINVAL, "mle_rho: log_rho_tol must be > 0");
+  TransformDev T;
+  LoglikLayout L;
+  PairArgs a;
+  int st = loglik_common(b, k0, z_dev, level, work_dev, work_bytes, &T, &L, &a);
+  if (st) return st;
+  int evals = 0;
+  auto f = [&](double lr, double* v) {
+    PairArgs q = a;
+    q.rho = std::exp(lr);
+    double out[3];
+    const int s2 = loglik_device(b->b, T, q, level, z_dev, work_dev, L, out, (hipStream_t)stream);
+    ++evals;
+    *v = out[0];
+    return s2;
+  };
+  // golden-section search for the maximum of l_n on [log rho_lo, log rho_hi]
+  const double g = 0.6180339887498949;
+  double lo = std::log(rho_lo), hi = std::log(rho_hi);
+  double x1 = hi - g * (hi - lo), x2 = lo + g * (hi - lo), f1, f2;
+  if ((st = f(x1, &f1)) || (st = f(x2, &f2))) return st;
+  while (hi - lo > log_rho_tol) {
+    if (f1 >= f2) {
+      hi = x2;
+      x2 = x1;
+      f2 = f1;
+      x1 = hi - g * (hi - lo);
+      if ((st = f(x1, &f1))) return st;
+    } else {
+      lo = x1;
+      x1 = x2;
+      f1 = f2;
+      x2 = lo + g * (hi - lo);
+      if ((st = f(x2, &f2))) return st;
+    }
+  }
+  const double lr = 0.5 * (lo + hi);
+  double fm;
+  if ((st = f(lr, &fm))) return st;
+  out4_host[0] = std::exp(lr);
+  out4_host[1] = fm;
+  out4_host[2] = (double)evals;
+  out4_host[3] = hi - lo;
+  return MLBLUP_OK;
+}
+
 }  // extern "C"

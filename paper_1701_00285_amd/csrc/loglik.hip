@@ -1,0 +1,452 @@
+// Multilevel log-likelihood of the partial transform (Sec. 3, the reduced
+// likelihoods after the Proposition on nested condition numbers):
+//
+//   l_n(theta) = -N~/2 log(2 pi) - 1/2 log det C^n_W - 1/2 (Z^n_W)^T (C^n_W)^-1 Z^n_W,
+//
+// with Z^n_W = [W_t; ...; W_n] Z (the first N~ rows of W, finest level
+// first) and C^n_W the leading N~ x N~ block of C_W = W C W^T.  The
+// determinant and the quadratic form come from one Cholesky factor G of
+// C^n_W (Sec. 7, estimator computation): log det = 2 sum log G_ii, and the
+// quadratic form is |y|^2 with G y = Z^n_W.
+//
+// Device steps (all FP64):
+//  1. Phi = sigma^2 phi(|x_i - x_j|), N x N, row-major (dense_cov);
+//  2. A = (W Phi) restricted to the first N~ rows: the multilevel analysis
+//     applied to column blocks of Phi, level by level from the finest to n
+//     (batched_analysis: one workgroup per cell and 256 columns);
+//  3. A^T (tiled transpose), then C^n_W = (W A^T) restricted to N~ rows;
+//  4. blocked right-looking Cholesky, blocks of 64 (diagonal factor in LDS,
+//     panel triangular solve, trailing update of the lower triangle);
+//  5. G y = Z^n_W by block forward substitution; 2 sum log G_ii and |y|^2 by
+//     fixed-order reductions.
+// The paper factorizes a sparsified C~^n_W with a sparse Cholesky and nested
+// dissection; here C^n_W is dense and exact (288 GB of HBM hold it for N~ up
+// to about 10^5).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "internal.h"
+#include "pairmath.h"
+
+namespace mlb {
+namespace {
+
+constexpr int kT = 256;
+constexpr int kNb = 64;       // Cholesky block
+constexpr int kTr = 32;       // transpose tile
+constexpr int kColBatch = 4096;
+
+// ---- 1. dense covariance -------------------------------------------------------
+template <int NU2>
+__global__ __launch_bounds__(kT) void dense_cov(const double* __restrict__ pts, int64_t n, int d, double zs,
+                                                double sigma2, const double* __restrict__ gtab,
+                                                double* __restrict__ phi) {
+  __shared__ double tab[kExpTab];
+  exp_table_fill(tab);
+  const double* gt = gtab;
+  if constexpr (NU2 == kNuGeneralT) {
+    __shared__ double gsh[kGenuDoubles];
+    const int nd = kGenuOffPoly + (int)gtab[5] * (kGenuDeg + 1);
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) gsh[i] = gtab[i];
+    gt = gsh;
+  }
+  __syncthreads();
+  const int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (j >= n) return;
+  for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
+    double s = 1e-300;  // keeps the self pair away from sqrt(0) in the series branch
+    for (int k = 0; k < d; ++k) {
+      const double t = (pts[i * d + k] - pts[j * d + k]) * zs;
+      s = fma(t, t, s);
+    }
+    double f = 0.0, g = 0.0;
+    pair_value<NU2, 1, false>(s, tab, f, g, gt);
+    phi[i * n + j] = sigma2 * f;
+  }
+}
+
+__global__ void clear_flag(int* __restrict__ flag) {
+  if (threadIdx.x == 0) flag[0] = 0;
+}
+
+// ---- 2./3. batched analysis: Y[rows < ny] = W X for the cells of one level ----
+__global__ __launch_bounds__(kT) void batched_analysis(const NodeDesc* __restrict__ desc,
+                                                       const int32_t* __restrict__ lnodes,
+                                                       const double* __restrict__ V, const double* __restrict__ X,
+                                                       int64_t ldx, double* __restrict__ scal, int64_t lds,
+                                                       double* __restrict__ Y, int64_t ldy, int64_t ny,
+                                                       int64_t ncols) {
+  const NodeDesc D = desc[lnodes[blockIdx.y]];
+  const int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (j >= ncols) return;
+  const double* cin = D.leaf ? X + D.in_off * ldx : scal + D.in_off * lds;
+  const int64_t ldc = D.leaf ? ldx : lds;
+  const double* B = V + D.v_off;
+  const int m = D.m;
+  for (int k0 = 0; k0 < m; k0 += 16) {
+    double acc[16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) acc[kk] = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double c = cin[(int64_t)i * ldc + j];
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk)
+        if (k0 + kk < m) acc[kk] = fma(B[(int64_t)i * m + k0 + kk], c, acc[kk]);
+    }
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = k0 + kk;
+      if (k >= m) break;
+      if (k < D.a) {
+        if (D.scal_off >= 0) scal[(D.scal_off + k) * lds + j] = acc[kk];
+      } else {
+        const int64_t row = D.w_off + (k - D.a);
+        if (row < ny) Y[row * ldy + j] = acc[kk];
+      }
+    }
+  }
+}
+
+// out (cols x rows) = in^T (in: rows x cols)
+__global__ __launch_bounds__(kTr * 8) void transpose(const double* __restrict__ in, int64_t rows, int64_t cols,
+                                                     int64_t ldi, double* __restrict__ out, int64_t ldo) {
+  __shared__ double t[kTr][kTr + 1];
+  const int64_t r0 = (int64_t)blockIdx.y * kTr, c0 = (int64_t)blockIdx.x * kTr;
+  const int tx = threadIdx.x % kTr, ty = threadIdx.x / kTr;
+  for (int r = ty; r < kTr; r += 8) {
+    const int64_t gr = r0 + r, gc = c0 + tx;
+    if (gr < rows && gc < cols) t[r][tx] = in[gr * ldi + gc];
+  }
+  __syncthreads();
+  for (int c = ty; c < kTr; c += 8) {
+    const int64_t gc = c0 + c, gr = r0 + tx;
+    if (gc < cols && gr < rows) out[gc * ldo + gr] = t[tx][c];
+  }
+}
+
+// ---- 4. blocked Cholesky (lower), A is n x n with leading dimension ld --------
+// factor of the diagonal block at k0 (size nb <= kNb) in LDS; a pivot that is
+// not positive and finite sets flag[0] (the factor then continues with 1)
+__global__ __launch_bounds__(kT) void potrf_diag(double* __restrict__ A, int64_t ld, int64_t k0, int nb,
+                                                 int* __restrict__ flag) {
+  __shared__ double a[kNb][kNb + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb * nb; e += kT) {
+    const int r = e / nb, c = e % nb;
+    a[r][c] = c <= r ? A[(k0 + r) * ld + k0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    if (tid == 0) {
+      double p = a[j][j];
+      if (!(p > 0.0) || !__builtin_isfinite(p)) {
+        flag[0] = 1;
+        p = 1.0;
+      }
+      a[j][j] = sqrt(p);
+    }
+    __syncthreads();
+    const double dj = a[j][j];
+    for (int r = j + 1 + tid; r < nb; r += kT) a[r][j] /= dj;
+    __syncthreads();
+    // trailing lower triangle of the block
+    const int rem = nb - j - 1;
+    for (int e = tid; e < rem * rem; e += kT) {
+      const int r = j + 1 + e / rem, c = j + 1 + e % rem;
+      if (c <= r) a[r][c] = fma(-a[r][j], a[c][j], a[r][c]);
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nb * nb; e += kT) {
+    const int r = e / nb, c = e % nb;
+    if (c <= r) A[(k0 + r) * ld + k0 + c] = a[r][c];
+  }
+}
+
+// panel below the diagonal block: rows [k0 + nb, n), columns [k0, k0 + nb):
+// X G_kk^T = B, one 64-row tile per workgroup, one row per thread (64 threads)
+__global__ __launch_bounds__(kNb) void trsm_panel(double* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
+                                                  int nb) {
+  __shared__ double L[kNb][kNb + 1];
+  __shared__ double X[kNb][kNb + 1];
+  const int tid = threadIdx.x;
+  const int64_t r0 = k0 + nb + (int64_t)blockIdx.x * kNb;
+  for (int e = tid; e < nb * nb; e += kNb) {
+    const int r = e / nb, c = e % nb;
+    L[r][c] = c <= r ? A[(k0 + r) * ld + k0 + c] : 0.0;
+  }
+  for (int e = tid; e < kNb * nb; e += kNb) {
+    const int r = e / nb, c = e % nb;
+    X[r][c] = (r0 + r < n) ? A[(r0 + r) * ld + k0 + c] : 0.0;
+  }
+  __syncthreads();
+  if (r0 + tid < n) {
+    for (int l = 0; l < nb; ++l) {
+      double s = X[tid][l];
+      for (int m = 0; m < l; ++m) s = fma(-X[tid][m], L[l][m], s);
+      X[tid][l] = s / L[l][l];
+    }
+    for (int c = 0; c < nb; ++c) A[(r0 + tid) * ld + k0 + c] = X[tid][c];
+  }
+}
+
+// trailing update of the lower triangle: for block rows I >= J after the
+// panel, A[I][J] -= P_I P_J^T with P the panel (K = nb); one 64x64 tile per
+// workgroup, a 4x4 micro-tile per thread
+__global__ __launch_bounds__(kT) void syrk_update(double* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
+                                                  int nb, int64_t nblk) {
+  __shared__ double Pi[kNb][kNb + 2];  // [k][row]
+  __shared__ double Pj[kNb][kNb + 2];
+  // tile index t -> (I, J), J <= I < nblk
+  const int64_t t = blockIdx.x;
+  int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > t) --I;
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  const int64_t J = t - I * (I + 1) / 2;
+  const int64_t base = k0 + nb;
+  const int64_t ri = base + I * kNb, rj = base + J * kNb;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kNb * nb; e += kT) {
+    const int r = e / nb, k = e % nb;
+    Pi[k][r] = (ri + r < n) ? A[(ri + r) * ld + k0 + k] : 0.0;
+    Pj[k][r] = (rj + r < n) ? A[(rj + r) * ld + k0 + k] : 0.0;
+  }
+  __syncthreads();
+  const int tx = tid % 16, ty = tid / 16;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int k = 0; k < nb; ++k) {
+    double x[4], y[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) x[a] = Pi[k][ty * 4 + a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) y[b] = Pj[k][tx * 4 + b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = fma(x[a], y[b], acc[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int64_t r = ri + ty * 4 + a;
+    if (r >= n) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int64_t c = rj + tx * 4 + b;
+      if (c < n && c <= r) A[r * ld + c] -= acc[a][b];
+    }
+  }
+}
+
+// ---- 5. forward substitution and the two reductions ---------------------------
+// diagonal block kb: y_kb = G_kb,kb^-1 b_kb (b already holds the updates of the
+// earlier blocks); one wave
+__global__ __launch_bounds__(kNb) void trsv_diag(const double* __restrict__ A, int64_t ld, int64_t k0, int nb,
+                                                 double* __restrict__ b) {
+  __shared__ double y[kNb];
+  const int tid = threadIdx.x;
+  double v = tid < nb ? b[k0 + tid] : 0.0;
+  for (int l = 0; l < nb; ++l) {
+    if (tid == l) y[l] = v / A[(k0 + l) * ld + k0 + l];
+    __syncthreads();
+    if (tid > l && tid < nb) v = fma(-A[(k0 + tid) * ld + k0 + l], y[l], v);
+    __syncthreads();
+  }
+  if (tid < nb) b[k0 + tid] = y[tid];
+}
+
+// rows below the block: b_i -= G[i, k0:k0+nb] y_kb
+__global__ __launch_bounds__(kT) void gemv_panel(const double* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
+                                                 int nb, double* __restrict__ b) {
+  const int64_t i = k0 + nb + (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  const double* row = A + i * ld + k0;
+  double s = 0.0;
+  for (int l = 0; l < nb; ++l) s = fma(row[l], b[k0 + l], s);
+  b[i] -= s;
+}
+
+// out[0] = 2 sum_i log G_ii, out[1] = sum_i y_i^2 (one workgroup, fixed order)
+__global__ __launch_bounds__(kT) void logdet_quad(const double* __restrict__ A, int64_t ld, int64_t n,
+                                                  const double* __restrict__ y, double* __restrict__ out) {
+  __shared__ double s0[kT], s1[kT];
+  const int tid = threadIdx.x;
+  double a = 0.0, q = 0.0;
+  for (int64_t i = tid; i < n; i += kT) {
+    a += log(A[i * ld + i]);
+    q = fma(y[i], y[i], q);
+  }
+  s0[tid] = a;
+  s1[tid] = q;
+  __syncthreads();
+  for (int w = kT / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      s0[tid] += s0[tid + w];
+      s1[tid] += s1[tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = 2.0 * s0[0];
+    out[1] = s1[0];
+  }
+}
+
+int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+// rows of [W_t; ...; W_n]: wavelets of the cells at depth >= n
+int64_t loglik_rows(const Basis& B, int32_t level) {
+  int64_t r = 0;
+  for (int q = level; q < B.levels; ++q) r += B.level_counts[q];
+  return r;
+}
+
+LoglikLayout loglik_layout(const Basis& B, int32_t level) {
+  LoglikLayout L;
+  const int64_t n = B.n, nt = loglik_rows(B, level);
+  const int64_t batch = std::min<int64_t>(std::max<int64_t>(n, 1), kColBatch);
+  int64_t o = 0;
+  L.phi = o;
+  o += align256(n * n * 8);
+  L.a = o;
+  o += align256(std::max<int64_t>(nt * n, 1) * 8);
+  L.scal = o;
+  o += align256(std::max<int64_t>(B.scal_total, 1) * batch * 8);
+  L.zw = o;
+  o += align256(std::max<int64_t>(n, 1) * 8);
+  L.scalz = o;
+  o += align256(std::max<int64_t>(B.scal_total, 1) * 8);
+  L.out = o;
+  o += 256;
+  L.flag = o;
+  o += 256;
+  L.gtab = o;
+  o += align256(kGenuBytes);
+  L.total = o;
+  L.rows = nt;
+  L.batch = batch;
+  return L;
+}
+
+// W X restricted to the first ny rows for the column range of X (levels B.levels-1 .. level)
+static int analysis_batched(const Basis& B, const TransformDev& T, int32_t level, const double* X, int64_t ldx,
+                            int64_t ncols, double* scal, int64_t batch, double* Y, int64_t ldy, int64_t ny,
+                            hipStream_t s) {
+  for (int64_t c0 = 0; c0 < ncols; c0 += batch) {
+    const int64_t nc = std::min(batch, ncols - c0);
+    for (int q = B.levels - 1; q >= level; --q) {
+      const int32_t lb = B.lvl_begin[q], cnt = B.lvl_begin[q + 1] - lb;
+      if (cnt <= 0) continue;
+      dim3 grid((unsigned)((nc + kT - 1) / kT), (unsigned)cnt);
+      hipLaunchKernelGGL(batched_analysis, grid, dim3(kT), 0, s, T.desc, T.level_nodes + lb, T.V, X + c0, ldx, scal,
+                         batch, Y + c0, ldy, ny, nc);
+    }
+  }
+  return hip_check(hipGetLastError(), "batched analysis launch");
+}
+
+int loglik_device(const Basis& B, const TransformDev& T, const PairArgs& k, int32_t level, const double* z,
+                  void* work, const LoglikLayout& L, double out[3], hipStream_t s) {
+  char* w = (char*)work;
+  double* phi = (double*)(w + L.phi);
+  double* A = (double*)(w + L.a);
+  double* scal = (double*)(w + L.scal);
+  double* zw = (double*)(w + L.zw);
+  double* scalz = (double*)(w + L.scalz);
+  double* dout = (double*)(w + L.out);
+  int* flag = (int*)(w + L.flag);
+  const int64_t n = B.n, nt = L.rows;
+  const double* pts = (const double*)((const char*)B.dev_base + B.off_pts);
+  const double zs = kernel_scale(k.nu2, k.nu, k.rho);
+  const double* gt = nullptr;
+  if (k.nu2 == kNuGeneral) {
+    const double* host = genu_table_cached(k.nu);
+    if (!host) return fail(MLBLUP_EINVAL, "loglik: nu out of range for the general-nu table");
+    double* dev = (double*)(w + L.gtab);
+    MLB_HIP(hipMemcpyAsync(dev, host, kGenuBytes, hipMemcpyHostToDevice, s));
+    gt = dev;
+  }
+  hipLaunchKernelGGL(clear_flag, dim3(1), dim3(64), 0, s, flag);
+  // 1. Phi
+  {
+    dim3 grid((unsigned)((n + kT - 1) / kT), (unsigned)std::min<int64_t>(n, 65535));
+    switch (k.nu2) {
+      case 0: hipLaunchKernelGGL(dense_cov<0>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
+      case 1: hipLaunchKernelGGL(dense_cov<1>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
+      case 3: hipLaunchKernelGGL(dense_cov<3>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
+      case 5: hipLaunchKernelGGL(dense_cov<5>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
+      default:
+        hipLaunchKernelGGL(dense_cov<kNuGeneralT>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi);
+    }
+    int st = hip_check(hipGetLastError(), "dense covariance launch");
+    if (st) return st;
+  }
+  // Z^n_W: the first N~ entries of W z
+  int st = transform_analysis(T, z, zw, nullptr, scalz, s);
+  if (st) return st;
+  if (nt == 0) {
+    out[0] = out[1] = 0.0;
+    out[2] = 0.0;
+    return MLBLUP_OK;
+  }
+  // 2. A = (W Phi)[0:N~, :]
+  if ((st = analysis_batched(B, T, level, phi, n, n, scal, L.batch, A, n, nt, s))) return st;
+  // 3. A^T into Phi's storage (N x N~), then C^n_W = (W A^T)[0:N~, :] into A's storage (ld N~)
+  {
+    dim3 grid((unsigned)((n + kTr - 1) / kTr), (unsigned)((nt + kTr - 1) / kTr));
+    hipLaunchKernelGGL(transpose, grid, dim3(kTr * 8), 0, s, A, nt, n, n, phi, nt);
+    if ((st = hip_check(hipGetLastError(), "transpose launch"))) return st;
+  }
+  double* C = A;
+  if ((st = analysis_batched(B, T, level, phi, nt, nt, scal, L.batch, C, nt, nt, s))) return st;
+  // 4. Cholesky
+  const int64_t nblk = (nt + kNb - 1) / kNb;
+  for (int64_t kb = 0; kb < nblk; ++kb) {
+    const int64_t k0 = kb * kNb;
+    const int nb = (int)std::min<int64_t>(kNb, nt - k0);
+    hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(kT), 0, s, C, nt, k0, nb, flag);
+    const int64_t below = nt - k0 - nb;
+    if (below > 0) {
+      const int64_t tiles = (below + kNb - 1) / kNb;
+      hipLaunchKernelGGL(trsm_panel, dim3((unsigned)tiles), dim3(kNb), 0, s, C, nt, nt, k0, nb);
+      hipLaunchKernelGGL(syrk_update, dim3((unsigned)(tiles * (tiles + 1) / 2)), dim3(kT), 0, s, C, nt, nt, k0, nb,
+                         tiles);
+    }
+  }
+  if ((st = hip_check(hipGetLastError(), "Cholesky launch"))) return st;
+  // 5. G y = Z^n_W (in place in zw), then the reductions
+  for (int64_t kb = 0; kb < nblk; ++kb) {
+    const int64_t k0 = kb * kNb;
+    const int nb = (int)std::min<int64_t>(kNb, nt - k0);
+    hipLaunchKernelGGL(trsv_diag, dim3(1), dim3(kNb), 0, s, C, nt, k0, nb, zw);
+    const int64_t below = nt - k0 - nb;
+    if (below > 0)
+      hipLaunchKernelGGL(gemv_panel, dim3((unsigned)((below + kT - 1) / kT)), dim3(kT), 0, s, C, nt, nt, k0, nb, zw);
+  }
+  hipLaunchKernelGGL(logdet_quad, dim3(1), dim3(kT), 0, s, C, nt, nt, zw, dout);
+  if ((st = hip_check(hipGetLastError(), "forward substitution launch"))) return st;
+  double host[2];
+  int hflag = 0;
+  MLB_HIP(hipMemcpyAsync(host, dout, sizeof(host), hipMemcpyDeviceToHost, s));
+  MLB_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  MLB_HIP(hipStreamSynchronize(s));
+  if (hflag) return fail(MLBLUP_EBREAKDOWN, "loglik: C^n_W is not numerically positive definite");
+  const double kLog2Pi = 1.8378770664093453;
+  out[1] = host[0];
+  out[2] = host[1];
+  out[0] = -0.5 * ((double)nt * kLog2Pi + host[0] + host[1]);
+  return MLBLUP_OK;
+}
+
+}  // namespace mlb

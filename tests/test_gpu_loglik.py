@@ -1,0 +1,98 @@
+"""Multilevel log-likelihood and its maximum in rho on the GPU against the
+oracle (dense C^n_W from the oracle's SVD basis, numpy Cholesky).  The two
+bases differ by rotations inside the cells, under which l_n is invariant."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import dev, require_gpu, say
+from helpers import workload
+from oracle import likelihood as OL
+from oracle.basis import build_basis
+from oracle.kdtree import build_kdtree
+from oracle.matern import cov_matrix
+
+pytestmark = pytest.mark.gpu
+
+
+def _both(k, n, nu=None):
+    from paper_1701_00285_amd import Solver
+    wl = workload(k, n=n, n_targets=1)
+    nu = wl.nu if nu is None else nu
+    tree = build_kdtree(wl.points, wl.leaf_max)
+    bas = build_basis(wl.points, tree, wl.degree_w)
+    s = Solver(wl.points, wl.degree_w, wl.leaf_max, nu, wl.rho, wl.sigma2)
+    return wl, nu, tree, bas, s
+
+
+def _cond(wl, nu, bas, nt):
+    C = cov_matrix(wl.points, wl.points, nu, wl.rho)
+    ev = np.linalg.eigvalsh(bas.W[:nt] @ C @ bas.W[:nt].T)
+    return ev[-1] / ev[0]
+
+
+@pytest.mark.parametrize("k,n,nu", [(1, 1000, None), (2, 900, None), (4, 700, None), (2, 650, 1.25), (1, 777, 1.5)])
+def test_loglik_matches_oracle(k, n, nu):
+    require_gpu()
+    wl, nu, tree, bas, s = _both(k, n, nu)
+    Z = dev(wl.z)
+    t = tree.max_depth
+    for level in sorted({t, t - 1, 1, 0}, reverse=True):
+        g = s.loglik(Z, level)
+        o = OL.multilevel_loglik(wl.points, wl.z, nu, wl.rho, bas, level)
+        kap = _cond(wl, nu, bas, o[3])
+        # backward-stable factorizations of C^n_W from two bases: errors of
+        # order kappa u in the quadratic form, N~ kappa u in log det (absolute)
+        tq = max(1e-12, 50 * kap * 2.2e-16)
+        td = max(1e-12, 50 * kap * 2.2e-16) * o[3]
+        say(f"loglik cfg{k} n={n} nu={nu} level={level} rows={g['rows']} kappa={kap:.1e} "
+            f"dlogdet={abs(g['logdet'] - o[1]):.1e} dquad={abs(g['quad'] - o[2]) / abs(o[2]):.1e}")
+        assert g["rows"] == o[3]
+        assert abs(g["logdet"] - o[1]) < td
+        assert abs(g["quad"] - o[2]) < tq * abs(o[2])
+        assert abs(g["loglik"] - o[0]) < td + tq * abs(o[2])
+
+
+def test_level0_quadratic_form_is_the_solve_Q():
+    """At level 0 the quadratic form is Z_W^T C_W^-1 Z_W, the Q of the PCG path."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import FP64, PcgOptions
+    wl, nu, tree, bas, s = _both(2, 800)
+    Z = dev(wl.z)
+    g = s.loglik(Z, 0)
+    out = s.predict(Z, None, PcgOptions(rtol=1e-13, max_iter=5000, precision=FP64))
+    q = float(torch.dot(Z, out["gamma"]))
+    assert abs(g["quad"] - q) < 1e-8 * abs(q)
+
+
+def test_mle_rho_matches_oracle():
+    require_gpu()
+    wl, nu, tree, bas, s = _both(1, 600)
+    Z = dev(wl.z)
+    level = tree.max_depth - 1
+    g = s.mle_rho(Z, level, 0.01, 1.0, 1e-5)
+    o = OL.mle_rho(wl.points, wl.z, nu, bas, level, 0.01, 1.0, 1e-5)
+    say(f"mle rho gpu {g['rho']:.8f} oracle {o[0]:.8f} evals {g['evals']}")
+    assert abs(math.log(g["rho"]) - math.log(o[0])) < 3e-5
+    assert abs(g["loglik"] - o[1]) < 1e-9 * abs(o[1])
+    assert g["bracket"] <= 1e-5
+
+
+def test_loglik_error_paths():
+    torch = require_gpu()
+    import ctypes as C
+    from paper_1701_00285_amd import MlblupError, matern
+    from paper_1701_00285_amd import _lib as L
+    wl, nu, tree, bas, s = _both(1, 300)
+    with pytest.raises(MlblupError, match="EINVAL"):
+        s.loglik(dev(wl.z), s.basis.levels)
+    k = matern(nu, wl.rho)
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    out = np.zeros(3)
+    zt = s.to_tree(dev(wl.z)).contiguous()
+    st = L.lib().mlblup_loglik(s.basis.h, C.byref(k), C.c_void_p(zt.data_ptr()), 0,
+                               out.ctypes.data_as(C.c_void_p), C.c_void_p(small.data_ptr()), small.numel(), None)
+    assert st == L.EINVAL
+    with pytest.raises(MlblupError, match="EINVAL"):
+        s.mle_rho(dev(wl.z), 0, 1.0, 0.5)

@@ -143,3 +143,23 @@ def test_large_workload_basis_builds():
     b = Basis(t, wl.degree_w)
     assert t.max_depth == 10 and b.n_minus_p == 65536 - 10
     assert sum(b.level_counts()) == 65536 - 10
+
+
+def test_loglik_workspace_counts_the_partial_transform_rows():
+    """Rows of [W_t; ...; W_n] = wavelets at levels >= n; the workspace holds
+    the N x N covariance and the N~ x N first analysis; level outside
+    [0, levels) is rejected."""
+    import ctypes as C
+    from paper_1701_00285_amd import _lib as L
+    pts = synth.uniform_cloud(1500, 2, seed=11)
+    t = Tree(pts, 32)
+    b = Basis(t, 1)
+    counts = b.level_counts()
+    for level in range(b.levels):
+        by, rows = C.c_int64(), C.c_int64()
+        assert L.lib().mlblup_loglik_workspace_bytes(b.h, level, C.byref(by), C.byref(rows)) == L.OK
+        assert rows.value == int(counts[level:].sum())
+        assert by.value >= 8 * (1500 * 1500 + rows.value * 1500)
+    by = C.c_int64()
+    assert L.lib().mlblup_loglik_workspace_bytes(b.h, b.levels, C.byref(by), None) == L.EINVAL
+    assert L.lib().mlblup_loglik_workspace_bytes(b.h, -1, C.byref(by), None) == L.EINVAL
