@@ -100,7 +100,7 @@ int transform_synthesis(const TransformDev& T, const double* vw, const double* v
 // ---- multilevel log-likelihood (loglik.hip) ----------------------------------------
 // workspace layout (byte offsets) for the levels >= level
 struct LoglikLayout {
-  int64_t phi = 0, a = 0, scal = 0, zw = 0, scalz = 0, out = 0, flag = 0, gtab = 0, total = 0;
+  int64_t phi = 0, a = 0, scal = 0, zw = 0, scalz = 0, out = 0, flag = 0, gtab = 0, linv = 0, total = 0;
   int64_t rows = 0;    // N~: rows of [W_t; ...; W_level]
   int64_t batch = 0;   // columns per batched-analysis pass
 };

@@ -85,6 +85,42 @@ __global__ __launch_bounds__(kThreads) void fma_only(float* out, int iters, floa
   out[blockIdx.x * kThreads + threadIdx.x] = r0 + r1 + r2 + r3;
 }
 
+__global__ __launch_bounds__(kThreads) void fma_f64(float* out, int iters, float a0) {
+  double r0 = a0, r1 = a0 + 1, r2 = a0 + 2, r3 = a0 + 3;
+  const double b = threadIdx.x * 1e-3;
+  for (int i = 0; i < iters; ++i) {
+    r0 = fma(r0, b, 0.5);
+    r1 = fma(r1, b, 0.5);
+    r2 = fma(r2, b, 0.5);
+    r3 = fma(r3, b, 0.5);
+  }
+  out[blockIdx.x * kThreads + threadIdx.x] = (float)(r0 + r1 + r2 + r3);
+}
+
+// the FP64 pair kernels' one hardware transcendental: reciprocal square root
+__global__ __launch_bounds__(kThreads) void rsq_f64(float* out, int iters, float a0) {
+  double r0 = a0 + threadIdx.x, r1 = r0 + 1, r2 = r0 + 2, r3 = r0 + 3;
+  for (int i = 0; i < iters; ++i) {
+    r0 = __builtin_amdgcn_rsq(r0) + 1.0;
+    r1 = __builtin_amdgcn_rsq(r1) + 1.0;
+    r2 = __builtin_amdgcn_rsq(r2) + 1.0;
+    r3 = __builtin_amdgcn_rsq(r3) + 1.0;
+  }
+  out[blockIdx.x * kThreads + threadIdx.x] = (float)(r0 + r1 + r2 + r3);
+}
+
+// FP32 sqrt and exp2 alone (with one add each to keep the chains live)
+__global__ __launch_bounds__(kThreads) void trans_f32(float* out, int iters, float a0) {
+  float r0 = a0 + threadIdx.x, r1 = r0 + 1, r2 = r0 + 2, r3 = r0 + 3;
+  for (int i = 0; i < iters; ++i) {
+    r0 = __builtin_amdgcn_exp2f(-__builtin_amdgcn_sqrtf(r0)) + 1.0f;
+    r1 = __builtin_amdgcn_exp2f(-__builtin_amdgcn_sqrtf(r1)) + 1.0f;
+    r2 = __builtin_amdgcn_exp2f(-__builtin_amdgcn_sqrtf(r2)) + 1.0f;
+    r3 = __builtin_amdgcn_exp2f(-__builtin_amdgcn_sqrtf(r3)) + 1.0f;
+  }
+  out[blockIdx.x * kThreads + threadIdx.x] = r0 + r1 + r2 + r3;
+}
+
 __global__ __launch_bounds__(kThreads) void mix_f32(float* out, int iters, float a0) {
   f4 g0 = {0, 0, 0, 0}, g1 = g0, g2 = g0, g3 = g0;
   const float a = a0 + threadIdx.x, b = a0 * 2.0f;
@@ -169,12 +205,16 @@ int main() {
       {"mfma 16x16x32 f16", mfma_f16_k32},
       {"pair values (sqrt, exp2, 2 fma, add)", pair_values},
       {"fma", fma_only},
+      {"fma f64", fma_f64},
+      {"rsq f64 + add f64", rsq_f64},
+      {"sqrt f32 + exp2 f32 + add", trans_f32},
       {"mfma f32 + pair values", mix_f32},
       {"mfma f32 + 4 fma", mix_f32_fma},
       {"mfma bf16 k16 + pair values", mix_bf16_k16},
       {"mfma f16 k32 + pair values", mix_f16_k32},
   };
-  printf("cycles per group per SIMD at 2.4 GHz (group: one MFMA and/or one pair's VALU work, or one fma)\n");
+  printf("cycles per group per SIMD at 2.4 GHz (group: one MFMA and/or one pair's VALU work, or the named "
+         "instructions)\n");
   for (int waves : {8, 2}) {
     const int blocks = kSimds * waves / (kThreads / 64);
     printf("--- %d waves per SIMD\n", waves);

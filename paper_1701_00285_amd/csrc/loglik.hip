@@ -15,10 +15,11 @@
 //     applied to column blocks of Phi, level by level from the finest to n
 //     (batched_analysis: one workgroup per cell and 256 columns);
 //  3. A^T (tiled transpose), then C^n_W = (W A^T) restricted to N~ rows;
-//  4. blocked right-looking Cholesky, blocks of 64 (diagonal factor in LDS,
-//     panel triangular solve, trailing update of the lower triangle);
-//  5. G y = Z^n_W by block forward substitution; 2 sum log G_ii and |y|^2 by
-//     fixed-order reductions.
+//  4. blocked right-looking Cholesky, blocks of 64: the diagonal factor and
+//     its inverse in LDS, the panel as a product with that inverse, the
+//     trailing update of the lower triangle in 128 x 128 tiles;
+//  5. G y = Z^n_W by block forward substitution with the stored inverses;
+//     2 sum log G_ii and |y|^2 by fixed-order reductions.
 // The paper factorizes a sparsified C~^n_W with a sparse Cholesky and nested
 // dissection; here C^n_W is dense and exact (288 GB of HBM hold it for N~ up
 // to about 10^5).
@@ -131,91 +132,79 @@ __global__ __launch_bounds__(kTr * 8) void transpose(const double* __restrict__ 
 }
 
 // ---- 4. blocked Cholesky (lower), A is n x n with leading dimension ld --------
-// factor of the diagonal block at k0 (size nb <= kNb) in LDS; a pivot that is
-// not positive and finite sets flag[0] (the factor then continues with 1)
+// Factor of the diagonal block at k0 (size nb <= kNb) in LDS, and the
+// inverse of that factor (into linv, kNb x kNb row-major), which turns the
+// panel solve and the forward substitution into products.  One barrier per
+// column: step j reads column j and the pivot unscaled, writes the scaled
+// column to a second array and updates the trailing triangle with
+// a_rj a_cj / a_jj.  A pivot that is not positive and finite sets flag[0]
+// (the factor then continues with 1).
 __global__ __launch_bounds__(kT) void potrf_diag(double* __restrict__ A, int64_t ld, int64_t k0, int nb,
-                                                 int* __restrict__ flag) {
+                                                 double* __restrict__ linv, int* __restrict__ flag) {
   __shared__ double a[kNb][kNb + 1];
+  __shared__ double l[kNb][kNb + 1];
   const int tid = threadIdx.x;
-  for (int e = tid; e < nb * nb; e += kT) {
-    const int r = e / nb, c = e % nb;
-    a[r][c] = c <= r ? A[(k0 + r) * ld + k0 + c] : 0.0;
+  for (int e = tid; e < kNb * kNb; e += kT) {
+    const int r = e / kNb, c = e % kNb;
+    a[r][c] = (r < nb && c <= r) ? A[(k0 + r) * ld + k0 + c] : 0.0;
+    l[r][c] = 0.0;
   }
-  __syncthreads();
   for (int j = 0; j < nb; ++j) {
-    if (tid == 0) {
-      double p = a[j][j];
-      if (!(p > 0.0) || !__builtin_isfinite(p)) {
-        flag[0] = 1;
-        p = 1.0;
-      }
-      a[j][j] = sqrt(p);
+    __syncthreads();
+    double p = a[j][j];
+    const bool ok = p > 0.0 && __builtin_isfinite(p);
+    if (!ok) {
+      if (tid == 0) flag[0] = 1;
+      p = 1.0;
     }
-    __syncthreads();
-    const double dj = a[j][j];
-    for (int r = j + 1 + tid; r < nb; r += kT) a[r][j] /= dj;
-    __syncthreads();
-    // trailing lower triangle of the block
+    const double dj = sqrt(p), inv = 1.0 / p;
+    for (int r = j + tid; r < nb; r += kT) l[r][j] = r == j ? dj : a[r][j] / dj;
     const int rem = nb - j - 1;
     for (int e = tid; e < rem * rem; e += kT) {
       const int r = j + 1 + e / rem, c = j + 1 + e % rem;
-      if (c <= r) a[r][c] = fma(-a[r][j], a[c][j], a[r][c]);
+      if (c <= r) a[r][c] = fma(-a[r][j] * inv, a[c][j], a[r][c]);
     }
-    __syncthreads();
   }
+  __syncthreads();
   for (int e = tid; e < nb * nb; e += kT) {
     const int r = e / nb, c = e % nb;
-    if (c <= r) A[(k0 + r) * ld + k0 + c] = a[r][c];
+    if (c <= r) A[(k0 + r) * ld + k0 + c] = l[r][c];
   }
+  // inverse of the lower factor, column c = L^-1 e_c by forward substitution,
+  // four adjacent lanes per column (each a quarter of every dot product,
+  // combined across the quad); a column's lanes share a wave, whose LDS
+  // accesses are ordered, so no barrier is needed inside.  a is free now and
+  // holds the inverse.
+  {
+    const int c = tid >> 2, q = tid & 3;
+    for (int i = q; i < kNb; i += 4) a[i][c] = 0.0;
+    if (c < nb) {
+      if (q == 0) a[c][c] = 1.0 / l[c][c];
+      for (int i = c + 1; i < nb; ++i) {
+        double s = 0.0;
+        for (int k = c + q; k < i; k += 4) s = fma(l[i][k], a[k][c], s);
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (q == 0) a[i][c] = -s / l[i][i];
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < kNb * kNb; e += kT) linv[e] = a[e / kNb][e % kNb];
 }
 
 // panel below the diagonal block: rows [k0 + nb, n), columns [k0, k0 + nb):
-// X G_kk^T = B, one 64-row tile per workgroup, one row per thread (64 threads)
-__global__ __launch_bounds__(kNb) void trsm_panel(double* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
-                                                  int nb) {
-  __shared__ double L[kNb][kNb + 1];
-  __shared__ double X[kNb][kNb + 1];
+// X = B G_kk^-T, one 64-row tile per workgroup, 4 x 4 outputs per thread
+__global__ __launch_bounds__(kT) void trsm_panel(double* __restrict__ A, int64_t ld, int64_t n, int64_t k0, int nb,
+                                                 const double* __restrict__ linv) {
+  __shared__ double Bt[kNb][kNb + 1];  // [k][row]
+  __shared__ double Li[kNb][kNb + 1];  // [k][col]: Li[k][c] = G^-1[c][k]
   const int tid = threadIdx.x;
   const int64_t r0 = k0 + nb + (int64_t)blockIdx.x * kNb;
-  for (int e = tid; e < nb * nb; e += kNb) {
-    const int r = e / nb, c = e % nb;
-    L[r][c] = c <= r ? A[(k0 + r) * ld + k0 + c] : 0.0;
-  }
-  for (int e = tid; e < kNb * nb; e += kNb) {
-    const int r = e / nb, c = e % nb;
-    X[r][c] = (r0 + r < n) ? A[(r0 + r) * ld + k0 + c] : 0.0;
-  }
-  __syncthreads();
-  if (r0 + tid < n) {
-    for (int l = 0; l < nb; ++l) {
-      double s = X[tid][l];
-      for (int m = 0; m < l; ++m) s = fma(-X[tid][m], L[l][m], s);
-      X[tid][l] = s / L[l][l];
-    }
-    for (int c = 0; c < nb; ++c) A[(r0 + tid) * ld + k0 + c] = X[tid][c];
-  }
-}
-
-// trailing update of the lower triangle: for block rows I >= J after the
-// panel, A[I][J] -= P_I P_J^T with P the panel (K = nb); one 64x64 tile per
-// workgroup, a 4x4 micro-tile per thread
-__global__ __launch_bounds__(kT) void syrk_update(double* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
-                                                  int nb, int64_t nblk) {
-  __shared__ double Pi[kNb][kNb + 2];  // [k][row]
-  __shared__ double Pj[kNb][kNb + 2];
-  // tile index t -> (I, J), J <= I < nblk
-  const int64_t t = blockIdx.x;
-  int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-  while (I * (I + 1) / 2 > t) --I;
-  while ((I + 1) * (I + 2) / 2 <= t) ++I;
-  const int64_t J = t - I * (I + 1) / 2;
-  const int64_t base = k0 + nb;
-  const int64_t ri = base + I * kNb, rj = base + J * kNb;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kNb * nb; e += kT) {
-    const int r = e / nb, k = e % nb;
-    Pi[k][r] = (ri + r < n) ? A[(ri + r) * ld + k0 + k] : 0.0;
-    Pj[k][r] = (rj + r < n) ? A[(rj + r) * ld + k0 + k] : 0.0;
+  for (int e = tid; e < kNb * kNb; e += kT) {
+    const int r = e / kNb, k = e % kNb;
+    Bt[k][r] = (k < nb && r0 + r < n) ? A[(r0 + r) * ld + k0 + k] : 0.0;
+    Li[k][r] = linv[r * kNb + k];
   }
   __syncthreads();
   const int tx = tid % 16, ty = tid / 16;
@@ -227,9 +216,9 @@ __global__ __launch_bounds__(kT) void syrk_update(double* __restrict__ A, int64_
   for (int k = 0; k < nb; ++k) {
     double x[4], y[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) x[a] = Pi[k][ty * 4 + a];
+    for (int a = 0; a < 4; ++a) x[a] = Bt[k][ty * 4 + a];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) y[b] = Pj[k][tx * 4 + b];
+    for (int b = 0; b < 4; ++b) y[b] = Li[k][tx * 4 + b];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -237,31 +226,91 @@ __global__ __launch_bounds__(kT) void syrk_update(double* __restrict__ A, int64_
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const int64_t r = ri + ty * 4 + a;
+    const int64_t r = r0 + ty * 4 + a;
     if (r >= n) continue;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const int64_t c = rj + tx * 4 + b;
+      const int c = tx * 4 + b;
+      if (c < nb) A[r * ld + k0 + c] = acc[a][b];
+    }
+  }
+}
+
+// trailing update of the lower triangle: for tile rows I >= J after the
+// panel, A[I][J] -= P_I P_J^T with P the panel (K = nb <= 64).  Tiles of
+// kUp x kUp (two Cholesky blocks a side), 8 x 8 outputs per thread (FP64
+// FMAs; the FP64 matrix cores have the same peak and need more registers);
+// the panel rows go through LDS in two halves of K, stored k-major so that
+// a thread's 8 rows (8 columns) are contiguous.
+constexpr int kUp = 128;
+constexpr int kUpK = 32;
+__global__ __launch_bounds__(kT) void syrk_update(double* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
+                                                  int nb, int64_t ntile) {
+  __shared__ __attribute__((aligned(16))) double Pi[kUpK][kUp + 2];  // [k][row]
+  __shared__ __attribute__((aligned(16))) double Pj[kUpK][kUp + 2];
+  // tile index t -> (I, J), J <= I < ntile
+  const int64_t t = blockIdx.x;
+  int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > t) --I;
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  const int64_t J = t - I * (I + 1) / 2;
+  const int64_t base = k0 + nb;
+  const int64_t ri = base + I * kUp, rj = base + J * kUp;
+  const int tid = threadIdx.x;
+  const int tx = tid % 16, ty = tid / 16;
+  double acc[8][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+  for (int kh = 0; kh < nb; kh += kUpK) {
+    const int kc = nb - kh < kUpK ? nb - kh : kUpK;
+    __syncthreads();
+    for (int e = tid; e < kUp * kUpK; e += kT) {
+      const int r = e / kUpK, k = e % kUpK;
+      const bool ok = k < kc;
+      Pi[k][r] = (ok && ri + r < n) ? A[(ri + r) * ld + k0 + kh + k] : 0.0;
+      Pj[k][r] = (ok && rj + r < n) ? A[(rj + r) * ld + k0 + kh + k] : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < kc; ++k) {
+      double x[8], y[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) x[a] = Pi[k][ty * 8 + a];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) y[b] = Pj[k][tx * 8 + b];
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] = fma(x[a], y[b], acc[a][b]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int64_t r = ri + ty * 8 + a;
+    if (r >= n) continue;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int64_t c = rj + tx * 8 + b;
       if (c < n && c <= r) A[r * ld + c] -= acc[a][b];
     }
   }
 }
 
 // ---- 5. forward substitution and the two reductions ---------------------------
-// diagonal block kb: y_kb = G_kb,kb^-1 b_kb (b already holds the updates of the
-// earlier blocks); one wave
-__global__ __launch_bounds__(kNb) void trsv_diag(const double* __restrict__ A, int64_t ld, int64_t k0, int nb,
+// diagonal block kb: y_kb = G_kb,kb^-1 b_kb with the stored inverse (b already
+// holds the updates of the earlier blocks); one wave, a row each
+__global__ __launch_bounds__(kNb) void trsv_diag(const double* __restrict__ linv, int64_t k0, int nb,
                                                  double* __restrict__ b) {
-  __shared__ double y[kNb];
+  __shared__ double v[kNb];
   const int tid = threadIdx.x;
-  double v = tid < nb ? b[k0 + tid] : 0.0;
-  for (int l = 0; l < nb; ++l) {
-    if (tid == l) y[l] = v / A[(k0 + l) * ld + k0 + l];
-    __syncthreads();
-    if (tid > l && tid < nb) v = fma(-A[(k0 + tid) * ld + k0 + l], y[l], v);
-    __syncthreads();
+  v[tid] = tid < nb ? b[k0 + tid] : 0.0;
+  __syncthreads();
+  if (tid < nb) {
+    double s = 0.0;
+    for (int k = 0; k <= tid; ++k) s = fma(linv[tid * kNb + k], v[k], s);
+    b[k0 + tid] = s;
   }
-  if (tid < nb) b[k0 + tid] = y[tid];
 }
 
 // rows below the block: b_i -= G[i, k0:k0+nb] y_kb
@@ -333,6 +382,8 @@ LoglikLayout loglik_layout(const Basis& B, int32_t level) {
   o += 256;
   L.gtab = o;
   o += align256(kGenuBytes);
+  L.linv = o;  // the inverse of every diagonal block of the factor
+  o += align256(std::max<int64_t>((nt + kNb - 1) / kNb, 1) * kNb * kNb * 8);
   L.total = o;
   L.rows = nt;
   L.batch = batch;
@@ -366,6 +417,7 @@ int loglik_device(const Basis& B, const TransformDev& T, const PairArgs& k, int3
   double* scalz = (double*)(w + L.scalz);
   double* dout = (double*)(w + L.out);
   int* flag = (int*)(w + L.flag);
+  double* linv = (double*)(w + L.linv);
   const int64_t n = B.n, nt = L.rows;
   const double* pts = (const double*)((const char*)B.dev_base + B.off_pts);
   const double zs = kernel_scale(k.nu2, k.nu, k.rho);
@@ -415,13 +467,14 @@ int loglik_device(const Basis& B, const TransformDev& T, const PairArgs& k, int3
   for (int64_t kb = 0; kb < nblk; ++kb) {
     const int64_t k0 = kb * kNb;
     const int nb = (int)std::min<int64_t>(kNb, nt - k0);
-    hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(kT), 0, s, C, nt, k0, nb, flag);
+    double* li = linv + kb * kNb * kNb;
+    hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(kT), 0, s, C, nt, k0, nb, li, flag);
     const int64_t below = nt - k0 - nb;
     if (below > 0) {
       const int64_t tiles = (below + kNb - 1) / kNb;
-      hipLaunchKernelGGL(trsm_panel, dim3((unsigned)tiles), dim3(kNb), 0, s, C, nt, nt, k0, nb);
-      hipLaunchKernelGGL(syrk_update, dim3((unsigned)(tiles * (tiles + 1) / 2)), dim3(kT), 0, s, C, nt, nt, k0, nb,
-                         tiles);
+      hipLaunchKernelGGL(trsm_panel, dim3((unsigned)tiles), dim3(kT), 0, s, C, nt, nt, k0, nb, li);
+      const int64_t ut = (below + kUp - 1) / kUp;
+      hipLaunchKernelGGL(syrk_update, dim3((unsigned)(ut * (ut + 1) / 2)), dim3(kT), 0, s, C, nt, nt, k0, nb, ut);
     }
   }
   if ((st = hip_check(hipGetLastError(), "Cholesky launch"))) return st;
@@ -429,7 +482,7 @@ int loglik_device(const Basis& B, const TransformDev& T, const PairArgs& k, int3
   for (int64_t kb = 0; kb < nblk; ++kb) {
     const int64_t k0 = kb * kNb;
     const int nb = (int)std::min<int64_t>(kNb, nt - k0);
-    hipLaunchKernelGGL(trsv_diag, dim3(1), dim3(kNb), 0, s, C, nt, k0, nb, zw);
+    hipLaunchKernelGGL(trsv_diag, dim3(1), dim3(kNb), 0, s, linv + kb * kNb * kNb, k0, nb, zw);
     const int64_t below = nt - k0 - nb;
     if (below > 0)
       hipLaunchKernelGGL(gemv_panel, dim3((unsigned)((below + kT - 1) / kT)), dim3(kT), 0, s, C, nt, nt, k0, nb, zw);
