@@ -134,7 +134,31 @@ void image_layout(Basis& B) {
   off = align_up(off + nv * (int64_t)sizeof(double));
   B.off_pts = off;
   off = align_up(off + B.n * B.d * (int64_t)sizeof(double));
+  int32_t nl = 0;
+  for (const NodeDesc& D : B.desc) nl += D.leaf ? 1 : 0;
+  B.n_leaves = nl;
+  B.off_parent = off;
+  off = align_up(off + nn * (int64_t)sizeof(int32_t));
+  B.off_leaves = off;
+  off = align_up(off + std::max<int64_t>(nl, 1) * (int64_t)sizeof(int32_t));
   B.dev_bytes = off;
+}
+
+// Device view of the multilevel transform of an uploaded basis.
+TransformDev transform_dev(const Basis& B) {
+  const char* img = (const char*)B.dev_base;
+  TransformDev T;
+  T.desc = (const NodeDesc*)(img + B.off_desc);
+  T.level_nodes = (const int32_t*)(img + B.off_levels);
+  T.lvl_begin_host = B.lvl_begin.data();
+  T.levels = B.levels;
+  T.V = (const double*)(img + B.off_V);
+  T.Vt = (const double*)(img + B.off_Vt);
+  T.parent = (const int32_t*)(img + B.off_parent);
+  T.leaves = (const int32_t*)(img + B.off_leaves);
+  T.n_leaves = B.n_leaves;
+  T.p = B.p;
+  return T;
 }
 
 // Workspace of the solve/predict/grad drivers.
@@ -201,12 +225,7 @@ struct Ctx {
   Ctx(const Basis& b, const mlblup_matern& km, void* work, const Ws& ws, hipStream_t st)
       : B(b), s(st), base((char*)work), w(ws), k(km) {
     const char* img = (const char*)B.dev_base;
-    T.desc = (const NodeDesc*)(img + B.off_desc);
-    T.level_nodes = (const int32_t*)(img + B.off_levels);
-    T.lvl_begin_host = B.lvl_begin.data();
-    T.levels = B.levels;
-    T.V = (const double*)(img + B.off_V);
-    T.Vt = (const double*)(img + B.off_Vt);
+    T = transform_dev(B);
     pts = (const double*)(img + B.off_pts);
     nu2 = nu2_of(&km);
   }
@@ -692,6 +711,15 @@ int mlblup_basis_upload(mlblup_basis bb, void* dev_buf, int64_t bytes, void* str
   MLB_HIP(hipMemcpyAsync(base + B.off_Vt, vt.data(), vt.size() * sizeof(double), hipMemcpyHostToDevice, s));
   MLB_HIP(hipMemcpyAsync(base + B.off_pts, B.pts_tree.data(), B.pts_tree.size() * sizeof(double),
                          hipMemcpyHostToDevice, s));
+  std::vector<int32_t> parent(nn, -1), leaves;
+  for (int32_t v = 0; v < nn; ++v) {
+    if (B.left[v] >= 0) parent[B.left[v]] = v;
+    if (B.right[v] >= 0) parent[B.right[v]] = v;
+    if (B.desc[v].leaf) leaves.push_back(v);
+  }
+  MLB_HIP(hipMemcpyAsync(base + B.off_parent, parent.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  MLB_HIP(hipMemcpyAsync(base + B.off_leaves, leaves.data(), leaves.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                         s));
   MLB_HIP(hipStreamSynchronize(s));  // host staging buffers die here
   B.dev_base = dev_buf;
   B.uploaded = true;
@@ -763,13 +791,7 @@ static int transform_common(mlblup_basis b, void* work, int64_t work_bytes, Tran
   const Basis& B = b->b;
   if (!work || work_bytes < std::max<int64_t>(B.scal_total, 1) * (int64_t)sizeof(double))
     return fail(MLBLUP_EINVAL, "transform workspace too small");
-  const char* img = (const char*)B.dev_base;
-  T->desc = (const NodeDesc*)(img + B.off_desc);
-  T->level_nodes = (const int32_t*)(img + B.off_levels);
-  T->lvl_begin_host = B.lvl_begin.data();
-  T->levels = B.levels;
-  T->V = (const double*)(img + B.off_V);
-  T->Vt = (const double*)(img + B.off_Vt);
+  *T = transform_dev(B);
   return MLBLUP_OK;
 }
 
@@ -962,13 +984,7 @@ static int loglik_common(mlblup_basis b, const mlblup_matern* k, const double* z
   *L = loglik_layout(B, level);
   if (!work_dev || work_bytes < L->total)
     return fail(MLBLUP_EINVAL, "loglik: workspace too small (need " + std::to_string(L->total) + " bytes)");
-  const char* img = (const char*)B.dev_base;
-  T->desc = (const NodeDesc*)(img + B.off_desc);
-  T->level_nodes = (const int32_t*)(img + B.off_levels);
-  T->lvl_begin_host = B.lvl_begin.data();
-  T->levels = B.levels;
-  T->V = (const double*)(img + B.off_V);
-  T->Vt = (const double*)(img + B.off_Vt);
+  *T = transform_dev(B);
   *a = PairArgs{nullptr, 0, nullptr, B.n, B.d, nu2_of(k), k->rho, k->sigma2, MLBLUP_FP64, MLBLUP_VALUE,
                 nullptr, nullptr, nullptr, k->nu, nullptr};
   return MLBLUP_OK;

@@ -98,6 +98,82 @@ __global__ __launch_bounds__(kT) void synthesis_level(const NodeDesc* __restrict
   synthesis_node(desc[lnodes[s]], lane, Vt, vw, vl, scal, v);
 }
 
+// The whole synthesis in one launch: a wave per leaf walks its path from the
+// root down.  At each cell on the path it forms only the scaling
+// coefficients of the next cell (the cell's outputs that belong to that
+// child), keeps them in LDS, and at the leaf writes the leaf's values.  An
+// ancestor's few coefficients are recomputed by every leaf below it; the
+// leaf blocks, which carry nearly all the bytes, are read once.  No
+// workgroup waits for another.
+constexpr int kPathMax = 64;   // tree depth bound of the fused form
+constexpr int kCoefMax = 64;   // scaling coefficients per cell (p) bound of the fused form
+
+__global__ __launch_bounds__(kT) void synthesis_fused(const NodeDesc* __restrict__ desc,
+                                                      const int32_t* __restrict__ parent,
+                                                      const int32_t* __restrict__ leaves, int32_t n_leaves,
+                                                      const double* __restrict__ Vt, const double* __restrict__ vw,
+                                                      const double* __restrict__ vl, double* __restrict__ v) {
+  __shared__ int32_t path[kWavesPerBlock][kPathMax];
+  __shared__ double cbuf[kWavesPerBlock][2][kCoefMax];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t g = blockIdx.x * kWavesPerBlock + wave;
+  if (g >= n_leaves) return;
+  // path leaf -> root
+  int len = 0;
+  if (lane == 0) {
+    int32_t u = leaves[g];
+    while (u >= 0 && len < kPathMax) {
+      path[wave][len++] = u;
+      u = parent[u];
+    }
+  }
+  len = __shfl(len, 0, 64);
+  __builtin_amdgcn_wave_barrier();
+  // lane k holds the descriptor of the k-th cell of the path (one round trip
+  // for the whole path); each step takes its fields from the step's lane
+  int64_t p_voff = 0, p_woff = 0, p_inoff = 0, p_scal = 0;
+  int p_m = 0, p_a = 0;
+  if (lane < len) {
+    const NodeDesc D = desc[path[wave][lane]];
+    p_voff = D.v_off;
+    p_woff = D.w_off;
+    p_inoff = D.in_off;
+    p_scal = D.scal_off;
+    p_m = D.m;
+    p_a = D.a;
+  }
+  auto from = [](int64_t x, int k) {
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)x, k);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), k);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+  };
+  int cur = 0;
+  for (int idx = len - 1; idx >= 0; --idx) {
+    const double* B = Vt + from(p_voff, idx);
+    const int m = __builtin_amdgcn_readlane(p_m, idx), a = __builtin_amdgcn_readlane(p_a, idx);
+    const int64_t in_off = from(p_inoff, idx);
+    const double* cs = idx == len - 1 ? vl : cbuf[wave][cur];  // the root's scaling part is L v (may be null)
+    const double* cw = vw + from(p_woff, idx) - a;
+    int lo = 0, cnt = m;
+    if (idx > 0) {
+      lo = (int)(from(p_scal, idx - 1) - in_off);  // 0 for the left child, a_left for the right
+      cnt = __builtin_amdgcn_readlane(p_a, idx - 1);
+    }
+    for (int i = lo + lane; i < lo + cnt; i += 64) {
+      double acc = 0.0;
+      if (cs) {
+        for (int j = 0; j < a; ++j) acc = fma(B[(int64_t)j * m + i], cs[j], acc);
+      }
+#pragma unroll 8
+      for (int j = a; j < m; ++j) acc = fma(B[(int64_t)j * m + i], cw[j], acc);
+      if (idx == 0) v[in_off + i] = acc;          // the leaf's values
+      else cbuf[wave][cur ^ 1][i - lo] = acc;     // the next cell's scaling coefficients
+    }
+    __builtin_amdgcn_wave_barrier();
+    cur ^= 1;
+  }
+}
+
 // The small top levels (few cells each) in one launch of one workgroup:
 // levels run in order with a workgroup barrier between them (the barrier
 // orders this workgroup's global writes and reads).
@@ -330,6 +406,12 @@ int transform_analysis(const TransformDev& T, const double* v, double* vw, doubl
 
 int transform_synthesis(const TransformDev& T, const double* vw, const double* vl, double* v, double* scal,
                         hipStream_t s) {
+  if (T.leaves && T.n_leaves > 0 && T.levels <= kPathMax && T.p <= kCoefMax) {
+    const unsigned g = (unsigned)((T.n_leaves + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL(synthesis_fused, dim3(g), dim3(kT), 0, s, T.desc, T.parent, T.leaves, T.n_leaves, T.Vt, vw,
+                       vl, v);
+    return hip_check(hipGetLastError(), "synthesis launch");
+  }
   const int nt = top_levels(T);
   if (nt > 0)
     hipLaunchKernelGGL(synthesis_top, dim3(1), dim3(kT), 0, s, T.desc, T.level_nodes, make_top(T, nt), T.Vt, vw, vl,
