@@ -134,13 +134,8 @@ void image_layout(Basis& B) {
   off = align_up(off + nv * (int64_t)sizeof(double));
   B.off_pts = off;
   off = align_up(off + B.n * B.d * (int64_t)sizeof(double));
-  int32_t nl = 0;
-  for (const NodeDesc& D : B.desc) nl += D.leaf ? 1 : 0;
-  B.n_leaves = nl;
-  B.off_parent = off;
-  off = align_up(off + nn * (int64_t)sizeof(int32_t));
-  B.off_leaves = off;
-  off = align_up(off + std::max<int64_t>(nl, 1) * (int64_t)sizeof(int32_t));
+  B.off_children = off;
+  off = align_up(off + 2 * nn * (int64_t)sizeof(int32_t));
   B.dev_bytes = off;
 }
 
@@ -154,10 +149,8 @@ TransformDev transform_dev(const Basis& B) {
   T.levels = B.levels;
   T.V = (const double*)(img + B.off_V);
   T.Vt = (const double*)(img + B.off_Vt);
-  T.parent = (const int32_t*)(img + B.off_parent);
-  T.leaves = (const int32_t*)(img + B.off_leaves);
-  T.n_leaves = B.n_leaves;
-  T.p = B.p;
+  T.children = (const int32_t*)(img + B.off_children);
+  T.n_nodes = (int32_t)B.desc.size();
   return T;
 }
 
@@ -711,15 +704,9 @@ int mlblup_basis_upload(mlblup_basis bb, void* dev_buf, int64_t bytes, void* str
   MLB_HIP(hipMemcpyAsync(base + B.off_Vt, vt.data(), vt.size() * sizeof(double), hipMemcpyHostToDevice, s));
   MLB_HIP(hipMemcpyAsync(base + B.off_pts, B.pts_tree.data(), B.pts_tree.size() * sizeof(double),
                          hipMemcpyHostToDevice, s));
-  std::vector<int32_t> parent(nn, -1), leaves;
-  for (int32_t v = 0; v < nn; ++v) {
-    if (B.left[v] >= 0) parent[B.left[v]] = v;
-    if (B.right[v] >= 0) parent[B.right[v]] = v;
-    if (B.desc[v].leaf) leaves.push_back(v);
-  }
-  MLB_HIP(hipMemcpyAsync(base + B.off_parent, parent.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  MLB_HIP(hipMemcpyAsync(base + B.off_leaves, leaves.data(), leaves.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                         s));
+  MLB_HIP(hipMemcpyAsync(base + B.off_children, B.left.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  MLB_HIP(hipMemcpyAsync(base + B.off_children + nn * sizeof(int32_t), B.right.data(), nn * sizeof(int32_t),
+                         hipMemcpyHostToDevice, s));
   MLB_HIP(hipStreamSynchronize(s));  // host staging buffers die here
   B.dev_base = dev_buf;
   B.uploaded = true;

@@ -89,10 +89,8 @@ struct TransformDev {
   int32_t levels;
   const double* V;
   const double* Vt;
-  const int32_t* parent = nullptr;  // parent of every node, -1 at the root
-  const int32_t* leaves = nullptr;  // leaf node ids
-  int32_t n_leaves = 0;
-  int32_t p = 0;
+  const int32_t* children = nullptr;  // left children (n_nodes), then right children; -1 for leaves
+  int32_t n_nodes = 0;
 };
 // vw = W v, vl = L v (vl may be null).  scal: scaling scratch.
 int transform_analysis(const TransformDev& T, const double* v, double* vw, double* vl, double* scal,

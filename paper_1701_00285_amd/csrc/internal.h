@@ -74,8 +74,7 @@ struct Basis {
   int64_t dev_bytes = 0;
   // offsets inside the device image (bytes)
   int64_t off_desc = 0, off_V = 0, off_Vt = 0, off_pts = 0, off_levels = 0, off_exps = 0;
-  int64_t off_parent = 0, off_leaves = 0;   // parent of every node (-1 at the root), the leaf node ids
-  int32_t n_leaves = 0;
+  int64_t off_children = 0;   // left, then right child of every node (-1 for leaves): 2 x nodes int32
   bool uploaded = false;
 };
 

@@ -34,8 +34,6 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kWavesPerBlock = 4;
-constexpr int kMaxTopLevels = 24;
-constexpr int kTopCells = 16;    // levels with at most this many cells go into the fused launch
 
 __device__ __forceinline__ void analysis_node(const NodeDesc& D, int lane, const double* __restrict__ V,
                                               const double* __restrict__ v, double* __restrict__ scal,
@@ -76,134 +74,50 @@ __device__ __forceinline__ void synthesis_node(const NodeDesc& D, int lane, cons
   }
 }
 
-__global__ __launch_bounds__(kT) void analysis_level(const NodeDesc* __restrict__ desc,
-                                                     const int32_t* __restrict__ lnodes, int32_t cnt,
+// Three levels per launch: a workgroup takes one cell at the group's top
+// depth and the cells of its subtree one and two levels below (up to 2 and
+// 4 cells, one per wave), with a workgroup barrier between the levels (the
+// barrier orders this workgroup's global writes and reads).  The analysis
+// runs a group from its deepest level up, the synthesis from its top down.
+constexpr int kGroupLevels = 3;
+
+// cell of the group for wave w at relative depth rel (0: the group's top
+// cell r; 1: its children, waves 0-1; 2: its grandchildren, waves 0-3), or -1
+__device__ __forceinline__ int32_t group_cell(const int32_t* __restrict__ children, int32_t n_nodes, int32_t r,
+                                              int rel, int w) {
+  if (rel == 0) return w == 0 ? r : -1;
+  if (rel == 1) return w < 2 ? children[(int64_t)w * n_nodes + r] : -1;
+  if (w >= 4) return -1;
+  const int32_t c = children[(int64_t)(w >> 1) * n_nodes + r];
+  return c >= 0 ? children[(int64_t)(w & 1) * n_nodes + c] : -1;
+}
+
+__global__ __launch_bounds__(kT) void analysis_group(const NodeDesc* __restrict__ desc,
+                                                     const int32_t* __restrict__ children, int32_t n_nodes,
+                                                     const int32_t* __restrict__ roots, int nlev,
                                                      const double* __restrict__ V, const double* __restrict__ v,
                                                      double* __restrict__ scal, double* __restrict__ vw,
                                                      double* __restrict__ vl) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int32_t s = blockIdx.x * kWavesPerBlock + wave;
-  if (s >= cnt) return;
-  analysis_node(desc[lnodes[s]], lane, V, v, scal, vw, vl);
-}
-
-__global__ __launch_bounds__(kT) void synthesis_level(const NodeDesc* __restrict__ desc,
-                                                      const int32_t* __restrict__ lnodes, int32_t cnt,
-                                                      const double* __restrict__ Vt, const double* __restrict__ vw,
-                                                      const double* __restrict__ vl, double* __restrict__ scal,
-                                                      double* __restrict__ v) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int32_t s = blockIdx.x * kWavesPerBlock + wave;
-  if (s >= cnt) return;
-  synthesis_node(desc[lnodes[s]], lane, Vt, vw, vl, scal, v);
-}
-
-// The whole synthesis in one launch: a wave per leaf walks its path from the
-// root down.  At each cell on the path it forms only the scaling
-// coefficients of the next cell (the cell's outputs that belong to that
-// child), keeps them in LDS, and at the leaf writes the leaf's values.  An
-// ancestor's few coefficients are recomputed by every leaf below it; the
-// leaf blocks, which carry nearly all the bytes, are read once.  No
-// workgroup waits for another.
-constexpr int kPathMax = 64;   // tree depth bound of the fused form
-constexpr int kCoefMax = 64;   // scaling coefficients per cell (p) bound of the fused form
-
-__global__ __launch_bounds__(kT) void synthesis_fused(const NodeDesc* __restrict__ desc,
-                                                      const int32_t* __restrict__ parent,
-                                                      const int32_t* __restrict__ leaves, int32_t n_leaves,
-                                                      const double* __restrict__ Vt, const double* __restrict__ vw,
-                                                      const double* __restrict__ vl, double* __restrict__ v) {
-  __shared__ int32_t path[kWavesPerBlock][kPathMax];
-  __shared__ double cbuf[kWavesPerBlock][2][kCoefMax];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int32_t g = blockIdx.x * kWavesPerBlock + wave;
-  if (g >= n_leaves) return;
-  // path leaf -> root
-  int len = 0;
-  if (lane == 0) {
-    int32_t u = leaves[g];
-    while (u >= 0 && len < kPathMax) {
-      path[wave][len++] = u;
-      u = parent[u];
-    }
-  }
-  len = __shfl(len, 0, 64);
-  __builtin_amdgcn_wave_barrier();
-  // lane k holds the descriptor of the k-th cell of the path (one round trip
-  // for the whole path); each step takes its fields from the step's lane
-  int64_t p_voff = 0, p_woff = 0, p_inoff = 0, p_scal = 0;
-  int p_m = 0, p_a = 0;
-  if (lane < len) {
-    const NodeDesc D = desc[path[wave][lane]];
-    p_voff = D.v_off;
-    p_woff = D.w_off;
-    p_inoff = D.in_off;
-    p_scal = D.scal_off;
-    p_m = D.m;
-    p_a = D.a;
-  }
-  auto from = [](int64_t x, int k) {
-    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)x, k);
-    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), k);
-    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-  };
-  int cur = 0;
-  for (int idx = len - 1; idx >= 0; --idx) {
-    const double* B = Vt + from(p_voff, idx);
-    const int m = __builtin_amdgcn_readlane(p_m, idx), a = __builtin_amdgcn_readlane(p_a, idx);
-    const int64_t in_off = from(p_inoff, idx);
-    const double* cs = idx == len - 1 ? vl : cbuf[wave][cur];  // the root's scaling part is L v (may be null)
-    const double* cw = vw + from(p_woff, idx) - a;
-    int lo = 0, cnt = m;
-    if (idx > 0) {
-      lo = (int)(from(p_scal, idx - 1) - in_off);  // 0 for the left child, a_left for the right
-      cnt = __builtin_amdgcn_readlane(p_a, idx - 1);
-    }
-    for (int i = lo + lane; i < lo + cnt; i += 64) {
-      double acc = 0.0;
-      if (cs) {
-        for (int j = 0; j < a; ++j) acc = fma(B[(int64_t)j * m + i], cs[j], acc);
-      }
-#pragma unroll 8
-      for (int j = a; j < m; ++j) acc = fma(B[(int64_t)j * m + i], cw[j], acc);
-      if (idx == 0) v[in_off + i] = acc;          // the leaf's values
-      else cbuf[wave][cur ^ 1][i - lo] = acc;     // the next cell's scaling coefficients
-    }
-    __builtin_amdgcn_wave_barrier();
-    cur ^= 1;
-  }
-}
-
-// The small top levels (few cells each) in one launch of one workgroup:
-// levels run in order with a workgroup barrier between them (the barrier
-// orders this workgroup's global writes and reads).
-struct TopLevels {
-  int32_t begin[kMaxTopLevels + 1];  // level q occupies [begin[q], begin[q+1]) of level_nodes, q = 0..nlev-1
-  int32_t nlev;
-};
-
-__global__ __launch_bounds__(kT) void analysis_top(const NodeDesc* __restrict__ desc,
-                                                   const int32_t* __restrict__ lnodes, TopLevels L,
-                                                   const double* __restrict__ V, const double* __restrict__ v,
-                                                   double* __restrict__ scal, double* __restrict__ vw,
-                                                   double* __restrict__ vl) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int q = L.nlev - 1; q >= 0; --q) {
-    for (int32_t s = L.begin[q] + wave; s < L.begin[q + 1]; s += kWavesPerBlock)
-      analysis_node(desc[lnodes[s]], lane, V, v, scal, vw, vl);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int32_t r = roots[blockIdx.x];
+  for (int rel = nlev - 1; rel >= 0; --rel) {
+    const int32_t u = group_cell(children, n_nodes, r, rel, wave);
+    if (u >= 0) analysis_node(desc[u], lane, V, v, scal, vw, vl);
     __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(kT) void synthesis_top(const NodeDesc* __restrict__ desc,
-                                                    const int32_t* __restrict__ lnodes, TopLevels L,
-                                                    const double* __restrict__ Vt, const double* __restrict__ vw,
-                                                    const double* __restrict__ vl, double* __restrict__ scal,
-                                                    double* __restrict__ v) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int q = 0; q < L.nlev; ++q) {
-    for (int32_t s = L.begin[q] + wave; s < L.begin[q + 1]; s += kWavesPerBlock)
-      synthesis_node(desc[lnodes[s]], lane, Vt, vw, vl, scal, v);
+__global__ __launch_bounds__(kT) void synthesis_group(const NodeDesc* __restrict__ desc,
+                                                      const int32_t* __restrict__ children, int32_t n_nodes,
+                                                      const int32_t* __restrict__ roots, int nlev,
+                                                      const double* __restrict__ Vt, const double* __restrict__ vw,
+                                                      const double* __restrict__ vl, double* __restrict__ scal,
+                                                      double* __restrict__ v) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int32_t r = roots[blockIdx.x];
+  for (int rel = 0; rel < nlev; ++rel) {
+    const int32_t u = group_cell(children, n_nodes, r, rel, wave);
+    if (u >= 0) synthesis_node(desc[u], lane, Vt, vw, vl, scal, v);
     __syncthreads();
   }
 }
@@ -373,55 +287,27 @@ Prof& prof() {
   return p;
 }
 
-// number of leading (shallow) levels small enough for the fused launch
-int top_levels(const TransformDev& T) {
-  int q = 0;
-  while (q < T.levels && q < kMaxTopLevels && T.lvl_begin_host[q + 1] - T.lvl_begin_host[q] <= kTopCells) ++q;
-  return q;
-}
-
-TopLevels make_top(const TransformDev& T, int nt) {
-  TopLevels L{};
-  for (int q = 0; q <= nt; ++q) L.begin[q] = T.lvl_begin_host[q];
-  L.nlev = nt;
-  return L;
-}
-
 }  // namespace
 
 int transform_analysis(const TransformDev& T, const double* v, double* vw, double* vl, double* scal, hipStream_t s) {
-  const int nt = top_levels(T);
-  for (int q = T.levels - 1; q >= nt; --q) {
-    const int32_t lb = T.lvl_begin_host[q], cnt = T.lvl_begin_host[q + 1] - lb;
+  for (int qhi = T.levels - 1; qhi >= 0; qhi -= kGroupLevels) {
+    const int qlo = qhi - (kGroupLevels - 1) > 0 ? qhi - (kGroupLevels - 1) : 0;
+    const int32_t lb = T.lvl_begin_host[qlo], cnt = T.lvl_begin_host[qlo + 1] - lb;
     if (cnt <= 0) continue;
-    const unsigned g = (unsigned)((cnt + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL(analysis_level, dim3(g), dim3(kT), 0, s, T.desc, T.level_nodes + lb, cnt, T.V, v, scal, vw,
-                       vl);
+    hipLaunchKernelGGL(analysis_group, dim3((unsigned)cnt), dim3(kT), 0, s, T.desc, T.children, T.n_nodes,
+                       T.level_nodes + lb, qhi - qlo + 1, T.V, v, scal, vw, vl);
   }
-  if (nt > 0)
-    hipLaunchKernelGGL(analysis_top, dim3(1), dim3(kT), 0, s, T.desc, T.level_nodes, make_top(T, nt), T.V, v, scal, vw,
-                       vl);
   return hip_check(hipGetLastError(), "analysis launch");
 }
 
 int transform_synthesis(const TransformDev& T, const double* vw, const double* vl, double* v, double* scal,
                         hipStream_t s) {
-  if (T.leaves && T.n_leaves > 0 && T.levels <= kPathMax && T.p <= kCoefMax) {
-    const unsigned g = (unsigned)((T.n_leaves + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL(synthesis_fused, dim3(g), dim3(kT), 0, s, T.desc, T.parent, T.leaves, T.n_leaves, T.Vt, vw,
-                       vl, v);
-    return hip_check(hipGetLastError(), "synthesis launch");
-  }
-  const int nt = top_levels(T);
-  if (nt > 0)
-    hipLaunchKernelGGL(synthesis_top, dim3(1), dim3(kT), 0, s, T.desc, T.level_nodes, make_top(T, nt), T.Vt, vw, vl,
-                       scal, v);
-  for (int q = nt; q < T.levels; ++q) {
-    const int32_t lb = T.lvl_begin_host[q], cnt = T.lvl_begin_host[q + 1] - lb;
+  for (int qlo = 0; qlo < T.levels; qlo += kGroupLevels) {
+    const int qhi = qlo + kGroupLevels - 1 < T.levels - 1 ? qlo + kGroupLevels - 1 : T.levels - 1;
+    const int32_t lb = T.lvl_begin_host[qlo], cnt = T.lvl_begin_host[qlo + 1] - lb;
     if (cnt <= 0) continue;
-    const unsigned g = (unsigned)((cnt + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL(synthesis_level, dim3(g), dim3(kT), 0, s, T.desc, T.level_nodes + lb, cnt, T.Vt, vw, vl,
-                       scal, v);
+    hipLaunchKernelGGL(synthesis_group, dim3((unsigned)cnt), dim3(kT), 0, s, T.desc, T.children, T.n_nodes,
+                       T.level_nodes + lb, qhi - qlo + 1, T.Vt, vw, vl, scal, v);
   }
   return hip_check(hipGetLastError(), "synthesis launch");
 }
