@@ -282,6 +282,14 @@ int mlblup_loglik(mlblup_basis b, const mlblup_matern* k, const double* z_dev, i
 int mlblup_mle_rho(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double rho_lo,
                    double rho_hi, double log_rho_tol, double* out4_host, void* work_dev, int64_t work_bytes,
                    void* stream);
+/* Maximum-likelihood (nu, rho) of l at the given level, sigma2 fixed, by the
+ * profile likelihood: golden-section search over nu in [nu_lo, nu_hi]
+ * (0 < nu_lo < nu_hi <= 8) until the bracket is below nu_tol, each point the
+ * rho maximum of mlblup_mle_rho on [rho_lo, rho_hi].  out5_host = {nu_hat,
+ * rho_hat, l(nu_hat, rho_hat), number of l evaluations, final nu bracket}. */
+int mlblup_mle_nu_rho(mlblup_basis b, double sigma2, const double* z_dev, int32_t level, double nu_lo, double nu_hi,
+                      double nu_tol, double rho_lo, double rho_hi, double log_rho_tol, double* out5_host,
+                      void* work_dev, int64_t work_bytes, void* stream);
 
 /* ---- preconditioner (remark on P_W = diag(C_W), Sec. 5.2) -----------------------
  * Built without forming C_W: the leaf kernel blocks and, for each internal

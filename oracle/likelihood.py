@@ -106,3 +106,19 @@ def mle_rho(S, Z, nu, basis: Basis, level: int, rho_lo: float, rho_hi: float, lo
 
     lr, val, evals = golden_max(f, math.log(rho_lo), math.log(rho_hi), log_tol)
     return math.exp(lr), val, evals
+
+
+def mle_nu_rho(S, Z, basis: Basis, level: int, nu_lo: float, nu_hi: float, rho_lo: float, rho_hi: float,
+               nu_tol: float = 1e-3, log_rho_tol: float = 1e-4, sigma2=1.0):
+    """(nu, rho) maximising l_level by the profile likelihood: golden
+    section over nu, each point the golden-section rho maximum.  Returns
+    (nu, rho, l)."""
+    best = {}
+
+    def profile(nu):
+        rho, val, _ = mle_rho(S, Z, nu, basis, level, rho_lo, rho_hi, log_rho_tol, sigma2)
+        best[nu] = rho
+        return val
+
+    nu, val, _ = golden_max(profile, nu_lo, nu_hi, nu_tol)
+    return nu, best[nu], val

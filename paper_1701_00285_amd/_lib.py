@@ -79,6 +79,8 @@ _SIGS = {
     "mlblup_loglik": (C.c_int, [_P, C.POINTER(Matern), _P, _I32, _P, _P, _I64, _P]),
     "mlblup_mle_rho": (C.c_int, [_P, C.POINTER(Matern), _P, _I32, C.c_double, C.c_double, C.c_double, _P, _P, _I64,
                                  _P]),
+    "mlblup_mle_nu_rho": (C.c_int, [_P, C.c_double, _P, _I32, C.c_double, C.c_double, C.c_double, C.c_double,
+                                    C.c_double, C.c_double, _P, _P, _I64, _P]),
     "mlblup_precond_workspace_bytes": (C.c_int, [_P, C.POINTER(_I64)]),
     "mlblup_precond_build": (C.c_int, [_P, C.POINTER(Matern), _I32, _P, _I64, _P, C.POINTER(_P)]),
     "mlblup_precond_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),

@@ -319,6 +319,18 @@ class Solver:
                                      float(log_rho_tol), _np_ptr(out), _ptr(ws), ws.numel(), _stream()))
         return dict(rho=out[0], loglik=out[1], evals=int(out[2]), bracket=out[3])
 
+    def mle_nu_rho(self, z, level, nu_lo, nu_hi, rho_lo, rho_hi, nu_tol=1e-3, log_rho_tol=1e-4):
+        """Maximum-likelihood (nu, rho) of the level's log-likelihood by the
+        profile likelihood (golden section over nu, each point the rho MLE):
+        dict(nu, rho, loglik, evals, bracket)."""
+        ws = self._loglik_ws(level)
+        out = np.zeros(5)
+        zt = self.to_tree(z).contiguous()
+        check(L.lib().mlblup_mle_nu_rho(self.basis.h, float(self.sigma2), _ptr(zt), int(level), float(nu_lo),
+                                        float(nu_hi), float(nu_tol), float(rho_lo), float(rho_hi), float(log_rho_tol),
+                                        _np_ptr(out), _ptr(ws), ws.numel(), _stream()))
+        return dict(nu=out[0], rho=out[1], loglik=out[2], evals=int(out[3]), bracket=out[4])
+
     # ---- solve / predict / grad ----
     def solve(self, zw, opts: PcgOptions | None = None, x0=None, rho=None, allow_noconv=False):
         torch = _torch()

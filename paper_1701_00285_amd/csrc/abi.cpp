@@ -1042,4 +1042,57 @@ int mlblup_mle_rho(mlblup_basis b, const mlblup_matern* k0, const double* z_dev,
   return MLBLUP_OK;
 }
 
+int mlblup_mle_nu_rho(mlblup_basis b, double sigma2, const double* z_dev, int32_t level, double nu_lo, double nu_hi,
+                      double nu_tol, double rho_lo, double rho_hi, double log_rho_tol, double* out5_host,
+                      void* work_dev, int64_t work_bytes, void* stream) {
+  clear_error();
+  if (!out5_host) return fail(MLBLUP_EINVAL, "mle_nu_rho: NULL output");
+  if (!(nu_lo > 0) || !(nu_hi > nu_lo) || nu_hi > 8.0) return fail(MLBLUP_EINVAL, "mle_nu_rho: need 0 < nu_lo < nu_hi <= 8");
+  if (!(nu_tol > 0)) return fail(MLBLUP_EINVAL, "mle_nu_rho: nu_tol must be > 0");
+  // profile likelihood: for each nu the rho MLE (golden section on log rho),
+  // then golden section over nu on that profile
+  int evals = 0;
+  auto profile = [&](double nu, double* val, double* rho) {
+    const mlblup_matern k{nu, 1.0, sigma2};
+    double o[4];
+    const int s2 = mlblup_mle_rho(b, &k, z_dev, level, rho_lo, rho_hi, log_rho_tol, o, work_dev, work_bytes, stream);
+    if (s2) return s2;
+    evals += (int)o[2];
+    *rho = o[0];
+    *val = o[1];
+    return MLBLUP_OK;
+  };
+  const double g = 0.6180339887498949;
+  double lo = nu_lo, hi = nu_hi;
+  double x1 = hi - g * (hi - lo), x2 = lo + g * (hi - lo), f1, f2, r1, r2;
+  int st;
+  if ((st = profile(x1, &f1, &r1)) || (st = profile(x2, &f2, &r2))) return st;
+  while (hi - lo > nu_tol) {
+    if (f1 >= f2) {
+      hi = x2;
+      x2 = x1;
+      f2 = f1;
+      r2 = r1;
+      x1 = hi - g * (hi - lo);
+      if ((st = profile(x1, &f1, &r1))) return st;
+    } else {
+      lo = x1;
+      x1 = x2;
+      f1 = f2;
+      r1 = r2;
+      x2 = lo + g * (hi - lo);
+      if ((st = profile(x2, &f2, &r2))) return st;
+    }
+  }
+  const double nu = 0.5 * (lo + hi);
+  double fm, rm;
+  if ((st = profile(nu, &fm, &rm))) return st;
+  out5_host[0] = nu;
+  out5_host[1] = rm;
+  out5_host[2] = fm;
+  out5_host[3] = (double)evals;
+  out5_host[4] = hi - lo;
+  return MLBLUP_OK;
+}
+
 }  // extern "C"

@@ -96,3 +96,19 @@ def test_loglik_error_paths():
     assert st == L.EINVAL
     with pytest.raises(MlblupError, match="EINVAL"):
         s.mle_rho(dev(wl.z), 0, 1.0, 0.5)
+
+
+def test_mle_nu_rho_matches_oracle():
+    """Profile-likelihood MLE of (nu, rho): golden section over nu with the
+    rho maximum at each point, on the GPU (general-nu FP64 kernel values) and
+    in the oracle (Bessel-form covariance)."""
+    require_gpu()
+    wl, nu, tree, bas, s = _both(1, 300)
+    Z = dev(wl.z)
+    level = tree.max_depth - 1
+    g = s.mle_nu_rho(Z, level, 0.3, 2.0, 0.02, 0.5, nu_tol=1e-2, log_rho_tol=1e-3)
+    o = OL.mle_nu_rho(wl.points, wl.z, bas, level, 0.3, 2.0, 0.02, 0.5, 1e-2, 1e-3)
+    say(f"mle (nu, rho) gpu ({g['nu']:.5f}, {g['rho']:.5f}) oracle ({o[0]:.5f}, {o[1]:.5f}) evals {g['evals']}")
+    assert abs(g["nu"] - o[0]) < 2e-2
+    assert abs(math.log(g["rho"]) - math.log(o[1])) < 5e-3
+    assert abs(g["loglik"] - o[2]) < 1e-8 * abs(o[2])

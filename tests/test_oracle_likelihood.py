@@ -91,3 +91,13 @@ def test_mle_is_a_local_maximum():
 def test_golden_max_on_a_parabola():
     x, fx, evals = OL.golden_max(lambda t: -(t - 0.3) ** 2, -2.0, 5.0, 1e-8)
     assert abs(x - 0.3) < 1e-8 and fx <= 0.0 and evals > 30
+
+
+def test_profile_mle_is_a_local_maximum_in_nu_and_rho():
+    wl, tree, bas = _case(1, 200)
+    level = tree.max_depth - 1
+    nu, rho, val = OL.mle_nu_rho(wl.points, wl.z, bas, level, 0.3, 2.0, 0.02, 0.5, 2e-2, 2e-3)
+    assert 0.3 < nu < 2.0 and 0.02 < rho < 0.5
+    for dn, dr in ((0.05, 0.0), (-0.05, 0.0), (0.0, 0.03), (0.0, -0.03)):
+        other = OL.multilevel_loglik(wl.points, wl.z, nu + dn, rho * math.exp(dr), bas, level)[0]
+        assert other <= val + 1e-9 * abs(val)
