@@ -193,7 +193,9 @@ def sweep(configs, reps: int = 10, warm: int = 3, nu=None):
 def loglik_bench(k: int, n: int, reps: int = 3):
     """Estimator path: l_n at the finest levels and at level 0 (each the
     median of `reps` calls after one untimed call, host clock around a call
-    that synchronises), and one golden-section MLE of rho at level t - 1.
+    that synchronises), the sparsified l~_n at levels t and t - 1 for tau from
+    0.05 (the distance of the paper's d = 3 estimation runs) to 0.4, with the
+    fill of C~^n_W, and one golden-section MLE of rho at level t - 1.
     Flops of one call: the dense Cholesky N~^3/3, the two batched analyses
     2 sum_cells m^2 (N + N~) and the covariance N^2 pairs."""
     import time
@@ -202,7 +204,7 @@ def loglik_bench(k: int, n: int, reps: int = 3):
     import torch
 
     import synth
-    from paper_1701_00285_amd import Solver
+    from paper_1701_00285_amd import MlblupError, Solver
     torch.cuda.set_device(0)
     wl = synth.make_config(k, n=n, n_targets=1)
     s = Solver(wl.points, wl.degree_w, wl.leaf_max, wl.nu, wl.rho, wl.sigma2)
@@ -223,6 +225,22 @@ def loglik_bench(k: int, n: int, reps: int = 3):
                                     "logdet": out["logdet"], "quad": out["quad"],
                                     "cholesky_gflop": round(nt ** 3 / 3 / 1e9, 2)}
         print(f"loglik level {level}: rows {nt}, {ms:.1f} ms", file=sys.stderr, flush=True)
+    res["sparsified"] = {}
+    for level in (t, t - 1):
+        for tau in (0.05, 0.1, 0.2, 0.4):
+            key = f"level {level} tau {tau}"
+            try:
+                t0 = time.perf_counter()
+                out = s.loglik(z, level, tau=tau)
+                ms = 1e3 * (time.perf_counter() - t0)
+                res["sparsified"][key] = {"ms": round(ms, 3), "fill": round(out["nnz"] / out["rows"] ** 2, 4),
+                                          "loglik": out["loglik"],
+                                          "exact_loglik": res["levels"][str(level)]["loglik"]}
+            except MlblupError as e:   # C~ not positive definite for this tau
+                res["sparsified"][key] = {"fill": round(s.basis.sparsity_pattern(level, tau) /
+                                                        res["levels"][str(level)]["rows"] ** 2, 4),
+                                          "error": str(e).split(":")[0]}
+            print(f"sparsified loglik {key}: {res['sparsified'][key]}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     m = s.mle_rho(z, t - 1, wl.rho / 10, wl.rho * 10, 1e-4)
     res["mle_rho_level_t_minus_1"] = {"rho_hat": m["rho"], "loglik": m["loglik"], "evals": m["evals"],

@@ -253,7 +253,7 @@ int mlblup_blup_grad(mlblup_basis b, const mlblup_matern* k, const double* z_dev
                      const double* lambda_dev, int32_t precision, double* Q_host, double* dQ_dlogrho_host,
                      void* work_dev, int64_t work_bytes, void* stream);
 
-/* ---- estimator: multilevel log-likelihood (Sec. 3 reduced likelihoods; Sec. 7) ----
+/* ---- estimator: multilevel log-likelihood (Sec. 5.1 reduced likelihoods; Sec. 6.1) ----
  * For the levels q >= level of W (rows [W_t; ...; W_level], the first
  * N~ rows of W, finest level first):
  *   l = -N~/2 log(2 pi) - 1/2 log det C^n_W - 1/2 (Z^n_W)^T (C^n_W)^-1 Z^n_W,
@@ -261,35 +261,52 @@ int mlblup_blup_grad(mlblup_basis b, const mlblup_matern* k, const double* z_dev
  * C^n_W is formed densely on the device from the N x N covariance and two
  * batched multilevel analyses, then factorized by a blocked FP64 Cholesky
  * G G^T = C^n_W: log det = 2 sum log G_ii, the quadratic form = |G^-1 Z^n_W|^2.
- * (The paper sparsifies C_W with distance rules and uses a sparse Cholesky;
- * this is the exact dense value.)  Any kernel of mlblup_matern.
+ * Any kernel of mlblup_matern.
+ * tau: the distance of the sparsification of Sec. 4.1.  tau = INFINITY gives
+ * the exact C^n_W.  A finite tau >= 0 gives the sparsified C~^n_W and l~: the
+ * block of two cells B_a (level i) and B_b (level j >= i) is kept when the
+ * kd-tree search from B_a reaches B_b at depth j, entering the left side of a
+ * split (axis k, threshold s) when min_{B_a} x_k - tau <= s and the right
+ * side when max_{B_a} x_k + tau > s (B_a's bounding box widened by tau meets
+ * that side); blocks of one level are kept when either search connects the
+ * pair, and every other block is zero.  The zeros are applied to the dense
+ * matrix (the factorization is not shortened by them).  C~^n_W need not be
+ * positive definite for small tau: then MLBLUP_EBREAKDOWN.
  * z_dev: N data values in tree order.  level: 0 .. levels - 1 (level 0 takes
  * all of W, where Z^0_W^T (C_W)^-1 Z^0_W is the Q of mlblup_blup_grad).
  * work_dev: at least the bytes from mlblup_loglik_workspace_bytes, which also
  * returns N~ in rows (may be NULL); about 8 (N^2 + N~ N) bytes, so N of a few
- * 10^4.  out3_host = {l, log det C^n_W, quadratic form}.  Synchronises
- * `stream`.  MLBLUP_EBREAKDOWN if a Cholesky pivot is not positive (C^n_W not
- * numerically positive definite, e.g. duplicate points). */
+ * 10^4.  out4_host = {l, log det, quadratic form, kept entries of the N~ x N~
+ * matrix}.  Synchronises `stream`.  MLBLUP_EINVAL for tau < 0 or NaN, a level
+ * outside the range or a short workspace; MLBLUP_EBREAKDOWN if a Cholesky
+ * pivot is not positive (not numerically positive definite, e.g. duplicate
+ * points or a small tau). */
 int mlblup_loglik_workspace_bytes(mlblup_basis b, int32_t level, int64_t* bytes, int64_t* rows);
-int mlblup_loglik(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double* out3_host,
-                  void* work_dev, int64_t work_bytes, void* stream);
-/* Maximum-likelihood rho of l at the given level, nu and sigma2 of k fixed
- * (k->rho is ignored): golden-section search on log rho over
- * [rho_lo, rho_hi] until the bracket is below log_rho_tol, each step one
- * mlblup_loglik evaluation (same workspace).  out4_host = {rho_hat,
- * l(rho_hat), number of evaluations, final bracket width in log rho}.  A
- * maximum on the boundary of the bracket is returned as found there. */
-int mlblup_mle_rho(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double rho_lo,
-                   double rho_hi, double log_rho_tol, double* out4_host, void* work_dev, int64_t work_bytes,
-                   void* stream);
-/* Maximum-likelihood (nu, rho) of l at the given level, sigma2 fixed, by the
- * profile likelihood: golden-section search over nu in [nu_lo, nu_hi]
+int mlblup_loglik(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double tau,
+                  double* out4_host, void* work_dev, int64_t work_bytes, void* stream);
+/* The pattern of C~^n_W for the given level and tau (Sec. 4.1 search, the
+ * rule of mlblup_loglik), on the host: *nnz = kept entries; mask_host (may be
+ * NULL) receives the N~ x N~ row-major 0/1 matrix in the row order of
+ * mlblup_loglik (caller-allocated, N~^2 bytes).  No device access. */
+int mlblup_sparsity_pattern(mlblup_basis b, int32_t level, double tau, int64_t* nnz, uint8_t* mask_host);
+/* Maximum-likelihood rho of l (or l~ for finite tau) at the given level, nu
+ * and sigma2 of k fixed (k->rho is ignored): golden-section search on log rho
+ * over [rho_lo, rho_hi] until the bracket is below log_rho_tol, each step one
+ * mlblup_loglik evaluation (same workspace; the pattern is built once).
+ * out4_host = {rho_hat, l(rho_hat), number of evaluations, final bracket width
+ * in log rho}.  A maximum on the boundary of the bracket is returned as found
+ * there. */
+int mlblup_mle_rho(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double tau,
+                   double rho_lo, double rho_hi, double log_rho_tol, double* out4_host, void* work_dev,
+                   int64_t work_bytes, void* stream);
+/* Maximum-likelihood (nu, rho) of l (or l~) at the given level, sigma2 fixed,
+ * by the profile likelihood: golden-section search over nu in [nu_lo, nu_hi]
  * (0 < nu_lo < nu_hi <= 8) until the bracket is below nu_tol, each point the
  * rho maximum of mlblup_mle_rho on [rho_lo, rho_hi].  out5_host = {nu_hat,
  * rho_hat, l(nu_hat, rho_hat), number of l evaluations, final nu bracket}. */
-int mlblup_mle_nu_rho(mlblup_basis b, double sigma2, const double* z_dev, int32_t level, double nu_lo, double nu_hi,
-                      double nu_tol, double rho_lo, double rho_hi, double log_rho_tol, double* out5_host,
-                      void* work_dev, int64_t work_bytes, void* stream);
+int mlblup_mle_nu_rho(mlblup_basis b, double sigma2, const double* z_dev, int32_t level, double tau, double nu_lo,
+                      double nu_hi, double nu_tol, double rho_lo, double rho_hi, double log_rho_tol,
+                      double* out5_host, void* work_dev, int64_t work_bytes, void* stream);
 
 /* ---- preconditioner (remark on P_W = diag(C_W), Sec. 5.2) -----------------------
  * Built without forming C_W: the leaf kernel blocks and, for each internal

@@ -76,11 +76,12 @@ _SIGS = {
                                       _P, _P, _P, _P, _I64, C.POINTER(PcgInfo), _P]),
     "mlblup_blup_grad": (C.c_int, [_P, C.POINTER(Matern), _P, _P, _P, _I32, _P, _P, _P, _I64, _P]),
     "mlblup_loglik_workspace_bytes": (C.c_int, [_P, _I32, C.POINTER(_I64), C.POINTER(_I64)]),
-    "mlblup_loglik": (C.c_int, [_P, C.POINTER(Matern), _P, _I32, _P, _P, _I64, _P]),
-    "mlblup_mle_rho": (C.c_int, [_P, C.POINTER(Matern), _P, _I32, C.c_double, C.c_double, C.c_double, _P, _P, _I64,
-                                 _P]),
+    "mlblup_loglik": (C.c_int, [_P, C.POINTER(Matern), _P, _I32, C.c_double, _P, _P, _I64, _P]),
+    "mlblup_sparsity_pattern": (C.c_int, [_P, _I32, C.c_double, C.POINTER(_I64), _P]),
+    "mlblup_mle_rho": (C.c_int, [_P, C.POINTER(Matern), _P, _I32, C.c_double, C.c_double, C.c_double, C.c_double, _P,
+                                 _P, _I64, _P]),
     "mlblup_mle_nu_rho": (C.c_int, [_P, C.c_double, _P, _I32, C.c_double, C.c_double, C.c_double, C.c_double,
-                                    C.c_double, C.c_double, _P, _P, _I64, _P]),
+                                    C.c_double, C.c_double, C.c_double, _P, _P, _I64, _P]),
     "mlblup_precond_workspace_bytes": (C.c_int, [_P, C.POINTER(_I64)]),
     "mlblup_precond_build": (C.c_int, [_P, C.POINTER(Matern), _I32, _P, _I64, _P, C.POINTER(_P)]),
     "mlblup_precond_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),

@@ -8,6 +8,7 @@ fallback: if the library is not built, the first call raises.
 from __future__ import annotations
 
 import ctypes as C
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -162,6 +163,17 @@ class Basis:
         check(self._lib.mlblup_basis_level_counts(self.h, _np_ptr(out)))
         return out
 
+    def sparsity_pattern(self, level, tau, mask=False):
+        """Kept entries of the sparsified C~^n_W (Sec. 4.1 tree search with
+        distance tau), and with mask=True also the N~ x N~ boolean pattern
+        (rows in the order of W)."""
+        nt = int(self.level_counts()[level:].sum())
+        nnz = C.c_int64()
+        m = np.zeros((nt, nt), dtype=np.uint8) if mask else None
+        check(self._lib.mlblup_sparsity_pattern(self.h, int(level), float(tau), C.byref(nnz),
+                                                _np_ptr(m) if mask else None))
+        return (nnz.value, m.astype(bool)) if mask else nnz.value
+
     def dense(self):
         """(W, L) with columns in tree order (small N only)."""
         W = np.empty((self.n_minus_p, self.n))
@@ -295,40 +307,42 @@ class Solver:
             ws = self._llws = torch.empty(need, dtype=torch.uint8, device=self.device)
         return ws
 
-    def loglik(self, z, level, rho=None, nu=None):
-        """Multilevel log-likelihood of z (input order) at `level`:
-        dict(loglik, logdet, quad, rows=N~)."""
+    def loglik(self, z, level, rho=None, nu=None, tau=math.inf):
+        """Multilevel log-likelihood of z (input order) at `level`; a finite
+        tau sparsifies C^n_W by the kd-tree search (Sec. 4.1):
+        dict(loglik, logdet, quad, rows=N~, nnz=kept entries)."""
         k = self.kernel(rho)
         if nu is not None:
             k = matern(nu, k.rho, k.sigma2)
         ws = self._loglik_ws(level)
-        out = np.zeros(3)
+        out = np.zeros(4)
         zt = self.to_tree(z).contiguous()
-        check(L.lib().mlblup_loglik(self.basis.h, C.byref(k), _ptr(zt), int(level), _np_ptr(out), _ptr(ws),
-                                    ws.numel(), _stream()))
-        return dict(loglik=out[0], logdet=out[1], quad=out[2], rows=self.loglik_workspace(level)[1])
+        check(L.lib().mlblup_loglik(self.basis.h, C.byref(k), _ptr(zt), int(level), float(tau), _np_ptr(out),
+                                    _ptr(ws), ws.numel(), _stream()))
+        return dict(loglik=out[0], logdet=out[1], quad=out[2], rows=self.loglik_workspace(level)[1], nnz=int(out[3]))
 
-    def mle_rho(self, z, level, rho_lo, rho_hi, log_rho_tol=1e-6, nu=None):
+    def mle_rho(self, z, level, rho_lo, rho_hi, log_rho_tol=1e-6, nu=None, tau=math.inf):
         """Maximum-likelihood rho of the level's log-likelihood (golden
         section on log rho): dict(rho, loglik, evals, bracket)."""
         k = matern(self.nu if nu is None else nu, 1.0, self.sigma2)
         ws = self._loglik_ws(level)
         out = np.zeros(4)
         zt = self.to_tree(z).contiguous()
-        check(L.lib().mlblup_mle_rho(self.basis.h, C.byref(k), _ptr(zt), int(level), float(rho_lo), float(rho_hi),
-                                     float(log_rho_tol), _np_ptr(out), _ptr(ws), ws.numel(), _stream()))
+        check(L.lib().mlblup_mle_rho(self.basis.h, C.byref(k), _ptr(zt), int(level), float(tau), float(rho_lo),
+                                     float(rho_hi), float(log_rho_tol), _np_ptr(out), _ptr(ws), ws.numel(),
+                                     _stream()))
         return dict(rho=out[0], loglik=out[1], evals=int(out[2]), bracket=out[3])
 
-    def mle_nu_rho(self, z, level, nu_lo, nu_hi, rho_lo, rho_hi, nu_tol=1e-3, log_rho_tol=1e-4):
+    def mle_nu_rho(self, z, level, nu_lo, nu_hi, rho_lo, rho_hi, nu_tol=1e-3, log_rho_tol=1e-4, tau=math.inf):
         """Maximum-likelihood (nu, rho) of the level's log-likelihood by the
         profile likelihood (golden section over nu, each point the rho MLE):
         dict(nu, rho, loglik, evals, bracket)."""
         ws = self._loglik_ws(level)
         out = np.zeros(5)
         zt = self.to_tree(z).contiguous()
-        check(L.lib().mlblup_mle_nu_rho(self.basis.h, float(self.sigma2), _ptr(zt), int(level), float(nu_lo),
-                                        float(nu_hi), float(nu_tol), float(rho_lo), float(rho_hi), float(log_rho_tol),
-                                        _np_ptr(out), _ptr(ws), ws.numel(), _stream()))
+        check(L.lib().mlblup_mle_nu_rho(self.basis.h, float(self.sigma2), _ptr(zt), int(level), float(tau),
+                                        float(nu_lo), float(nu_hi), float(nu_tol), float(rho_lo), float(rho_hi),
+                                        float(log_rho_tol), _np_ptr(out), _ptr(ws), ws.numel(), _stream()))
         return dict(nu=out[0], rho=out[1], loglik=out[2], evals=int(out[3]), bracket=out[4])
 
     # ---- solve / predict / grad ----

@@ -959,14 +959,16 @@ int mlblup_loglik_workspace_bytes(mlblup_basis b, int32_t level, int64_t* bytes,
   return MLBLUP_OK;
 }
 
-static int loglik_common(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, void* work_dev,
-                         int64_t work_bytes, TransformDev* T, LoglikLayout* L, PairArgs* a) {
+static int loglik_common(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double tau,
+                         void* work_dev, int64_t work_bytes, TransformDev* T, LoglikLayout* L, PairArgs* a,
+                         int64_t* nnz, hipStream_t stream) {
   int st = check_basis_dev(b);
   if (st) return st;
   if ((st = check_kernel(k))) return st;
   const Basis& B = b->b;
   if (level < 0 || level >= B.levels)
     return fail(MLBLUP_EINVAL, "loglik: level must be in [0, " + std::to_string(B.levels - 1) + "]");
+  if (!(tau >= 0)) return fail(MLBLUP_EINVAL, "loglik: tau must be >= 0 (inf = no sparsification)");
   if (!z_dev) return fail(MLBLUP_EINVAL, "loglik: NULL data vector");
   *L = loglik_layout(B, level);
   if (!work_dev || work_bytes < L->total)
@@ -974,24 +976,55 @@ static int loglik_common(mlblup_basis b, const mlblup_matern* k, const double* z
   *T = transform_dev(B);
   *a = PairArgs{nullptr, 0, nullptr, B.n, B.d, nu2_of(k), k->rho, k->sigma2, MLBLUP_FP64, MLBLUP_VALUE,
                 nullptr, nullptr, nullptr, k->nu, nullptr};
+  *nnz = L->rows * L->rows;
+  if (std::isfinite(tau)) {
+    Pattern P;
+    build_pattern(B, level, tau, P);
+    *nnz = P.nnz;
+    if ((st = loglik_upload_pattern(P, work_dev, *L, stream))) return st;
+  }
   return MLBLUP_OK;
 }
 
-int mlblup_loglik(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double* out3_host,
-                  void* work_dev, int64_t work_bytes, void* stream) {
+int mlblup_sparsity_pattern(mlblup_basis b, int32_t level, double tau, int64_t* nnz, uint8_t* mask_host) {
   clear_error();
-  if (!out3_host) return fail(MLBLUP_EINVAL, "loglik: NULL output");
+  if (!b || !nnz) return fail(MLBLUP_EINVAL, "NULL argument");
+  const Basis& B = b->b;
+  if (level < 0 || level >= B.levels)
+    return fail(MLBLUP_EINVAL, "sparsity_pattern: level must be in [0, " + std::to_string(B.levels - 1) + "]");
+  if (!(tau >= 0)) return fail(MLBLUP_EINVAL, "sparsity_pattern: tau must be >= 0 (inf = no sparsification)");
+  Pattern P;
+  build_pattern(B, level, tau, P);
+  *nnz = P.nnz;
+  if (mask_host) {
+    const int64_t nt = (int64_t)P.rowcell.size();
+    for (int64_t r = 0; r < nt; ++r) {
+      const uint8_t* kr = &P.keep[(size_t)P.rowcell[r] * P.nc];
+      for (int64_t c = 0; c < nt; ++c) mask_host[r * nt + c] = kr[P.rowcell[c]];
+    }
+  }
+  return MLBLUP_OK;
+}
+
+int mlblup_loglik(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double tau,
+                  double* out4_host, void* work_dev, int64_t work_bytes, void* stream) {
+  clear_error();
+  if (!out4_host) return fail(MLBLUP_EINVAL, "loglik: NULL output");
   TransformDev T;
   LoglikLayout L;
   PairArgs a;
-  int st = loglik_common(b, k, z_dev, level, work_dev, work_bytes, &T, &L, &a);
+  int64_t nnz = 0;
+  int st = loglik_common(b, k, z_dev, level, tau, work_dev, work_bytes, &T, &L, &a, &nnz, (hipStream_t)stream);
   if (st) return st;
-  return loglik_device(b->b, T, a, level, z_dev, work_dev, L, out3_host, (hipStream_t)stream);
+  if ((st = loglik_device(b->b, T, a, level, z_dev, work_dev, L, std::isfinite(tau), out4_host, (hipStream_t)stream)))
+    return st;
+  out4_host[3] = (double)nnz;
+  return MLBLUP_OK;
 }
 
-int mlblup_mle_rho(mlblup_basis b, const mlblup_matern* k0, const double* z_dev, int32_t level, double rho_lo,
-                   double rho_hi, double log_rho_tol, double* out4_host, void* work_dev, int64_t work_bytes,
-                   void* stream) {
+int mlblup_mle_rho(mlblup_basis b, const mlblup_matern* k0, const double* z_dev, int32_t level, double tau,
+                   double rho_lo, double rho_hi, double log_rho_tol, double* out4_host, void* work_dev,
+                   int64_t work_bytes, void* stream) {
   clear_error();
   if (!out4_host) return fail(MLBLUP_EINVAL, "mle_rho: NULL output");
   if (!(rho_lo > 0) || !(rho_hi > rho_lo) || !std::isfinite(rho_hi))
@@ -1000,14 +1033,16 @@ int mlblup_mle_rho(mlblup_basis b, const mlblup_matern* k0, const double* z_dev,
   TransformDev T;
   LoglikLayout L;
   PairArgs a;
-  int st = loglik_common(b, k0, z_dev, level, work_dev, work_bytes, &T, &L, &a);
+  int64_t nnz = 0;
+  int st = loglik_common(b, k0, z_dev, level, tau, work_dev, work_bytes, &T, &L, &a, &nnz, (hipStream_t)stream);
   if (st) return st;
+  const bool masked = std::isfinite(tau);
   int evals = 0;
   auto f = [&](double lr, double* v) {
     PairArgs q = a;
     q.rho = std::exp(lr);
     double out[3];
-    const int s2 = loglik_device(b->b, T, q, level, z_dev, work_dev, L, out, (hipStream_t)stream);
+    const int s2 = loglik_device(b->b, T, q, level, z_dev, work_dev, L, masked, out, (hipStream_t)stream);
     ++evals;
     *v = out[0];
     return s2;
@@ -1042,9 +1077,9 @@ int mlblup_mle_rho(mlblup_basis b, const mlblup_matern* k0, const double* z_dev,
   return MLBLUP_OK;
 }
 
-int mlblup_mle_nu_rho(mlblup_basis b, double sigma2, const double* z_dev, int32_t level, double nu_lo, double nu_hi,
-                      double nu_tol, double rho_lo, double rho_hi, double log_rho_tol, double* out5_host,
-                      void* work_dev, int64_t work_bytes, void* stream) {
+int mlblup_mle_nu_rho(mlblup_basis b, double sigma2, const double* z_dev, int32_t level, double tau, double nu_lo,
+                      double nu_hi, double nu_tol, double rho_lo, double rho_hi, double log_rho_tol,
+                      double* out5_host, void* work_dev, int64_t work_bytes, void* stream) {
   clear_error();
   if (!out5_host) return fail(MLBLUP_EINVAL, "mle_nu_rho: NULL output");
   if (!(nu_lo > 0) || !(nu_hi > nu_lo) || nu_hi > 8.0) return fail(MLBLUP_EINVAL, "mle_nu_rho: need 0 < nu_lo < nu_hi <= 8");
@@ -1055,7 +1090,8 @@ int mlblup_mle_nu_rho(mlblup_basis b, double sigma2, const double* z_dev, int32_
   auto profile = [&](double nu, double* val, double* rho) {
     const mlblup_matern k{nu, 1.0, sigma2};
     double o[4];
-    const int s2 = mlblup_mle_rho(b, &k, z_dev, level, rho_lo, rho_hi, log_rho_tol, o, work_dev, work_bytes, stream);
+    const int s2 =
+        mlblup_mle_rho(b, &k, z_dev, level, tau, rho_lo, rho_hi, log_rho_tol, o, work_dev, work_bytes, stream);
     if (s2) return s2;
     evals += (int)o[2];
     *rho = o[0];

@@ -181,6 +181,9 @@ int build_basis(const Tree& t, int32_t w, double rank_rtol, Basis& B) {
   B.end = t.end;
   B.left = t.left;
   B.right = t.right;
+  B.depth = t.depth;
+  B.axis = t.axis;
+  B.threshold = t.threshold;
 
   B.pts_tree.resize((size_t)n * d);
   for (int64_t i = 0; i < n; ++i)

@@ -103,14 +103,19 @@ int transform_synthesis(const TransformDev& T, const double* vw, const double* v
 // workspace layout (byte offsets) for the levels >= level
 struct LoglikLayout {
   int64_t phi = 0, a = 0, scal = 0, zw = 0, scalz = 0, out = 0, flag = 0, gtab = 0, linv = 0, total = 0;
+  int64_t rowcell = 0, keep = 0;   // sparsity pattern of C~^n_W: cell of each row, cell-pair keep matrix
   int64_t rows = 0;    // N~: rows of [W_t; ...; W_level]
+  int32_t cells = 0;   // cells with wavelets at levels >= level
   int64_t batch = 0;   // columns per batched-analysis pass
 };
 int64_t loglik_rows(const Basis& B, int32_t level);
 LoglikLayout loglik_layout(const Basis& B, int32_t level);
-// out = {l, log det C^n_W, (Z^n_W)^T (C^n_W)^-1 Z^n_W}; k supplies nu2, nu, rho, sigma2
+// copies the pattern (built for the same level) into the workspace; synchronises s
+int loglik_upload_pattern(const Pattern& P, void* work, const LoglikLayout& L, hipStream_t s);
+// out = {l, log det C^n_W, (Z^n_W)^T (C^n_W)^-1 Z^n_W}; k supplies nu2, nu, rho, sigma2.
+// masked: zero the blocks the uploaded pattern drops (C~^n_W in place of C^n_W)
 int loglik_device(const Basis& B, const TransformDev& T, const PairArgs& k, int32_t level, const double* z,
-                  void* work, const LoglikLayout& L, double out[3], hipStream_t s);
+                  void* work, const LoglikLayout& L, bool masked, double out[3], hipStream_t s);
 
 // ---- vector kernels (deterministic FP64 reductions) -------------------------------
 constexpr int kRedBlocks = 512;   // fixed partial count of every reduction

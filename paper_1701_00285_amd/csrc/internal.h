@@ -65,6 +65,8 @@ struct Basis {
   std::vector<double> pts_tree;   // points in tree order, row-major
   std::vector<int64_t> begin, end;   // node point ranges (tree order)
   std::vector<int32_t> left, right;  // children (-1 for leaves)
+  std::vector<int32_t> depth, axis;  // node depth; split axis (-1 for leaves)
+  std::vector<double> threshold;     // split threshold: x_axis <= threshold goes left
   // trend: root frame (centre, scale) and L X_loc = Ms^T (p x p) for beta
   std::vector<double> root_c;
   double root_h = 1.0;
@@ -79,6 +81,17 @@ struct Basis {
 };
 
 int build_basis(const Tree& t, int32_t w, double rank_rtol, Basis& b);
+
+// Sparsity pattern of C~^n_W (Sec. 4.1): the cells with wavelets at levels
+// >= level, each row's cell, and a symmetric cell-pair keep matrix.
+struct Pattern {
+  int32_t nc = 0;                  // cells
+  std::vector<int32_t> rowcell;    // N~: cell of every row of C^n_W
+  std::vector<uint8_t> keep;       // nc x nc, 1 = block kept
+  int64_t nnz = 0;                 // kept entries of the N~ x N~ matrix
+};
+int32_t pattern_cells(const Basis& b, int32_t level);
+void build_pattern(const Basis& b, int32_t level, double tau, Pattern& P);
 int64_t basis_device_bytes(const Basis& b);
 
 // exponent tuples of the total-degree set, graded lexicographic

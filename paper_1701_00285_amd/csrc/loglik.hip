@@ -1,12 +1,12 @@
-// Multilevel log-likelihood of the partial transform (Sec. 3, the reduced
-// likelihoods after the Proposition on nested condition numbers):
+// Multilevel log-likelihood of the partial transform (Sec. 5.1, the reduced
+// likelihoods and the Proposition on nested condition numbers):
 //
 //   l_n(theta) = -N~/2 log(2 pi) - 1/2 log det C^n_W - 1/2 (Z^n_W)^T (C^n_W)^-1 Z^n_W,
 //
 // with Z^n_W = [W_t; ...; W_n] Z (the first N~ rows of W, finest level
 // first) and C^n_W the leading N~ x N~ block of C_W = W C W^T.  The
 // determinant and the quadratic form come from one Cholesky factor G of
-// C^n_W (Sec. 7, estimator computation): log det = 2 sum log G_ii, and the
+// C^n_W (Sec. 6.1, estimator computation): log det = 2 sum log G_ii, and the
 // quadratic form is |y|^2 with G y = Z^n_W.
 //
 // Device steps (all FP64):
@@ -20,9 +20,12 @@
 //     trailing update of the lower triangle in 128 x 128 tiles;
 //  5. G y = Z^n_W by block forward substitution with the stored inverses;
 //     2 sum log G_ii and |y|^2 by fixed-order reductions.
-// The paper factorizes a sparsified C~^n_W with a sparse Cholesky and nested
-// dissection; here C^n_W is dense and exact (288 GB of HBM hold it for N~ up
-// to about 10^5).
+// With a finite distance tau, the blocks of cell pairs that the tree search
+// of Sec. 4.1 does not connect are zeroed after step 3 (apply_pattern), which
+// gives the sparsified C~^n_W and l~_n.  The paper factorizes C~^n_W with a
+// sparse Cholesky and nested dissection; here the factorization is dense
+// (288 GB of HBM hold C^n_W for N~ up to about 10^5), so the zeros do not
+// shorten it, and tau = inf gives the exact C^n_W.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -129,6 +132,19 @@ __global__ __launch_bounds__(kTr * 8) void transpose(const double* __restrict__ 
     const int64_t gc = c0 + c, gr = r0 + tx;
     if (gc < cols && gr < rows) out[gc * ldo + gr] = t[tx][c];
   }
+}
+
+// ---- 3b. sparsity pattern: zero the blocks of unconnected cell pairs --------
+// One thread per column, rows strided over grid.y; rowcell maps a row or a
+// column of C^n_W to its cell, keep is the nc x nc cell-pair matrix.
+__global__ __launch_bounds__(kT) void apply_pattern(double* __restrict__ C, int64_t nt,
+                                                    const int32_t* __restrict__ rowcell,
+                                                    const uint8_t* __restrict__ keep, int32_t nc) {
+  const int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (c >= nt) return;
+  const int64_t cc = rowcell[c];
+  for (int64_t r = blockIdx.y; r < nt; r += gridDim.y)
+    if (!keep[(int64_t)rowcell[r] * nc + cc]) C[r * nt + c] = 0.0;
 }
 
 // ---- 4. blocked Cholesky (lower), A is n x n with leading dimension ld --------
@@ -384,6 +400,11 @@ LoglikLayout loglik_layout(const Basis& B, int32_t level) {
   o += align256(kGenuBytes);
   L.linv = o;  // the inverse of every diagonal block of the factor
   o += align256(std::max<int64_t>((nt + kNb - 1) / kNb, 1) * kNb * kNb * 8);
+  L.cells = pattern_cells(B, level);
+  L.rowcell = o;
+  o += align256(std::max<int64_t>(nt, 1) * 4);
+  L.keep = o;
+  o += align256(std::max<int64_t>((int64_t)L.cells * L.cells, 1));
   L.total = o;
   L.rows = nt;
   L.batch = batch;
@@ -407,8 +428,20 @@ static int analysis_batched(const Basis& B, const TransformDev& T, int32_t level
   return hip_check(hipGetLastError(), "batched analysis launch");
 }
 
+int loglik_upload_pattern(const Pattern& P, void* work, const LoglikLayout& L, hipStream_t s) {
+  if (P.nc != L.cells || (int64_t)P.rowcell.size() != L.rows)
+    return fail(MLBLUP_EINVAL, "loglik: sparsity pattern does not match the level");
+  char* w = (char*)work;
+  if (L.rows > 0) {
+    MLB_HIP(hipMemcpyAsync(w + L.rowcell, P.rowcell.data(), P.rowcell.size() * 4, hipMemcpyHostToDevice, s));
+    MLB_HIP(hipMemcpyAsync(w + L.keep, P.keep.data(), P.keep.size(), hipMemcpyHostToDevice, s));
+  }
+  MLB_HIP(hipStreamSynchronize(s));
+  return MLBLUP_OK;
+}
+
 int loglik_device(const Basis& B, const TransformDev& T, const PairArgs& k, int32_t level, const double* z,
-                  void* work, const LoglikLayout& L, double out[3], hipStream_t s) {
+                  void* work, const LoglikLayout& L, bool masked, double out[3], hipStream_t s) {
   char* w = (char*)work;
   double* phi = (double*)(w + L.phi);
   double* A = (double*)(w + L.a);
@@ -462,6 +495,12 @@ int loglik_device(const Basis& B, const TransformDev& T, const PairArgs& k, int3
   }
   double* C = A;
   if ((st = analysis_batched(B, T, level, phi, nt, nt, scal, L.batch, C, nt, nt, s))) return st;
+  if (masked) {
+    dim3 grid((unsigned)((nt + kT - 1) / kT), (unsigned)std::min<int64_t>(nt, 65535));
+    hipLaunchKernelGGL(apply_pattern, grid, dim3(kT), 0, s, C, nt, (const int32_t*)(w + L.rowcell),
+                       (const uint8_t*)(w + L.keep), L.cells);
+    if ((st = hip_check(hipGetLastError(), "sparsity pattern launch"))) return st;
+  }
   // 4. Cholesky
   const int64_t nblk = (nt + kNb - 1) / kNb;
   for (int64_t kb = 0; kb < nblk; ++kb) {

@@ -89,13 +89,16 @@ def test_loglik_error_paths():
         s.loglik(dev(wl.z), s.basis.levels)
     k = matern(nu, wl.rho)
     small = torch.empty(1024, dtype=torch.uint8, device="cuda")
-    out = np.zeros(3)
+    out = np.zeros(4)
     zt = s.to_tree(dev(wl.z)).contiguous()
-    st = L.lib().mlblup_loglik(s.basis.h, C.byref(k), C.c_void_p(zt.data_ptr()), 0,
+    st = L.lib().mlblup_loglik(s.basis.h, C.byref(k), C.c_void_p(zt.data_ptr()), 0, math.inf,
                                out.ctypes.data_as(C.c_void_p), C.c_void_p(small.data_ptr()), small.numel(), None)
     assert st == L.EINVAL
     with pytest.raises(MlblupError, match="EINVAL"):
         s.mle_rho(dev(wl.z), 0, 1.0, 0.5)
+    for tau in (-0.5, float("nan")):
+        with pytest.raises(MlblupError, match="EINVAL"):
+            s.loglik(dev(wl.z), 0, tau=tau)
 
 
 def test_mle_nu_rho_matches_oracle():
@@ -112,3 +115,78 @@ def test_mle_nu_rho_matches_oracle():
     assert abs(g["nu"] - o[0]) < 2e-2
     assert abs(math.log(g["rho"]) - math.log(o[1])) < 5e-3
     assert abs(g["loglik"] - o[2]) < 1e-8 * abs(o[2])
+
+
+# ---- sparsified C~^n_W (Sec. 4.1 tree search with distance tau) ------------------
+
+def _cond_sparse(wl, nu, tree, bas, level, tau):
+    nt = OL.level_rows(bas, level)
+    C = cov_matrix(wl.points, wl.points, nu, wl.rho)
+    Cn = bas.W[:nt] @ C @ bas.W[:nt].T
+    ev = np.linalg.eigvalsh(np.where(OL.sparsity_mask(wl.points, tree, bas, level, tau), Cn, 0.0))
+    return ev[-1] / ev[0]
+
+
+# (cfg, n, levels below the finest, tau): cases where C~^n_W stays positive definite
+SPARSE = [(1, 1000, 0, 0.0), (1, 1000, 0, 0.05), (1, 1000, 1, 0.05), (1, 1000, 1, 0.2),
+          (2, 900, 0, 0.0), (2, 900, 0, 0.05), (2, 900, 1, 0.1), (4, 700, 0, 0.0), (4, 700, 1, 0.2)]
+
+
+@pytest.mark.parametrize("k,n,up,tau", SPARSE)
+def test_sparsified_loglik_matches_oracle(k, n, up, tau):
+    require_gpu()
+    wl, nu, tree, bas, s = _both(k, n)
+    level = tree.max_depth - up
+    g = s.loglik(dev(wl.z), level, tau=tau)
+    o = OL.multilevel_loglik(wl.points, wl.z, nu, wl.rho, bas, level, tree=tree, tau=tau)
+    kap = _cond_sparse(wl, nu, tree, bas, level, tau)
+    assert kap > 0
+    tq = max(1e-12, 50 * kap * 2.2e-16)
+    td = tq * o[3]
+    say(f"sparse loglik cfg{k} n={n} level={level} tau={tau} nnz={g['nnz']} kappa={kap:.1e} "
+        f"dlogdet={abs(g['logdet'] - o[1]):.1e} dquad={abs(g['quad'] - o[2]) / abs(o[2]):.1e}")
+    assert g["nnz"] == s.basis.sparsity_pattern(level, tau) == int(
+        OL.sparsity_mask(wl.points, tree, bas, level, tau).sum())
+    assert abs(g["logdet"] - o[1]) < td
+    assert abs(g["quad"] - o[2]) < tq * abs(o[2])
+    assert abs(g["loglik"] - o[0]) < td + tq * abs(o[2])
+
+
+def test_sparsified_loglik_with_everything_kept_is_the_exact_value():
+    require_gpu()
+    wl, nu, tree, bas, s = _both(2, 900)
+    z = dev(wl.z)
+    for level in (tree.max_depth, 1):
+        a = s.loglik(z, level)
+        b = s.loglik(z, level, tau=4.0)   # the widened unit cube covers every region
+        assert a["nnz"] == b["nnz"] == a["rows"] ** 2
+        assert (a["loglik"], a["logdet"], a["quad"]) == (b["loglik"], b["logdet"], b["quad"])
+
+
+@pytest.mark.parametrize("k,n,level,tau", [(1, 1000, 0, 0.0), (4, 700, -1, 0.02)])
+def test_indefinite_sparsified_matrix_is_a_breakdown(k, n, level, tau):
+    """Small tau at coarse levels drops enough of C^n_W to make it indefinite
+    (smallest eigenvalue about -0.2 and -0.1 here): EBREAKDOWN, as the
+    oracle's Cholesky fails too."""
+    require_gpu()
+    from paper_1701_00285_amd import MlblupError
+    wl, nu, tree, bas, s = _both(k, n)
+    level = tree.max_depth if level < 0 else level
+    with pytest.raises(np.linalg.LinAlgError):
+        OL.multilevel_loglik(wl.points, wl.z, nu, wl.rho, bas, level, tree=tree, tau=tau)
+    with pytest.raises(MlblupError, match="EBREAKDOWN"):
+        s.loglik(dev(wl.z), level, tau=tau)
+    # the workspace stays usable
+    g = s.loglik(dev(wl.z), tree.max_depth, tau=0.0 if k == 1 else 0.2)
+    assert math.isfinite(g["loglik"])
+
+
+def test_sparsified_mle_rho_matches_oracle():
+    require_gpu()
+    wl, nu, tree, bas, s = _both(1, 600)
+    level = tree.max_depth - 1
+    g = s.mle_rho(dev(wl.z), level, 0.01, 1.0, 1e-5, tau=0.05)
+    o = OL.mle_rho(wl.points, wl.z, nu, bas, level, 0.01, 1.0, 1e-5, tree=tree, tau=0.05)
+    say(f"sparse mle rho gpu {g['rho']:.8f} oracle {o[0]:.8f} evals {g['evals']}")
+    assert abs(math.log(g["rho"]) - math.log(o[0])) < 3e-5
+    assert abs(g["loglik"] - o[1]) < 1e-9 * abs(o[1])
