@@ -15,10 +15,13 @@
 //     applied to column blocks of Phi, level by level from the finest to n
 //     (batched_analysis: one workgroup per cell and 256 columns);
 //  3. A^T (tiled transpose), then C^n_W = (W A^T) restricted to N~ rows;
-//  4. blocked right-looking Cholesky, blocks of 64: the diagonal factor and
-//     its inverse in LDS, the panel as a product with that inverse, the
-//     trailing update of the lower triangle in 128 x 128 tiles;
-//  5. G y = Z^n_W by block forward substitution with the stored inverses;
+//  4. blocked right-looking Cholesky: panels of 256 columns, each factored
+//     in blocks of 64 (the diagonal factor and its inverse in one wave, the
+//     panel below as a product with that inverse, the update of the panel's
+//     remaining columns), then one rank-256 update of the trailing lower
+//     triangle in 128 x 128 tiles;
+//  5. G y = Z^n_W inside the factorization: Z^n_W is appended as row N~ of
+//     the matrix, which the panel products and updates turn into y;
 //     2 sum log G_ii and |y|^2 by fixed-order reductions.
 // With a finite distance tau, the blocks of cell pairs that the tree search
 // of Sec. 4.1 does not connect are zeroed after step 3 (apply_pattern), which
@@ -31,6 +34,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -148,65 +152,70 @@ __global__ __launch_bounds__(kT) void apply_pattern(double* __restrict__ C, int6
 }
 
 // ---- 4. blocked Cholesky (lower), A is n x n with leading dimension ld --------
-// Factor of the diagonal block at k0 (size nb <= kNb) in LDS, and the
-// inverse of that factor (into linv, kNb x kNb row-major), which turns the
-// panel solve and the forward substitution into products.  One barrier per
-// column: step j reads column j and the pivot unscaled, writes the scaled
-// column to a second array and updates the trailing triangle with
-// a_rj a_cj / a_jj.  A pivot that is not positive and finite sets flag[0]
-// (the factor then continues with 1).
-__global__ __launch_bounds__(kT) void potrf_diag(double* __restrict__ A, int64_t ld, int64_t k0, int nb,
-                                                 double* __restrict__ linv, int* __restrict__ flag) {
-  __shared__ double a[kNb][kNb + 1];
-  __shared__ double l[kNb][kNb + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kNb * kNb; e += kT) {
+// Factor of the diagonal block at k0 (size nb <= kNb) and the inverse of that
+// factor (into linv, kNb x kNb row-major), which turns the panel solve and
+// the forward substitution into products.  One wave: lane i keeps row i of
+// the block in registers.  Step j takes the pivot from lane j, scales each
+// lane's column-j entry, passes the scaled column through LDS and updates
+// every lane's row with it (right-looking, no workgroup-wide barrier beyond
+// the wave's own).  A pivot that is not positive and finite sets flag[0]
+// (the factor then continues with 1).  The inverse: lane c forms column c of
+// G^-1 by forward substitution, reading the factor's rows from LDS (the same
+// address on every lane).
+__global__ __launch_bounds__(kNb) void potrf_diag(double* __restrict__ A, int64_t ld, int64_t k0, int nb,
+                                                  double* __restrict__ linv, int* __restrict__ flag) {
+  __shared__ double s[kNb][kNb + 1];
+  __shared__ double col[kNb];
+  const int i = threadIdx.x;
+  for (int e = i; e < kNb * kNb; e += kNb) {
     const int r = e / kNb, c = e % kNb;
-    a[r][c] = (r < nb && c <= r) ? A[(k0 + r) * ld + k0 + c] : 0.0;
-    l[r][c] = 0.0;
-  }
-  for (int j = 0; j < nb; ++j) {
-    __syncthreads();
-    double p = a[j][j];
-    const bool ok = p > 0.0 && __builtin_isfinite(p);
-    if (!ok) {
-      if (tid == 0) flag[0] = 1;
-      p = 1.0;
-    }
-    const double dj = sqrt(p), inv = 1.0 / p;
-    for (int r = j + tid; r < nb; r += kT) l[r][j] = r == j ? dj : a[r][j] / dj;
-    const int rem = nb - j - 1;
-    for (int e = tid; e < rem * rem; e += kT) {
-      const int r = j + 1 + e / rem, c = j + 1 + e % rem;
-      if (c <= r) a[r][c] = fma(-a[r][j] * inv, a[c][j], a[r][c]);
-    }
+    s[r][c] = (r < nb && c <= r) ? A[(k0 + r) * ld + k0 + c] : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < nb * nb; e += kT) {
-    const int r = e / nb, c = e % nb;
-    if (c <= r) A[(k0 + r) * ld + k0 + c] = l[r][c];
-  }
-  // inverse of the lower factor, column c = L^-1 e_c by forward substitution,
-  // four adjacent lanes per column (each a quarter of every dot product,
-  // combined across the quad); a column's lanes share a wave, whose LDS
-  // accesses are ordered, so no barrier is needed inside.  a is free now and
-  // holds the inverse.
-  {
-    const int c = tid >> 2, q = tid & 3;
-    for (int i = q; i < kNb; i += 4) a[i][c] = 0.0;
-    if (c < nb) {
-      if (q == 0) a[c][c] = 1.0 / l[c][c];
-      for (int i = c + 1; i < nb; ++i) {
-        double s = 0.0;
-        for (int k = c + q; k < i; k += 4) s = fma(l[i][k], a[k][c], s);
-        s += __shfl_xor(s, 1, 64);
-        s += __shfl_xor(s, 2, 64);
-        if (q == 0) a[i][c] = -s / l[i][i];
+  double a[kNb];
+#pragma unroll
+  for (int c = 0; c < kNb; ++c) a[c] = s[i][c];
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) {
+    if (j < nb) {
+      col[i] = a[j];
+      __syncthreads();
+      double p = col[j];
+      if (!(p > 0.0 && __builtin_isfinite(p))) {
+        bad = true;
+        p = 1.0;
       }
+      const double d = sqrt(p), rd = 1.0 / d;
+      const double lij = i > j ? a[j] * rd : (i == j ? d : 0.0);
+      a[j] = lij;
+      __syncthreads();
+      col[i] = lij;
+      __syncthreads();
+#pragma unroll
+      for (int c = j + 1; c < kNb; ++c) a[c] = fma(-lij, col[c], a[c]);
+      __syncthreads();
     }
   }
+  if (bad && i == 0) flag[0] = 1;
+#pragma unroll
+  for (int c = 0; c < kNb; ++c) s[i][c] = c <= i ? a[c] : 0.0;
   __syncthreads();
-  for (int e = tid; e < kNb * kNb; e += kT) linv[e] = a[e / kNb][e % kNb];
+  for (int e = i; e < kNb * kNb; e += kNb) {
+    const int r = e / kNb, c = e % kNb;
+    if (r < nb && c <= r) A[(k0 + r) * ld + k0 + c] = s[r][c];
+  }
+  // column i of the inverse: x_r = (delta_ri - sum_{k<r} G_rk x_k) / G_rr
+  double x[kNb];
+#pragma unroll
+  for (int r = 0; r < kNb; ++r) {
+    double t = r == i ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < r; ++k) t = fma(-s[r][k], x[k], t);
+    x[r] = r < nb ? t / s[r][r] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < kNb; ++r) linv[r * kNb + i] = x[r];
 }
 
 // panel below the diagonal block: rows [k0 + nb, n), columns [k0, k0 + nb):
@@ -252,95 +261,106 @@ __global__ __launch_bounds__(kT) void trsm_panel(double* __restrict__ A, int64_t
   }
 }
 
-// trailing update of the lower triangle: for tile rows I >= J after the
-// panel, A[I][J] -= P_I P_J^T with P the panel (K = nb <= 64).  Tiles of
-// kUp x kUp (two Cholesky blocks a side), 8 x 8 outputs per thread (FP64
-// FMAs; the FP64 matrix cores have the same peak and need more registers);
-// the panel rows go through LDS in two halves of K, stored k-major so that
-// a thread's 8 rows (8 columns) are contiguous.
+// Rank-K update of the lower triangle: A[r][c] -= sum_{k < K} A[r][kc + k] A[c][kc + k]
+// for rows r in [rb, n) and columns c in [cb, ce) with c <= r.  Tiles of
+// kUp x kUp on the FP64 matrix cores: each of the four waves owns a 64 x 64
+// quarter as 4 x 4 blocks of v_mfma_f64_16x16x4 (operands from LDS, one
+// double per lane for each of A and B; the product of block (R, C) lands in
+// lane l's four registers as rows l/16 + 4j, column l%16).  The matrix
+// cores have the FP64 peak of the vector units, but read their operands
+// from registers: a k-step of 4 reads 8 doubles per lane from LDS for 16
+// products of 1,024 FMAs, where FMAs from LDS need a read per 4 FMAs.
+// tri: the tiles I >= J of the square [rb, n)^2 (the trailing matrix after a
+// panel of K = 256 columns); otherwise a rectangular grid of row tiles x nct
+// column tiles (updates of one panel's columns).  The panel rows go through
+// LDS in chunks of kUpK columns, stored k-major; each thread fetches its
+// share of the next chunk into registers while the current one is used.
 constexpr int kUp = 128;
-constexpr int kUpK = 32;
-__global__ __launch_bounds__(kT) void syrk_update(double* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
-                                                  int nb, int64_t ntile) {
-  __shared__ __attribute__((aligned(16))) double Pi[kUpK][kUp + 2];  // [k][row]
-  __shared__ __attribute__((aligned(16))) double Pj[kUpK][kUp + 2];
-  // tile index t -> (I, J), J <= I < ntile
+constexpr int kUpK = 16;
+constexpr int kOuter = 256;        // panel width of the trailing update
+typedef double d4 __attribute__((ext_vector_type(4)));
+// two workgroups per CU: the registers stay within 256 per lane
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2, 2))) void update_tiles(
+    double* __restrict__ A, int64_t ld, int64_t n, int64_t kc, int K, int64_t rb, int64_t cb, int64_t ce,
+    int64_t nct, int tri) {
+  __shared__ double Pi[kUpK][kUp + 2];  // [k][row]
+  __shared__ double Pj[kUpK][kUp + 2];
   const int64_t t = blockIdx.x;
-  int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-  while (I * (I + 1) / 2 > t) --I;
-  while ((I + 1) * (I + 2) / 2 <= t) ++I;
-  const int64_t J = t - I * (I + 1) / 2;
-  const int64_t base = k0 + nb;
-  const int64_t ri = base + I * kUp, rj = base + J * kUp;
+  int64_t I, J;
+  if (tri) {
+    I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > t) --I;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    J = t - I * (I + 1) / 2;
+  } else {
+    I = t / nct;
+    J = t % nct;
+  }
+  const int64_t ri = rb + I * kUp, rj = cb + J * kUp;
   const int tid = threadIdx.x;
-  const int tx = tid % 16, ty = tid / 16;
-  double acc[8][8];
+  const int l = tid % 64, w = tid / 64;
+  const int wr = (w / 2) * 64, wc = (w % 2) * 64;   // the wave's quarter
+  const int li = l % 16, lk = l / 16;
+  d4 acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
-  for (int kh = 0; kh < nb; kh += kUpK) {
-    const int kc = nb - kh < kUpK ? nb - kh : kUpK;
+    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  constexpr int kPf = kUp * kUpK / kT;
+  double fi[kPf], fj[kPf];
+  // element q of a thread: tile row pr + q kT / kUpK, chunk column pk
+  const int pr = tid / kUpK, pk = tid % kUpK;
+  const int64_t oi = (ri + pr) * ld + kc + pk, oj = (rj + pr) * ld + kc + pk;
+  const int64_t step = (int64_t)(kT / kUpK) * ld;
+  auto fetch = [&](int kh) {
+    const bool ok = kh + pk < K;
+#pragma unroll
+    for (int q = 0; q < kPf; ++q) {
+      const int64_t r = pr + q * (kT / kUpK);
+      fi[q] = (ok && ri + r < n) ? A[oi + q * step + kh] : 0.0;
+      fj[q] = (ok && rj + r < ce) ? A[oj + q * step + kh] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int kh = 0; kh < K; kh += kUpK) {
     __syncthreads();
-    for (int e = tid; e < kUp * kUpK; e += kT) {
-      const int r = e / kUpK, k = e % kUpK;
-      const bool ok = k < kc;
-      Pi[k][r] = (ok && ri + r < n) ? A[(ri + r) * ld + k0 + kh + k] : 0.0;
-      Pj[k][r] = (ok && rj + r < n) ? A[(rj + r) * ld + k0 + kh + k] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kPf; ++q) {
+      Pi[pk][pr + q * (kT / kUpK)] = fi[q];
+      Pj[pk][pr + q * (kT / kUpK)] = fj[q];
     }
     __syncthreads();
-    for (int k = 0; k < kc; ++k) {
-      double x[8], y[8];
+    if (kh + kUpK < K) fetch(kh + kUpK);
+#pragma unroll 2
+    for (int k4 = 0; k4 < kUpK; k4 += 4) {
+      double x[4], y[4];
 #pragma unroll
-      for (int a = 0; a < 8; ++a) x[a] = Pi[k][ty * 8 + a];
+      for (int a = 0; a < 4; ++a) x[a] = Pi[k4 + lk][wr + a * 16 + li];
 #pragma unroll
-      for (int b = 0; b < 8; ++b) y[b] = Pj[k][tx * 8 + b];
+      for (int b = 0; b < 4; ++b) y[b] = Pj[k4 + lk][wc + b * 16 + li];
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 8; ++b) acc[a][b] = fma(x[a], y[b], acc[a][b]);
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a], y[b], acc[a][b], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    const int64_t r = ri + ty * 8 + a;
-    if (r >= n) continue;
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int64_t c = rj + tx * 8 + b;
-      if (c < n && c <= r) A[r * ld + c] -= acc[a][b];
+    for (int j = 0; j < 4; ++j) {
+      const int64_t r = ri + wr + a * 16 + lk + 4 * j;
+      if (r >= n) continue;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t c = rj + wc + b * 16 + li;
+        if (c < ce && c <= r) A[r * ld + c] -= acc[a][b][j];
+      }
     }
-  }
 }
 
-// ---- 5. forward substitution and the two reductions ---------------------------
-// diagonal block kb: y_kb = G_kb,kb^-1 b_kb with the stored inverse (b already
-// holds the updates of the earlier blocks); one wave, a row each
-__global__ __launch_bounds__(kNb) void trsv_diag(const double* __restrict__ linv, int64_t k0, int nb,
-                                                 double* __restrict__ b) {
-  __shared__ double v[kNb];
-  const int tid = threadIdx.x;
-  v[tid] = tid < nb ? b[k0 + tid] : 0.0;
-  __syncthreads();
-  if (tid < nb) {
-    double s = 0.0;
-    for (int k = 0; k <= tid; ++k) s = fma(linv[tid * kNb + k], v[k], s);
-    b[k0 + tid] = s;
-  }
-}
-
-// rows below the block: b_i -= G[i, k0:k0+nb] y_kb
-__global__ __launch_bounds__(kT) void gemv_panel(const double* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
-                                                 int nb, double* __restrict__ b) {
-  const int64_t i = k0 + nb + (int64_t)blockIdx.x * kT + threadIdx.x;
-  if (i >= n) return;
-  const double* row = A + i * ld + k0;
-  double s = 0.0;
-  for (int l = 0; l < nb; ++l) s = fma(row[l], b[k0 + l], s);
-  b[i] -= s;
-}
-
-// out[0] = 2 sum_i log G_ii, out[1] = sum_i y_i^2 (one workgroup, fixed order)
+// ---- 5. the two reductions ------------------------------------------------------
+// 2 sum log G_ii and |y|^2 in one fixed-order pass (y = G^-1 Z^n_W, the
+// border row of the factor)
 __global__ __launch_bounds__(kT) void logdet_quad(const double* __restrict__ A, int64_t ld, int64_t n,
                                                   const double* __restrict__ y, double* __restrict__ out) {
   __shared__ double s0[kT], s1[kT];
@@ -367,6 +387,29 @@ __global__ __launch_bounds__(kT) void logdet_quad(const double* __restrict__ A, 
 }
 
 int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+// A second stream per device (default priority, created once) for the
+// trailing updates, which then run beside the factorization of the next
+// panel; events order the two.
+int side_stream(hipStream_t* out) {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  MLB_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(MLBLUP_EHIP, "loglik: device index out of range");
+  std::lock_guard<std::mutex> g(mu);
+  if (!streams[dev]) MLB_HIP(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+  *out = streams[dev];
+  return MLBLUP_OK;
+}
+
+struct Events {
+  hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+  ~Events() {
+    for (hipEvent_t x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
 
 }  // namespace
 
@@ -501,33 +544,68 @@ int loglik_device(const Basis& B, const TransformDev& T, const PairArgs& k, int3
                        (const uint8_t*)(w + L.keep), L.cells);
     if ((st = hip_check(hipGetLastError(), "sparsity pattern launch"))) return st;
   }
-  // 4. Cholesky
-  const int64_t nblk = (nt + kNb - 1) / kNb;
-  for (int64_t kb = 0; kb < nblk; ++kb) {
-    const int64_t k0 = kb * kNb;
-    const int nb = (int)std::min<int64_t>(kNb, nt - k0);
-    double* li = linv + kb * kNb * kNb;
-    hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(kT), 0, s, C, nt, k0, nb, li, flag);
-    const int64_t below = nt - k0 - nb;
-    if (below > 0) {
-      const int64_t tiles = (below + kNb - 1) / kNb;
-      hipLaunchKernelGGL(trsm_panel, dim3((unsigned)tiles), dim3(kT), 0, s, C, nt, nt, k0, nb, li);
-      const int64_t ut = (below + kUp - 1) / kUp;
-      hipLaunchKernelGGL(syrk_update, dim3((unsigned)(ut * (ut + 1) / 2)), dim3(kT), 0, s, C, nt, nt, k0, nb, ut);
+  // 4. Cholesky: panels of kOuter columns, each factored in blocks of kNb
+  // (diagonal factor and inverse, panel product, update of the panel's
+  // remaining columns), then one rank-kOuter update of the trailing matrix.
+  // Z^n_W rides along as an extra row nt (the bordered matrix [C z; z^T .]):
+  // the panel products and updates that make the factor's rows also carry
+  // out the forward substitution, so that row nt ends as y = G^-1 Z^n_W.
+  const int64_t nr = nt + 1;
+  double* y = C + nt * nt;   // A's storage holds nt x n >= (nt + 1) x nt doubles
+  MLB_HIP(hipMemcpyAsync(y, zw, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // Lookahead: after panel [ob, oe) is factored, the main stream updates
+  // only the next panel's columns [oe, oe2) and goes on to factor it, while
+  // the side stream updates the columns >= oe2.  The next lookahead writes
+  // columns that this trailing update writes too, so it waits for it.
+  hipStream_t side;
+  if ((st = side_stream(&side))) return st;
+  Events ev;
+  for (hipEvent_t& e : ev.e) MLB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  hipEvent_t ev_fork = ev.e[0], ev_panel = ev.e[1], ev_trail = ev.e[2];
+  MLB_HIP(hipEventRecord(ev_fork, s));
+  MLB_HIP(hipStreamWaitEvent(side, ev_fork, 0));
+  bool trail_pending = false;
+  for (int64_t ob = 0; ob < nt; ob += kOuter) {
+    const int64_t oe = std::min<int64_t>(nt, ob + kOuter);
+    for (int64_t k0 = ob; k0 < oe; k0 += kNb) {
+      const int nb = (int)std::min<int64_t>(kNb, nt - k0);
+      double* li = linv + (k0 / kNb) * kNb * kNb;
+      hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(kNb), 0, s, C, nt, k0, nb, li, flag);
+      const int64_t below = nr - k0 - nb;   // >= 1: the border row
+      hipLaunchKernelGGL(trsm_panel, dim3((unsigned)((below + kNb - 1) / kNb)), dim3(kT), 0, s, C, nt, nr, k0, nb,
+                         li);
+      const int64_t cb = k0 + nb;
+      if (cb < oe) {
+        const int64_t nct = (oe - cb + kUp - 1) / kUp, nrt = (nr - cb + kUp - 1) / kUp;
+        hipLaunchKernelGGL(update_tiles, dim3((unsigned)(nrt * nct)), dim3(kT), 0, s, C, nt, nr, k0, nb, cb, cb, oe,
+                           nct, 0);
+      }
+    }
+    if (oe >= nt) break;
+    const int64_t oe2 = std::min<int64_t>(nt, oe + kOuter), K = oe - ob;
+    if (oe2 < nt) {
+      MLB_HIP(hipEventRecord(ev_panel, s));
+    }
+    if (trail_pending) MLB_HIP(hipStreamWaitEvent(s, ev_trail, 0));
+    {
+      const int64_t nct = (oe2 - oe + kUp - 1) / kUp, nrt = (nr - oe + kUp - 1) / kUp;
+      hipLaunchKernelGGL(update_tiles, dim3((unsigned)(nrt * nct)), dim3(kT), 0, s, C, nt, nr, ob, (int)K, oe, oe,
+                         oe2, nct, 0);
+    }
+    if (oe2 < nt) {
+      MLB_HIP(hipStreamWaitEvent(side, ev_panel, 0));
+      const int64_t ut = (nr - oe2 + kUp - 1) / kUp;
+      hipLaunchKernelGGL(update_tiles, dim3((unsigned)(ut * (ut + 1) / 2)), dim3(kT), 0, side, C, nt, nr, ob, (int)K,
+                         oe2, oe2, nt, (int64_t)1, 1);
+      MLB_HIP(hipEventRecord(ev_trail, side));
+      trail_pending = true;
     }
   }
+  if (trail_pending) MLB_HIP(hipStreamWaitEvent(s, ev_trail, 0));
   if ((st = hip_check(hipGetLastError(), "Cholesky launch"))) return st;
-  // 5. G y = Z^n_W (in place in zw), then the reductions
-  for (int64_t kb = 0; kb < nblk; ++kb) {
-    const int64_t k0 = kb * kNb;
-    const int nb = (int)std::min<int64_t>(kNb, nt - k0);
-    hipLaunchKernelGGL(trsv_diag, dim3(1), dim3(kNb), 0, s, linv + kb * kNb * kNb, k0, nb, zw);
-    const int64_t below = nt - k0 - nb;
-    if (below > 0)
-      hipLaunchKernelGGL(gemv_panel, dim3((unsigned)((below + kT - 1) / kT)), dim3(kT), 0, s, C, nt, nt, k0, nb, zw);
-  }
-  hipLaunchKernelGGL(logdet_quad, dim3(1), dim3(kT), 0, s, C, nt, nt, zw, dout);
-  if ((st = hip_check(hipGetLastError(), "forward substitution launch"))) return st;
+  // 5. 2 sum log G_ii and |y|^2
+  hipLaunchKernelGGL(logdet_quad, dim3(1), dim3(kT), 0, s, C, nt, nt, y, dout);
+  if ((st = hip_check(hipGetLastError(), "reduction launch"))) return st;
   double host[2];
   int hflag = 0;
   MLB_HIP(hipMemcpyAsync(host, dout, sizeof(host), hipMemcpyDeviceToHost, s));
