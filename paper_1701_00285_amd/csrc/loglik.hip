@@ -18,8 +18,10 @@
 //  4. blocked right-looking Cholesky: panels of 256 columns, each factored
 //     in blocks of 64 (the diagonal factor and its inverse in one wave, the
 //     panel below as a product with that inverse, the update of the panel's
-//     remaining columns), then one rank-256 update of the trailing lower
-//     triangle in 128 x 128 tiles;
+//     remaining columns), then the rank-256 update of the trailing lower
+//     triangle in 128 x 128 tiles on the FP64 matrix cores: the next panel's
+//     columns first, the rest on a second stream while the next panel is
+//     factored;
 //  5. G y = Z^n_W inside the factorization: Z^n_W is appended as row N~ of
 //     the matrix, which the panel products and updates turn into y;
 //     2 sum log G_ii and |y|^2 by fixed-order reductions.
