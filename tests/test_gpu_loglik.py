@@ -190,3 +190,21 @@ def test_sparsified_mle_rho_matches_oracle():
     say(f"sparse mle rho gpu {g['rho']:.8f} oracle {o[0]:.8f} evals {g['evals']}")
     assert abs(math.log(g["rho"]) - math.log(o[0])) < 3e-5
     assert abs(g["loglik"] - o[1]) < 1e-9 * abs(o[1])
+
+
+@pytest.mark.parametrize("n", [67, 68, 131, 259, 260, 387, 515, 771])
+def test_loglik_at_block_and_panel_boundaries(n):
+    """Level 0 of the d = 2 linear-trend workload has N~ = n - 3 rows: 64, 65,
+    128, 256, 257, 384, 512 and 768 put the end of the matrix (and the border
+    row that carries Z^n_W) exactly on, or one past, the 64-column blocks, the
+    128-row update tiles and the 256-column panels."""
+    require_gpu()
+    wl, nu, tree, bas, s = _both(1, n)
+    g = s.loglik(dev(wl.z), 0)
+    o = OL.multilevel_loglik(wl.points, wl.z, nu, wl.rho, bas, 0)
+    assert g["rows"] == o[3] == n - 3
+    kap = _cond(wl, nu, bas, o[3])
+    tq = max(1e-12, 50 * kap * 2.2e-16)
+    say(f"loglik boundary n={n} rows={o[3]} kappa={kap:.1e} dlogdet={abs(g['logdet'] - o[1]):.1e}")
+    assert abs(g["logdet"] - o[1]) < tq * o[3]
+    assert abs(g["quad"] - o[2]) < tq * abs(o[2])
