@@ -275,7 +275,8 @@ int mlblup_blup_grad(mlblup_basis b, const mlblup_matern* k, const double* z_dev
  * z_dev: N data values in tree order.  level: 0 .. levels - 1 (level 0 takes
  * all of W, where Z^0_W^T (C_W)^-1 Z^0_W is the Q of mlblup_blup_grad).
  * work_dev: at least the bytes from mlblup_loglik_workspace_bytes, which also
- * returns N~ in rows (may be NULL); about 8 (N^2 + N~ N) bytes, so N of a few
+ * returns N~ in rows (may be NULL); about 8 (N^2 + N~ N) bytes plus at most
+ * N~^2 + 4 N~ for the sparsity pattern, so N of a few
  * 10^4.  out4_host = {l, log det, quadratic form, kept entries of the N~ x N~
  * matrix}.  Synchronises `stream`.  MLBLUP_EINVAL for tau < 0 or NaN, a level
  * outside the range or a short workspace; MLBLUP_EBREAKDOWN if a Cholesky
