@@ -190,12 +190,13 @@ def sweep(configs, reps: int = 10, warm: int = 3, nu=None):
                           "transform": res}), flush=True)
 
 
-def loglik_bench(k: int, n: int, reps: int = 3):
+def loglik_bench(k: int, n: int, reps: int = 3, quick: bool = False):
     """Estimator path: l_n at the finest levels and at level 0 (each the
     median of `reps` calls after one untimed call, host clock around a call
     that synchronises), the sparsified l~_n at levels t and t - 1 for tau from
     0.05 (the distance of the paper's d = 3 estimation runs) to 0.4, with the
     fill of C~^n_W, and one golden-section MLE of rho at level t - 1.
+    quick: levels t and 0 only, one timed call each (large n).
     Flops of one call: the dense Cholesky N~^3/3, the two batched analyses
     2 sum_cells m^2 (N + N~) and the covariance N^2 pairs."""
     import time
@@ -211,7 +212,9 @@ def loglik_bench(k: int, n: int, reps: int = 3):
     z = torch.as_tensor(wl.z, dtype=torch.float64, device="cuda")
     t = s.basis.levels - 1
     res = {"workload": f"cfg{k} generator, n={n}, d={wl.d}, nu={wl.nu}, rho={wl.rho}", "levels": {}}
-    for level in (t, t - 1, t - 2, 0):
+    if quick:
+        reps = 1
+    for level in ((t, 0) if quick else (t, t - 1, t - 2, 0)):
         s.loglik(z, level)
         times = []
         for _ in range(reps):
@@ -225,6 +228,9 @@ def loglik_bench(k: int, n: int, reps: int = 3):
                                     "logdet": out["logdet"], "quad": out["quad"],
                                     "cholesky_gflop": round(nt ** 3 / 3 / 1e9, 2)}
         print(f"loglik level {level}: rows {nt}, {ms:.1f} ms", file=sys.stderr, flush=True)
+    if quick:
+        print(json.dumps(res), flush=True)
+        return
     res["sparsified"] = {}
     for level in (t, t - 1):
         for tau in (0.05, 0.1, 0.2, 0.4):
@@ -282,6 +288,8 @@ def main():
     ap.add_argument("--loglik", type=int, default=0,
                     help="estimator: time the multilevel log-likelihood (dense C^n_W, blocked Cholesky) and the "
                          "rho MLE on this many points of the workload's generator (one JSON line) instead of the step")
+    ap.add_argument("--loglik-quick", action="store_true",
+                    help="with --loglik: levels t and 0 only, one timed call each")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 512 MiB three times with a plain device copy (reference for HBM counters)")
     a = ap.parse_args()
@@ -298,7 +306,7 @@ def main():
         return
 
     if a.loglik:
-        loglik_bench(a.config, a.loglik)
+        loglik_bench(a.config, a.loglik, quick=a.loglik_quick)
         return
 
     if a.copy_calibration:
