@@ -294,7 +294,7 @@ def main():
                     help="only copy 512 MiB three times with a plain device copy (reference for HBM counters)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {a.gpus} is not supported (run with --gpus 1)",
+        print(f"bench.py: the path runs on one GPU; --gpus {a.gpus} is not supported (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 
