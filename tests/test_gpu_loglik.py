@@ -208,3 +208,17 @@ def test_loglik_at_block_and_panel_boundaries(n):
     say(f"loglik boundary n={n} rows={o[3]} kappa={kap:.1e} dlogdet={abs(g['logdet'] - o[1]):.1e}")
     assert abs(g["logdet"] - o[1]) < tq * o[3]
     assert abs(g["quad"] - o[2]) < tq * abs(o[2])
+
+
+def test_sparsified_mle_nu_rho_matches_oracle():
+    """Profile MLE of (nu, rho) on the sparsified likelihood (tau = 0.05,
+    the finest level, where C~ stays positive definite over the search box)."""
+    require_gpu()
+    wl, nu, tree, bas, s = _both(1, 300)
+    level = tree.max_depth
+    g = s.mle_nu_rho(dev(wl.z), level, 0.3, 2.0, 0.02, 0.5, nu_tol=1e-2, log_rho_tol=1e-3, tau=0.05)
+    o = OL.mle_nu_rho(wl.points, wl.z, bas, level, 0.3, 2.0, 0.02, 0.5, 1e-2, 1e-3, tree=tree, tau=0.05)
+    say(f"sparse mle (nu, rho) gpu ({g['nu']:.5f}, {g['rho']:.5f}) oracle ({o[0]:.5f}, {o[1]:.5f})")
+    assert abs(g["nu"] - o[0]) < 2e-2
+    assert abs(math.log(g["rho"]) - math.log(o[1])) < 5e-3
+    assert abs(g["loglik"] - o[2]) < 1e-8 * abs(o[2])
