@@ -108,6 +108,114 @@ def cpu_baseline(wl, rows: int):
                       f"{dt:.1f} s, one thread)"}
 
 
+def _host_cores() -> int:
+    import os
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_oracle_report(parts: str = "all"):
+    """The oracle timed on the host's cores beside the GPU (one JSON line):
+    (i) the row-block FP64 covariance product on all cores (a thread pool over
+    blocks of 1,024 rows, one BLAS thread each; NumPy releases the GIL inside
+    its array operations) and on one core: all cores take every row of
+    workloads 1 and 2, 32,768 rows of workload 4 and 4,096 rows of workloads 3
+    and 5; one core takes every row of workload 1, 512 rows of workloads 2 and
+    4 and 128 rows of workloads 3 and 5; rates in Gpairs/s and the full
+    product's time extrapolated where sampled;
+    (ii) the dense classic BLUP (Cholesky, GLS beta, kriging; LAPACK on all
+    cores) on workload 1, the workload 4 generator at 4,096 points and the
+    workload 2 generator at 32,768 points, beside the GPU predictor (FP64
+    solve to relres 1e-8, block preconditioner) on the same inputs, and the
+    largest prediction difference between the two.  parts: "products",
+    "blup" or "all"."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    import torch
+    from threadpoolctl import threadpool_limits
+
+    from oracle import blup, brute
+    import synth
+    from paper_1701_00285_amd import FP64, PREC_BLOCK, PcgOptions, Solver
+    cores = _host_cores()
+    out = {"cores": cores, "kind": "oracle", "products": {}, "dense_blup": {}}
+
+    def product(wl, rows, threads):
+        x = synth.standard_normal(wl.n, 12345)
+        blocks = [(i, min(rows, i + 1024)) for i in range(0, rows, 1024)]
+        inner = max(16, min(256, (1 << 25) // wl.n))   # rows per dense block: at most 256 MB per temporary
+
+        def run(b):
+            return brute.cov_matvec(wl.points[b[0]:b[1]], wl.points, x, wl.nu, wl.rho, wl.sigma2, block=inner)
+
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            if threads == 1:
+                for b in blocks:
+                    run(b)
+            else:
+                with ThreadPoolExecutor(max_workers=threads) as ex:
+                    list(ex.map(run, blocks))
+            return time.perf_counter() - t0
+
+    for k in ((1, 2, 3, 4, 5) if parts in ("all", "products") else ()):
+        wl = synth.make_config(k, with_z=False)
+        rows_all = {1: wl.n, 2: wl.n, 4: 32768}.get(k, 4096)
+        rows_one = {1: wl.n, 2: 512, 4: 512}.get(k, 128)
+        dt_all = product(wl, rows_all, cores)
+        dt_one = product(wl, rows_one, 1)
+        rec = {"n": wl.n, "d": wl.d,
+               "all_cores": {"rows": rows_all, "s": round(dt_all, 3),
+                             "gpairs_s": round(rows_all * wl.n / dt_all / 1e9, 4),
+                             "full_product_s": round(dt_all * wl.n / rows_all, 2)},
+               "one_core": {"rows": rows_one, "s": round(dt_one, 3),
+                            "gpairs_s": round(rows_one * wl.n / dt_one / 1e9, 4),
+                            "full_product_s": round(dt_one * wl.n / rows_one, 1)}}
+        out["products"][f"cfg{k}"] = rec
+        print(f"cpu product cfg{k}: {rec}", file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    for k, n in (((1, None), (4, 4096), (2, 32768)) if parts in ("all", "blup") else ()):
+        wl = synth.make_config(k, n=n)
+        if wl.z is None:   # workload 1: Z = X beta + G xi with G = chol(C), drawn with the oracle's C
+            from oracle.design import design_matrix
+            from oracle.matern import cov_matrix
+            import scipy.linalg as sla
+            X = design_matrix(wl.points, wl.degree_w)
+            G = sla.cholesky(cov_matrix(wl.points, wl.points, wl.nu, wl.rho, wl.sigma2), lower=True)
+            wl.z = X @ wl.extra["beta_gen"][: X.shape[1]] + G @ wl.extra["xi"]
+        print(f"cpu dense blup cfg{k} n={wl.n}: start", file=sys.stderr, flush=True)
+        with threadpool_limits(limits=cores):
+            t0 = time.perf_counter()
+            ref = blup.classic_blup(wl.points, wl.z, wl.targets, wl.degree_w, wl.nu, wl.rho, wl.sigma2)
+            dt_cpu = time.perf_counter() - t0
+        print(f"cpu dense blup cfg{k} n={wl.n}: {dt_cpu:.2f} s", file=sys.stderr, flush=True)
+        s = Solver(wl.points, wl.degree_w, wl.leaf_max, wl.nu, wl.rho, wl.sigma2, max_targets=wl.targets.shape[0])
+        z = torch.as_tensor(wl.z, dtype=torch.float64, device="cuda")
+        tg = torch.as_tensor(wl.targets, dtype=torch.float64, device="cuda")
+        pc = s.precond(PREC_BLOCK)
+        opts = PcgOptions(rtol=1e-8, max_iter=20000, precision=FP64, precond=pc)
+        s.predict(z, tg, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = s.predict(z, tg, opts)
+        torch.cuda.synchronize()
+        dt_gpu = time.perf_counter() - t0
+        zh = g["zhat"].cpu().numpy()
+        err = float(np.max(np.abs(zh - ref.zhat)) / np.max(np.abs(ref.zhat)))
+        rec = {"n": wl.n, "d": wl.d, "targets": int(wl.targets.shape[0]), "cpu_s": round(dt_cpu, 3),
+               "gpu_predict_s": round(dt_gpu, 4), "gpu_iters": g["info"]["inner_iters"],
+               "zhat_max_rel_diff": err}
+        out["dense_blup"][f"cfg{k}"] = rec
+        print(f"gpu predict cfg{k} n={wl.n}: {rec}", file=sys.stderr, flush=True)
+        del s
+    print(json.dumps(out), flush=True)
+
+
 def sweep(configs, reps: int = 10, warm: int = 3, nu=None):
     """Per workload: the square product in every precision that applies
     (median of `reps` HIP-event timings after `warm` untimed launches), the
@@ -288,6 +396,9 @@ def main():
     ap.add_argument("--loglik", type=int, default=0,
                     help="estimator: time the multilevel log-likelihood (dense C^n_W, blocked Cholesky) and the "
                          "rho MLE on this many points of the workload's generator (one JSON line) instead of the step")
+    ap.add_argument("--cpu-oracle", choices=("all", "products", "blup"), default=None,
+                    help="time the oracle on the host's cores (covariance products, dense classic BLUP) beside "
+                         "the GPU predictor; one JSON line instead of the step")
     ap.add_argument("--loglik-quick", action="store_true",
                     help="with --loglik: levels t and 0 only, one timed call each")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -307,6 +418,10 @@ def main():
 
     if a.loglik:
         loglik_bench(a.config, a.loglik, quick=a.loglik_quick)
+        return
+
+    if a.cpu_oracle:
+        cpu_oracle_report(a.cpu_oracle)
         return
 
     if a.copy_calibration:
