@@ -384,7 +384,7 @@ def main():
                     help="full: independent FP64 solve (timed against the mixed one); refine: FP64 PCG from the mixed "
                          "solution to relres 1e-10 as the error reference (for workloads where a full FP64 solve "
                          "does not fit the time budget); skip: none")
-    ap.add_argument("--precond", choices=("block", "jacobi", "none"), default="block",
+    ap.add_argument("--precond", choices=("block", "jacobi", "coarse", "none"), default="block",
                     help="preconditioner of both solves (cell blocks of C_W, its diagonal, or none)")
     ap.add_argument("--cpu-rows", type=int, default=3072)
     ap.add_argument("--no-cpu", action="store_true")
@@ -435,7 +435,8 @@ def main():
 
     import synth
     from paper_1701_00285_amd import (FP32, FP64, MFMA_BF16X3, MIXED_FLEXIBLE, MIXED_RELIABLE, PREC_BLOCK,
-                                      PREC_JACOBI, VALUE, PcgOptions, Solver, profile_enable, profile_read)
+                                      PREC_COARSE, PREC_JACOBI, VALUE, PcgOptions, Solver, profile_enable,
+                                      profile_read)
 
     torch.cuda.set_device(0)
     wl = synth.make_config(a.config, n=a.n or None, n_targets=a.targets or None)
@@ -450,7 +451,7 @@ def main():
         t = [time.perf_counter()]
         pts_host = P.cpu().numpy()
         s = Solver(pts_host, wl.degree_w, wl.leaf_max, wl.nu, wl.rho, wl.sigma2, max_targets=T.shape[0])
-        pc = {"block": PREC_BLOCK, "jacobi": PREC_JACOBI}.get(a.precond)
+        pc = {"block": PREC_BLOCK, "jacobi": PREC_JACOBI, "coarse": PREC_COARSE}.get(a.precond)
         pc = s.precond(pc) if pc is not None else None
         zt = s.to_tree(Z)
         zw, _ = s.apply_W(zt)
@@ -558,7 +559,9 @@ def main():
         "data": "synthetic (seeded)",
         "config": {"workload": wname, "n": n, "d": wl.d, "nu": wl.nu, "rho": wl.rho, "trend_p": last["p"],
                    "leaf": wl.leaf_max, "targets": int(T.shape[0]), "rtol": 1e-8,
-                   "preconditioner": {"block": "cell blocks of C_W", "jacobi": "diag(C_W)", "none": "none"}[a.precond],
+                   "preconditioner": {"block": "cell blocks of C_W", "jacobi": "diag(C_W)",
+                                      "coarse": "cell blocks of the two finest levels + dense coarse block of C_W",
+                                      "none": "none"}[a.precond],
                    "mixed_precision": mixed, "mixed_scheme": a.scheme, "inner_rtol": a.inner_rtol,
                    "fp64_solve": a.fp64_solve},
         "phases_s": {k: rnd(last[k]) for k in ("setup", "solve_fp64", "solve_mixed", "reference_fp64", "predict",

@@ -70,6 +70,8 @@ typedef struct mlblup_precond_s* mlblup_precond;
 /* Preconditioner kinds (preconditioner remark of Sec. 5.2). */
 #define MLBLUP_PREC_JACOBI 1   /* P_W = diag(C_W) */
 #define MLBLUP_PREC_BLOCK 2    /* P_W = the diagonal blocks of C_W, one per cell (its own wavelets) */
+#define MLBLUP_PREC_COARSE 3   /* the cell blocks of the two finest levels and one dense block of C_W over all
+                                  coarser levels (a coarse space; not in the paper) */
 
 /* mixed-precision schemes (mlblup_pcg_opts.mixed_scheme) */
 #define MLBLUP_MIXED_FLEXIBLE 0
@@ -320,6 +322,16 @@ int mlblup_mle_nu_rho(mlblup_basis b, double sigma2, const double* z_dev, int32_
  * are fixed at build time: rebuild when rho changes.  work_dev: at least
  * mlblup_precond_workspace_bytes(b).  Synchronises `stream`. */
 int mlblup_precond_workspace_bytes(mlblup_basis b, int64_t* bytes);
+/* MLBLUP_PREC_COARSE: the wavelets of every level above the two finest
+ * (the last nc rows of W, from c0 on) form one block C_c = W_c C W_c^T,
+ * formed densely on the device (the N x N covariance and two batched
+ * analyses) and factored G G^T = C_c with G^-T and G^-1 kept (2 nc^2
+ * doubles in the device image); the apply is two row products with them plus
+ * the cell blocks of the finer wavelets.  Workspace about 8 (N^2 + nc N)
+ * bytes, so N of about 10^5 at most; needs three or more levels with the two
+ * finest holding at least half of the rows (EINVAL otherwise).  This query
+ * gives the workspace of any kind. */
+int mlblup_precond_workspace_bytes_kind(mlblup_basis b, int32_t kind, int64_t* bytes);
 int mlblup_precond_build(mlblup_basis b, const mlblup_matern* k, int32_t kind, void* work_dev, int64_t work_bytes,
                          void* stream, mlblup_precond* out);
 /* device_bytes: size of the device image; n_blocks: cells with wavelets;
@@ -331,6 +343,9 @@ int mlblup_precond_upload(mlblup_precond pc, void* dev_buf, int64_t bytes, void*
 /* Host copies for tests: blocks B_v (row-major, concatenated in coefficient
  * order), each block's first coefficient and size (any pointer may be NULL). */
 int mlblup_precond_blocks(mlblup_precond pc, double* blocks_host, int64_t* w_off_host, int32_t* mw_host);
+/* Coarse kind, for tests: c0, nc and G^-T of the coarse block (nc x nc
+ * row-major, host, caller-allocated; may be NULL).  Other kinds: nc = 0. */
+int mlblup_precond_coarse(mlblup_precond pc, int64_t* c0, int64_t* nc, double* y_host);
 void mlblup_precond_free(mlblup_precond pc);
 
 /* ---- instrumentation --------------------------------------------------------

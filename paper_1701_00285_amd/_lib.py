@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(_HERE, "libmlblup.so")
 OK, EINVAL, ERANK, ENOCONV, EBREAKDOWN, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32, MFMA_FP32, MFMA_BF16X3 = 0, 1, 2, 3
 VALUE, DLOGRHO = 1, 2
-PREC_JACOBI, PREC_BLOCK = 1, 2
+PREC_JACOBI, PREC_BLOCK, PREC_COARSE = 1, 2, 3
 MIXED_FLEXIBLE, MIXED_RELIABLE = 0, 1
 
 _NAMES = {EINVAL: "EINVAL", ERANK: "ERANK", ENOCONV: "ENOCONV", EBREAKDOWN: "EBREAKDOWN", EHIP: "EHIP",
@@ -85,6 +85,8 @@ _SIGS = {
     "mlblup_precond_workspace_bytes": (C.c_int, [_P, C.POINTER(_I64)]),
     "mlblup_precond_build": (C.c_int, [_P, C.POINTER(Matern), _I32, _P, _I64, _P, C.POINTER(_P)]),
     "mlblup_precond_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
+    "mlblup_precond_workspace_bytes_kind": (C.c_int, [_P, _I32, C.POINTER(_I64)]),
+    "mlblup_precond_coarse": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), _P]),
     "mlblup_precond_upload": (C.c_int, [_P, _P, _I64, _P]),
     "mlblup_precond_blocks": (C.c_int, [_P, _P, _P, _P]),
     "mlblup_precond_free": (None, [_P]),

@@ -18,7 +18,7 @@ from ._lib import check
 
 FP64, FP32, MFMA_FP32, MFMA_BF16X3 = L.FP64, L.FP32, L.MFMA_FP32, L.MFMA_BF16X3
 VALUE, DLOGRHO = L.VALUE, L.DLOGRHO
-PREC_JACOBI, PREC_BLOCK = L.PREC_JACOBI, L.PREC_BLOCK
+PREC_JACOBI, PREC_BLOCK, PREC_COARSE = L.PREC_JACOBI, L.PREC_BLOCK, L.PREC_COARSE
 MIXED_FLEXIBLE, MIXED_RELIABLE = L.MIXED_FLEXIBLE, L.MIXED_RELIABLE
 
 
@@ -63,7 +63,8 @@ class PcgOptions:
 
 
 class Precond:
-    """Preconditioner P_W (diag(C_W) or its per-cell blocks) for a basis and
+    """Preconditioner P_W (diag(C_W), its per-cell blocks, or the cell blocks
+    of the two finest levels with one dense coarse block) for a basis and
     fixed kernel parameters, built on the device and uploaded."""
 
     def __init__(self, basis, kern, kind=PREC_BLOCK, device="cuda"):
@@ -71,7 +72,7 @@ class Precond:
         lib = L.lib()
         self._lib = lib
         wb = C.c_int64()
-        check(lib.mlblup_precond_workspace_bytes(basis.h, C.byref(wb)))
+        check(lib.mlblup_precond_workspace_bytes_kind(basis.h, int(kind), C.byref(wb)))
         work = torch.empty(max(wb.value, 256), dtype=torch.uint8, device=device)
         h = C.c_void_p()
         check(lib.mlblup_precond_build(basis.h, C.byref(kern), int(kind), _ptr(work), work.numel(), _stream(),
@@ -83,6 +84,17 @@ class Precond:
         self.n_blocks, self.block_entries = nb.value, be.value
         self.buf = torch.empty(max(db.value, 256), dtype=torch.uint8, device=device)
         check(lib.mlblup_precond_upload(h, _ptr(self.buf), self.buf.numel(), _stream()))
+        del work
+
+    def coarse(self):
+        """(c0, G^-T of the coarse block as an nc x nc numpy array) of the
+        coarse kind; (0, empty) for the others."""
+        c0, nc = C.c_int64(), C.c_int64()
+        check(self._lib.mlblup_precond_coarse(self.h, C.byref(c0), C.byref(nc), None))
+        y = np.empty((nc.value, nc.value))
+        if nc.value:
+            check(self._lib.mlblup_precond_coarse(self.h, None, None, _np_ptr(y)))
+        return c0.value, y
 
     def blocks(self):
         """(list of B_v as numpy arrays, their first coefficient index)."""

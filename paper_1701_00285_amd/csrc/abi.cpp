@@ -46,6 +46,21 @@ int nu2_of_nu(double nu) {
   return -1;
 }
 
+// Device view of the multilevel transform of an uploaded basis.
+TransformDev transform_dev(const Basis& B) {
+  const char* img = (const char*)B.dev_base;
+  TransformDev T;
+  T.desc = (const NodeDesc*)(img + B.off_desc);
+  T.level_nodes = (const int32_t*)(img + B.off_levels);
+  T.lvl_begin_host = B.lvl_begin.data();
+  T.levels = B.levels;
+  T.V = (const double*)(img + B.off_V);
+  T.Vt = (const double*)(img + B.off_Vt);
+  T.children = (const int32_t*)(img + B.off_children);
+  T.n_nodes = (int32_t)B.desc.size();
+  return T;
+}
+
 namespace {
 
 // progress log of long solves: MLBLUP_LOG_EVERY=k prints the residual every k iterations to stderr
@@ -139,20 +154,6 @@ void image_layout(Basis& B) {
   B.dev_bytes = off;
 }
 
-// Device view of the multilevel transform of an uploaded basis.
-TransformDev transform_dev(const Basis& B) {
-  const char* img = (const char*)B.dev_base;
-  TransformDev T;
-  T.desc = (const NodeDesc*)(img + B.off_desc);
-  T.level_nodes = (const int32_t*)(img + B.off_levels);
-  T.lvl_begin_host = B.lvl_begin.data();
-  T.levels = B.levels;
-  T.V = (const double*)(img + B.off_V);
-  T.Vt = (const double*)(img + B.off_Vt);
-  T.children = (const int32_t*)(img + B.off_children);
-  T.n_nodes = (int32_t)B.desc.size();
-  return T;
-}
 
 // Workspace of the solve/predict/grad drivers.
 struct Ws {

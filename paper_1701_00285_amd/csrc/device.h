@@ -101,6 +101,9 @@ int transform_synthesis(const TransformDev& T, const double* vw, const double* v
 
 // ---- multilevel log-likelihood (loglik.hip) ----------------------------------------
 // workspace layout (byte offsets) for the levels >= level
+// device view of the multilevel transform of an uploaded basis
+TransformDev transform_dev(const Basis& B);
+
 struct LoglikLayout {
   int64_t phi = 0, a = 0, scal = 0, zw = 0, scalz = 0, out = 0, flag = 0, gtab = 0, linv = 0, total = 0;
   int64_t rowcell = 0, keep = 0;   // sparsity pattern of C~^n_W: cell of each row, cell-pair keep matrix
@@ -110,6 +113,14 @@ struct LoglikLayout {
 };
 int64_t loglik_rows(const Basis& B, int32_t level);
 LoglikLayout loglik_layout(const Basis& B, int32_t level);
+// coarse block of C_W (rows [c0, c0 + nc) of W) for the preconditioner
+struct CoarseLayout {
+  int64_t phi = 0, a = 0, scal = 0, flag = 0, gtab = 0, linv = 0, total = 0, batch = 0;
+};
+CoarseLayout coarse_layout(const Basis& B, int64_t nc);
+// Y = G^-T (nc x nc row-major, host) with G G^T = (W C W^T)[c0:c0+nc, c0:c0+nc]
+int coarse_inverse_factor(const Basis& B, const PairArgs& k, int64_t c0, int64_t nc, void* work, int64_t work_bytes,
+                          std::vector<double>& Y, hipStream_t s);
 // copies the pattern (built for the same level) into the workspace; synchronises s
 int loglik_upload_pattern(const Pattern& P, void* work, const LoglikLayout& L, hipStream_t s);
 // out = {l, log det C^n_W, (Z^n_W)^T (C^n_W)^-1 Z^n_W}; k supplies nu2, nu, rho, sigma2.

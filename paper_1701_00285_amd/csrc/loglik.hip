@@ -31,6 +31,9 @@
 // sparse Cholesky and nested dissection; here the factorization is dense
 // (288 GB of HBM hold C^n_W for N~ up to about 10^5), so the zeros do not
 // shorten it, and tau = inf gives the exact C^n_W.
+//
+// The same dense formation and bordered Cholesky give the coarse block of
+// C_W used by the coarse preconditioner (coarse_inverse_factor, at the end).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -85,13 +88,14 @@ __global__ void clear_flag(int* __restrict__ flag) {
   if (threadIdx.x == 0) flag[0] = 0;
 }
 
-// ---- 2./3. batched analysis: Y[rows < ny] = W X for the cells of one level ----
+// ---- 2./3. batched analysis: Y[row - row_lo] = (W X)[row] for the rows
+// row_lo <= row < row_lo + ny of W produced by the cells of one level -------
 __global__ __launch_bounds__(kT) void batched_analysis(const NodeDesc* __restrict__ desc,
                                                        const int32_t* __restrict__ lnodes,
                                                        const double* __restrict__ V, const double* __restrict__ X,
                                                        int64_t ldx, double* __restrict__ scal, int64_t lds,
-                                                       double* __restrict__ Y, int64_t ldy, int64_t ny,
-                                                       int64_t ncols) {
+                                                       double* __restrict__ Y, int64_t ldy, int64_t row_lo,
+                                                       int64_t ny, int64_t ncols) {
   const NodeDesc D = desc[lnodes[blockIdx.y]];
   const int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x;
   if (j >= ncols) return;
@@ -116,8 +120,8 @@ __global__ __launch_bounds__(kT) void batched_analysis(const NodeDesc* __restric
       if (k < D.a) {
         if (D.scal_off >= 0) scal[(D.scal_off + k) * lds + j] = acc[kk];
       } else {
-        const int64_t row = D.w_off + (k - D.a);
-        if (row < ny) Y[row * ldy + j] = acc[kk];
+        const int64_t row = D.w_off + (k - D.a) - row_lo;
+        if (row >= 0 && row < ny) Y[row * ldy + j] = acc[kk];
       }
     }
   }
@@ -151,6 +155,13 @@ __global__ __launch_bounds__(kT) void apply_pattern(double* __restrict__ C, int6
   const int64_t cc = rowcell[c];
   for (int64_t r = blockIdx.y; r < nt; r += gridDim.y)
     if (!keep[(int64_t)rowcell[r] * nc + cc]) C[r * nt + c] = 0.0;
+}
+
+// rows [0, nc) of an nc x nc row-major block set to the identity
+__global__ __launch_bounds__(kT) void identity_rows(double* __restrict__ Y, int64_t nc) {
+  const int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (c >= nc) return;
+  for (int64_t r = blockIdx.y; r < nc; r += gridDim.y) Y[r * nc + c] = r == c ? 1.0 : 0.0;
 }
 
 // ---- 4. blocked Cholesky (lower), A is n x n with leading dimension ld --------
@@ -456,10 +467,10 @@ LoglikLayout loglik_layout(const Basis& B, int32_t level) {
   return L;
 }
 
-// W X restricted to the first ny rows for the column range of X (levels B.levels-1 .. level)
+// rows [row_lo, row_lo + ny) of W X for the column range of X (levels B.levels-1 .. level)
 static int analysis_batched(const Basis& B, const TransformDev& T, int32_t level, const double* X, int64_t ldx,
-                            int64_t ncols, double* scal, int64_t batch, double* Y, int64_t ldy, int64_t ny,
-                            hipStream_t s) {
+                            int64_t ncols, double* scal, int64_t batch, double* Y, int64_t ldy, int64_t row_lo,
+                            int64_t ny, hipStream_t s) {
   for (int64_t c0 = 0; c0 < ncols; c0 += batch) {
     const int64_t nc = std::min(batch, ncols - c0);
     for (int q = B.levels - 1; q >= level; --q) {
@@ -467,98 +478,64 @@ static int analysis_batched(const Basis& B, const TransformDev& T, int32_t level
       if (cnt <= 0) continue;
       dim3 grid((unsigned)((nc + kT - 1) / kT), (unsigned)cnt);
       hipLaunchKernelGGL(batched_analysis, grid, dim3(kT), 0, s, T.desc, T.level_nodes + lb, T.V, X + c0, ldx, scal,
-                         batch, Y + c0, ldy, ny, nc);
+                         batch, Y + c0, ldy, row_lo, ny, nc);
     }
   }
   return hip_check(hipGetLastError(), "batched analysis launch");
 }
 
-int loglik_upload_pattern(const Pattern& P, void* work, const LoglikLayout& L, hipStream_t s) {
-  if (P.nc != L.cells || (int64_t)P.rowcell.size() != L.rows)
-    return fail(MLBLUP_EINVAL, "loglik: sparsity pattern does not match the level");
-  char* w = (char*)work;
-  if (L.rows > 0) {
-    MLB_HIP(hipMemcpyAsync(w + L.rowcell, P.rowcell.data(), P.rowcell.size() * 4, hipMemcpyHostToDevice, s));
-    MLB_HIP(hipMemcpyAsync(w + L.keep, P.keep.data(), P.keep.size(), hipMemcpyHostToDevice, s));
-  }
-  MLB_HIP(hipStreamSynchronize(s));
-  return MLBLUP_OK;
-}
-
-int loglik_device(const Basis& B, const TransformDev& T, const PairArgs& k, int32_t level, const double* z,
-                  void* work, const LoglikLayout& L, bool masked, double out[3], hipStream_t s) {
-  char* w = (char*)work;
-  double* phi = (double*)(w + L.phi);
-  double* A = (double*)(w + L.a);
-  double* scal = (double*)(w + L.scal);
-  double* zw = (double*)(w + L.zw);
-  double* scalz = (double*)(w + L.scalz);
-  double* dout = (double*)(w + L.out);
-  int* flag = (int*)(w + L.flag);
-  double* linv = (double*)(w + L.linv);
-  const int64_t n = B.n, nt = L.rows;
+// Phi = sigma^2 phi(|x_i - x_j|), N x N row-major; gtab: device room for the
+// general-nu table
+static int dense_phi(const Basis& B, const PairArgs& k, double* phi, double* gtab, hipStream_t s) {
+  const int64_t n = B.n;
   const double* pts = (const double*)((const char*)B.dev_base + B.off_pts);
   const double zs = kernel_scale(k.nu2, k.nu, k.rho);
   const double* gt = nullptr;
   if (k.nu2 == kNuGeneral) {
     const double* host = genu_table_cached(k.nu);
-    if (!host) return fail(MLBLUP_EINVAL, "loglik: nu out of range for the general-nu table");
-    double* dev = (double*)(w + L.gtab);
-    MLB_HIP(hipMemcpyAsync(dev, host, kGenuBytes, hipMemcpyHostToDevice, s));
-    gt = dev;
+    if (!host) return fail(MLBLUP_EINVAL, "dense covariance: nu out of range for the general-nu table");
+    MLB_HIP(hipMemcpyAsync(gtab, host, kGenuBytes, hipMemcpyHostToDevice, s));
+    gt = gtab;
   }
-  hipLaunchKernelGGL(clear_flag, dim3(1), dim3(64), 0, s, flag);
-  // 1. Phi
-  {
-    dim3 grid((unsigned)((n + kT - 1) / kT), (unsigned)std::min<int64_t>(n, 65535));
-    switch (k.nu2) {
-      case 0: hipLaunchKernelGGL(dense_cov<0>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
-      case 1: hipLaunchKernelGGL(dense_cov<1>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
-      case 3: hipLaunchKernelGGL(dense_cov<3>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
-      case 5: hipLaunchKernelGGL(dense_cov<5>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
-      default:
-        hipLaunchKernelGGL(dense_cov<kNuGeneralT>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi);
-    }
-    int st = hip_check(hipGetLastError(), "dense covariance launch");
-    if (st) return st;
+  dim3 grid((unsigned)((n + kT - 1) / kT), (unsigned)std::min<int64_t>(n, 65535));
+  switch (k.nu2) {
+    case 0: hipLaunchKernelGGL(dense_cov<0>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
+    case 1: hipLaunchKernelGGL(dense_cov<1>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
+    case 3: hipLaunchKernelGGL(dense_cov<3>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
+    case 5: hipLaunchKernelGGL(dense_cov<5>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
+    default:
+      hipLaunchKernelGGL(dense_cov<kNuGeneralT>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi);
   }
-  // Z^n_W: the first N~ entries of W z
-  int st = transform_analysis(T, z, zw, nullptr, scalz, s);
-  if (st) return st;
-  if (nt == 0) {
-    out[0] = out[1] = 0.0;
-    out[2] = 0.0;
-    return MLBLUP_OK;
-  }
-  // 2. A = (W Phi)[0:N~, :]
-  if ((st = analysis_batched(B, T, level, phi, n, n, scal, L.batch, A, n, nt, s))) return st;
-  // 3. A^T into Phi's storage (N x N~), then C^n_W = (W A^T)[0:N~, :] into A's storage (ld N~)
-  {
-    dim3 grid((unsigned)((n + kTr - 1) / kTr), (unsigned)((nt + kTr - 1) / kTr));
-    hipLaunchKernelGGL(transpose, grid, dim3(kTr * 8), 0, s, A, nt, n, n, phi, nt);
-    if ((st = hip_check(hipGetLastError(), "transpose launch"))) return st;
-  }
-  double* C = A;
-  if ((st = analysis_batched(B, T, level, phi, nt, nt, scal, L.batch, C, nt, nt, s))) return st;
-  if (masked) {
-    dim3 grid((unsigned)((nt + kT - 1) / kT), (unsigned)std::min<int64_t>(nt, 65535));
-    hipLaunchKernelGGL(apply_pattern, grid, dim3(kT), 0, s, C, nt, (const int32_t*)(w + L.rowcell),
-                       (const uint8_t*)(w + L.keep), L.cells);
-    if ((st = hip_check(hipGetLastError(), "sparsity pattern launch"))) return st;
-  }
-  // 4. Cholesky: panels of kOuter columns, each factored in blocks of kNb
-  // (diagonal factor and inverse, panel product, update of the panel's
-  // remaining columns), then one rank-kOuter update of the trailing matrix.
-  // Z^n_W rides along as an extra row nt (the bordered matrix [C z; z^T .]):
-  // the panel products and updates that make the factor's rows also carry
-  // out the forward substitution, so that row nt ends as y = G^-1 Z^n_W.
-  const int64_t nr = nt + 1;
-  double* y = C + nt * nt;   // A's storage holds nt x n >= (nt + 1) x nt doubles
-  MLB_HIP(hipMemcpyAsync(y, zw, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
-  // Lookahead: after panel [ob, oe) is factored, the main stream updates
-  // only the next panel's columns [oe, oe2) and goes on to factor it, while
-  // the side stream updates the columns >= oe2.  The next lookahead writes
-  // columns that this trailing update writes too, so it waits for it.
+  return hip_check(hipGetLastError(), "dense covariance launch");
+}
+
+// (W Phi W^T) restricted to the rows and columns [row_lo, row_lo + ny) of W,
+// levels >= level: A = (W Phi)[rows, :] (ny x N), A^T into Phi's storage,
+// then W A^T restricted to the same rows, into A's storage with ld ny
+static int dense_cw_block(const Basis& B, const TransformDev& T, int32_t level, double* phi, double* A,
+                          double* scal, int64_t batch, int64_t row_lo, int64_t ny, hipStream_t s) {
+  const int64_t n = B.n;
+  int st;
+  if ((st = analysis_batched(B, T, level, phi, n, n, scal, batch, A, n, row_lo, ny, s))) return st;
+  dim3 grid((unsigned)((n + kTr - 1) / kTr), (unsigned)((ny + kTr - 1) / kTr));
+  hipLaunchKernelGGL(transpose, grid, dim3(kTr * 8), 0, s, A, ny, n, n, phi, ny);
+  if ((st = hip_check(hipGetLastError(), "transpose launch"))) return st;
+  return analysis_batched(B, T, level, phi, ny, ny, scal, batch, A, ny, row_lo, ny, s);
+}
+
+// Blocked right-looking Cholesky of the nt x nt lower triangle of C (ld nt),
+// with the rows [nt, nr) below it as border rows: panels of kOuter columns,
+// each factored in blocks of kNb (diagonal factor and inverse into linv,
+// panel product, update of the panel's remaining columns), then the rank-
+// kOuter update of the trailing matrix.  The border rows B end as B G^-T:
+// a vector z as one border row gives y = G^-1 z (forward substitution), the
+// identity gives G^-T.  Lookahead: after panel [ob, oe) is factored, the
+// main stream updates only the next panel's columns [oe, oe2) and goes on to
+// factor it, while the side stream updates the columns >= oe2; the next
+// lookahead writes columns that this trailing update writes too, so it
+// waits for it.  A pivot that is not positive sets flag[0].
+static int cholesky_bordered(double* C, int64_t nt, int64_t nr, double* linv, int* flag, hipStream_t s) {
+  int st;
   hipStream_t side;
   if ((st = side_stream(&side))) return st;
   Events ev;
@@ -573,9 +550,10 @@ int loglik_device(const Basis& B, const TransformDev& T, const PairArgs& k, int3
       const int nb = (int)std::min<int64_t>(kNb, nt - k0);
       double* li = linv + (k0 / kNb) * kNb * kNb;
       hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(kNb), 0, s, C, nt, k0, nb, li, flag);
-      const int64_t below = nr - k0 - nb;   // >= 1: the border row
-      hipLaunchKernelGGL(trsm_panel, dim3((unsigned)((below + kNb - 1) / kNb)), dim3(kT), 0, s, C, nt, nr, k0, nb,
-                         li);
+      const int64_t below = nr - k0 - nb;
+      if (below > 0)
+        hipLaunchKernelGGL(trsm_panel, dim3((unsigned)((below + kNb - 1) / kNb)), dim3(kT), 0, s, C, nt, nr, k0, nb,
+                           li);
       const int64_t cb = k0 + nb;
       if (cb < oe) {
         const int64_t nct = (oe - cb + kUp - 1) / kUp, nrt = (nr - cb + kUp - 1) / kUp;
@@ -604,8 +582,58 @@ int loglik_device(const Basis& B, const TransformDev& T, const PairArgs& k, int3
     }
   }
   if (trail_pending) MLB_HIP(hipStreamWaitEvent(s, ev_trail, 0));
-  if ((st = hip_check(hipGetLastError(), "Cholesky launch"))) return st;
-  // 5. 2 sum log G_ii and |y|^2
+  return hip_check(hipGetLastError(), "Cholesky launch");
+}
+
+int loglik_upload_pattern(const Pattern& P, void* work, const LoglikLayout& L, hipStream_t s) {
+  if (P.nc != L.cells || (int64_t)P.rowcell.size() != L.rows)
+    return fail(MLBLUP_EINVAL, "loglik: sparsity pattern does not match the level");
+  char* w = (char*)work;
+  if (L.rows > 0) {
+    MLB_HIP(hipMemcpyAsync(w + L.rowcell, P.rowcell.data(), P.rowcell.size() * 4, hipMemcpyHostToDevice, s));
+    MLB_HIP(hipMemcpyAsync(w + L.keep, P.keep.data(), P.keep.size(), hipMemcpyHostToDevice, s));
+  }
+  MLB_HIP(hipStreamSynchronize(s));
+  return MLBLUP_OK;
+}
+
+int loglik_device(const Basis& B, const TransformDev& T, const PairArgs& k, int32_t level, const double* z,
+                  void* work, const LoglikLayout& L, bool masked, double out[3], hipStream_t s) {
+  char* w = (char*)work;
+  double* phi = (double*)(w + L.phi);
+  double* A = (double*)(w + L.a);
+  double* scal = (double*)(w + L.scal);
+  double* zw = (double*)(w + L.zw);
+  double* scalz = (double*)(w + L.scalz);
+  double* dout = (double*)(w + L.out);
+  int* flag = (int*)(w + L.flag);
+  double* linv = (double*)(w + L.linv);
+  const int64_t nt = L.rows;
+  hipLaunchKernelGGL(clear_flag, dim3(1), dim3(64), 0, s, flag);
+  // 1. Phi
+  int st = dense_phi(B, k, phi, (double*)(w + L.gtab), s);
+  if (st) return st;
+  // Z^n_W: the first N~ entries of W z
+  if ((st = transform_analysis(T, z, zw, nullptr, scalz, s))) return st;
+  if (nt == 0) {
+    out[0] = out[1] = 0.0;
+    out[2] = 0.0;
+    return MLBLUP_OK;
+  }
+  // 2./3. C^n_W = (W Phi W^T)[0:N~, 0:N~] into A's storage (ld N~)
+  if ((st = dense_cw_block(B, T, level, phi, A, scal, L.batch, 0, nt, s))) return st;
+  double* C = A;
+  if (masked) {
+    dim3 grid((unsigned)((nt + kT - 1) / kT), (unsigned)std::min<int64_t>(nt, 65535));
+    hipLaunchKernelGGL(apply_pattern, grid, dim3(kT), 0, s, C, nt, (const int32_t*)(w + L.rowcell),
+                       (const uint8_t*)(w + L.keep), L.cells);
+    if ((st = hip_check(hipGetLastError(), "sparsity pattern launch"))) return st;
+  }
+  // 4./5. Cholesky with Z^n_W as the border row nt: row nt ends as y = G^-1 Z^n_W
+  double* y = C + nt * nt;   // A's storage holds nt x n >= (nt + 1) x nt doubles
+  MLB_HIP(hipMemcpyAsync(y, zw, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if ((st = cholesky_bordered(C, nt, nt + 1, linv, flag, s))) return st;
+  // 2 sum log G_ii and |y|^2
   hipLaunchKernelGGL(logdet_quad, dim3(1), dim3(kT), 0, s, C, nt, nt, y, dout);
   if ((st = hip_check(hipGetLastError(), "reduction launch"))) return st;
   double host[2];
@@ -618,6 +646,65 @@ int loglik_device(const Basis& B, const TransformDev& T, const PairArgs& k, int3
   out[1] = host[0];
   out[2] = host[1];
   out[0] = -0.5 * ((double)nt * kLog2Pi + host[0] + host[1]);
+  return MLBLUP_OK;
+}
+
+// ---- coarse block of C_W for the preconditioner ------------------------------
+// The rows [c0, c0 + nc) of W (the coarse levels: they come last) give
+// C_c = (W C W^T)[c0:, c0:].  Formed densely (Phi, then the two batched
+// analyses over every level, keeping those rows), factored G G^T = C_c with
+// the identity as nc border rows, which end as Y = G^-T; then
+// C_c^-1 = G^-T G^-1 = Y Y^T.  Y (nc x nc, row-major) is copied to the host.
+CoarseLayout coarse_layout(const Basis& B, int64_t nc) {
+  CoarseLayout L;
+  const int64_t n = B.n;
+  const int64_t batch = std::min<int64_t>(std::max<int64_t>(n, 1), kColBatch);
+  int64_t o = 0;
+  L.phi = o;
+  o += align256(n * n * 8);
+  L.a = o;
+  o += align256(std::max<int64_t>(std::max(nc * n, 2 * nc * nc), 1) * 8);
+  L.scal = o;
+  o += align256(std::max<int64_t>(B.scal_total, 1) * batch * 8);
+  L.flag = o;
+  o += 256;
+  L.gtab = o;
+  o += align256(kGenuBytes);
+  L.linv = o;
+  o += align256(std::max<int64_t>((nc + kNb - 1) / kNb, 1) * kNb * kNb * 8);
+  L.total = o;
+  L.batch = batch;
+  return L;
+}
+
+int coarse_inverse_factor(const Basis& B, const PairArgs& k, int64_t c0, int64_t nc, void* work, int64_t work_bytes,
+                          std::vector<double>& Y, hipStream_t s) {
+  const CoarseLayout L = coarse_layout(B, nc);
+  if (!work || work_bytes < L.total)
+    return fail(MLBLUP_EINVAL, "coarse preconditioner: workspace too small (need " + std::to_string(L.total) + ")");
+  if (nc <= 0 || c0 < 0 || c0 + nc > B.n - B.p) return fail(MLBLUP_EINVAL, "coarse preconditioner: bad row range");
+  char* w = (char*)work;
+  double* phi = (double*)(w + L.phi);
+  double* C = (double*)(w + L.a);
+  int* flag = (int*)(w + L.flag);
+  const TransformDev T = transform_dev(B);
+  hipLaunchKernelGGL(clear_flag, dim3(1), dim3(64), 0, s, flag);
+  int st = dense_phi(B, k, phi, (double*)(w + L.gtab), s);
+  if (st) return st;
+  if ((st = dense_cw_block(B, T, 0, phi, C, (double*)(w + L.scal), L.batch, c0, nc, s))) return st;
+  double* border = C + nc * nc;
+  {
+    dim3 grid((unsigned)((nc + kT - 1) / kT), (unsigned)std::min<int64_t>(nc, 65535));
+    hipLaunchKernelGGL(identity_rows, grid, dim3(kT), 0, s, border, nc);
+    if ((st = hip_check(hipGetLastError(), "identity launch"))) return st;
+  }
+  if ((st = cholesky_bordered(C, nc, 2 * nc, (double*)(w + L.linv), flag, s))) return st;
+  Y.resize((size_t)nc * nc);
+  int hflag = 0;
+  MLB_HIP(hipMemcpyAsync(Y.data(), border, (size_t)nc * nc * sizeof(double), hipMemcpyDeviceToHost, s));
+  MLB_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  MLB_HIP(hipStreamSynchronize(s));
+  if (hflag) return fail(MLBLUP_EBREAKDOWN, "coarse preconditioner: the coarse block of C_W is not positive definite");
   return MLBLUP_OK;
 }
 

@@ -31,10 +31,11 @@ int prec_cross(const CrossTask* tasks, int32_t ntasks, int NR, const double* pts
 int prec_apply_blocks(const int64_t* w_off, const int32_t* mw, const int64_t* boff, int32_t cnt, const double* Binv,
                       const double* r, double* z, hipStream_t s);
 int prec_apply_diag(const double* inv, const double* r, double* z, int64_t n, hipStream_t s);
+int prec_gemv_rows(const double* M, int64_t n, const double* x, double* out, hipStream_t s);
 
 // Host-side preconditioner object.
 struct Precond {
-  int32_t kind = 0;              // MLBLUP_PREC_JACOBI or MLBLUP_PREC_BLOCK
+  int32_t kind = 0;              // MLBLUP_PREC_JACOBI, MLBLUP_PREC_BLOCK or MLBLUP_PREC_COARSE
   int64_t nw = 0;
   // blocks B_v of C_W per cell (host, row-major mw x mw) and their inverses
   std::vector<int32_t> node;     // cells with mw > 0
@@ -43,14 +44,21 @@ struct Precond {
   std::vector<int64_t> boff;
   std::vector<double> blocks;    // B_v
   std::vector<double> inv;       // block inverses (block kind) or 1/diag (Jacobi, nw entries)
+  // coarse kind: the rows [c0, c0 + nc) of the coarse levels form one block
+  // C_c with C_c^-1 = Y X, Y = G^-T and X = G^-1 (nc x nc row-major each);
+  // the cell blocks above cover only the rows < c0
+  int64_t c0 = 0, nc = 0;
+  std::vector<double> ycoarse, xcoarse;
   // device image (caller-owned)
   void* dev = nullptr;
   int64_t dev_bytes = 0;
-  int64_t off_woff = 0, off_mw = 0, off_boff = 0, off_inv = 0;
+  int64_t off_woff = 0, off_mw = 0, off_boff = 0, off_inv = 0, off_y = 0, off_x = 0;
   bool uploaded = false;
 };
 
 int precond_workspace_bytes(const Basis& B, int64_t* bytes);
+// rows of the coarse block of the coarse kind: every level above the two finest
+void coarse_rows(const Basis& B, int64_t* c0, int64_t* nc);
 int precond_build(const Basis& B, double nu2, double rho, double sigma2, int kind, void* work, int64_t work_bytes,
                   hipStream_t s, Precond& P);
 int precond_apply(const Precond& P, const double* r, double* z, hipStream_t s);

@@ -162,6 +162,13 @@ int precond_workspace_bytes(const Basis& B, int64_t* bytes) {
   return MLBLUP_OK;
 }
 
+void coarse_rows(const Basis& B, int64_t* c0, int64_t* nc) {
+  int64_t f = 0;
+  for (int q = std::max(0, B.levels - 2); q < B.levels; ++q) f += B.level_counts[q];
+  *c0 = f;
+  *nc = (B.n - B.p) - f;
+}
+
 int precond_build(const Basis& B, double nu2d, double rho, double sigma2, int kind, void* work, int64_t work_bytes,
                   hipStream_t s, Precond& P) {
   const WsLayout w = layout(B);
@@ -303,13 +310,17 @@ int precond_build(const Basis& B, double nu2d, double rho, double sigma2, int ki
       }
     }
   }
-  // pack blocks in W-coefficient order (by w_off) and invert
+  // pack blocks in W-coefficient order (by w_off) and invert; the coarse
+  // kind keeps the cells of the two finest levels (rows < c0) only
   P = Precond();
   P.kind = kind;
   P.nw = B.n - B.p;
+  const bool coarse = kind == MLBLUP_PREC_COARSE;
+  int64_t c0 = 0, nc = 0;
+  if (coarse) coarse_rows(B, &c0, &nc);
   std::vector<int32_t> order;
   for (int32_t v = 0; v < nn; ++v)
-    if (B.desc[v].m - B.desc[v].a > 0) order.push_back(v);
+    if (B.desc[v].m - B.desc[v].a > 0 && (!coarse || B.desc[v].w_off < c0)) order.push_back(v);
   std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return B.desc[x].w_off < B.desc[y].w_off; });
   int64_t bo = 0;
   for (int32_t v : order) {
@@ -338,6 +349,16 @@ int precond_build(const Basis& B, double nu2d, double rho, double sigma2, int ki
       ok = spd_inverse(P.mw[k], &P.blocks[P.boff[k]], &P.inv[P.boff[k]]);
     if (!ok) return fail(MLBLUP_EBREAKDOWN, "preconditioner: a diagonal block of C_W is not positive definite");
   }
+  if (coarse) {
+    PairArgs k{nullptr, 0, nullptr, B.n, B.d, nu2, rho, sigma2, MLBLUP_FP64, MLBLUP_VALUE, nullptr, nullptr, nullptr,
+               nu2 == 0 ? INFINITY : 0.5 * nu2, nullptr};
+    if ((st = coarse_inverse_factor(B, k, c0, nc, work, work_bytes, P.ycoarse, s))) return st;
+    P.xcoarse.resize(P.ycoarse.size());
+    for (int64_t i = 0; i < nc; ++i)
+      for (int64_t j = 0; j < nc; ++j) P.xcoarse[(size_t)j * nc + i] = P.ycoarse[(size_t)i * nc + j];
+    P.c0 = c0;
+    P.nc = nc;
+  }
   // device image layout
   int64_t off = 0;
   auto take = [&](int64_t bytes) {
@@ -350,6 +371,8 @@ int precond_build(const Basis& B, double nu2d, double rho, double sigma2, int ki
   P.off_mw = take(nb * 4);
   P.off_boff = take(nb * 8);
   P.off_inv = take((int64_t)P.inv.size() * 8);
+  P.off_y = take(P.nc * P.nc * 8);
+  P.off_x = take(P.nc * P.nc * 8);
   P.dev_bytes = off;
   return MLBLUP_OK;
 }
@@ -357,6 +380,13 @@ int precond_build(const Basis& B, double nu2d, double rho, double sigma2, int ki
 int precond_apply(const Precond& P, const double* r, double* z, hipStream_t s) {
   const char* base = (const char*)P.dev;
   if (P.kind == MLBLUP_PREC_JACOBI) return prec_apply_diag((const double*)(base + P.off_inv), r, z, P.nw, s);
+  if (P.kind == MLBLUP_PREC_COARSE) {
+    // z[0:nc] = X r_c as scratch (c0 >= nc), then z_c = Y (X r_c); the cell
+    // blocks then overwrite z[0:c0]
+    int st = prec_gemv_rows((const double*)(base + P.off_x), P.nc, r + P.c0, z, s);
+    if (st) return st;
+    if ((st = prec_gemv_rows((const double*)(base + P.off_y), P.nc, z, z + P.c0, s))) return st;
+  }
   return prec_apply_blocks((const int64_t*)(base + P.off_woff), (const int32_t*)(base + P.off_mw),
                            (const int64_t*)(base + P.off_boff), (int32_t)P.node.size(),
                            (const double*)(base + P.off_inv), r, z, s);
@@ -380,7 +410,14 @@ int mlblup_precond_build(mlblup_basis b, const mlblup_matern* k, int32_t kind, v
   if (!b || !k || !out) return fail(MLBLUP_EINVAL, "NULL argument");
   *out = nullptr;
   if (!b->b.uploaded) return fail(MLBLUP_ESTATE, "basis not uploaded");
-  if (kind != MLBLUP_PREC_JACOBI && kind != MLBLUP_PREC_BLOCK) return fail(MLBLUP_EINVAL, "unknown preconditioner kind");
+  if (kind != MLBLUP_PREC_JACOBI && kind != MLBLUP_PREC_BLOCK && kind != MLBLUP_PREC_COARSE)
+    return fail(MLBLUP_EINVAL, "unknown preconditioner kind");
+  if (kind == MLBLUP_PREC_COARSE) {
+    int64_t c0, nc;
+    coarse_rows(b->b, &c0, &nc);
+    if (b->b.levels < 3 || nc <= 0 || c0 < nc)
+      return fail(MLBLUP_EINVAL, "coarse preconditioner: needs three or more levels, the two finest holding most rows");
+  }
   const int n2 = nu2_of_nu(k->nu);
   if (n2 < 0) return fail(MLBLUP_EINVAL, "preconditioner: nu must be 0.5, 1.5, 2.5 or +inf (Gaussian)");
   if (!(k->rho > 0) || !(k->sigma2 > 0) || !std::isfinite(k->rho) || !std::isfinite(k->sigma2))
@@ -415,6 +452,10 @@ int mlblup_precond_upload(mlblup_precond pc, void* dev_buf, int64_t bytes, void*
   MLB_HIP(hipMemcpyAsync(base + P.off_mw, P.mw.data(), P.mw.size() * 4, hipMemcpyHostToDevice, s));
   MLB_HIP(hipMemcpyAsync(base + P.off_boff, P.boff.data(), P.boff.size() * 8, hipMemcpyHostToDevice, s));
   MLB_HIP(hipMemcpyAsync(base + P.off_inv, P.inv.data(), P.inv.size() * 8, hipMemcpyHostToDevice, s));
+  if (P.nc > 0) {
+    MLB_HIP(hipMemcpyAsync(base + P.off_y, P.ycoarse.data(), P.ycoarse.size() * 8, hipMemcpyHostToDevice, s));
+    MLB_HIP(hipMemcpyAsync(base + P.off_x, P.xcoarse.data(), P.xcoarse.size() * 8, hipMemcpyHostToDevice, s));
+  }
   MLB_HIP(hipStreamSynchronize(s));
   P.dev = dev_buf;
   P.uploaded = true;
@@ -428,6 +469,27 @@ int mlblup_precond_blocks(mlblup_precond pc, double* blocks_host, int64_t* w_off
   if (blocks_host) std::memcpy(blocks_host, P.blocks.data(), P.blocks.size() * 8);
   if (w_off_host) std::memcpy(w_off_host, P.w_off.data(), P.w_off.size() * 8);
   if (mw_host) std::memcpy(mw_host, P.mw.data(), P.mw.size() * 4);
+  return MLBLUP_OK;
+}
+
+int mlblup_precond_workspace_bytes_kind(mlblup_basis b, int32_t kind, int64_t* bytes) {
+  clear_error();
+  if (!b || !bytes) return fail(MLBLUP_EINVAL, "NULL argument");
+  int st = precond_workspace_bytes(b->b, bytes);
+  if (st || kind != MLBLUP_PREC_COARSE) return st;
+  int64_t c0, nc;
+  coarse_rows(b->b, &c0, &nc);
+  *bytes = std::max(*bytes, coarse_layout(b->b, std::max<int64_t>(nc, 1)).total);
+  return MLBLUP_OK;
+}
+
+int mlblup_precond_coarse(mlblup_precond pc, int64_t* c0, int64_t* nc, double* y_host) {
+  clear_error();
+  if (!pc) return fail(MLBLUP_EINVAL, "NULL preconditioner");
+  const Precond& P = pc->p;
+  if (c0) *c0 = P.c0;
+  if (nc) *nc = P.nc;
+  if (y_host && P.nc > 0) std::memcpy(y_host, P.ycoarse.data(), P.ycoarse.size() * 8);
   return MLBLUP_OK;
 }
 

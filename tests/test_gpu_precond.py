@@ -67,3 +67,63 @@ def test_preconditioned_solves_agree_and_converge_faster(k, n):
     assert relerr(res["block"][0], res["none"][0]) < 1e-6
     assert res["block"][1] < res["none"][1]
     assert res["jacobi"][1] < res["none"][1]
+
+
+@pytest.mark.parametrize("k,n", [(2, 1500), (1, 1000), (4, 1200)])
+def test_coarse_block_inverts_dense_cw(k, n):
+    """Coarse kind: G^-T of the coarse block (every level above the two
+    finest, the last rows of W) against C_W formed densely from the oracle's
+    covariance and the library's own W: Y Y^T C_c = I, Y upper triangular; the
+    cell blocks kept are those of the rows < c0."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import PREC_BLOCK, PREC_COARSE, Solver
+    wl = workload(k, n=n, n_targets=1)
+    say(f"coarse precond cfg{k} n={n}")
+    s = Solver(wl.points, wl.degree_w, wl.leaf_max, wl.nu, wl.rho)
+    pc = s.precond(PREC_COARSE)
+    c0, Y = pc.coarse()
+    counts = s.basis.level_counts()
+    nw = n - s.p
+    assert c0 == int(counts[-2:].sum()) and Y.shape == (nw - c0, nw - c0) and c0 >= Y.shape[0]
+    W, _ = s.basis.dense()
+    pts_t = wl.points[s.tree.perm]
+    CW = W @ cov_matrix(pts_t, pts_t, wl.nu, wl.rho) @ W.T
+    Cc = CW[c0:, c0:]
+    kap = np.linalg.cond(Cc)
+    err = np.abs(Y @ Y.T @ Cc - np.eye(Cc.shape[0])).max()
+    say(f"  nc={Cc.shape[0]} kappa={kap:.1e} |YY^T C_c - I|={err:.1e}")
+    assert err < 100 * kap * 2.2e-16
+    assert np.abs(np.tril(Y, -1)).max() == 0.0
+    blocks, woff = pc.blocks()
+    fine, fwoff = s.precond(PREC_BLOCK).blocks()
+    keep = [i for i, o in enumerate(fwoff) if o < c0]
+    assert list(woff) == [int(fwoff[i]) for i in keep]
+    for B, i in zip(blocks, keep):
+        np.testing.assert_array_equal(B, fine[i])
+
+
+@pytest.mark.parametrize("k,n", [(2, 3000), (4, 3000), (1, 2000)])
+def test_coarse_preconditioned_solve_agrees_and_converges_faster(k, n):
+    torch = require_gpu()
+    from paper_1701_00285_amd import PREC_BLOCK, PREC_COARSE, PcgOptions, Solver
+    wl = workload(k, n=n, n_targets=1)
+    say(f"coarse preconditioned solve cfg{k} n={n}")
+    s = Solver(wl.points, wl.degree_w, wl.leaf_max, wl.nu, wl.rho)
+    zw, _ = s.apply_W(s.to_tree(dev(wl.z)))
+    res = {}
+    for name, kind in (("block", PREC_BLOCK), ("coarse", PREC_COARSE)):
+        gw, info, st = s.solve(zw, PcgOptions(rtol=1e-10, max_iter=20000, precond=s.precond(kind)))
+        assert st == 0 and info["relres_fp64"] <= 1e-10
+        res[name] = (host(gw), info["inner_iters"])
+    say(f"  iterations block {res['block'][1]} coarse {res['coarse'][1]}")
+    assert relerr(res["coarse"][0], res["block"][0]) < 1e-6
+    assert res["coarse"][1] < res["block"][1]
+
+
+def test_coarse_preconditioner_rejects_shallow_trees():
+    require_gpu()
+    from paper_1701_00285_amd import MlblupError, PREC_COARSE, Solver
+    wl = workload(1, n=100, n_targets=1)
+    s = Solver(wl.points, wl.degree_w, 64, wl.nu, wl.rho)   # two levels
+    with pytest.raises(MlblupError, match="EINVAL"):
+        s.precond(PREC_COARSE)
