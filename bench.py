@@ -384,8 +384,10 @@ def main():
                     help="full: independent FP64 solve (timed against the mixed one); refine: FP64 PCG from the mixed "
                          "solution to relres 1e-10 as the error reference (for workloads where a full FP64 solve "
                          "does not fit the time budget); skip: none")
-    ap.add_argument("--precond", choices=("block", "jacobi", "coarse", "none"), default="block",
-                    help="preconditioner of both solves (cell blocks of C_W, its diagonal, or none)")
+    ap.add_argument("--precond", choices=("block", "jacobi", "coarse", "none"), default="coarse",
+                    help="preconditioner of both solves: cell blocks of the two finest levels and one dense "
+                         "coarse block of C_W (coarse; N^2 doubles of workspace while it is built), the cell "
+                         "blocks of every level (block), diag(C_W) (jacobi), or none")
     ap.add_argument("--cpu-rows", type=int, default=3072)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-iter", type=int, default=40000,
