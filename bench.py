@@ -378,7 +378,7 @@ def main():
     ap.add_argument("--scheme", choices=("flexible", "reliable"), default="flexible",
                     help="mixed-precision scheme: flexible CG around inner solves, or one recurrence with reliable "
                          "updates")
-    ap.add_argument("--inner-rtol", type=float, default=0.1,
+    ap.add_argument("--inner-rtol", type=float, default=0.35,
                     help="inner tolerance (flexible) or residual-replacement factor (reliable)")
     ap.add_argument("--fp64-solve", choices=("full", "refine", "skip"), default="full",
                     help="full: independent FP64 solve (timed against the mixed one); refine: FP64 PCG from the mixed "

@@ -325,9 +325,10 @@ int mlblup_precond_workspace_bytes(mlblup_basis b, int64_t* bytes);
 /* MLBLUP_PREC_COARSE: the wavelets of every level above the two finest
  * (the last nc rows of W, from c0 on) form one block C_c = W_c C W_c^T,
  * formed densely on the device (the N x N covariance and two batched
- * analyses) and factored G G^T = C_c with G^-T and G^-1 kept (2 nc^2
- * doubles in the device image); the apply is two row products with them plus
- * the cell blocks of the finer wavelets.  Workspace about 8 (N^2 + nc N)
+ * analyses) and factored G G^T = C_c with G^-T and G^-1 kept, rounded to
+ * FP32 (2 nc^2 floats in the device image; the rounded pair is still an exact
+ * symmetric positive definite preconditioner); the apply is two row products
+ * with them (FP64 sums) plus the cell blocks of the finer wavelets.  Workspace about 8 (N^2 + nc N)
  * bytes, so N of about 10^5 at most; needs three or more levels with the two
  * finest holding at least half of the rows (EINVAL otherwise).  This query
  * gives the workspace of any kind. */

@@ -31,7 +31,7 @@ int prec_cross(const CrossTask* tasks, int32_t ntasks, int NR, const double* pts
 int prec_apply_blocks(const int64_t* w_off, const int32_t* mw, const int64_t* boff, int32_t cnt, const double* Binv,
                       const double* r, double* z, hipStream_t s);
 int prec_apply_diag(const double* inv, const double* r, double* z, int64_t n, hipStream_t s);
-int prec_gemv_rows(const double* M, int64_t n, const double* x, double* out, hipStream_t s);
+int prec_gemv_rows(const float* M, int64_t n, const double* x, double* out, hipStream_t s);
 
 // Host-side preconditioner object.
 struct Precond {
@@ -46,9 +46,13 @@ struct Precond {
   std::vector<double> inv;       // block inverses (block kind) or 1/diag (Jacobi, nw entries)
   // coarse kind: the rows [c0, c0 + nc) of the coarse levels form one block
   // C_c with C_c^-1 = Y X, Y = G^-T and X = G^-1 (nc x nc row-major each);
-  // the cell blocks above cover only the rows < c0
+  // the cell blocks above cover only the rows < c0.  The device image holds
+  // Y and X rounded to FP32 (X32 = Y32^T exactly, so Y32 X32 stays symmetric
+  // positive definite: a fixed preconditioner of the same quality at half the
+  // bytes of each apply)
   int64_t c0 = 0, nc = 0;
-  std::vector<double> ycoarse, xcoarse;
+  std::vector<double> ycoarse;
+  std::vector<float> y32, x32;
   // device image (caller-owned)
   void* dev = nullptr;
   int64_t dev_bytes = 0;

@@ -190,16 +190,17 @@ __global__ __launch_bounds__(kT) void apply_diag(const double* __restrict__ inv,
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) z[i] = inv[i] * r[i];
 }
 
-// out[i] = sum_j M[i][j] x[j] for an n x n row-major M: one wave per row,
-// lanes over j, a fixed-order reduction across the wave
-__global__ __launch_bounds__(kT) void gemv_rows(const double* __restrict__ M, int64_t n, const double* __restrict__ x,
+// out[i] = sum_j M[i][j] x[j] for an n x n row-major M stored in FP32 (the
+// products and sums in FP64): one wave per row, lanes over j, a fixed-order
+// reduction across the wave
+__global__ __launch_bounds__(kT) void gemv_rows(const float* __restrict__ M, int64_t n, const double* __restrict__ x,
                                                double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * (kT / 64) + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (i >= n) return;
-  const double* row = M + i * n;
+  const float* row = M + i * n;
   double acc = 0.0;
-  for (int64_t j = lane; j < n; j += 64) acc = fma(row[j], x[j], acc);
+  for (int64_t j = lane; j < n; j += 64) acc = fma((double)row[j], x[j], acc);
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
   if (lane == 0) out[i] = acc;
 }
@@ -252,7 +253,7 @@ int prec_apply_blocks(const int64_t* w_off, const int32_t* mw, const int64_t* bo
   return hip_check(hipGetLastError(), "apply_blocks launch");
 }
 
-int prec_gemv_rows(const double* M, int64_t n, const double* x, double* out, hipStream_t s) {
+int prec_gemv_rows(const float* M, int64_t n, const double* x, double* out, hipStream_t s) {
   if (n <= 0) return MLBLUP_OK;
   const int64_t g = (n + kT / 64 - 1) / (kT / 64);
   hipLaunchKernelGGL(gemv_rows, dim3((unsigned)g), dim3(kT), 0, s, M, n, x, out);
