@@ -163,3 +163,22 @@ def test_loglik_workspace_counts_the_partial_transform_rows():
     by = C.c_int64()
     assert L.lib().mlblup_loglik_workspace_bytes(b.h, b.levels, C.byref(by), None) == L.EINVAL
     assert L.lib().mlblup_loglik_workspace_bytes(b.h, -1, C.byref(by), None) == L.EINVAL
+
+
+def test_precond_workspace_by_kind():
+    """The coarse kind needs the N x N covariance besides the cell-block
+    build; the other kinds need what the plain query gives."""
+    import ctypes as C
+    from paper_1701_00285_amd import PREC_BLOCK, PREC_COARSE, PREC_JACOBI
+    from paper_1701_00285_amd import _lib as L
+    pts = synth.uniform_cloud(3000, 3, seed=12)
+    b = Basis(Tree(pts, 64), 2)
+    plain, by = C.c_int64(), C.c_int64()
+    assert L.lib().mlblup_precond_workspace_bytes(b.h, C.byref(plain)) == L.OK
+    for kind in (PREC_JACOBI, PREC_BLOCK):
+        assert L.lib().mlblup_precond_workspace_bytes_kind(b.h, kind, C.byref(by)) == L.OK
+        assert by.value == plain.value
+    assert L.lib().mlblup_precond_workspace_bytes_kind(b.h, PREC_COARSE, C.byref(by)) == L.OK
+    counts = b.level_counts()
+    nc = int(counts[:-2].sum())
+    assert by.value >= 8 * (3000 * 3000 + nc * 3000) and by.value >= plain.value
