@@ -385,7 +385,7 @@ def main():
                          "solution to relres 1e-10 as the error reference (for workloads where a full FP64 solve "
                          "does not fit the time budget); skip: none")
     ap.add_argument("--precond", choices=("block", "jacobi", "coarse", "none"), default="coarse",
-                    help="preconditioner of both solves: cell blocks of the two finest levels and one dense "
+                    help="preconditioner of both solves: cell blocks of the finest level and one dense "
                          "coarse block of C_W (coarse; N^2 doubles of workspace while it is built), the cell "
                          "blocks of every level (block), diag(C_W) (jacobi), or none")
     ap.add_argument("--cpu-rows", type=int, default=3072)
@@ -562,7 +562,7 @@ def main():
         "config": {"workload": wname, "n": n, "d": wl.d, "nu": wl.nu, "rho": wl.rho, "trend_p": last["p"],
                    "leaf": wl.leaf_max, "targets": int(T.shape[0]), "rtol": 1e-8,
                    "preconditioner": {"block": "cell blocks of C_W", "jacobi": "diag(C_W)",
-                                      "coarse": "cell blocks of the two finest levels + dense coarse block of C_W",
+                                      "coarse": "cell blocks of the finest level + dense coarse block of C_W",
                                       "none": "none"}[a.precond],
                    "mixed_precision": mixed, "mixed_scheme": a.scheme, "inner_rtol": a.inner_rtol,
                    "fp64_solve": a.fp64_solve},

@@ -70,7 +70,7 @@ typedef struct mlblup_precond_s* mlblup_precond;
 /* Preconditioner kinds (preconditioner remark of Sec. 5.2). */
 #define MLBLUP_PREC_JACOBI 1   /* P_W = diag(C_W) */
 #define MLBLUP_PREC_BLOCK 2    /* P_W = the diagonal blocks of C_W, one per cell (its own wavelets) */
-#define MLBLUP_PREC_COARSE 3   /* the cell blocks of the two finest levels and one dense block of C_W over all
+#define MLBLUP_PREC_COARSE 3   /* the cell blocks of the finest level and one dense block of C_W over all
                                   coarser levels (a coarse space; not in the paper) */
 
 /* mixed-precision schemes (mlblup_pcg_opts.mixed_scheme) */
@@ -322,14 +322,14 @@ int mlblup_mle_nu_rho(mlblup_basis b, double sigma2, const double* z_dev, int32_
  * are fixed at build time: rebuild when rho changes.  work_dev: at least
  * mlblup_precond_workspace_bytes(b).  Synchronises `stream`. */
 int mlblup_precond_workspace_bytes(mlblup_basis b, int64_t* bytes);
-/* MLBLUP_PREC_COARSE: the wavelets of every level above the two finest
- * (the last nc rows of W, from c0 on) form one block C_c = W_c C W_c^T,
+/* MLBLUP_PREC_COARSE: the wavelets of every level above the finest (the
+ * last nc rows of W, from c0 on) form one block C_c = W_c C W_c^T,
  * formed densely on the device (the N x N covariance and two batched
  * analyses) and factored G G^T = C_c with G^-T and G^-1 kept, rounded to
  * FP32 (2 nc^2 floats in the device image; the rounded pair is still an exact
  * symmetric positive definite preconditioner); the apply is two row products
  * with them (FP64 sums) plus the cell blocks of the finer wavelets.  Workspace about 8 (N^2 + nc N)
- * bytes, so N of about 10^5 at most; needs three or more levels with the two
+ * bytes, so N of about 10^5 at most; needs three or more levels with the
  * finest holding at least half of the rows (EINVAL otherwise).  This query
  * gives the workspace of any kind. */
 int mlblup_precond_workspace_bytes_kind(mlblup_basis b, int32_t kind, int64_t* bytes);

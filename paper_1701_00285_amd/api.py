@@ -64,7 +64,7 @@ class PcgOptions:
 
 class Precond:
     """Preconditioner P_W (diag(C_W), its per-cell blocks, or the cell blocks
-    of the two finest levels with one dense coarse block) for a basis and
+    of the finest level with one dense coarse block) for a basis and
     fixed kernel parameters, built on the device and uploaded."""
 
     def __init__(self, basis, kern, kind=PREC_BLOCK, device="cuda"):

@@ -61,7 +61,7 @@ struct Precond {
 };
 
 int precond_workspace_bytes(const Basis& B, int64_t* bytes);
-// rows of the coarse block of the coarse kind: every level above the two finest
+// rows of the coarse block of the coarse kind: every level above the finest
 void coarse_rows(const Basis& B, int64_t* c0, int64_t* nc);
 int precond_build(const Basis& B, double nu2, double rho, double sigma2, int kind, void* work, int64_t work_bytes,
                   hipStream_t s, Precond& P);

@@ -163,8 +163,7 @@ int precond_workspace_bytes(const Basis& B, int64_t* bytes) {
 }
 
 void coarse_rows(const Basis& B, int64_t* c0, int64_t* nc) {
-  int64_t f = 0;
-  for (int q = std::max(0, B.levels - 2); q < B.levels; ++q) f += B.level_counts[q];
+  const int64_t f = B.levels > 0 ? B.level_counts[B.levels - 1] : 0;   // the finest level's rows come first
   *c0 = f;
   *nc = (B.n - B.p) - f;
 }
@@ -311,7 +310,7 @@ int precond_build(const Basis& B, double nu2d, double rho, double sigma2, int ki
     }
   }
   // pack blocks in W-coefficient order (by w_off) and invert; the coarse
-  // kind keeps the cells of the two finest levels (rows < c0) only
+  // kind keeps the cells of the finest level (rows < c0) only
   P = Precond();
   P.kind = kind;
   P.nw = B.n - B.p;
@@ -421,7 +420,7 @@ int mlblup_precond_build(mlblup_basis b, const mlblup_matern* k, int32_t kind, v
     int64_t c0, nc;
     coarse_rows(b->b, &c0, &nc);
     if (b->b.levels < 3 || nc <= 0 || c0 < nc)
-      return fail(MLBLUP_EINVAL, "coarse preconditioner: needs three or more levels, the two finest holding most rows");
+      return fail(MLBLUP_EINVAL, "coarse preconditioner: needs three or more levels, the finest holding most rows");
   }
   const int n2 = nu2_of_nu(k->nu);
   if (n2 < 0) return fail(MLBLUP_EINVAL, "preconditioner: nu must be 0.5, 1.5, 2.5 or +inf (Gaussian)");

@@ -71,8 +71,8 @@ def test_preconditioned_solves_agree_and_converge_faster(k, n):
 
 @pytest.mark.parametrize("k,n", [(2, 1500), (1, 1000), (4, 1200)])
 def test_coarse_block_inverts_dense_cw(k, n):
-    """Coarse kind: G^-T of the coarse block (every level above the two
-    finest, the last rows of W) against C_W formed densely from the oracle's
+    """Coarse kind: G^-T of the coarse block (every level above the finest,
+    the last rows of W) against C_W formed densely from the oracle's
     covariance and the library's own W: Y Y^T C_c = I, Y upper triangular; the
     cell blocks kept are those of the rows < c0."""
     torch = require_gpu()
@@ -84,7 +84,7 @@ def test_coarse_block_inverts_dense_cw(k, n):
     c0, Y = pc.coarse()
     counts = s.basis.level_counts()
     nw = n - s.p
-    assert c0 == int(counts[-2:].sum()) and Y.shape == (nw - c0, nw - c0) and c0 >= Y.shape[0]
+    assert c0 == int(counts[-1]) and Y.shape == (nw - c0, nw - c0) and c0 >= Y.shape[0]
     W, _ = s.basis.dense()
     pts_t = wl.points[s.tree.perm]
     CW = W @ cov_matrix(pts_t, pts_t, wl.nu, wl.rho) @ W.T

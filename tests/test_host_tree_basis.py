@@ -180,5 +180,5 @@ def test_precond_workspace_by_kind():
         assert by.value == plain.value
     assert L.lib().mlblup_precond_workspace_bytes_kind(b.h, PREC_COARSE, C.byref(by)) == L.OK
     counts = b.level_counts()
-    nc = int(counts[:-2].sum())
+    nc = int(counts[:-1].sum())
     assert by.value >= 8 * (3000 * 3000 + nc * 3000) and by.value >= plain.value
