@@ -31,7 +31,7 @@ int prec_cross(const CrossTask* tasks, int32_t ntasks, int NR, const double* pts
 int prec_apply_blocks(const int64_t* w_off, const int32_t* mw, const int64_t* boff, int32_t cnt, const double* Binv,
                       const double* r, double* z, hipStream_t s);
 int prec_apply_diag(const double* inv, const double* r, double* z, int64_t n, hipStream_t s);
-int prec_gemv_rows(const float* M, int64_t n, const double* x, double* out, hipStream_t s);
+int prec_gemv_rows(const float* M, int64_t n, int64_t ld, const double* x, double* out, hipStream_t s);
 
 // Host-side preconditioner object.
 struct Precond {
@@ -50,7 +50,7 @@ struct Precond {
   // Y and X rounded to FP32 (X32 = Y32^T exactly, so Y32 X32 stays symmetric
   // positive definite: a fixed preconditioner of the same quality at half the
   // bytes of each apply)
-  int64_t c0 = 0, nc = 0;
+  int64_t c0 = 0, nc = 0, ldc = 0;   // ldc: row stride of Y32 and X32 (nc rounded up to 4, zero padding)
   std::vector<double> ycoarse;
   std::vector<float> y32, x32;
   // device image (caller-owned)

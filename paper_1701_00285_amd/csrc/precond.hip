@@ -190,17 +190,31 @@ __global__ __launch_bounds__(kT) void apply_diag(const double* __restrict__ inv,
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) z[i] = inv[i] * r[i];
 }
 
-// out[i] = sum_j M[i][j] x[j] for an n x n row-major M stored in FP32 (the
-// products and sums in FP64): one wave per row, lanes over j, a fixed-order
-// reduction across the wave
-__global__ __launch_bounds__(kT) void gemv_rows(const float* __restrict__ M, int64_t n, const double* __restrict__ x,
-                                               double* __restrict__ out) {
+// out[i] = sum_j M[i][j] x[j] for an n x n row-major M stored in FP32 with
+// rows of ld floats (ld a multiple of 4, zero padding): one wave per row,
+// 16-byte loads of four entries per lane, products and sums in FP64, a
+// fixed-order reduction across the wave; x has n entries
+__global__ __launch_bounds__(kT) void gemv_rows(const float* __restrict__ M, int64_t n, int64_t ld,
+                                               const double* __restrict__ x, double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * (kT / 64) + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (i >= n) return;
-  const float* row = M + i * n;
+  const float4* row = (const float4*)(M + i * ld);
   double acc = 0.0;
-  for (int64_t j = lane; j < n; j += 64) acc = fma((double)row[j], x[j], acc);
+  for (int64_t c = lane; c < ld / 4; c += 64) {
+    const float4 v = row[c];
+    const int64_t j = 4 * c;
+    if (j + 3 < n) {
+      acc = fma((double)v.x, x[j], acc);
+      acc = fma((double)v.y, x[j + 1], acc);
+      acc = fma((double)v.z, x[j + 2], acc);
+      acc = fma((double)v.w, x[j + 3], acc);
+    } else {
+      if (j < n) acc = fma((double)v.x, x[j], acc);
+      if (j + 1 < n) acc = fma((double)v.y, x[j + 1], acc);
+      if (j + 2 < n) acc = fma((double)v.z, x[j + 2], acc);
+    }
+  }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
   if (lane == 0) out[i] = acc;
 }
@@ -253,10 +267,11 @@ int prec_apply_blocks(const int64_t* w_off, const int32_t* mw, const int64_t* bo
   return hip_check(hipGetLastError(), "apply_blocks launch");
 }
 
-int prec_gemv_rows(const float* M, int64_t n, const double* x, double* out, hipStream_t s) {
+int prec_gemv_rows(const float* M, int64_t n, int64_t ld, const double* x, double* out, hipStream_t s) {
   if (n <= 0) return MLBLUP_OK;
+  if (ld < n || ld % 4) return fail(MLBLUP_EINVAL, "gemv_rows: row stride must be >= n and a multiple of 4");
   const int64_t g = (n + kT / 64 - 1) / (kT / 64);
-  hipLaunchKernelGGL(gemv_rows, dim3((unsigned)g), dim3(kT), 0, s, M, n, x, out);
+  hipLaunchKernelGGL(gemv_rows, dim3((unsigned)g), dim3(kT), 0, s, M, n, ld, x, out);
   return hip_check(hipGetLastError(), "gemv_rows launch");
 }
 

@@ -352,14 +352,16 @@ int precond_build(const Basis& B, double nu2d, double rho, double sigma2, int ki
     PairArgs k{nullptr, 0, nullptr, B.n, B.d, nu2, rho, sigma2, MLBLUP_FP64, MLBLUP_VALUE, nullptr, nullptr, nullptr,
                nu2 == 0 ? INFINITY : 0.5 * nu2, nullptr};
     if ((st = coarse_inverse_factor(B, k, c0, nc, work, work_bytes, P.ycoarse, s))) return st;
-    P.y32.resize(P.ycoarse.size());
-    P.x32.resize(P.ycoarse.size());
+    const int64_t ldc = (nc + 3) / 4 * 4;
+    P.y32.assign((size_t)nc * ldc, 0.0f);
+    P.x32.assign((size_t)nc * ldc, 0.0f);
     for (int64_t i = 0; i < nc; ++i)
       for (int64_t j = 0; j < nc; ++j) {
         const float v = (float)P.ycoarse[(size_t)i * nc + j];
-        P.y32[(size_t)i * nc + j] = v;
-        P.x32[(size_t)j * nc + i] = v;
+        P.y32[(size_t)i * ldc + j] = v;
+        P.x32[(size_t)j * ldc + i] = v;
       }
+    P.ldc = ldc;
     P.c0 = c0;
     P.nc = nc;
   }
@@ -375,8 +377,8 @@ int precond_build(const Basis& B, double nu2d, double rho, double sigma2, int ki
   P.off_mw = take(nb * 4);
   P.off_boff = take(nb * 8);
   P.off_inv = take((int64_t)P.inv.size() * 8);
-  P.off_y = take(P.nc * P.nc * 4);
-  P.off_x = take(P.nc * P.nc * 4);
+  P.off_y = take(P.nc * P.ldc * 4);
+  P.off_x = take(P.nc * P.ldc * 4);
   P.dev_bytes = off;
   return MLBLUP_OK;
 }
@@ -387,9 +389,9 @@ int precond_apply(const Precond& P, const double* r, double* z, hipStream_t s) {
   if (P.kind == MLBLUP_PREC_COARSE) {
     // z[0:nc] = X r_c as scratch (c0 >= nc), then z_c = Y (X r_c); the cell
     // blocks then overwrite z[0:c0]
-    int st = prec_gemv_rows((const float*)(base + P.off_x), P.nc, r + P.c0, z, s);
+    int st = prec_gemv_rows((const float*)(base + P.off_x), P.nc, P.ldc, r + P.c0, z, s);
     if (st) return st;
-    if ((st = prec_gemv_rows((const float*)(base + P.off_y), P.nc, z, z + P.c0, s))) return st;
+    if ((st = prec_gemv_rows((const float*)(base + P.off_y), P.nc, P.ldc, z, z + P.c0, s))) return st;
   }
   return prec_apply_blocks((const int64_t*)(base + P.off_woff), (const int32_t*)(base + P.off_mw),
                            (const int64_t*)(base + P.off_boff), (int32_t)P.node.size(),
