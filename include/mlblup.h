@@ -222,6 +222,14 @@ int mlblup_apply_Wt(mlblup_basis b, const double* vw_dev, const double* vl_dev, 
  * m_targets) (m_targets = largest target count used with it, 0 if none). */
 int mlblup_solve_workspace_bytes(mlblup_basis b, const mlblup_pcg_opts* opts, int64_t m_targets, int64_t* bytes);
 
+/* The operator of the Krylov solve: out = C_W in = W C(theta) W^T in, the
+ * three-step product of Sec. 6.2 (W^T, the dense covariance product, W) in
+ * the arithmetic `precision` of the pair kernel; in_dev and out_dev hold
+ * N - p values (coefficients of the rows of W) and must not overlap.
+ * Asynchronous on `stream`; workspace as for the solve (m_targets = 0). */
+int mlblup_cw_matvec(mlblup_basis b, const mlblup_matern* k, const double* in_dev, double* out_dev,
+                     int32_t precision, void* work_dev, int64_t work_bytes, void* stream);
+
 /* Solves C_W gamma_W = zw by PCG (initial guess: gw_dev on entry when
  * use_x0 != 0, else 0).  An all-zero right-hand side returns gamma_W = 0.
  * Returns MLBLUP_ENOCONV with the last iterate if rtol is not reached. */
@@ -250,7 +258,8 @@ int mlblup_blup_predict(mlblup_basis b, const mlblup_matern* k, const double* z_
  * likelihood, Sec. 3): Q = z . gamma (= Z_W . gamma_W) and
  * dQ/dlog rho = -lambda^T (rho dC/drho) gamma, lambda = gamma when
  * lambda_dev is NULL (the adjoint of Q is gamma itself), else the W^T image
- * of an adjoint solve.  One fused value/derivative pass over the pairs. */
+ * of an adjoint solve.  One pass of the rho-derivative pair kernel
+ * (MLBLUP_DLOGRHO output only) over the pairs; Q is a plain dot product. */
 int mlblup_blup_grad(mlblup_basis b, const mlblup_matern* k, const double* z_dev, const double* gamma_dev,
                      const double* lambda_dev, int32_t precision, double* Q_host, double* dQ_dlogrho_host,
                      void* work_dev, int64_t work_bytes, void* stream);

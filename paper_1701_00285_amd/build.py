@@ -4,8 +4,7 @@
 
 Every source is compiled by hipcc for gfx950 with packed FP32 instructions
 disabled, objects go to _build/ at the repository root, the library to
-paper_1701_00285_amd/libmlblup.so; the issue-rate probe (csrc/issue_rates.hip)
-to paper_1701_00285_amd/issue_rates.
+paper_1701_00285_amd/libmlblup.so.
 """
 from __future__ import annotations
 
@@ -21,7 +20,6 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmlblup.so")
-PROBE = os.path.join(PKG, "issue_rates")
 SOURCES = ["tree.cpp", "basis.cpp", "sparsify.cpp", "abi.cpp", "precond_host.cpp", "genu.cpp", "ops.hip", "pair.hip", "pair_sym.hip", "precond.hip",
            "pair_mfma.hip", "loglik.hip"]
 
@@ -61,11 +59,6 @@ def build(jobs: int = 8, verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
-    # the issue-rate probe (a standalone program, not part of the library)
-    cmd = [hipcc()] + [f for f in FLAGS if f not in ("-fPIC",)] + [os.path.join(CSRC, "issue_rates.hip"), "-o", PROBE]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"probe build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     if verbose:
         print(f"built {LIB}")
     return LIB

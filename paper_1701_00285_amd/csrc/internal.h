@@ -76,6 +76,7 @@ struct Basis {
   int64_t dev_bytes = 0;
   // offsets inside the device image (bytes)
   int64_t off_desc = 0, off_V = 0, off_Vt = 0, off_pts = 0, off_levels = 0, off_exps = 0;
+  int64_t off_rootc = 0;      // root-frame centre (d doubles, 256-byte aligned)
   int64_t off_children = 0;   // left, then right child of every node (-1 for leaves): 2 x nodes int32
   bool uploaded = false;
 };

@@ -105,7 +105,7 @@ struct ExpParts {
 };
 __device__ __forceinline__ ExpParts exp_neg_parts(double z, const double* __restrict__ tab) {
   z = fmin(z, 700.0);
-  // k = nearest integer to -z 64/ln2: adding 1.5 * 2^52 leaves k in the low
+  // k = nearest integer to -z 256/ln2: adding 1.5 * 2^52 leaves k in the low
   // mantissa bits (exact rounding by the FMA); subtracting it back gives k
   constexpr double kShift = 6755399441055744.0;  // 1.5 * 2^52
   const double t = fma(-z, kExpInvL, kShift);
