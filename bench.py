@@ -1,27 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the multilevel BLUP solve on one MI355X.
 
-One step = one pass of the whole hot path over one synthetic workload:
-kd-tree and multilevel basis (host C++), basis upload, the preconditioner
-(cell blocks of C_W by default), W Z, the FP64 PCG solve of
-C_W gamma_W = Z_W to relres 1e-8, the mixed-precision solve of the same
-system to the same FP64 relres (FP32 kernel values inside the Krylov
-recurrence; flexible CG around inner solves by default), the predictor of
-each path (warm-started from its own solution: true FP64 residual, gamma,
-beta-hat, predictions at the targets with FP64 products) and Q, dQ/dlog rho
-of each.  The errors of the mixed path against the FP64 path are reported,
-and for the record also those of low-precision target and gradient
-products.  Inputs (points, Z, targets) are resident in HBM when the timed
-region starts.
+Default line (the headline metric, Matern C.x Gpairs/s): one step = one
+application of the solve's operator C_W = W C(theta) W^T in FP64 (W^T, the
+dense covariance product over all N^2 ordered pairs, W) on the largest
+workload: 1,048,576 points in d = 20 (half uniform in [0,1]^20, half near a
+random 3-dimensional affine subspace), Matern nu = 1/2, rho = 1, linear trend
+(p = 21), leaf 64.  The points, the basis image and the input vector are
+resident in HBM before the timed region; `value` = N^2 logical pairs per
+step over the wall-clock time of the K timed steps.  The same line carries:
+the FP64 product's rate from HIP events on the launch stream and its
+roofline object (sym_kernel, FP64 vector peak), the evaluated (unordered)
+pair count, the mixed-precision operator (BF16 x3 matrix-core Gram for
+d >= 8, FP32 otherwise) with its error against the FP64 one, the FP64
+product against the oracle on sampled rows, a record of the whole predictor
+path (tree, basis, preconditioner, FP64 and mixed solves to relres 1e-8,
+predictors, gradients) on the 65,536-point d = 3 workload under its own
+key, and the oracle's CPU baseline.
 
-The default workload is 65,536 uniform points in [0,1]^3, Matern nu=3/2,
-rho=0.2, quadratic trend (p=10), leaf 64, 4,096 targets.
-
-Prints ONE JSON line.  `value` = logical covariance pairs evaluated per
-second over the whole step (Gpairs/s); the per-phase times, the solve
-times (FP64 vs mixed), the pair-kernel rates measured with HIP events on
-the launch stream, the roofline object of the dominant kernel (the FP64
-pair kernel) and the CPU oracle baseline are added to the same line.
+`--solve` prints the whole-path line for one workload instead (the records
+under profiles/blup_solve_* come from it); `--sweep`, `--loglik` and
+`--cpu-oracle` are the other measurement modes.
 """
 from __future__ import annotations
 
@@ -48,7 +47,9 @@ def flops_per_unordered_pair(d: int, nu: float) -> int:
     return 3 * d + 6 + poly
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sym_kernel_fp64_cfg2_n65536_d3.txt")
+TRAFFIC_FILES = {"cfg2_n65536_d3_nu1.5": os.path.join(ROOT, "profiles", "traffic_sym_kernel_fp64_cfg2_n65536_d3.txt"),
+                 "cfg5_n1048576_d20_nu0.5": os.path.join(ROOT, "profiles",
+                                                         "traffic_sym_kernel_fp64_cfg5_n1048576_d20.txt")}
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_per_pair_sym_kernel.txt")
 VALU_LANE_RATE = 256 * 4 * 16 * 2.4e9   # VALU lane-instructions per second (CUs x SIMDs x lanes x clock)
 
@@ -83,11 +84,13 @@ def valu_per_pair(kind: str, d: int, nu: float):
     return float(v) if v is not None else None
 
 
-def measured_traffic():
-    """HBM bytes per FP64 symmetric product from the calibrated rocprofv3
-    FETCH_SIZE / WRITE_SIZE runs recorded under profiles/, or None when the
-    kernel sources changed since they were taken (hash mismatch)."""
-    kv = _hashed_file(TRAFFIC_FILE)
+def measured_traffic(workload: str):
+    """HBM bytes per FP64 symmetric product of a full-size workload from the
+    calibrated rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded under
+    profiles/, or None when there is no record or the kernel sources changed
+    since it was taken (hash mismatch)."""
+    path = TRAFFIC_FILES.get(workload)
+    kv = _hashed_file(path) if path else None
     return int(float(kv["hbm_bytes_per_product"])) if kv else None
 
 
@@ -362,78 +365,18 @@ def loglik_bench(k: int, n: int, reps: int = 3, quick: bool = False):
     print(json.dumps(res), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--n", type=int, default=0, help="number of points drawn from the workload generator (0: its full size)")
-    ap.add_argument("--targets", type=int, default=0, help="number of targets (0: the workload's)")
-    ap.add_argument("--nu", type=float, default=0.0,
-                    help="smoothness in place of the workload's (sweep: products only; a nu other than 1/2, 3/2, "
-                         "5/2 or +inf has FP64 values only)")
-    ap.add_argument("--mixed", type=int, default=-1, help="precision of the mixed solve (default: FP32 for d<8, "
-                                                          "matrix-core BF16 x3 for d>=8)")
-    ap.add_argument("--scheme", choices=("flexible", "reliable"), default="flexible",
-                    help="mixed-precision scheme: flexible CG around inner solves, or one recurrence with reliable "
-                         "updates")
-    ap.add_argument("--inner-rtol", type=float, default=0.35,
-                    help="inner tolerance (flexible) or residual-replacement factor (reliable)")
-    ap.add_argument("--fp64-solve", choices=("full", "refine", "skip"), default="full",
-                    help="full: independent FP64 solve (timed against the mixed one); refine: FP64 PCG from the mixed "
-                         "solution to relres 1e-10 as the error reference (for workloads where a full FP64 solve "
-                         "does not fit the time budget); skip: none")
-    ap.add_argument("--precond", choices=("block", "jacobi", "coarse", "none"), default="coarse",
-                    help="preconditioner of both solves: cell blocks of the finest level and one dense "
-                         "coarse block of C_W (coarse; N^2 doubles of workspace while it is built), the cell "
-                         "blocks of every level (block), diag(C_W) (jacobi), or none")
-    ap.add_argument("--cpu-rows", type=int, default=3072)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--max-iter", type=int, default=40000,
-                    help="Krylov iteration cap (lower it only for short profiling runs)")
-    ap.add_argument("--sweep", default="",
-                    help="comma-separated workloads: time every precision's product, the target product and W / W^T "
-                         "(one JSON line each) instead of the step")
-    ap.add_argument("--loglik", type=int, default=0,
-                    help="estimator: time the multilevel log-likelihood (dense C^n_W, blocked Cholesky) and the "
-                         "rho MLE on this many points of the workload's generator (one JSON line) instead of the step")
-    ap.add_argument("--cpu-oracle", choices=("all", "products", "blup"), default=None,
-                    help="time the oracle on the host's cores (covariance products, dense classic BLUP) beside "
-                         "the GPU predictor; one JSON line instead of the step")
-    ap.add_argument("--loglik-quick", action="store_true",
-                    help="with --loglik: levels t and 0 only, one timed call each")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only copy 512 MiB three times with a plain device copy (reference for HBM counters)")
-    a = ap.parse_args()
-    if a.gpus != 1:
-        print(f"bench.py: the path runs on one GPU; --gpus {a.gpus} is not supported (run with --gpus 1)",
-              file=sys.stderr)
-        sys.exit(2)
-
+def solve_bench(a):
+    """The whole predictor path on one workload (a.config), a.warmup untimed
+    and a.steps timed steps; returns the result dict (one JSON line):
+    kd-tree and multilevel basis (host C++), basis upload, the
+    preconditioner, W Z, the FP64 PCG solve of C_W gamma_W = Z_W to relres
+    1e-8, the mixed-precision solve of the same system to the same FP64
+    relres, the predictor of each path (warm-started from its own solution:
+    true FP64 residual, gamma, beta-hat, predictions at the targets with FP64
+    products) and Q, dQ/dlog rho of each.  `value` = logical covariance
+    pairs of every product per second over the step."""
     import numpy as np
     import torch
-
-    if a.sweep:
-        sweep([int(v) for v in a.sweep.split(",")], nu=a.nu or None)
-        return
-
-    if a.loglik:
-        loglik_bench(a.config, a.loglik, quick=a.loglik_quick)
-        return
-
-    if a.cpu_oracle:
-        cpu_oracle_report(a.cpu_oracle)
-        return
-
-    if a.copy_calibration:
-        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_per_launch": src.numel() * 8, "launches": 3}), flush=True)
-        return
 
     import synth
     from paper_1701_00285_amd import (FP32, FP64, MFMA_BF16X3, MIXED_FLEXIBLE, MIXED_RELIABLE, PREC_BLOCK,
@@ -547,7 +490,7 @@ def main():
     i64, im, ip = last["info64"], last["infom"], last["infop"]
     rnd = lambda v, k=4: None if v is None else round(v, k)
     out = {
-        "metric": "Matern C.x Gpairs/s (whole step); BLUP solve time to relres 1e-8, FP64 vs mixed",
+        "metric": "Matern C.x Gpairs/s (whole predictor step); BLUP solve time to relres 1e-8, FP64 vs mixed",
         "value": round(value, 3),
         "unit": "Gpairs/s",
         "n_gpus": 1,
@@ -596,7 +539,7 @@ def main():
         frac_sq = sq64 * n * n / pairs64
         t_sq = ms64 * 1e-3 * frac_sq
         achieved = sq64 * (n * (n + 1) / 2) * fpp / t_sq / 1e12
-        traffic = measured_traffic() if (wl.n == 65536 and wl.d == 3) else None
+        traffic = measured_traffic(wl.name) if not a.n else None
         out["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU_TFLOPS,
                            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4),
                            "traffic": traffic,
@@ -613,8 +556,228 @@ def main():
                                                 "frac": round(got / ceil, 4)}
     out["grad"] = {"Q": last["q"], "dQ_dlogrho": last["dq"], "Q_mixed": last["qm"], "dQ_dlogrho_mixed": last["dqm"]}
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl, a.cpu_rows)
-    print(json.dumps(out), flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, a.cpu_rows or default_cpu_rows(wl))
+    return out
+
+
+
+
+def default_cpu_rows(wl) -> int:
+    """Rows of the oracle's CPU product sample: about 4e9 / (n (d + 3))
+    (10-20 s of one host core at the oracle's measured rates)."""
+    return int(max(16, min(wl.n, 4e9 / (wl.n * (wl.d + 3)))))
+
+
+def product_bench(a):
+    """The headline line: a.warmup untimed and a.steps timed applications of
+    the FP64 operator C_W of the solve on workload a.config (full size unless
+    a.n), plus the records described in the module docstring."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import brute
+    from paper_1701_00285_amd import (FP32, FP64, MFMA_BF16X3, VALUE, Solver, profile_enable, profile_read)
+
+    torch.cuda.set_device(0)
+    wl = synth.make_config(a.config, n=a.n or None, n_targets=1, with_z=False)
+    wname = wl.name if not a.n else f"{wl.name}, generator at n={wl.n}"
+    n, d = wl.n, wl.d
+    print(f"bench: product line, {wname}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    s = Solver(wl.points, wl.degree_w, wl.leaf_max, wl.nu, wl.rho, wl.sigma2)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    nw = n - s.p
+    x = torch.as_tensor(synth.standard_normal(nw, 11), dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    mixed = a.mixed if a.mixed >= 0 else (FP32 if d < 8 else MFMA_BF16X3)
+    for _ in range(a.warmup):
+        s.cw_matvec(x, FP64, out=y)
+    torch.cuda.synchronize()
+    profile_enable(True)
+    profile_read()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        s.cw_matvec(x, FP64, out=y)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = profile_read()
+    ms64, n64, _ = prof[(FP64, VALUE)]
+    print(f"bench: {a.steps} FP64 operator applications in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    # the mixed-precision operator (the inner products of the mixed solve)
+    ym = torch.empty_like(x)
+    for _ in range(2):
+        s.cw_matvec(x, mixed, out=ym)
+    torch.cuda.synchronize()
+    profile_read()
+    reps = 5
+    for _ in range(reps):
+        s.cw_matvec(x, mixed, out=ym)
+    torch.cuda.synchronize()
+    msm, nm, _ = profile_read()[(mixed, VALUE)]
+    profile_enable(False)
+    err_mixed = float(torch.max(torch.abs(ym - y)) / torch.max(torch.abs(y)))
+    # the FP64 covariance product itself against the oracle on 16 sampled rows
+    av = s.apply_Wt(x)
+    cv, _ = s.cov_matvec_tree(av, FP64)
+    pts = s.basis.points_dev.cpu().numpy()
+    a_host = av.cpu().numpy()
+    idx = np.random.default_rng(a.config).choice(n, 16, replace=False)
+    ref = brute.cov_matvec(pts[idx], pts, a_host, wl.nu, wl.rho, wl.sigma2)
+    scale = brute.cov_matvec(pts[idx], pts, np.abs(a_host), wl.nu, wl.rho, wl.sigma2)
+    rowerr = float(np.max(np.abs(cv.cpu().numpy()[idx] - ref) / scale))
+    value = a.steps * n * n / elapsed / 1e9
+    fpp = flops_per_unordered_pair(d, wl.nu)
+    t_prod = ms64 * 1e-3 / n64                      # HIP-event time of one FP64 square product
+    evaluated = n * (n + 1) / 2
+    achieved = evaluated * fpp / t_prod / 1e12
+    out = {
+        "metric": "Matern C.x Gpairs/s; BLUP solve time to relres 1e-8, FP64 vs mixed",
+        "value": round(value, 3),
+        "unit": "Gpairs/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(elapsed / a.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded)",
+        "config": {"workload": wname, "n": n, "d": d, "nu": wl.nu, "rho": wl.rho, "trend_p": s.p,
+                   "leaf": wl.leaf_max,
+                   "step": "one FP64 application of C_W = W C W^T (W^T, dense N x N covariance product, W)",
+                   "pairs_per_step": "N^2 logical (ordered) pairs"},
+        "setup_s": round(setup_s, 3),
+        "fp64_product": {"events_ms": round(t_prod * 1e3, 3), "launches": n64,
+                         "logical_gpairs_s": round(n * n / t_prod / 1e9, 2),
+                         "evaluated_pairs_per_product": evaluated,
+                         "evaluated_gpairs_s": round(evaluated / t_prod / 1e9, 2),
+                         "rowerr_vs_oracle": rowerr},
+        "mixed_product": {"precision": {FP32: "fp32", MFMA_BF16X3: "mfma_bf16x3"}.get(mixed, str(mixed)),
+                          "events_ms": round(msm / nm, 3), "launches": nm,
+                          "logical_gpairs_s": round(n * n / (msm / nm * 1e-3) / 1e9, 2),
+                          "maxrelerr_vs_fp64_operator": err_mixed},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4),
+                     "traffic": measured_traffic(wl.name) if not a.n else None,
+                     "kernel": "sym_kernel FP64 value (square C x; all dispatches of one product)",
+                     "avg_launch_ms": round(t_prod * 1e3, 3), "flops_per_unordered_pair": fpp,
+                     "unordered_pairs_per_launch": evaluated},
+    }
+    vpp = valu_per_pair("fp64", d, wl.nu)
+    if vpp:
+        ceil = 2 * VALU_LANE_RATE / vpp / 1e9
+        got = n * n / t_prod / 1e9
+        out["roofline"]["issue_ceiling"] = {"valu_instr_per_pair": vpp, "ceiling_logical_gpairs_s": round(ceil, 1),
+                                            "achieved_logical_gpairs_s": round(got, 1), "frac": round(got / ceil, 4)}
+    del s, x, y, ym, av, cv
+    torch.cuda.empty_cache()
+    if a.record_config:
+        # the whole predictor path on its own workload, one warm and one timed step
+        import argparse as _ap
+        ra = _ap.Namespace(**vars(a))
+        ra.config, ra.n, ra.targets, ra.steps, ra.warmup, ra.no_cpu = a.record_config, 0, 0, 1, 1, True
+        ra.mixed = -1
+        print(f"bench: whole-path record on workload {ra.config}", file=sys.stderr, flush=True)
+        r = solve_bench(ra)
+        out["solve_record"] = {"workload": r["config"]["workload"], "preconditioner": r["config"]["preconditioner"],
+                               "mixed_precision": r["config"]["mixed_precision"],
+                               "inner_rtol": r["config"]["inner_rtol"], "phases_s": r["phases_s"],
+                               "solve": r["solve"], "grad": r["grad"],
+                               "fp64_product_logical_gpairs_s": r["pair_kernel"]["fp64_logical_gpairs_s"]}
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, a.cpu_rows or default_cpu_rows(wl))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=0,
+                    help="workload 1-5 (default: 5 for the product line, 2 for --solve and --loglik)")
+    ap.add_argument("--solve", action="store_true",
+                    help="time the whole predictor path (tree, basis, preconditioner, FP64 and mixed solves to relres "
+                         "1e-8, predictors, gradients) on --config instead of the product line")
+    ap.add_argument("--record-config", type=int, default=2,
+                    help="workload of the whole-path record carried by the product line (0: none)")
+    ap.add_argument("--n", type=int, default=0, help="number of points drawn from the workload generator (0: its full size)")
+    ap.add_argument("--targets", type=int, default=0, help="number of targets (0: the workload's)")
+    ap.add_argument("--nu", type=float, default=0.0,
+                    help="smoothness in place of the workload's (sweep: products only; a nu other than 1/2, 3/2, "
+                         "5/2 or +inf has FP64 values only)")
+    ap.add_argument("--mixed", type=int, default=-1, help="precision of the mixed solve (default: FP32 for d<8, "
+                                                          "matrix-core BF16 x3 for d>=8)")
+    ap.add_argument("--scheme", choices=("flexible", "reliable"), default="flexible",
+                    help="mixed-precision scheme: flexible CG around inner solves, or one recurrence with reliable "
+                         "updates")
+    ap.add_argument("--inner-rtol", type=float, default=0.35,
+                    help="inner tolerance (flexible) or residual-replacement factor (reliable)")
+    ap.add_argument("--fp64-solve", choices=("full", "refine", "skip"), default="full",
+                    help="full: independent FP64 solve (timed against the mixed one); refine: FP64 PCG from the mixed "
+                         "solution to relres 1e-10 as the error reference (for workloads where a full FP64 solve "
+                         "does not fit the time budget); skip: none")
+    ap.add_argument("--precond", choices=("block", "jacobi", "coarse", "none"), default="coarse",
+                    help="preconditioner of both solves: cell blocks of the finest level and one dense "
+                         "coarse block of C_W (coarse; N^2 doubles of workspace while it is built), the cell "
+                         "blocks of every level (block), diag(C_W) (jacobi), or none")
+    ap.add_argument("--cpu-rows", type=int, default=0,
+                    help="rows of the oracle's CPU product sample (0: about 15 s of one core's work)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=40000,
+                    help="Krylov iteration cap (lower it only for short profiling runs)")
+    ap.add_argument("--sweep", default="",
+                    help="comma-separated workloads: time every precision's product, the target product and W / W^T "
+                         "(one JSON line each) instead of the step")
+    ap.add_argument("--loglik", type=int, default=0,
+                    help="estimator: time the multilevel log-likelihood (dense C^n_W, blocked Cholesky) and the "
+                         "rho MLE on this many points of the workload's generator (one JSON line) instead of the step")
+    ap.add_argument("--cpu-oracle", choices=("all", "products", "blup"), default=None,
+                    help="time the oracle on the host's cores (covariance products, dense classic BLUP) beside "
+                         "the GPU predictor; one JSON line instead of the step")
+    ap.add_argument("--loglik-quick", action="store_true",
+                    help="with --loglik: levels t and 0 only, one timed call each")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 512 MiB three times with a plain device copy (reference for HBM counters)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py: the path runs on one GPU; --gpus {a.gpus} is not supported (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if a.sweep:
+        sweep([int(v) for v in a.sweep.split(",")], nu=a.nu or None)
+        return
+
+    if a.loglik:
+        loglik_bench(a.config or 2, a.loglik, quick=a.loglik_quick)
+        return
+
+    if a.cpu_oracle:
+        cpu_oracle_report(a.cpu_oracle)
+        return
+
+    if a.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": src.numel() * 8, "launches": 3}), flush=True)
+        return
+
+    if a.solve:
+        a.config = a.config or 2
+        print(json.dumps(solve_bench(a)), flush=True)
+        return
+    a.config = a.config or 5
+    print(json.dumps(product_bench(a)), flush=True)
 
 
 if __name__ == "__main__":

@@ -70,6 +70,7 @@ _SIGS = {
     "mlblup_apply_W": (C.c_int, [_P, _P, _P, _P, _P, _I64, _P]),
     "mlblup_apply_Wt": (C.c_int, [_P, _P, _P, _P, _P, _I64, _P]),
     "mlblup_solve_workspace_bytes": (C.c_int, [_P, C.POINTER(PcgOpts), _I64, C.POINTER(_I64)]),
+    "mlblup_cw_matvec": (C.c_int, [_P, C.POINTER(Matern), _P, _P, _I32, _P, _I64, _P]),
     "mlblup_pcg_solve": (C.c_int, [_P, C.POINTER(Matern), _P, _P, _I32, C.POINTER(PcgOpts), _P, _I64,
                                    C.POINTER(PcgInfo), _P]),
     "mlblup_blup_predict": (C.c_int, [_P, C.POINTER(Matern), _P, _P, _I64, C.POINTER(PcgOpts), _I32, _I32, _P, _P,

@@ -298,6 +298,16 @@ class Solver:
                                       b.transform_ws.numel(), _stream()))
         return v
 
+    def cw_matvec(self, vw, precision=FP64, rho=None, out=None):
+        """C_W vw = W C W^T vw (the solve's operator) in the pair kernel's
+        arithmetic `precision`; vw and the result hold N - p values."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.n - self.p, dtype=torch.float64, device=self.device)
+        check(L.lib().mlblup_cw_matvec(self.basis.h, C.byref(self.kernel(rho)), _ptr(vw), _ptr(out), int(precision),
+                                       _ptr(self.ws), self.ws.numel(), _stream()))
+        return out
+
     def cov_matvec_tree(self, x_tree, precision=FP64, outputs=VALUE, rho=None):
         k = self.kernel(rho)
         pts = self.basis.points_dev

@@ -142,7 +142,9 @@ void image_layout(Basis& B) {
   B.off_levels = off;
   off = align_up(off + nn * (int64_t)sizeof(int32_t));
   B.off_exps = off;
-  off = align_up(off + (int64_t)B.p * B.d * (int64_t)sizeof(int32_t) + B.d * (int64_t)sizeof(double));
+  off = align_up(off + (int64_t)B.p * B.d * (int64_t)sizeof(int32_t));
+  B.off_rootc = off;
+  off = align_up(off + B.d * (int64_t)sizeof(double));
   B.off_V = off;
   off = align_up(off + nv * (int64_t)sizeof(double));
   B.off_Vt = off;
@@ -699,8 +701,7 @@ int mlblup_basis_upload(mlblup_basis bb, void* dev_buf, int64_t bytes, void* str
     for (int i = 0; i < D.m; ++i)
       for (int j = 0; j < D.m; ++j) vt[D.v_off + (size_t)j * D.m + i] = B.V[D.v_off + (size_t)i * D.m + j];
   MLB_HIP(hipMemcpyAsync(base + B.off_exps, ex.data(), ex.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  MLB_HIP(hipMemcpyAsync(base + B.off_exps + ex.size() * sizeof(int32_t), B.root_c.data(), B.d * sizeof(double),
-                         hipMemcpyHostToDevice, s));
+  MLB_HIP(hipMemcpyAsync(base + B.off_rootc, B.root_c.data(), B.d * sizeof(double), hipMemcpyHostToDevice, s));
   MLB_HIP(hipMemcpyAsync(base + B.off_V, B.V.data(), B.V.size() * sizeof(double), hipMemcpyHostToDevice, s));
   MLB_HIP(hipMemcpyAsync(base + B.off_Vt, vt.data(), vt.size() * sizeof(double), hipMemcpyHostToDevice, s));
   MLB_HIP(hipMemcpyAsync(base + B.off_pts, B.pts_tree.data(), B.pts_tree.size() * sizeof(double),
@@ -822,6 +823,20 @@ static int check_opts(const mlblup_pcg_opts* opts, mlblup_pcg_opts* o) {
   return MLBLUP_OK;
 }
 
+int mlblup_cw_matvec(mlblup_basis b, const mlblup_matern* k, const double* in_dev, double* out_dev,
+                     int32_t precision, void* work_dev, int64_t work_bytes, void* stream) {
+  clear_error();
+  int st = check_basis_dev(b);
+  if (st) return st;
+  if ((st = check_kernel(k))) return st;
+  if (!in_dev || !out_dev || in_dev == out_dev) return fail(MLBLUP_EINVAL, "cw_matvec: NULL or aliased vectors");
+  if (precision < MLBLUP_FP64 || precision > MLBLUP_MFMA_BF16X3) return fail(MLBLUP_EINVAL, "unknown precision");
+  Ws w;
+  if ((st = check_ws(b, 0, work_dev, work_bytes, &w))) return st;
+  Ctx c(b->b, *k, work_dev, w, (hipStream_t)stream);
+  return c.matvec_cw(in_dev, out_dev, precision);
+}
+
 int mlblup_pcg_solve(mlblup_basis b, const mlblup_matern* k, const double* zw_dev, double* gw_dev, int32_t use_x0,
                      const mlblup_pcg_opts* opts, void* work_dev, int64_t work_bytes, mlblup_pcg_info* info,
                      void* stream) {
@@ -914,7 +929,7 @@ int mlblup_blup_predict(mlblup_basis b, const mlblup_matern* k, const double* z_
     if ((st = c.pair(tgt_dev, m_t, gam, zhat_dev, nullptr, predict_precision, MLBLUP_VALUE))) return st;
     const char* img = (const char*)B.dev_base;
     const int32_t* ex = (const int32_t*)(img + B.off_exps);
-    const double* rc = (const double*)(img + B.off_exps + (int64_t)B.p * B.d * sizeof(int32_t));
+    const double* rc = (const double*)(img + B.off_rootc);
     if ((st = trend_add(tgt_dev, m_t, B.d, ex, B.p, rc, B.root_h, betad, zhat_dev, s))) return st;
     MLB_HIP(hipStreamSynchronize(s));  // bl (host) must outlive the copy
   }
