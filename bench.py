@@ -732,6 +732,8 @@ def main():
     ap.add_argument("--sweep", default="",
                     help="comma-separated workloads: time every precision's product, the target product and W / W^T "
                          "(one JSON line each) instead of the step")
+    ap.add_argument("--reps", type=int, default=10,
+                    help="with --sweep: timed launches per product (after min(3, reps) untimed ones)")
     ap.add_argument("--loglik", type=int, default=0,
                     help="estimator: time the multilevel log-likelihood (dense C^n_W, blocked Cholesky) and the "
                          "rho MLE on this many points of the workload's generator (one JSON line) instead of the step")
@@ -752,7 +754,7 @@ def main():
     import torch
 
     if a.sweep:
-        sweep([int(v) for v in a.sweep.split(",")], nu=a.nu or None)
+        sweep([int(v) for v in a.sweep.split(",")], reps=a.reps, warm=min(3, a.reps), nu=a.nu or None)
         return
 
     if a.loglik:
