@@ -207,6 +207,23 @@ int mlblup_cov_matvec(const mlblup_matern* k, const double* rows_dev, int64_t m,
                       int32_t d, int32_t precision, int32_t outputs, const double* x_dev, double* y_dev,
                       double* dy_dev, void* work_dev, int64_t work_bytes, void* stream);
 
+/* The same product for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): no workspace
+ * argument, no hipMalloc / hipFree / event creation.  The scratch is a
+ * static array of MLBLUP_NOALLOC_SCRATCH_BYTES in the library's device code,
+ * one per GPU, held until the process ends; its address on the current
+ * device is looked up on the first call there.  A product whose
+ * mlblup_cov_workspace_bytes exceeds that size returns MLBLUP_EINVAL
+ * (square FP64 values: up to about 226,000 points; both outputs: 113,000).
+ * All calls on one GPU share the array: calls that overlap in time on the
+ * same GPU (other streams, other threads) race and must not be issued.
+ * Results are bitwise those of mlblup_cov_matvec.  Profiling
+ * (mlblup_profile_enable) does not record these calls. */
+#define MLBLUP_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int mlblup_cov_matvec_noalloc(const mlblup_matern* k, const double* rows_dev, int64_t m, const double* cols_dev,
+                              int64_t n, int32_t d, int32_t precision, int32_t outputs, const double* x_dev,
+                              double* y_dev, double* dy_dev, void* stream);
+
 /* ---- multilevel transform (operators W and W^T, Sec. 3.1 and Sec. 6.2) -----
  * apply_W:  vw = W v (N - p), vl = L v (p; NULL to skip).
  * apply_Wt: v = W^T vw + L^T vl (vl NULL = 0).

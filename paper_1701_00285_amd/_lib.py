@@ -66,6 +66,8 @@ _SIGS = {
     "mlblup_cov_workspace_bytes": (C.c_int, [_I64, _I64, _I32, _I32, _I32, C.POINTER(_I64)]),
     "mlblup_cov_matvec": (C.c_int, [C.POINTER(Matern), _P, _I64, _P, _I64, _I32, _I32, _I32, _P, _P, _P, _P,
                                     _I64, _P]),
+    "mlblup_cov_matvec_noalloc": (C.c_int, [C.POINTER(Matern), _P, _I64, _P, _I64, _I32, _I32, _I32, _P, _P, _P,
+                                            _P]),
     "mlblup_transform_workspace_bytes": (C.c_int, [_P, C.POINTER(_I64)]),
     "mlblup_apply_W": (C.c_int, [_P, _P, _P, _P, _P, _I64, _P]),
     "mlblup_apply_Wt": (C.c_int, [_P, _P, _P, _P, _P, _I64, _P]),

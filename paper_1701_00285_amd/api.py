@@ -244,6 +244,27 @@ def cov_matvec(rows, cols, x, nu, rho, sigma2=1.0, precision=FP64, outputs=VALUE
     return y, dy
 
 
+NOALLOC_SCRATCH_BYTES = 64 << 20   # MLBLUP_NOALLOC_SCRATCH_BYTES
+
+
+def cov_matvec_noalloc(rows, cols, x, nu, rho, sigma2=1.0, precision=FP64, outputs=VALUE, y=None, dy=None):
+    """cov_matvec on the library's static per-device scratch: the library
+    allocates nothing; the caller passes the outputs (float64 device tensors
+    of length m, allocated here only when not given)."""
+    torch = _torch()
+    m, d = rows.shape
+    n = cols.shape[0]
+    if outputs & VALUE and y is None:
+        y = torch.empty(m, dtype=torch.float64, device=rows.device)
+    if outputs & DLOGRHO and dy is None:
+        dy = torch.empty(m, dtype=torch.float64, device=rows.device)
+    k = matern(nu, rho, sigma2)
+    check(L.lib().mlblup_cov_matvec_noalloc(C.byref(k), _ptr(rows), m, _ptr(cols), n, d, int(precision),
+                                            int(outputs), _ptr(x), _ptr(y if outputs & VALUE else None),
+                                            _ptr(dy if outputs & DLOGRHO else None), _stream()))
+    return y, dy
+
+
 class Solver:
     """Tree + basis + device state for one point set and trend degree.
 

@@ -767,6 +767,17 @@ int mlblup_cov_matvec(const mlblup_matern* k, const double* rows_dev, int64_t m,
   return pair_launch(a, work_dev, work_bytes, (hipStream_t)stream);
 }
 
+int mlblup_cov_matvec_noalloc(const mlblup_matern* k, const double* rows_dev, int64_t m, const double* cols_dev,
+                              int64_t n, int32_t d, int32_t precision, int32_t outputs, const double* x_dev,
+                              double* y_dev, double* dy_dev, void* stream) {
+  clear_error();
+  int st = check_kernel(k);
+  if (st) return st;
+  PairArgs a{rows_dev, m, cols_dev, n, d, nu2_of(k), k->rho, k->sigma2, precision, outputs, x_dev, y_dev, dy_dev,
+             k->nu, nullptr};
+  return pair_launch_noalloc(a, (hipStream_t)stream);
+}
+
 int mlblup_transform_workspace_bytes(mlblup_basis b, int64_t* bytes) {
   clear_error();
   if (!b || !bytes) return fail(MLBLUP_EINVAL, "NULL argument");

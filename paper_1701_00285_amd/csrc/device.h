@@ -80,6 +80,8 @@ int mfma_launch(const PairArgs& a, double zs, double* part, hipStream_t s);
 int mfma_sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s);
 // Validates and launches (pair kernel + split reduction).
 int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s);
+// pair_launch on the library's static per-device scratch (no allocation)
+int pair_launch_noalloc(const PairArgs& a, hipStream_t s);
 
 // ---- multilevel transform ------------------------------------------------------
 struct TransformDev {
@@ -168,5 +170,15 @@ int trend_add(const double* tgt, int64_t m, int32_t d, const int32_t* exps, int3
 // ---- instrumentation -------------------------------------------------------
 void profile_note(hipEvent_t a, hipEvent_t b, double pairs, int bucket);
 bool profile_on();
+// While one lives on a thread, profile_on() is false there: the timing
+// events (hipEventCreate) stay out of calls that must not allocate.
+struct ProfileSuppress {
+  ProfileSuppress();
+  ~ProfileSuppress();
+  ProfileSuppress(const ProfileSuppress&) = delete;
+  ProfileSuppress& operator=(const ProfileSuppress&) = delete;
+ private:
+  bool prev_;
+};
 
 }  // namespace mlb

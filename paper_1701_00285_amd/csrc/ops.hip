@@ -395,8 +395,15 @@ int trend_add(const double* tgt, int64_t m, int32_t d, const int32_t* exps, int3
   return hip_check(hipGetLastError(), "trend launch");
 }
 
+namespace {
+thread_local bool tl_profile_suppressed = false;
+}
+
+ProfileSuppress::ProfileSuppress() : prev_(tl_profile_suppressed) { tl_profile_suppressed = true; }
+ProfileSuppress::~ProfileSuppress() { tl_profile_suppressed = prev_; }
+
 bool profile_on() {
-  return prof().on;
+  return prof().on && !tl_profile_suppressed;
 }
 
 void profile_note(hipEvent_t a, hipEvent_t b, double pairs, int bucket) {

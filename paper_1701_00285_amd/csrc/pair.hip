@@ -380,4 +380,54 @@ int pair_launch_body(const PairArgs& a, double zs, void* work, hipStream_t s) {
   return hip_check(hipGetLastError(), "reduce_splits launch");
 }
 
+// ---- products for callers that cannot allocate ------------------------------
+// The workspace of mlblup_cov_matvec_noalloc is this file-scope array: every
+// GPU the library runs on holds its own copy until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): the device address comes from
+// hipGetSymbolAddress, once per device with that device current, and that
+// address is what the launches receive.  The pair kernels write every
+// partial they read in the same call, so nothing in it has to start at zero;
+// calls that overlap on one GPU share the array and race.
+namespace {
+constexpr int kMaxScratchDevices = 64;
+__device__ __align__(256) unsigned char scratch[MLBLUP_NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxScratchDevices] = {};
+
+int scratch_address(void** out) {
+  int dev = -1;
+  MLB_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(MLBLUP_EINVAL, "cov_matvec_noalloc: device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_check(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return MLBLUP_OK;
+}
+}  // namespace
+
+int pair_launch_noalloc(const PairArgs& a, hipStream_t s) {
+  void* ptr = nullptr;
+  const int st = scratch_address(&ptr);
+  if (st) return st;
+  // malformed arguments go to pair_launch, which reports them
+  const bool sized = a.m > 0 && a.n > 0 && a.d >= 1 && a.d <= 64 && a.outputs >= 1 && a.outputs <= 3 &&
+                     a.precision >= MLBLUP_FP64 && a.precision <= MLBLUP_MFMA_BF16X3;
+  if (sized) {
+    const int64_t need = pair_workspace_bytes(a.m, a.n, a.d, a.precision, a.outputs);
+    if (need > MLBLUP_NOALLOC_SCRATCH_BYTES)
+      return fail(MLBLUP_EINVAL, "cov_matvec_noalloc: this product needs " + std::to_string(need) +
+                                     " bytes of scratch, above the static " +
+                                     std::to_string((long long)MLBLUP_NOALLOC_SCRATCH_BYTES) +
+                                     " (use mlblup_cov_matvec with a workspace)");
+  }
+  ProfileSuppress quiet;  // no timing events: they would be created here
+  return pair_launch(a, ptr, MLBLUP_NOALLOC_SCRATCH_BYTES, s);
+}
+
 }  // namespace mlb
