@@ -387,6 +387,10 @@ def solve_bench(a):
     wl = synth.make_config(a.config, n=a.n or None, n_targets=a.targets or None)
     wname = wl.name if not a.n else f"{wl.name}, generator at n={wl.n}"
     mixed = a.mixed if a.mixed >= 0 else (FP32 if wl.d < 8 else MFMA_BF16X3)
+    if a.precond == "auto":
+        # the coarse space for the smooth low-dimensional workloads; the rough
+        # nu = 1/2 kernels in 10 and 20 dimensions converge fastest without one
+        a.precond = "coarse" if wl.d < 8 else "none"
     scheme = {"flexible": MIXED_FLEXIBLE, "reliable": MIXED_RELIABLE}[a.scheme]
     dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda")
     P, Z, T = dev(wl.points), dev(wl.z), dev(wl.targets)
@@ -720,10 +724,11 @@ def main():
                     help="full: independent FP64 solve (timed against the mixed one); refine: FP64 PCG from the mixed "
                          "solution to relres 1e-10 as the error reference (for workloads where a full FP64 solve "
                          "does not fit the time budget); skip: none")
-    ap.add_argument("--precond", choices=("block", "jacobi", "coarse", "none"), default="coarse",
+    ap.add_argument("--precond", choices=("auto", "block", "jacobi", "coarse", "none"), default="auto",
                     help="preconditioner of both solves: cell blocks of the finest level and one dense "
-                         "coarse block of C_W (coarse; N^2 doubles of workspace while it is built), the cell "
-                         "blocks of every level (block), diag(C_W) (jacobi), or none")
+                         "coarse block of C_W (coarse; 2 N nc doubles of workspace while it is built), the cell "
+                         "blocks of every level (block), diag(C_W) (jacobi), none, or auto (coarse for d < 8, "
+                         "none otherwise)")
     ap.add_argument("--cpu-rows", type=int, default=0,
                     help="rows of the oracle's CPU product sample (0: about 15 s of one core's work)")
     ap.add_argument("--no-cpu", action="store_true")

@@ -56,10 +56,11 @@ constexpr int kTr = 32;       // transpose tile
 constexpr int kColBatch = 4096;
 
 // ---- 1. dense covariance -------------------------------------------------------
+// columns [j0, j0 + ncols) of Phi into phi (row i at phi + i ld)
 template <int NU2>
 __global__ __launch_bounds__(kT) void dense_cov(const double* __restrict__ pts, int64_t n, int d, double zs,
                                                 double sigma2, const double* __restrict__ gtab,
-                                                double* __restrict__ phi) {
+                                                double* __restrict__ phi, int64_t j0, int64_t ncols, int64_t ld) {
   __shared__ double tab[kExpTab];
   exp_table_fill(tab);
   const double* gt = gtab;
@@ -70,8 +71,9 @@ __global__ __launch_bounds__(kT) void dense_cov(const double* __restrict__ pts, 
     gt = gsh;
   }
   __syncthreads();
-  const int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x;
-  if (j >= n) return;
+  const int64_t jl = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (jl >= ncols) return;
+  const int64_t j = j0 + jl;
   for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
     double s = 1e-300;  // keeps the self pair away from sqrt(0) in the series branch
     for (int k = 0; k < d; ++k) {
@@ -80,7 +82,7 @@ __global__ __launch_bounds__(kT) void dense_cov(const double* __restrict__ pts, 
     }
     double f = 0.0, g = 0.0;
     pair_value<NU2, 1, false>(s, tab, f, g, gt);
-    phi[i * n + j] = sigma2 * f;
+    phi[i * ld + jl] = sigma2 * f;
   }
 }
 
@@ -486,8 +488,11 @@ static int analysis_batched(const Basis& B, const TransformDev& T, int32_t level
 
 // Phi = sigma^2 phi(|x_i - x_j|), N x N row-major; gtab: device room for the
 // general-nu table
-static int dense_phi(const Basis& B, const PairArgs& k, double* phi, double* gtab, hipStream_t s) {
+static int dense_phi(const Basis& B, const PairArgs& k, double* phi, double* gtab, hipStream_t s, int64_t j0 = 0,
+                     int64_t ncols = -1, int64_t ld = -1) {
   const int64_t n = B.n;
+  if (ncols < 0) ncols = n;
+  if (ld < 0) ld = n;
   const double* pts = (const double*)((const char*)B.dev_base + B.off_pts);
   const double zs = kernel_scale(k.nu2, k.nu, k.rho);
   const double* gt = nullptr;
@@ -497,14 +502,15 @@ static int dense_phi(const Basis& B, const PairArgs& k, double* phi, double* gta
     MLB_HIP(hipMemcpyAsync(gtab, host, kGenuBytes, hipMemcpyHostToDevice, s));
     gt = gtab;
   }
-  dim3 grid((unsigned)((n + kT - 1) / kT), (unsigned)std::min<int64_t>(n, 65535));
+  dim3 grid((unsigned)((ncols + kT - 1) / kT), (unsigned)std::min<int64_t>(n, 65535));
   switch (k.nu2) {
-    case 0: hipLaunchKernelGGL(dense_cov<0>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
-    case 1: hipLaunchKernelGGL(dense_cov<1>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
-    case 3: hipLaunchKernelGGL(dense_cov<3>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
-    case 5: hipLaunchKernelGGL(dense_cov<5>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi); break;
+    case 0: hipLaunchKernelGGL(dense_cov<0>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi, j0, ncols, ld); break;
+    case 1: hipLaunchKernelGGL(dense_cov<1>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi, j0, ncols, ld); break;
+    case 3: hipLaunchKernelGGL(dense_cov<3>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi, j0, ncols, ld); break;
+    case 5: hipLaunchKernelGGL(dense_cov<5>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi, j0, ncols, ld); break;
     default:
-      hipLaunchKernelGGL(dense_cov<kNuGeneralT>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi);
+      hipLaunchKernelGGL(dense_cov<kNuGeneralT>, grid, dim3(kT), 0, s, pts, n, B.d, zs, k.sigma2, gt, phi, j0, ncols,
+                         ld);
   }
   return hip_check(hipGetLastError(), "dense covariance launch");
 }
@@ -651,18 +657,22 @@ int loglik_device(const Basis& B, const TransformDev& T, const PairArgs& k, int3
 
 // ---- coarse block of C_W for the preconditioner ------------------------------
 // The rows [c0, c0 + nc) of W (the coarse levels: they come last) give
-// C_c = (W C W^T)[c0:, c0:].  Formed densely (Phi, then the two batched
-// analyses over every level, keeping those rows), factored G G^T = C_c with
-// the identity as nc border rows, which end as Y = G^-T; then
+// C_c = (W C W^T)[c0:, c0:].  Formed without any N x N array: Phi is made in
+// panels of `batch` columns, and the batched analysis of each panel keeps
+// the rows [c0, c0 + nc) of W Phi, giving A = (W Phi)[c0:, :] (nc x N);
+// A^T (N x nc) then goes through the analysis once more, which gives C_c
+// in A's storage (2 nc <= N since c0 >= nc).  C_c is factored G G^T = C_c
+// with the identity as nc border rows, which end as Y = G^-T; then
 // C_c^-1 = G^-T G^-1 = Y Y^T.  Y (nc x nc, row-major) is copied to the host.
+// Workspace: N batch + 2 N nc doubles (13 GB at 65,536 points and nc = 10,230).
 CoarseLayout coarse_layout(const Basis& B, int64_t nc) {
   CoarseLayout L;
   const int64_t n = B.n;
   const int64_t batch = std::min<int64_t>(std::max<int64_t>(n, 1), kColBatch);
   int64_t o = 0;
-  L.phi = o;
-  o += align256(n * n * 8);
-  L.a = o;
+  L.phi = o;   // the Phi panel (N x batch), later A^T (N x nc)
+  o += align256(std::max<int64_t>(n * std::max(batch, nc), 1) * 8);
+  L.a = o;     // A (nc x N), later C_c and its border rows (2 nc x nc)
   o += align256(std::max<int64_t>(std::max(nc * n, 2 * nc * nc), 1) * 8);
   L.scal = o;
   o += align256(std::max<int64_t>(B.scal_total, 1) * batch * 8);
@@ -682,16 +692,30 @@ int coarse_inverse_factor(const Basis& B, const PairArgs& k, int64_t c0, int64_t
   const CoarseLayout L = coarse_layout(B, nc);
   if (!work || work_bytes < L.total)
     return fail(MLBLUP_EINVAL, "coarse preconditioner: workspace too small (need " + std::to_string(L.total) + ")");
-  if (nc <= 0 || c0 < 0 || c0 + nc > B.n - B.p) return fail(MLBLUP_EINVAL, "coarse preconditioner: bad row range");
+  if (nc <= 0 || c0 < nc || c0 + nc > B.n - B.p)
+    return fail(MLBLUP_EINVAL, "coarse preconditioner: bad row range (need nc <= c0, c0 + nc <= N - p)");
   char* w = (char*)work;
-  double* phi = (double*)(w + L.phi);
-  double* C = (double*)(w + L.a);
+  double* panel = (double*)(w + L.phi);
+  double* A = (double*)(w + L.a);
+  double* scal = (double*)(w + L.scal);
   int* flag = (int*)(w + L.flag);
+  const int64_t n = B.n;
   const TransformDev T = transform_dev(B);
   hipLaunchKernelGGL(clear_flag, dim3(1), dim3(64), 0, s, flag);
-  int st = dense_phi(B, k, phi, (double*)(w + L.gtab), s);
-  if (st) return st;
-  if ((st = dense_cw_block(B, T, 0, phi, C, (double*)(w + L.scal), L.batch, c0, nc, s))) return st;
+  int st;
+  for (int64_t j0 = 0; j0 < n; j0 += L.batch) {
+    const int64_t nb = std::min(L.batch, n - j0);
+    if ((st = dense_phi(B, k, panel, (double*)(w + L.gtab), s, j0, nb, nb))) return st;
+    if ((st = analysis_batched(B, T, 0, panel, nb, nb, scal, L.batch, A + j0, n, c0, nc, s))) return st;
+  }
+  double* at = panel;  // A^T, N x nc
+  {
+    dim3 grid((unsigned)((n + kTr - 1) / kTr), (unsigned)((nc + kTr - 1) / kTr));
+    hipLaunchKernelGGL(transpose, grid, dim3(kTr * 8), 0, s, A, nc, n, n, at, nc);
+    if ((st = hip_check(hipGetLastError(), "transpose launch"))) return st;
+  }
+  double* C = A;
+  if ((st = analysis_batched(B, T, 0, at, nc, nc, scal, L.batch, C, nc, c0, nc, s))) return st;
   double* border = C + nc * nc;
   {
     dim3 grid((unsigned)((nc + kT - 1) / kT), (unsigned)std::min<int64_t>(nc, 65535));
