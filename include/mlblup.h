@@ -122,6 +122,12 @@ typedef struct {
   mlblup_precond precond;        /* NULL: P_W = I; else an uploaded preconditioner of the same basis */
   double* history_host;          /* optional: |r_k| / |Z_W| after each Krylov iteration k (recurrence residual) */
   int32_t mixed_scheme;          /* MLBLUP_MIXED_FLEXIBLE or MLBLUP_MIXED_RELIABLE (ignored for MLBLUP_FP64) */
+  double* state_dev;             /* MLBLUP_FP64 only, else ignored: NULL, or a device buffer of 2 (N - p) + 8
+                                    doubles that receives the Krylov state (residual, search direction, r.z) when
+                                    the solve returns, so that a later call can continue the same recurrence */
+  int32_t resume;                /* with state_dev and use_x0 = 1 (gamma_W of the earlier call as the initial
+                                    guess): continue the recurrence stored in state_dev instead of restarting it;
+                                    the iterates are those of one uninterrupted solve */
 } mlblup_pcg_opts;
 
 typedef struct {
@@ -280,6 +286,32 @@ int mlblup_blup_predict(mlblup_basis b, const mlblup_matern* k, const double* z_
 int mlblup_blup_grad(mlblup_basis b, const mlblup_matern* k, const double* z_dev, const double* gamma_dev,
                      const double* lambda_dev, int32_t precision, double* Q_host, double* dQ_dlogrho_host,
                      void* work_dev, int64_t work_bytes, void* stream);
+
+/* ---- accuracy under ill-conditioning (Sec. 8, Table numericalresults:table5) ----
+ * The multilevel predictor with the covariance formed in double-double
+ * arithmetic, for small N (N <= 4096 sites, m_t <= 4096 targets) and
+ * nu = 1/2, 3/2, 5/2 or +inf.  Every entry of P C P^T (P = [W; L], the dense
+ * multilevel basis of Sec. 3.1) and of K(targets, S) P^T is formed in
+ * double-double (about 32 digits) from the FP64 coordinates and basis, so W's
+ * vanishing moments cancel the kernel's low-degree Taylor terms without
+ * rounding noise (for the flat Gaussians of the experiment the entries of
+ * C_W lie some 25 orders of magnitude below those of C, beneath the rounding
+ * of any FP64 product).  C_W gamma_W = W z is solved by CG in FP64 on the
+ * rounded C_W from gamma_W = 0, stopping when |W z - C_W gamma_W| <= rtol |W z|,
+ * after max_iter iterations, or at a breakdown p.q <= 0 (the last iterate is
+ * kept and the call still returns MLBLUP_OK).  Then, in double-double,
+ * L v = L z - (L C W^T) gamma_W, (L X) beta = L v (X the raw-coordinate
+ * monomials, graded-lex, Sec. 2) and zhat = X(targets) beta + (K W^T) gamma_W
+ * (Sec. 5.2 eqs. Spatial:eqn1-3).
+ * z_dev: N values in tree order; tgt_dev: m_t x d targets; zhat_dev: m_t values;
+ * beta_host: p values (or NULL); cw_dev: optional (N-p) x (N-p) row-major copy
+ * of the rounded C_W (NULL to skip); info_host: 4 doubles, the CG iterations,
+ * 1 if it stopped at a breakdown, the recurrence and the true relative
+ * residual.  Workspace: mlblup_dd_workspace_bytes(b, m_t).  Synchronises. */
+int mlblup_dd_workspace_bytes(mlblup_basis b, int64_t m_t, int64_t* bytes);
+int mlblup_blup_predict_dd(mlblup_basis b, const mlblup_matern* k, const double* z_dev, const double* tgt_dev,
+                           int64_t m_t, double rtol, int32_t max_iter, double* zhat_dev, double* beta_host,
+                           double* cw_dev, double* info_host, void* work_dev, int64_t work_bytes, void* stream);
 
 /* ---- estimator: multilevel log-likelihood (Sec. 5.1 reduced likelihoods; Sec. 6.1) ----
  * For the levels q >= level of W (rows [W_t; ...; W_level], the first

@@ -95,3 +95,31 @@ def gaussian_blup(S, Z, T, w: int, theta: float, dps: int = 60):
         kappa_lb = (max(diag) / min(diag)) ** 2
         return (np.array([float(beta[a]) for a in range(p)]), np.array([float(v) for v in zhat]),
                 [mp.nstr(beta[a], 25) for a in range(p)], [mp.nstr(v, 25) for v in zhat], mp.nstr(kappa_lb, 6))
+
+
+def gaussian_cov_in_basis(S, P, theta: float, T=None, dps: int = 40):
+    """P C P^T (and K(T, S) P^T when targets T are given) for the Gaussian
+    kernel exp(-r^2 / (2 theta^2)), every entry formed at `dps` digits from
+    the FP64 sites and the FP64 rows of P taken exactly, then rounded to FP64.
+    With P = [W; L] the multilevel basis (Sec. 3.1) this is C_W and its
+    companions of Sec. 5.2, free of the rounding that FP64 products leave
+    when W's vanishing moments cancel the kernel's low-degree part (the
+    accuracy experiment of Sec. 8)."""
+    with mp.workdps(dps):
+        S = [[mp.mpf(float(v)) for v in row] for row in np.asarray(S, dtype=np.float64)]
+        P = [[mp.mpf(float(v)) for v in row] for row in np.asarray(P, dtype=np.float64)]
+        h = 1 / (2 * mp.mpf(float(theta)) ** 2)
+
+        def kern(a, b):
+            return mp.exp(-h * mp.fsum((ai - bi) ** 2 for ai, bi in zip(a, b)))
+
+        n = len(S)
+        C = [[kern(S[i], S[j]) for j in range(n)] for i in range(n)]
+        CPt = [[mp.fdot(C[i], P[r]) for r in range(len(P))] for i in range(n)]
+        G = np.array([[float(mp.fdot(P[r], [CPt[i][s] for i in range(n)])) for s in range(len(P))]
+                      for r in range(len(P))])
+        if T is None:
+            return G
+        T = [[mp.mpf(float(v)) for v in row] for row in np.asarray(T, dtype=np.float64)]
+        KPt = np.array([[float(mp.fdot([kern(t, S[j]) for j in range(n)], P[r])) for r in range(len(P))] for t in T])
+        return G, KPt

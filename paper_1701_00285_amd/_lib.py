@@ -24,7 +24,8 @@ class Matern(C.Structure):
 class PcgOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
                 ("refine_max", C.c_int32), ("history_cap", C.c_int32), ("inner_rtol", C.c_double),
-                ("precond", C.c_void_p), ("history_host", C.c_void_p), ("mixed_scheme", C.c_int32)]
+                ("precond", C.c_void_p), ("history_host", C.c_void_p), ("mixed_scheme", C.c_int32),
+                ("state_dev", C.c_void_p), ("resume", C.c_int32)]
 
 
 class PcgInfo(C.Structure):
@@ -78,6 +79,9 @@ _SIGS = {
     "mlblup_blup_predict": (C.c_int, [_P, C.POINTER(Matern), _P, _P, _I64, C.POINTER(PcgOpts), _I32, _I32, _P, _P,
                                       _P, _P, _P, _P, _I64, C.POINTER(PcgInfo), _P]),
     "mlblup_blup_grad": (C.c_int, [_P, C.POINTER(Matern), _P, _P, _P, _I32, _P, _P, _P, _I64, _P]),
+    "mlblup_dd_workspace_bytes": (C.c_int, [_P, _I64, C.POINTER(_I64)]),
+    "mlblup_blup_predict_dd": (C.c_int, [_P, C.POINTER(Matern), _P, _P, _I64, C.c_double, _I32, _P, _P, _P, _P, _P,
+                                         _I64, _P]),
     "mlblup_loglik_workspace_bytes": (C.c_int, [_P, _I32, C.POINTER(_I64), C.POINTER(_I64)]),
     "mlblup_loglik": (C.c_int, [_P, C.POINTER(Matern), _P, _I32, C.c_double, _P, _P, _I64, _P]),
     "mlblup_sparsity_pattern": (C.c_int, [_P, _I32, C.c_double, C.POINTER(_I64), _P]),

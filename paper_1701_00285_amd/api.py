@@ -54,12 +54,16 @@ class PcgOptions:
     precond: object = None          # Precond (uploaded) or None for P_W = I
     history: object = None          # numpy float64 array receiving |r_k|/|Z_W| per iteration, or None
     mixed_scheme: int = 0           # MIXED_FLEXIBLE or MIXED_RELIABLE (reduced precisions)
+    state: object = None            # FP64: device tensor of 2 (N - p) + 8 doubles receiving the Krylov state
+    resume: bool = False            # continue the recurrence in `state` (with x0 = the earlier gamma_W)
 
     def to_c(self):
         hist = None if self.history is None else self.history.ctypes.data
         cap = 0 if self.history is None else int(self.history.size)
+        st = None if self.state is None else self.state.data_ptr()
         return L.PcgOpts(self.rtol, self.max_iter, self.precision, self.refine_max, cap, self.inner_rtol,
-                         None if self.precond is None else self.precond.h, hist, self.mixed_scheme)
+                         None if self.precond is None else self.precond.h, hist, self.mixed_scheme, st,
+                         1 if self.resume else 0)
 
 
 class Precond:
@@ -431,6 +435,30 @@ class Solver:
             check(st)
         return dict(zhat=zhat, beta=beta, gamma=self.from_tree(gamma), gamma_tree=gamma, gamma_w=gw,
                     interp_res=ires.value, info=info.as_dict(), status=st)
+
+    def predict_dd(self, z, targets, rtol=1e-8, max_iter=1000, want_cw=False):
+        """The multilevel predictor with P C P^T and K P^T formed in
+        double-double (small N; mlblup_blup_predict_dd).  z: (N,) device
+        tensor in input order; targets: (m, d) device tensor.  Returns
+        dict(zhat, beta, cw (rounded C_W or None), iters, breakdown, relres,
+        true_relres)."""
+        torch = _torch()
+        z_tree = self.to_tree(z).contiguous()
+        m = targets.shape[0]
+        wb = C.c_int64()
+        check(L.lib().mlblup_dd_workspace_bytes(self.basis.h, m, C.byref(wb)))
+        work = torch.empty(max(wb.value, 256), dtype=torch.uint8, device=self.device)
+        zhat = torch.empty(max(m, 1), dtype=torch.float64, device=self.device)
+        nw = self.n - self.p
+        cw = torch.empty((nw, nw), dtype=torch.float64, device=self.device) if want_cw else None
+        beta = np.empty(self.p)
+        info = np.zeros(4)
+        k = self.kernel()
+        check(L.lib().mlblup_blup_predict_dd(self.basis.h, C.byref(k), _ptr(z_tree), _ptr(targets.contiguous()), m,
+                                             float(rtol), int(max_iter), _ptr(zhat), _np_ptr(beta), _ptr(cw),
+                                             _np_ptr(info), _ptr(work), work.numel(), _stream()))
+        return dict(zhat=zhat[:m], beta=beta, cw=cw, iters=int(info[0]), breakdown=bool(info[1]),
+                    relres=float(info[2]), true_relres=float(info[3]))
 
     def quad_grad(self, z_tree, gamma_tree, lambda_tree=None, precision=FP64, rho=None):
         """(Q, dQ/dlog rho) from gamma = W^T gamma_W (tree order)."""

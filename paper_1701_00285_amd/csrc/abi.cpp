@@ -270,7 +270,7 @@ struct Ctx {
   // recurrence residual drops to tol_abs or the iteration budget is spent.
   // history: record |r_k| / bnorm per iteration (plain FP64 solve only).
   int inner_pcg(const double* rhs, double* d, double tol_abs, int prec, const Precond* pc, int& iters_left,
-                const mlblup_pcg_opts& o, mlblup_pcg_info& info, double bnorm, bool history) {
+                const mlblup_pcg_opts& o, mlblup_pcg_info& info, double bnorm, bool history, bool resume = false) {
     const int64_t nw = B.n - B.p;
     double* r = at(w.r);
     double* p = at(w.p);
@@ -278,15 +278,29 @@ struct Ctx {
     double* z = at(w.z);
     double* sc = at(w.sc);
     int st;
-    if ((st = vec_copy(rhs, r, nw, s))) return st;
+    // Krylov state of the FP64 recurrence kept for a later call: r, p and r.z
+    double* state = (prec == MLBLUP_FP64) ? o.state_dev : nullptr;
+    auto save_state = [&]() -> int {
+      if (!state) return MLBLUP_OK;
+      int e;
+      if ((e = vec_copy(r, state, nw, s))) return e;
+      if ((e = vec_copy(p, state + nw, nw, s))) return e;
+      return hip_check(hipMemcpyAsync(state + 2 * nw, sc + S_RZ, sizeof(double), hipMemcpyDeviceToDevice, s),
+                       "state copy");
+    };
     if ((st = vec_zero(d, nw, s))) return st;
     const double* zz = r;
-    if (pc) {
-      if ((st = precond_apply(*pc, r, z, s))) return st;
-      zz = z;
+    if (pc) zz = z;
+    if (state && resume) {
+      if ((st = vec_copy(state, r, nw, s))) return st;
+      if ((st = vec_copy(state + nw, p, nw, s))) return st;
+      MLB_HIP(hipMemcpyAsync(sc + S_RZ, state + 2 * nw, sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+      if ((st = vec_copy(rhs, r, nw, s))) return st;
+      if (pc && (st = precond_apply(*pc, r, z, s))) return st;
+      if ((st = vec_copy(zz, p, nw, s))) return st;
+      if ((st = pcg_start(r, zz, nw, at(w.part), sc, s))) return st;
     }
-    if ((st = vec_copy(zz, p, nw, s))) return st;
-    if ((st = pcg_start(r, zz, nw, at(w.part), sc, s))) return st;
     while (iters_left > 0) {
       if ((st = matvec_cw(p, q, prec))) return st;
       if (prec == MLBLUP_FP64) info.fp64_matvecs++;
@@ -312,7 +326,7 @@ struct Ctx {
       if (std::sqrt(sc_host[S_RR]) <= tol_abs) break;
       if ((st = pcg_update_p(p, zz, nw, sc, s))) return st;
     }
-    return MLBLUP_OK;
+    return save_state();
   }
 
   // Reduced precision, reliable updates (G. L. G. Sleijpen and H. A. van der
@@ -456,7 +470,9 @@ struct Ctx {
         if (relres <= o.rtol) return MLBLUP_OK;
         if (outer >= std::max(o.refine_max, 1) || iters_left <= 0) return noconv(relres);
         info.outer_iters++;
-        st = inner_pcg(r2, z2, 0.7 * o.rtol * bnorm, MLBLUP_FP64, pc, iters_left, o, info, bnorm, true);
+        // the first inner solve continues a stored recurrence when asked to
+        st = inner_pcg(r2, z2, 0.7 * o.rtol * bnorm, MLBLUP_FP64, pc, iters_left, o, info, bnorm, true,
+                       o.resume != 0 && outer == 0);
         const int st2 = vec_axpy(1.0, z2, x, nw, s);  // keep the progress even on breakdown
         if (st) return st;
         if (st2) return st2;
@@ -531,6 +547,8 @@ mlblup_pcg_opts default_opts() {
   o.history_cap = 0;
   o.history_host = nullptr;
   o.mixed_scheme = MLBLUP_MIXED_FLEXIBLE;
+  o.state_dev = nullptr;
+  o.resume = 0;
   return o;
 }
 
@@ -858,6 +876,8 @@ int mlblup_pcg_solve(mlblup_basis b, const mlblup_matern* k, const double* zw_de
   mlblup_pcg_opts o;
   if ((st = check_opts(opts, &o))) return st;
   if (!zw_dev || !gw_dev) return fail(MLBLUP_EINVAL, "pcg_solve: NULL vector");
+  if (o.resume && (!o.state_dev || !use_x0 || o.precision != MLBLUP_FP64))
+    return fail(MLBLUP_EINVAL, "pcg_solve: resume needs state_dev, use_x0 = 1 and MLBLUP_FP64");
   Ws w;
   if ((st = check_ws(b, 0, work_dev, work_bytes, &w))) return st;
   Ctx c(b->b, *k, work_dev, w, (hipStream_t)stream);
@@ -946,6 +966,42 @@ int mlblup_blup_predict(mlblup_basis b, const mlblup_matern* k, const double* z_
   }
   if (solve_st) return fail(solve_st, solve_msg);
   return MLBLUP_OK;
+}
+
+int mlblup_dd_workspace_bytes(mlblup_basis b, int64_t m_t, int64_t* bytes) {
+  clear_error();
+  if (!b || !bytes || m_t < 0) return fail(MLBLUP_EINVAL, "dd_workspace_bytes: bad argument");
+  *bytes = dd_workspace_bytes(b->b.n, m_t);
+  return MLBLUP_OK;
+}
+
+int mlblup_blup_predict_dd(mlblup_basis b, const mlblup_matern* k, const double* z_dev, const double* tgt_dev,
+                           int64_t m_t, double rtol, int32_t max_iter, double* zhat_dev, double* beta_host,
+                           double* cw_dev, double* info_host, void* work_dev, int64_t work_bytes, void* stream) {
+  clear_error();
+  int st = check_basis_dev(b);
+  if (st) return st;
+  if ((st = check_kernel(k))) return st;
+  const Basis& B = b->b;
+  const int nu2 = nu2_of(k);
+  if (nu2 == kNuGeneral) return fail(MLBLUP_EINVAL, "blup_predict_dd: nu must be 1/2, 3/2, 5/2 or +inf");
+  if (B.n > kDdMaxN || m_t < 0 || m_t > kDdMaxN)
+    return fail(MLBLUP_EINVAL, "blup_predict_dd: N and the target count must be at most " + std::to_string(kDdMaxN));
+  if (!z_dev || !info_host || (m_t > 0 && (!tgt_dev || !zhat_dev)) || !(rtol >= 0) || max_iter < 0)
+    return fail(MLBLUP_EINVAL, "blup_predict_dd: bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = B.n, m = n - B.p;
+  std::vector<double> P((size_t)n * n), W((size_t)m * n), Lm((size_t)B.p * n);
+  if ((st = mlblup_basis_dense(b, W.data(), Lm.data()))) return st;
+  std::copy(W.begin(), W.end(), P.begin());
+  std::copy(Lm.begin(), Lm.end(), P.begin() + (size_t)m * n);
+  std::vector<double> tgt((size_t)std::max<int64_t>(m_t, 1) * B.d);
+  if (m_t > 0) {
+    MLB_HIP(hipMemcpyAsync(tgt.data(), tgt_dev, (size_t)m_t * B.d * 8, hipMemcpyDeviceToHost, s));
+    MLB_HIP(hipStreamSynchronize(s));
+  }
+  return dd_blup_predict(B, P, nu2, k->nu, k->rho, k->sigma2, z_dev, tgt_dev, tgt.data(), m_t, rtol, max_iter,
+                         zhat_dev, beta_host, cw_dev, info_host, work_dev, work_bytes, s);
 }
 
 int mlblup_blup_grad(mlblup_basis b, const mlblup_matern* k, const double* z_dev, const double* gamma_dev,

@@ -80,6 +80,15 @@ int mfma_launch(const PairArgs& a, double zs, double* part, hipStream_t s);
 int mfma_sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s);
 // Validates and launches (pair kernel + split reduction).
 int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s);
+// multilevel predictor with P C P^T and K P^T formed in double-double (small N;
+// P = [W; L] dense, n x n row-major on the host).  info_host: iterations,
+// breakdown flag, recurrence relres, true relres of the FP64 CG on C_W.
+constexpr int64_t kDdMaxN = 4096;
+int64_t dd_workspace_bytes(int64_t n, int64_t mt);
+int dd_blup_predict(const Basis& B, const std::vector<double>& P_host, int nu2, double nu, double rho, double sigma2,
+                    const double* z_dev, const double* tgt_dev, const double* tgt_host, int64_t mt, double rtol,
+                    int32_t max_iter, double* zhat_dev, double* beta_host, double* cw_dev, double* info_host,
+                    void* work, int64_t work_bytes, hipStream_t s);
 // pair_launch on the library's static per-device scratch (no allocation)
 int pair_launch_noalloc(const PairArgs& a, hipStream_t s);
 

@@ -76,3 +76,41 @@ def test_fp64_behaviour_on_the_accuracy_experiment():
     W = build_basis(pts, build_kdtree(pts, 64), 8).W
     ev = np.linalg.eigvalsh(W @ cov_matrix(pts, pts, np.inf, 10.0) @ W.T)
     assert ev[0] < 0 < ev[-1] and ev[-1] < 1e-13
+
+
+def test_cov_in_basis_matches_fp64_when_no_cancellation():
+    """A rough Gaussian (theta = 0.05) and a random orthogonal P: nothing
+    cancels, so the high-precision P C P^T equals the FP64 product to FP64
+    rounding; the trace is that of C (N, since phi(0) = 1) for orthogonal P."""
+    g = np.random.default_rng(11)
+    S, T = synth.unit_disk(30, g), synth.unit_disk(5, g)
+    P, _ = np.linalg.qr(g.standard_normal((30, 30)))
+    G, KP = H.gaussian_cov_in_basis(S, P, 0.05, T=T, dps=40)
+    C = cov_matrix(S, S, np.inf, 0.05)
+    ref = P @ C @ P.T
+    assert np.max(np.abs(G - ref)) < 1e-14 * np.max(np.abs(C))
+    assert np.max(np.abs(KP - cov_matrix(T, S, np.inf, 0.05) @ P.T)) < 1e-14
+    assert abs(np.trace(G) - 30.0) < 1e-12
+    assert np.max(np.abs(G - G.T)) < 1e-15
+
+
+def test_cov_in_basis_shows_the_cancellation_of_flat_kernels():
+    """With the multilevel basis of degree w = 4 and a flat Gaussian
+    (theta = 3), W C W^T is the part of the kernel above degree 4: the
+    high-precision block is about 1e-8 of C and positive definite (smallest
+    eigenvalue ~1e-23), while the FP64 product carries rounding of about
+    1e-16 of C on top of it, which makes it indefinite."""
+    g = np.random.default_rng(12)
+    S = synth.unit_disk(60, g)
+    tree = build_kdtree(S, 16)
+    basis = build_basis(S, tree, 4)
+    W, Lm = basis.W, basis.L
+    P = np.vstack([W, Lm])                  # columns in input order
+    G = H.gaussian_cov_in_basis(S, P, 3.0, dps=40)
+    m = W.shape[0]
+    Cw = G[:m, :m]
+    assert np.linalg.eigvalsh(Cw)[0] > 0
+    fp = (W @ cov_matrix(S, S, np.inf, 3.0) @ W.T)
+    assert np.max(np.abs(Cw)) < 1e-6
+    assert 1e-18 < np.max(np.abs(fp - Cw)) < 1e-13
+    assert np.linalg.eigvalsh(fp)[0] < 0
