@@ -566,6 +566,103 @@ def solve_bench(a):
 
 
 
+def segment_bench(a):
+    """FP64 vs mixed solve to relres 1e-8 on a workload whose FP64 solve is
+    longer than one run may last, in separate runs (a.segment):
+      fp64-start:  the FP64 PCG from gamma_W = 0 for a.max_iter iterations;
+                   gamma_W and the Krylov state (r, p, r.z) go to a.ckpt_out;
+      fp64-resume: the same recurrence continued from a.ckpt_in to relres 1e-8
+                   (an exact continuation: the iterates are those of one
+                   uninterrupted solve), then the FP64 predictor at the targets
+                   and Q, dQ/dlog rho; all of it to a.ckpt_out;
+      mixed:       the mixed-precision solve (flexible CG, inner products on the
+                   matrix cores or FP32), its predictor and gradient, compared
+                   with the FP64 results in a.ckpt_in.
+    Each run times its own solve with the host clock around synchronised calls
+    (setup excluded) and prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1701_00285_amd import FP32, FP64, MFMA_BF16X3, MIXED_FLEXIBLE, PREC_COARSE, PcgOptions, Solver
+    torch.cuda.set_device(0)
+    wl = synth.make_config(a.config, n=a.n or None, n_targets=a.targets or None)
+    mixed = a.mixed if a.mixed >= 0 else (FP32 if wl.d < 8 else MFMA_BF16X3)
+    dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    s = Solver(wl.points, wl.degree_w, wl.leaf_max, wl.nu, wl.rho, wl.sigma2, max_targets=wl.targets.shape[0])
+    pc = s.precond(PREC_COARSE) if a.precond == "coarse" else None
+    Z, T = dev(wl.z), dev(wl.targets)
+    zt = s.to_tree(Z)
+    zw, _ = s.apply_W(zt)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    nw = s.n - s.p
+    out = {"mode": f"segmented solve: {a.segment}", "workload": wl.name, "n": wl.n, "d": wl.d, "nu": wl.nu,
+           "rho": wl.rho, "targets": int(T.shape[0]), "rtol": 1e-8,
+           "preconditioner": "coarse" if pc is not None else "none", "setup_s": round(setup, 3)}
+    if a.segment in ("fp64-start", "fp64-resume"):
+        state = torch.empty(2 * nw + 8, dtype=torch.float64, device="cuda")
+        x0, done_iters, done_s = None, 0, 0.0
+        if a.segment == "fp64-resume":
+            ck = np.load(os.path.join(a.ckpt_in, "fp64_state.npz"))
+            x0 = dev(ck["gamma_w"])
+            state.copy_(dev(ck["state"]))
+            done_iters, done_s = int(ck["iters"]), float(ck["solve_s"])
+        opts = PcgOptions(rtol=1e-8, max_iter=a.max_iter, precision=FP64, precond=pc, state=state,
+                          resume=x0 is not None)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gw, info, st = s.solve(zw, opts, x0=x0, allow_noconv=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        os.makedirs(a.ckpt_out, exist_ok=True)
+        out.update({"segment_s": round(dt, 3), "segment_iters": info["inner_iters"],
+                    "fp64_s_total": round(done_s + dt, 3), "fp64_iters_total": done_iters + info["inner_iters"],
+                    "relres_fp64": info["relres_fp64"], "converged": st == 0})
+        rec = dict(gamma_w=gw.cpu().numpy(), state=state.cpu().numpy(), iters=done_iters + info["inner_iters"],
+                   solve_s=done_s + dt)
+        if st == 0:
+            o64 = PcgOptions(rtol=1e-8, max_iter=a.max_iter, precision=FP64, precond=pc)
+            t2 = time.perf_counter()
+            pr = s.predict(Z, T, o64, gamma_w0=gw, allow_noconv=True)
+            q, dq = s.quad_grad(zt, pr["gamma_tree"])
+            torch.cuda.synchronize()
+            out.update({"predict_grad_s": round(time.perf_counter() - t2, 3), "Q": q, "dQ_dlogrho": dq})
+            rec.update(zhat=pr["zhat"].cpu().numpy(), beta=pr["beta"], Q=q, dQ=dq)
+        np.savez(os.path.join(a.ckpt_out, "fp64_state.npz"), **rec)
+        return out
+    # mixed
+    om = PcgOptions(rtol=1e-8, max_iter=a.max_iter, precision=mixed, inner_rtol=a.inner_rtol, precond=pc,
+                    mixed_scheme=MIXED_FLEXIBLE)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gwm, infom, stm = s.solve(zw, om, allow_noconv=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    o64 = PcgOptions(rtol=1e-8, max_iter=a.max_iter, precision=FP64, precond=pc)
+    pr = s.predict(Z, T, o64, gamma_w0=gwm, allow_noconv=True)
+    qm, dqm = s.quad_grad(zt, pr["gamma_tree"])
+    torch.cuda.synchronize()
+    out.update({"mixed_precision": mixed, "inner_rtol": a.inner_rtol, "mixed_s": round(dt, 3),
+                "mixed_inner": infom["inner_iters"], "mixed_outer": infom["outer_iters"],
+                "mixed_fp64_matvecs": infom["fp64_matvecs"], "mixed_lowp_matvecs": infom["lowp_matvecs"],
+                "relres_fp64": infom["relres_fp64"], "converged": stm == 0, "Q_mixed": qm, "dQ_dlogrho_mixed": dqm})
+    if a.ckpt_in:
+        ck = np.load(os.path.join(a.ckpt_in, "fp64_state.npz"))
+        zh = pr["zhat"].cpu().numpy()
+        g64 = ck["gamma_w"]
+        out.update({"fp64_s": round(float(ck["solve_s"]), 3), "fp64_iters": int(ck["iters"]),
+                    "speedup": round(float(ck["solve_s"]) / dt, 3),
+                    "zhat_maxrelerr_mixed_vs_fp64": float(np.max(np.abs(zh - ck["zhat"])) / np.max(np.abs(ck["zhat"]))),
+                    "beta_maxrelerr_mixed_vs_fp64": float(np.max(np.abs(pr["beta"] - ck["beta"])) /
+                                                          np.max(np.abs(ck["beta"]))),
+                    "gamma_w_reldiff_mixed_vs_fp64": float(np.linalg.norm(gwm.cpu().numpy() - g64) /
+                                                           np.linalg.norm(g64)),
+                    "dQ_relerr_mixed_vs_fp64": abs(dqm - float(ck["dQ"])) / abs(float(ck["dQ"]))})
+    return out
+
+
 def default_cpu_rows(wl) -> int:
     """Rows of the oracle's CPU product sample: about 4e9 / (n (d + 3))
     (10-20 s of one host core at the oracle's measured rates)."""
@@ -747,6 +844,11 @@ def main():
                          "the GPU predictor; one JSON line instead of the step")
     ap.add_argument("--loglik-quick", action="store_true",
                     help="with --loglik: levels t and 0 only, one timed call each")
+    ap.add_argument("--segment", choices=("fp64-start", "fp64-resume", "mixed"), default=None,
+                    help="one segment of a FP64 vs mixed comparison split over several runs (default workload 5): "
+                         "the FP64 solve for --max-iter iterations, its exact continuation, or the mixed solve")
+    ap.add_argument("--ckpt-in", default="", help="directory of the FP64 segment to continue or compare with")
+    ap.add_argument("--ckpt-out", default="", help="directory receiving the FP64 segment's state")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 512 MiB three times with a plain device copy (reference for HBM counters)")
     a = ap.parse_args()
@@ -777,6 +879,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": src.numel() * 8, "launches": 3}), flush=True)
+        return
+
+    if a.segment:
+        a.config = a.config or 5
+        if a.precond == "auto":
+            a.precond = "none"
+        print(json.dumps(segment_bench(a)), flush=True)
         return
 
     if a.solve:

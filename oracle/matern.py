@@ -76,6 +76,8 @@ def matern_rho_drho(r, nu: float, rho: float, sigma2: float = 1.0):
         r = np.asarray(r, dtype=np.float64)
         u2 = (r / rho) ** 2
         return sigma2 * u2 * np.exp(-u2 / 2.0)
+    if abs(nu - 0.5 - round(nu - 0.5)) > 1e-12:
+        return matern_bessel_rho_drho(r, nu, rho, sigma2)
     n = _halfint_n(nu)
     r = np.asarray(r, dtype=np.float64)
     z = math.sqrt(2.0 * nu) * r / rho
@@ -98,6 +100,22 @@ def matern_bessel(r, nu: float, rho: float, sigma2: float = 1.0):
     out = np.full_like(z, sigma2)
     nz = z > 0
     out[nz] = sigma2 * (z[nz] ** nu) * kv(nu, z[nz]) / (gamma(nu) * 2.0 ** (nu - 1.0))
+    return out
+
+
+def matern_bessel_rho_drho(r, nu: float, rho: float, sigma2: float = 1.0):
+    """rho d phi / d rho for any nu > 0 from the Definition: with
+    z = sqrt(2 nu) r / rho, rho d/d rho = -z d/dz, and the derivative of the
+    Bessel product, d/dz [z^nu K_nu(z)] = -z^nu K_{nu-1}(z) (Abramowitz &
+    Stegun 9.6.28 with K_{-mu} = K_mu), gives
+        rho d phi / d rho = sigma2 z^(nu+1) K_{nu-1}(z) / (Gamma(nu) 2^(nu-1)),
+    zero at r = 0.  scipy's K_nu as in `matern_bessel`."""
+    from scipy.special import gamma, kv
+    r = np.asarray(r, dtype=np.float64)
+    z = np.sqrt(2.0 * nu) * r / rho
+    out = np.zeros_like(z)
+    nz = z > 0
+    out[nz] = sigma2 * (z[nz] ** (nu + 1.0)) * kv(nu - 1.0, z[nz]) / (gamma(nu) * 2.0 ** (nu - 1.0))
     return out
 
 

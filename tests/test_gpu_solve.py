@@ -187,3 +187,34 @@ def test_general_nu_blup_matches_oracle(nu):
     ref = OB.classic_blup(wl.points, wl.z, wl.targets, wl.degree_w, nu, wl.rho)
     assert relerr(host(out["zhat"]), ref.zhat) < 1e-9
     assert relerr(out["beta"], ref.beta) < 1e-8
+
+
+@pytest.mark.parametrize("precond", [None, "block"])
+def test_fp64_solve_resumes_its_recurrence(precond):
+    """Checkpoint / resume of the FP64 PCG: a solve stopped after half its
+    iterations, with its Krylov state (r, p, r.z) kept, and continued from
+    gamma_W with that state, takes exactly the iterations that remain in the
+    uninterrupted solve and ends on the same gamma_W (up to the rounding of
+    splitting the update of gamma_W in two); the result matches the oracle."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import FP64, PREC_BLOCK, MlblupError, PcgOptions, Solver
+    wl = workload(2, n=3000, n_targets=1)
+    s = Solver(wl.points, wl.degree_w, wl.leaf_max, wl.nu, wl.rho, wl.sigma2)
+    pc = s.precond(PREC_BLOCK) if precond else None
+    zw, _ = s.apply_W(s.to_tree(dev(wl.z)))
+    full, info_full, _ = s.solve(zw, PcgOptions(rtol=1e-10, max_iter=20000, precision=FP64, precond=pc))
+    n_full = info_full["inner_iters"]
+    half = n_full // 2
+    state = torch.empty(2 * (s.n - s.p) + 8, dtype=torch.float64, device="cuda")
+    g1, info1, st1 = s.solve(zw, PcgOptions(rtol=1e-10, max_iter=half, precision=FP64, precond=pc, state=state),
+                             allow_noconv=True)
+    assert st1 != 0 and info1["inner_iters"] == half
+    g2, info2, st2 = s.solve(zw, PcgOptions(rtol=1e-10, max_iter=20000, precision=FP64, precond=pc, state=state,
+                                            resume=True), x0=g1)
+    say(f"resume ({precond}): uninterrupted {n_full} iterations, segments {half} + {info2['inner_iters']}, "
+        f"relres {info2['relres_fp64']:.2e}")
+    assert st2 == 0 and info2["relres_fp64"] <= 1e-10
+    assert half + info2["inner_iters"] == n_full
+    assert float(torch.linalg.norm(g2 - full) / torch.linalg.norm(full)) < 1e-9
+    with pytest.raises(MlblupError):
+        s.solve(zw, PcgOptions(rtol=1e-10, max_iter=10, precision=FP64, state=state, resume=True))  # no x0

@@ -87,3 +87,18 @@ def test_gaussian_rho_derivative_central_difference():
     rho, h = 0.6, 1e-6
     fd = rho * (M.matern(r, np.inf, rho * (1 + h)) - M.matern(r, np.inf, rho * (1 - h))) / (2 * rho * h)
     np.testing.assert_allclose(M.matern_rho_drho(r, np.inf, rho), fd, rtol=1e-7, atol=1e-10)
+
+
+@pytest.mark.parametrize("nu", [0.3, 0.75, 1.0, 1.25, 2.2, 4.0])
+def test_general_nu_rho_derivative_central_difference(nu):
+    """rho d phi / d rho from the Bessel-derivative identity against central
+    differences of the Definition in log rho (any nu, including integer nu
+    where K_{nu-1} has integer order and nu < 1 where the order is negative)."""
+    from oracle.matern import matern_bessel, matern_bessel_rho_drho, matern_rho_drho
+    r = np.linspace(0.0, 2.0, 41)
+    rho, h = 0.4, 1e-5
+    fd = (matern_bessel(r, nu, rho * np.exp(h)) - matern_bessel(r, nu, rho * np.exp(-h))) / (2 * h)
+    d = matern_bessel_rho_drho(r, nu, rho)
+    assert np.max(np.abs(d - fd)) < 1e-8
+    assert d[0] == 0.0
+    assert np.array_equal(matern_rho_drho(r, nu, rho), d)
