@@ -13,17 +13,18 @@ constexpr int kNuGeneralT = -2;  // template code of a general smoothness (see d
 // e^{-z} for 0 <= z, FP64, by the table-driven method of P. T. P. Tang
 // ("Table-driven implementation of the exponential function in IEEE
 // floating-point arithmetic", ACM TOMS 15(2), 1989): with k the integer
-// nearest to -z 256/ln2, -z = k ln2/256 + r, |r| <= ln2/512, and
-// e^{-z} = 2^{k >> 8} 2^{(k & 255)/256} e^r.  e^r comes from its degree-4
-// Taylor polynomial (truncation < 4e-17 relative), the 256 values
-// 2^{j/256} from a table in LDS, and the power of two is added to the
-// exponent field.  ln2/256 is split in two parts (Cody-Waite; the high part
-// has 34 significant bits, so k L_HI is exact for |k| < 2^18); z is clamped
-// to 700, which bounds |k| and keeps every scaled result a normal number.
-// About 2 ulp.
+// nearest to -z 256/ln2, -z = (k + u) ln2/256 with |u| <= 1/2, and
+// e^{-z} = 2^{k >> 8} 2^{(k & 255)/256} e^{u ln2/256}.  e^{u ln2/256} comes
+// from its degree-4 Taylor polynomial in u (truncation < 4e-17 relative),
+// the 256 values 2^{j/256} from a table in LDS, and the power of two is added
+// to the exponent field.  u is one FMA, -z c - k with c = 256/ln2 rounded to
+// FP64: the rounding of c (below 2^-45 relative) gives u an error below
+// 3e-14 z, i.e. a relative error below 8e-17 z in the result (at most 3e-17
+// absolute over all z), which the covariance products cannot see next to the
+// rounding of their sums.  z is clamped to 700, which bounds |k| and keeps
+// every scaled result a normal number.
 constexpr double kExpInvL = 369.3299304675746;          // 256 / ln 2
-constexpr double kExpLHi = 0.002707606173999011;        // ln 2 / 256 to 34 bits
-constexpr double kExpLLo = 6.327543041662719e-14;       // ln 2 / 256 - L_HI
+constexpr double kExpL = 0.0027076061740622863;         // ln 2 / 256
 constexpr int kExpTab = 256;
 constexpr int kExpTabBits = 8;
 
@@ -111,12 +112,13 @@ __device__ __forceinline__ ExpParts exp_neg_parts(double z, const double* __rest
   const double t = fma(-z, kExpInvL, kShift);
   const int k = __double2loint(t);
   const double kn = t - kShift;
-  double r = fma(-kn, kExpLHi, -z);
-  r = fma(-kn, kExpLLo, r);
-  double p = fma(r, 1.0 / 24.0, 1.0 / 6.0);
-  p = fma(r, p, 0.5);
-  p = fma(r, p, 1.0);
-  p = fma(r, p, 1.0);
+  const double u = fma(-z, kExpInvL, -kn);
+  // e^{u L} = 1 + L u + (L u)^2/2 + (L u)^3/6 + (L u)^4/24, L = ln2/256
+  constexpr double c2 = kExpL * kExpL / 2.0, c3 = c2 * kExpL / 3.0, c4 = c3 * kExpL / 4.0;
+  double p = fma(u, c4, c3);
+  p = fma(u, p, c2);
+  p = fma(u, p, kExpL);
+  p = fma(u, p, 1.0);
   // m = k >> 8 as a signed bitfield extract
   return {p * tab[k & (kExpTab - 1)], (int)__builtin_amdgcn_sbfe(k, kExpTabBits, 32 - kExpTabBits)};
 }
@@ -130,17 +132,16 @@ __device__ __forceinline__ double exp_neg_f64(double z, const double* __restrict
 }
 
 // sqrt(s) for s > 0 (callers keep s away from 0 by a 1e-300 offset): the
-// hardware reciprocal square root, one Goldschmidt step for g ~ sqrt(s),
-// h ~ 1/(2 sqrt(s)), then one Newton correction of g.
+// hardware reciprocal square root y (relative error below 2^-24 on gfx950,
+// measured over [1e-6, 1e8]), g = s y, then two Newton corrections
+// g += (s - g^2) y/2 with the same y/2: the relative error goes from
+// e <= 2^-24 to 1.5 e^2 and then 1.5 e^3 (below 2^-70).
 __device__ __forceinline__ double sqrt_pos_f64(double s) {
   const double y = __builtin_amdgcn_rsq(s);
+  const double h = 0.5 * y;
   double g = s * y;
-  double h = 0.5 * y;
-  const double e = fma(-g, h, 0.5);
-  g = fma(g, e, g);
-  h = fma(h, e, h);
-  const double d = fma(-g, g, s);
-  return fma(d, h, g);
+  g = fma(fma(-g, g, s), h, g);
+  return fma(fma(-g, g, s), h, g);
 }
 
 // Matern closed forms in z = sqrt(2 nu) r / rho (nu = NU2 / 2)
@@ -177,8 +178,18 @@ template <int NU2, int OUT, bool FP32T>
 __device__ __forceinline__ void pair_value(double s, const double* __restrict__ tab, double& f, double& g,
                                            const double* __restrict__ gtab = nullptr) {
   if constexpr (NU2 == kNuGeneralT) {
-    // general nu: FP64 values from the table (genu.h); no derivative
-    if constexpr (OUT & 1) f = genu_f(s, gtab);
+    // general nu (genu.h): FP64 from the value and derivative tables that
+    // gtab points at, or FP32 from their float copies (then gtab points at
+    // floats: the value table, the derivative table kGenuDoubles further on)
+    if constexpr (FP32T) {
+      const float* T = reinterpret_cast<const float*>(gtab);
+      const float sf = fmaxf((float)s, 1e-30f);
+      if constexpr (OUT & 1) f = (double)genu_f32(sf, T);
+      if constexpr (OUT & 2) g = (double)genu_d32(sf, T + kGenuOffDeriv);
+    } else {
+      if constexpr (OUT & 1) f = genu_f(s, gtab);
+      if constexpr (OUT & 2) g = genu_d(s, gtab);
+    }
   } else if constexpr (NU2 == 0) {
     // Gaussian: s = r^2 / rho^2, phi = e^{-s/2}, rho dphi/drho = s e^{-s/2}
     if constexpr (FP32T) {
