@@ -263,7 +263,7 @@ def sweep(configs, reps: int = 10, warm: int = 3, nu=None):
             profile_enable(False)
             return float(np.median(times)), out
 
-        precs = ([FP64, FP32] + ([MFMA_FP32, MFMA_BF16X3] if 8 <= d <= 32 else [])) if closed else [FP64]
+        precs = [FP64, FP32] + ([MFMA_FP32, MFMA_BF16X3] if closed and 8 <= d <= 32 else [])
         prods, y64 = {}, None
         for prec in precs:
             work = torch.empty(max(cov_workspace_bytes(n, n, d, prec, VALUE), 256), dtype=torch.uint8, device="cuda")
@@ -809,7 +809,7 @@ def main():
     ap.add_argument("--targets", type=int, default=0, help="number of targets (0: the workload's)")
     ap.add_argument("--nu", type=float, default=0.0,
                     help="smoothness in place of the workload's (sweep: products only; a nu other than 1/2, 3/2, "
-                         "5/2 or +inf has FP64 values only)")
+                         "5/2 or +inf takes the general-nu tables, FP64 and FP32)")
     ap.add_argument("--mixed", type=int, default=-1, help="precision of the mixed solve (default: FP32 for d<8, "
                                                           "matrix-core BF16 x3 for d>=8)")
     ap.add_argument("--scheme", choices=("flexible", "reliable"), default="flexible",

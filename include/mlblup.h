@@ -43,7 +43,7 @@ extern "C" {
 
 #define MLBLUP_OK 0
 #define MLBLUP_EINVAL (-1)     /* bad argument: shape, NULL, nu outside (0, 8] and not +inf, NaN input, small
-                                  workspace, or an option the kernel's nu does not provide */
+                                  workspace */
 #define MLBLUP_ERANK (-2)      /* design matrix rank < p on the point set (e.g. collinear points, duplicates) */
 #define MLBLUP_ENOCONV (-3)    /* iteration limit reached; outputs hold the last iterate, info is filled */
 #define MLBLUP_EBREAKDOWN (-4) /* Krylov breakdown: p.q <= 0 or a non-finite scalar */
@@ -82,9 +82,12 @@ typedef struct mlblup_precond_s* mlblup_precond;
  *   nu = 1/2, 3/2, 5/2: the half-integer closed forms, every precision and output;
  *   nu = +INFINITY: the Gaussian exp(-r^2 / (2 rho^2)) (the Definition's limit;
  *     the kernel of the accuracy experiment in Sec. 8), every precision and output;
- *   any other 0 < nu <= 8: FP64 values from a series at the origin and tables
- *     (entries below 1e-18 sigma2 dropped); no derivative, no low precision, no
- *     preconditioner (EINVAL). */
+ *   any other 0 < nu <= 8: values from a series at the origin and tables
+ *     (entries below 1e-18 sigma2 dropped), FP64 or FP32 (the matrix-core
+ *     precisions take the FP32 path); the rho-derivative sigma2 z^{nu+1}
+ *     K_{nu-1}(z) from a second table; the preconditioners with FP32 values.
+ *     Square FP64 value products use the symmetric kernel, the other general-nu
+ *     products the row-tiled one. */
 typedef struct {
   double nu;
   double rho;

@@ -27,10 +27,13 @@ double digamma_int(int m) {
 
 }  // namespace
 
-bool genu_build(double nu, std::vector<double>& T) {
-  if (!(nu > 0.0) || nu > 8.0) return false;
-  T.assign(kGenuDoubles, 0.0);
-  const double c = std::pow(2.0, 1.0 - nu) / std::tgamma(nu);
+namespace {
+
+// One table of c z^nu K_nu(z) for an order 0 <= nu <= 8 and a given constant
+// c (the Matern normalisation for the value table), cut where it falls below
+// `cut`.
+void build_one(double nu, double c, double cut, double* T) {
+  std::fill(T, T + kGenuDoubles, 0.0);
   const bool integer = std::fabs(nu - std::round(nu)) < 1e-12;
   T[0] = integer ? std::round(nu) : nu;
   T[1] = integer ? 1.0 : 0.0;
@@ -60,10 +63,10 @@ bool genu_build(double nu, std::vector<double>& T) {
     T[kGenuOffLog + 2 * j] = 1.0 / cj;
     T[kGenuOffLog + 2 * j + 1] = std::log(cj);
   }
-  // g(z) = f(z) e^z on [Z0, zcut), zcut where f < 1e-18
+  // g(z) = f(z) e^z on [Z0, zcut), zcut where f < cut
   auto f = [&](double z) { return c * std::pow(z, nu) * std::cyl_bessel_k(nu, z); };
   double zcut = kGenuZ0;
-  while (zcut < kGenuZ0 + kGenuMaxInt * kGenuH && f(zcut) >= 1e-18) zcut += kGenuH;
+  while (zcut < kGenuZ0 + kGenuMaxInt * kGenuH && f(zcut) >= cut) zcut += kGenuH;
   const int nint = std::max(1, (int)std::lround((zcut - kGenuZ0) / kGenuH));
   T[4] = kGenuZ0 + nint * kGenuH;
   T[5] = nint;
@@ -96,6 +99,21 @@ bool genu_build(double nu, std::vector<double>& T) {
     }
     for (int j = 0; j < N; ++j) T[kGenuOffPoly + i * N + j] = mono[j];
   }
+}
+
+}  // namespace
+
+bool genu_build(double nu, std::vector<double>& T) {
+  if (!(nu > 0.0) || nu > 8.0) return false;
+  T.assign((size_t)(kGenuBytes / 8), 0.0);
+  const double c = std::pow(2.0, 1.0 - nu) / std::tgamma(nu);
+  build_one(nu, c, 1e-18, T.data());
+  // derivative: -z f'(z) = c z^{nu+1} K_{nu-1}(z) = s^e c z^mu K_mu(z), mu = |nu - 1|
+  // (the cut is lower: s^e grows to about 2e3 where the table ends)
+  build_one(std::fabs(nu - 1.0), c, 1e-22, T.data() + kGenuOffDeriv);
+  T[kGenuOffDeriv + kGenuSlotDexp] = nu >= 1.0 ? 1.0 : nu;
+  float* f32 = reinterpret_cast<float*>(T.data() + kGenuOffF32);
+  for (int i = 0; i < 2 * kGenuDoubles; ++i) f32[i] = (float)T[i];
   return true;
 }
 

@@ -38,6 +38,31 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kTile = 128;
 
+// Copies the general-nu tables a kernel reads into LDS: the value table, and
+// the derivative table when OUT asks for it; FP64 tables for the FP64
+// kernels, their float copies for FP32T.  Returns the LDS address (for
+// FP32T, of floats).  Only the used part of each table is copied.
+template <int OUT, bool FP32T>
+__device__ const double* stage_genu(const double* __restrict__ gtab) {
+  constexpr int kTabs = (OUT & 2) ? 2 : 1;
+  const int nd0 = kGenuOffPoly + (int)gtab[5] * (kGenuDeg + 1);
+  const int nd1 = kGenuOffPoly + (int)gtab[kGenuOffDeriv + 5] * (kGenuDeg + 1);
+  if constexpr (!FP32T) {
+    __shared__ double gsh[kTabs * kGenuDoubles];
+    for (int i = threadIdx.x; i < nd0; i += blockDim.x) gsh[i] = gtab[i];
+    if constexpr (OUT & 2)
+      for (int i = threadIdx.x; i < nd1; i += blockDim.x) gsh[kGenuOffDeriv + i] = gtab[kGenuOffDeriv + i];
+    return gsh;
+  } else {
+    __shared__ float gshf[kTabs * kGenuDoubles];
+    const float* src = reinterpret_cast<const float*>(gtab + kGenuOffF32);
+    for (int i = threadIdx.x; i < nd0; i += blockDim.x) gshf[i] = src[i];
+    if constexpr (OUT & 2)
+      for (int i = threadIdx.x; i < nd1; i += blockDim.x) gshf[kGenuOffDeriv + i] = src[kGenuOffDeriv + i];
+    return reinterpret_cast<const double*>(gshf);
+  }
+}
+
 // D > 0: compile-time dimension.  FP32T: FP32 transcendentals.
 template <int D, int NU2, int OUT, int R, bool FP32T>
 __global__ __launch_bounds__(kThreads) void pair_kernel(const double* __restrict__ rows, int64_t m,
@@ -49,14 +74,9 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const double* __restrict
   __shared__ double tile[kTile * SD];
   __shared__ double tab[kExpTab];
   exp_table_fill(tab);
-  // general nu: the table in LDS (read by every pair)
+  // general nu: the tables in LDS (read by every pair)
   const double* gt = gtab;
-  if constexpr (NU2 == kNuGeneralT) {
-    __shared__ double gsh[kGenuDoubles];
-    const int nd = kGenuOffPoly + (int)gtab[5] * (kGenuDeg + 1);
-    for (int i = threadIdx.x; i < nd; i += blockDim.x) gsh[i] = gtab[i];
-    gt = gsh;
-  }
+  if constexpr (NU2 == kNuGeneralT) gt = stage_genu<OUT, FP32T>(gtab);
   const int tid = threadIdx.x;
   const int64_t rbase = (int64_t)blockIdx.x * (kThreads * R);
   double xr[R][D];
@@ -123,14 +143,9 @@ __global__ __launch_bounds__(kThreads) void pair_kernel_any(const double* __rest
                                                             const double* __restrict__ gtab) {
   __shared__ double tab[kExpTab];
   exp_table_fill(tab);
-  // general nu: the table in LDS (read by every pair)
+  // general nu: the tables in LDS (read by every pair)
   const double* gt = gtab;
-  if constexpr (NU2 == kNuGeneralT) {
-    __shared__ double gsh[kGenuDoubles];
-    const int nd = kGenuOffPoly + (int)gtab[5] * (kGenuDeg + 1);
-    for (int i = threadIdx.x; i < nd; i += blockDim.x) gsh[i] = gtab[i];
-    gt = gsh;
-  }
+  if constexpr (NU2 == kNuGeneralT) gt = stage_genu<OUT, FP32T>(gtab);
   __syncthreads();
   const int64_t i0 = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t i = i0 < m ? i0 : m - 1;
@@ -213,11 +228,9 @@ void dispatch_out(const PairArgs& a, double zs, int S, int64_t cps, double* py, 
 
 template <bool F>
 void dispatch_nu(const PairArgs& a, double zs, int S, int64_t cps, double* py, double* pdy, hipStream_t s) {
-  if constexpr (!F) {
-    if (a.nu2 == kNuGeneral) {  // FP64 values only
-      dispatch_d<kNuGeneralT, 1, false>(a, zs, S, cps, py, pdy, s);
-      return;
-    }
+  if (a.nu2 == kNuGeneral) {
+    dispatch_out<kNuGeneralT, F>(a, zs, S, cps, py, pdy, s);
+    return;
   }
   switch (a.nu2) {
     case 0: dispatch_out<0, F>(a, zs, S, cps, py, pdy, s); break;
@@ -282,8 +295,6 @@ int pair_launch(const PairArgs& a, void* work, int64_t work_bytes, hipStream_t s
     return fail(MLBLUP_EINVAL, "cov_matvec: rho and sigma2 must be finite and > 0");
   if (a.nu2 != 0 && a.nu2 != 1 && a.nu2 != 3 && a.nu2 != 5 && a.nu2 != kNuGeneral)
     return fail(MLBLUP_EINVAL, "cov_matvec: nu must be in (0, 8] or +inf (Gaussian)");
-  if (a.nu2 == kNuGeneral && (a.precision != MLBLUP_FP64 || a.outputs != MLBLUP_VALUE))
-    return fail(MLBLUP_EINVAL, "cov_matvec: a nu other than 1/2, 3/2, 5/2 or +inf has FP64 values only");
   if (a.precision < MLBLUP_FP64 || a.precision > MLBLUP_MFMA_BF16X3)
     return fail(MLBLUP_EINVAL, "cov_matvec: unknown precision");
   if (a.m == 0) return MLBLUP_OK;
@@ -335,7 +346,10 @@ int pair_launch_body(const PairArgs& a, double zs, void* work, hipStream_t s) {
     }
     return hip_check(hipGetLastError(), "matrix-core pair kernel launch");
   }
-  if (a.rows == a.cols && a.m == a.n && sym_supported(a.d) && sym_worthwhile(a.n)) {
+  // general nu: the symmetric kernel takes FP64 values; other arithmetic and
+  // the derivative run the row-tiled kernel
+  const bool genu_sym = a.nu2 != kNuGeneral || (a.precision == MLBLUP_FP64 && a.outputs == MLBLUP_VALUE);
+  if (a.rows == a.cols && a.m == a.n && genu_sym && sym_supported(a.d) && sym_worthwhile(a.n)) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (profile_on()) {
       MLB_HIP(hipEventCreate(&e0));

@@ -22,12 +22,12 @@ struct CrossTask {
 };
 
 int prec_leaf_blocks(const int64_t* lbegin, const int32_t* lsize, const int64_t* koff, int32_t nleaves,
-                     const double* pts, int d, double zs, int nu2, double* K, hipStream_t s);
+                     const double* pts, int d, double zs, int nu2, const float* g32, double* K, hipStream_t s);
 int prec_scal_values(const PrecNode* nodes, const int32_t* lvl, int32_t cnt, const double* V, const double* phi_in,
                      double* phi_out, int P, int64_t n, hipStream_t s);
 int prec_zero(double* p, int64_t n, hipStream_t s);
 int prec_cross(const CrossTask* tasks, int32_t ntasks, int NR, const double* pts, int d, double zs, int nu2,
-               const double* phi, int P, double* part, hipStream_t s);
+               const float* g32, const double* phi, int P, double* part, hipStream_t s);
 int prec_apply_blocks(const int64_t* w_off, const int32_t* mw, const int64_t* boff, int32_t cnt, const double* Binv,
                       const double* r, double* z, hipStream_t s);
 int prec_apply_diag(const double* inv, const double* r, double* z, int64_t n, hipStream_t s);
@@ -63,7 +63,8 @@ struct Precond {
 int precond_workspace_bytes(const Basis& B, int64_t* bytes);
 // rows of the coarse block of the coarse kind: every level above the finest
 void coarse_rows(const Basis& B, int64_t* c0, int64_t* nc);
-int precond_build(const Basis& B, double nu2, double rho, double sigma2, int kind, void* work, int64_t work_bytes,
+// nu: the smoothness (+inf for the Gaussian; any 0 < nu <= 8)
+int precond_build(const Basis& B, double nu, double rho, double sigma2, int kind, void* work, int64_t work_bytes,
                   hipStream_t s, Precond& P);
 int precond_apply(const Precond& P, const double* r, double* z, hipStream_t s);
 

@@ -21,6 +21,7 @@
 #include <cmath>
 
 #include "device.h"
+#include "genu.h"
 #include "precond.h"
 
 namespace mlb {
@@ -29,7 +30,9 @@ namespace {
 constexpr int kT = 256;
 constexpr int kMaxD = 64;
 
-__device__ __forceinline__ double phi32(double s, int nu2) {
+// g32: the float value table of a general nu (genu.h), else unused
+__device__ __forceinline__ double phi32(double s, int nu2, const float* __restrict__ g32) {
+  if (nu2 == kNuGeneral) return (double)genu_f32(fmaxf((float)s, 1e-30f), g32);
   if (nu2 == 0) return (double)__builtin_amdgcn_exp2f(-0.72134752044448170f * (float)s);  // Gaussian e^{-s/2}
   const float z = __builtin_amdgcn_sqrtf((float)s);
   const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
@@ -41,7 +44,8 @@ __device__ __forceinline__ double phi32(double s, int nu2) {
 
 __global__ __launch_bounds__(kT) void leaf_blocks(const int64_t* __restrict__ lbegin, const int32_t* __restrict__ lsize,
                                                   const int64_t* __restrict__ koff, const double* __restrict__ pts,
-                                                  int d, double zs, int nu2, double* __restrict__ K) {
+                                                  int d, double zs, int nu2, const float* __restrict__ g32,
+                                                  double* __restrict__ K) {
   const int leaf = blockIdx.x;
   const int64_t b = lbegin[leaf];
   const int s = lsize[leaf];
@@ -52,7 +56,7 @@ __global__ __launch_bounds__(kT) void leaf_blocks(const int64_t* __restrict__ lb
       const double t = (pts[(b + i) * d + k] - pts[(b + j) * d + k]) * zs;
       acc = fma(t, t, acc);
     }
-    K[koff[leaf] + e] = phi32(acc, nu2);
+    K[koff[leaf] + e] = phi32(acc, nu2, g32);
   }
 }
 
@@ -108,8 +112,8 @@ __device__ __forceinline__ double wave_sum(double x) {
 // Sibling cross term partial: rows [r0, r1) of S_L, columns [c0, c1) of S_R.
 template <int NR>
 __global__ __launch_bounds__(kT) void cross_gram(const CrossTask* __restrict__ tasks, const double* __restrict__ pts,
-                                                 int d, double zs, int nu2, const double* __restrict__ phi, int P,
-                                                 double* __restrict__ part) {
+                                                 int d, double zs, int nu2, const float* __restrict__ g32,
+                                                 const double* __restrict__ phi, int P, double* __restrict__ part) {
   constexpr int TC = 64;
   __shared__ double cpts[TC * kMaxD];
   __shared__ double crhs[TC * NR];
@@ -146,7 +150,7 @@ __global__ __launch_bounds__(kT) void cross_gram(const CrossTask* __restrict__ t
           const double t = xr[k] - cpts[j * kMaxD + k];
           s = fma(t, t, s);
         }
-      const double f = phi32(s, nu2);
+      const double f = phi32(s, nu2, g32);
 #pragma unroll
       for (int b = 0; b < NR; ++b) y[b] = fma(f, crhs[j * NR + b], y[b]);
     }
@@ -227,9 +231,9 @@ __global__ void fill0(double* p, int64_t n) {
 }  // namespace
 
 int prec_leaf_blocks(const int64_t* lbegin, const int32_t* lsize, const int64_t* koff, int32_t nleaves,
-                     const double* pts, int d, double zs, int nu2, double* K, hipStream_t s) {
+                     const double* pts, int d, double zs, int nu2, const float* g32, double* K, hipStream_t s) {
   if (nleaves <= 0) return MLBLUP_OK;
-  hipLaunchKernelGGL(leaf_blocks, dim3(nleaves), dim3(kT), 0, s, lbegin, lsize, koff, pts, d, zs, nu2, K);
+  hipLaunchKernelGGL(leaf_blocks, dim3(nleaves), dim3(kT), 0, s, lbegin, lsize, koff, pts, d, zs, nu2, g32, K);
   return hip_check(hipGetLastError(), "leaf_blocks launch");
 }
 
@@ -247,14 +251,14 @@ int prec_zero(double* p, int64_t n, hipStream_t s) {
 }
 
 int prec_cross(const CrossTask* tasks, int32_t ntasks, int NR, const double* pts, int d, double zs, int nu2,
-               const double* phi, int P, double* part, hipStream_t s) {
+               const float* g32, const double* phi, int P, double* part, hipStream_t s) {
   if (ntasks <= 0) return MLBLUP_OK;
   if (d > kMaxD) return fail(MLBLUP_EINVAL, "preconditioner: d > 64");
   switch (NR) {
-    case 8: hipLaunchKernelGGL(cross_gram<8>, dim3(ntasks), dim3(kT), 0, s, tasks, pts, d, zs, nu2, phi, P, part); break;
-    case 16: hipLaunchKernelGGL(cross_gram<16>, dim3(ntasks), dim3(kT), 0, s, tasks, pts, d, zs, nu2, phi, P, part); break;
-    case 24: hipLaunchKernelGGL(cross_gram<24>, dim3(ntasks), dim3(kT), 0, s, tasks, pts, d, zs, nu2, phi, P, part); break;
-    case 32: hipLaunchKernelGGL(cross_gram<32>, dim3(ntasks), dim3(kT), 0, s, tasks, pts, d, zs, nu2, phi, P, part); break;
+    case 8: hipLaunchKernelGGL(cross_gram<8>, dim3(ntasks), dim3(kT), 0, s, tasks, pts, d, zs, nu2, g32, phi, P, part); break;
+    case 16: hipLaunchKernelGGL(cross_gram<16>, dim3(ntasks), dim3(kT), 0, s, tasks, pts, d, zs, nu2, g32, phi, P, part); break;
+    case 24: hipLaunchKernelGGL(cross_gram<24>, dim3(ntasks), dim3(kT), 0, s, tasks, pts, d, zs, nu2, g32, phi, P, part); break;
+    case 32: hipLaunchKernelGGL(cross_gram<32>, dim3(ntasks), dim3(kT), 0, s, tasks, pts, d, zs, nu2, g32, phi, P, part); break;
     default: return fail(MLBLUP_EINVAL, "preconditioner: trend dimension p > 32 not supported");
   }
   return hip_check(hipGetLastError(), "cross_gram launch");

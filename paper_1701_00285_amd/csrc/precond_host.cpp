@@ -12,6 +12,7 @@
 #include <thread>
 
 #include "device.h"
+#include "genu.h"
 #include "precond.h"
 
 
@@ -54,7 +55,7 @@ std::vector<CrossTask> level_tasks(const Basis& B, int q) {
 }
 
 struct WsLayout {
-  int64_t nodes, lbegin, lsize, koff, K, phi0, phi1, tasks, part, total;
+  int64_t nodes, lbegin, lsize, koff, K, phi0, phi1, tasks, part, gtab, total;
   int64_t max_tasks, k_entries;
   int32_t nleaves;
   int NR;
@@ -91,6 +92,7 @@ WsLayout layout(const Basis& B) {
   w.phi1 = take(B.n * NR * 8);
   w.tasks = take(mt * (int64_t)sizeof(CrossTask));
   w.part = take(mt * NR * NR * 8);
+  w.gtab = take(kGenuBytes);
   w.total = off;
   return w;
 }
@@ -168,14 +170,15 @@ void coarse_rows(const Basis& B, int64_t* c0, int64_t* nc) {
   *nc = (B.n - B.p) - f;
 }
 
-int precond_build(const Basis& B, double nu2d, double rho, double sigma2, int kind, void* work, int64_t work_bytes,
+int precond_build(const Basis& B, double nu, double rho, double sigma2, int kind, void* work, int64_t work_bytes,
                   hipStream_t s, Precond& P) {
   const WsLayout w = layout(B);
   if (w.NR < 0) return fail(MLBLUP_EINVAL, "preconditioner: trend dimension p > 32 not supported");
   if (!work || work_bytes < w.total)
     return fail(MLBLUP_EINVAL, "preconditioner workspace too small (need " + std::to_string(w.total) + ")");
-  const int nu2 = (int)std::lround(nu2d);
-  const double zs = kernel_scale(nu2, 0.5 * nu2d, rho);
+  const int nu2 = nu2_of_nu(nu);
+  if (nu2 == -1) return fail(MLBLUP_EINVAL, "preconditioner: nu must be in (0, 8] or +inf");
+  const double zs = kernel_scale(nu2, nu, rho);
   const int32_t nn = (int32_t)B.desc.size();
   char* base = (char*)work;
   const char* img = (const char*)B.dev_base;
@@ -198,12 +201,21 @@ int precond_build(const Basis& B, double nu2d, double rho, double sigma2, int ki
       ko += (int64_t)D.m * D.m;
     }
   }
+  // general nu: the FP32 value table (the pair values here are FP32)
+  const float* g32 = nullptr;
+  if (nu2 == kNuGeneral) {
+    const double* host = genu_table_cached(nu);
+    if (!host) return fail(MLBLUP_EINVAL, "preconditioner: nu out of range for the general-nu table");
+    MLB_HIP(hipMemcpyAsync(base + w.gtab, host, kGenuBytes, hipMemcpyHostToDevice, s));
+    g32 = reinterpret_cast<const float*>((const double*)(base + w.gtab) + kGenuOffF32);
+  }
   MLB_HIP(hipMemcpyAsync(base + w.nodes, nodes.data(), nn * sizeof(PrecNode), hipMemcpyHostToDevice, s));
   MLB_HIP(hipMemcpyAsync(base + w.lbegin, lbegin.data(), lbegin.size() * 8, hipMemcpyHostToDevice, s));
   MLB_HIP(hipMemcpyAsync(base + w.lsize, lsize.data(), lsize.size() * 4, hipMemcpyHostToDevice, s));
   MLB_HIP(hipMemcpyAsync(base + w.koff, koff.data(), koff.size() * 8, hipMemcpyHostToDevice, s));
   int st = prec_leaf_blocks((const int64_t*)(base + w.lbegin), (const int32_t*)(base + w.lsize),
-                            (const int64_t*)(base + w.koff), w.nleaves, pts, B.d, zs, nu2, (double*)(base + w.K), s);
+                            (const int64_t*)(base + w.koff), w.nleaves, pts, B.d, zs, nu2, g32, (double*)(base + w.K),
+                            s);
   if (st) return st;
   std::vector<double> Kh(w.k_entries);
   MLB_HIP(hipMemcpyAsync(Kh.data(), base + w.K, w.k_entries * 8, hipMemcpyDeviceToHost, s));
@@ -223,7 +235,7 @@ int precond_build(const Basis& B, double nu2d, double rho, double sigma2, int ki
     if (!tasks.empty()) {
       MLB_HIP(hipMemcpyAsync(base + w.tasks, tasks.data(), tasks.size() * sizeof(CrossTask), hipMemcpyHostToDevice,
                              s));
-      if ((st = prec_cross((const CrossTask*)(base + w.tasks), (int32_t)tasks.size(), NR, pts, B.d, zs, nu2, phi_cur,
+      if ((st = prec_cross((const CrossTask*)(base + w.tasks), (int32_t)tasks.size(), NR, pts, B.d, zs, nu2, g32, phi_cur,
                            NR, (double*)(base + w.part), s)))
         return st;
       parth.assign(tasks.size() * NR * NR, 0.0);
@@ -350,7 +362,7 @@ int precond_build(const Basis& B, double nu2d, double rho, double sigma2, int ki
   }
   if (coarse) {
     PairArgs k{nullptr, 0, nullptr, B.n, B.d, nu2, rho, sigma2, MLBLUP_FP64, MLBLUP_VALUE, nullptr, nullptr, nullptr,
-               nu2 == 0 ? INFINITY : 0.5 * nu2, nullptr};
+               nu, nullptr};
     if ((st = coarse_inverse_factor(B, k, c0, nc, work, work_bytes, P.ycoarse, s))) return st;
     const int64_t ldc = (nc + 3) / 4 * 4;
     P.y32.assign((size_t)nc * ldc, 0.0f);
@@ -424,13 +436,12 @@ int mlblup_precond_build(mlblup_basis b, const mlblup_matern* k, int32_t kind, v
     if (b->b.levels < 3 || nc <= 0 || c0 < nc)
       return fail(MLBLUP_EINVAL, "coarse preconditioner: needs three or more levels, the finest holding most rows");
   }
-  const int n2 = nu2_of_nu(k->nu);
-  if (n2 < 0) return fail(MLBLUP_EINVAL, "preconditioner: nu must be 0.5, 1.5, 2.5 or +inf (Gaussian)");
+  if (nu2_of_nu(k->nu) == -1) return fail(MLBLUP_EINVAL, "preconditioner: nu must be in (0, 8] or +inf (Gaussian)");
   if (!(k->rho > 0) || !(k->sigma2 > 0) || !std::isfinite(k->rho) || !std::isfinite(k->sigma2))
     return fail(MLBLUP_EINVAL, "rho and sigma2 must be finite and > 0");
   std::unique_ptr<mlblup_precond_s> pc(new (std::nothrow) mlblup_precond_s);
   if (!pc) return fail(MLBLUP_EINVAL, "out of host memory");
-  const int st = precond_build(b->b, (double)n2, k->rho, k->sigma2, kind, work_dev, work_bytes,
+  const int st = precond_build(b->b, k->nu, k->rho, k->sigma2, kind, work_dev, work_bytes,
                                (hipStream_t)stream, pc->p);
   if (st) return st;
   *out = pc.release();

@@ -262,13 +262,45 @@ def test_general_nu_products(nu):
     assert row_relerr(host(yr), host(y), host(cov_matvec(P, P.clone(), torch.abs(dev(x)), nu, 0.25)[0])) < GENERAL_TOL
 
 
-def test_general_nu_rejects_what_it_does_not_provide():
+GENERAL_FP32_TOL = 2e-5   # FP32 series / tables: ~1e-6 per value, a few 1e-6 from s^nu at tiny s
+
+
+@pytest.mark.parametrize("nu", [0.75, 1.0, 1.25, 3.5])
+def test_general_nu_fp32_and_derivative_products(nu):
+    """General smoothness beyond FP64 values: the FP32 kernel values (series
+    at the origin with hardware log2 / exp2, FP32 tables beyond; the
+    matrix-core precisions take the same FP32 path) and the rho-derivative
+    rho dphi/drho = sigma2 z^{nu+1} K_{nu-1}(z) (FP64 and FP32), against the
+    oracle's Definition through scipy's K_nu and K_{nu-1}, on the row-tiled
+    path and a square product at 16,385 points."""
     torch = require_gpu()
-    from paper_1701_00285_amd import DLOGRHO, FP32, MFMA_FP32, MlblupError, VALUE, cov_matvec
-    P = dev(synth.uniform_cloud(300, 3, 5))
-    x = dev(synth.standard_normal(300, 6))
-    for prec, out in ((FP32, VALUE), (MFMA_FP32, VALUE)):
-        with pytest.raises(MlblupError, match="EINVAL"):
-            cov_matvec(P, P, x, 1.25, 0.3, precision=prec, outputs=out)
-    with pytest.raises(MlblupError, match="EINVAL"):
-        cov_matvec(P, P, x, 1.25, 0.3, outputs=VALUE | DLOGRHO)
+    from paper_1701_00285_amd import DLOGRHO, FP32, FP64, MFMA_BF16X3, VALUE, cov_matvec
+    for (m, n, d) in ((41, 64, 2), (700, 1031, 3), (513, 700, 10)):
+        rows = synth.uniform_cloud(m, d, 200 + d)
+        cols = synth.uniform_cloud(n, d, 201 + d)
+        x = synth.standard_normal(n, 202 + d)
+        rho = 0.3 * np.sqrt(d)
+        say(f"general nu={nu} fp32 / derivative m={m} n={n} d={d}")
+        ref = brute.cov_matvec(rows, cols, x, nu, rho, 1.4)
+        dref = brute.cov_matvec(rows, cols, x, nu, rho, 1.4, deriv=True)
+        sc = 1.4 * _scale(rows, cols, x, nu, rho)
+        y64, dy64 = cov_matvec(dev(rows), dev(cols), dev(x), nu, rho, 1.4, precision=FP64, outputs=VALUE | DLOGRHO)
+        assert row_relerr(host(y64), ref, sc) < GENERAL_TOL
+        assert row_relerr(host(dy64), dref, sc) < GENERAL_TOL
+        for prec in (FP32, MFMA_BF16X3):
+            y, dy = cov_matvec(dev(rows), dev(cols), dev(x), nu, rho, 1.4, precision=prec, outputs=VALUE | DLOGRHO)
+            assert row_relerr(host(y), ref, sc) < GENERAL_FP32_TOL
+            assert row_relerr(host(dy), dref, sc) < GENERAL_FP32_TOL
+    n = 16385
+    pts = synth.uniform_cloud(n, 3, 203)
+    x = synth.standard_normal(n, 204)
+    idx = np.unique(np.concatenate([np.arange(0, n, n // 40), np.arange(n - 8, n)]))
+    ref = brute.cov_matvec(pts[idx], pts, x, nu, 0.25)
+    dref = brute.cov_matvec(pts[idx], pts, x, nu, 0.25, deriv=True)
+    sc = _scale(pts[idx], pts, x, nu, 0.25)
+    P = dev(pts)
+    y, dy = cov_matvec(P, P, dev(x), nu, 0.25, precision=FP32, outputs=VALUE | DLOGRHO)
+    assert row_relerr(host(y)[idx], ref, sc) < GENERAL_FP32_TOL
+    assert row_relerr(host(dy)[idx], dref, sc) < GENERAL_FP32_TOL
+    _, dy64 = cov_matvec(P, P, dev(x), nu, 0.25, precision=FP64, outputs=DLOGRHO)
+    assert row_relerr(host(dy64)[idx], dref, sc) < GENERAL_TOL

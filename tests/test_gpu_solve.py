@@ -189,6 +189,38 @@ def test_general_nu_blup_matches_oracle(nu):
     assert relerr(out["beta"], ref.beta) < 1e-8
 
 
+def test_general_nu_mixed_solve_gradient_and_preconditioner():
+    """nu = 5/4 (the smoothness of the paper's prediction experiments) through
+    the whole path: the block preconditioner built with FP32 general-nu
+    values, the flexible-CG mixed solve with FP32 inner products, the FP64
+    predictor, and Q, dQ/dlog rho from the general-nu derivative kernel;
+    against the oracle's classic BLUP and dense gradient (scipy K_nu, K_{nu-1})."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import FP32, FP64, PREC_BLOCK, PcgOptions
+    nu = 1.25
+    wl = workload(4, n=2000, n_targets=150)
+    s = _solver(wl, max_targets=150, nu=nu)
+    pc = s.precond(PREC_BLOCK)
+    ref = OB.classic_blup(wl.points, wl.z, wl.targets, wl.degree_w, nu, wl.rho)
+    q_ref, dq_ref = OB.quad_form_grad(wl.points, wl.z, wl.degree_w, nu, wl.rho)
+    plain = s.predict(dev(wl.z), dev(wl.targets), PcgOptions(rtol=1e-12, max_iter=6000, precision=FP64))
+    a = s.predict(dev(wl.z), dev(wl.targets), PcgOptions(rtol=1e-12, max_iter=6000, precision=FP64, precond=pc))
+    b = s.predict(dev(wl.z), dev(wl.targets), PcgOptions(rtol=1e-8, max_iter=6000, precision=FP32, inner_rtol=0.1,
+                                                         precond=pc))
+    say(f"general nu={nu}: fp64 {plain['info']['inner_iters']} it (block: {a['info']['inner_iters']}), mixed "
+        f"{b['info']['inner_iters']} inner / {b['info']['outer_iters']} outer, zhat err "
+        f"{relerr(host(a['zhat']), ref.zhat):.2e} / {relerr(host(b['zhat']), ref.zhat):.2e}")
+    assert a["info"]["inner_iters"] < plain["info"]["inner_iters"]
+    assert relerr(host(a["zhat"]), ref.zhat) < 1e-9
+    assert b["info"]["relres_fp64"] <= 1e-8 and b["info"]["lowp_matvecs"] > 0
+    assert relerr(host(b["zhat"]), ref.zhat) < 1e-6
+    zt = s.to_tree(dev(wl.z))
+    q, dq = s.quad_grad(zt, a["gamma_tree"])
+    say(f"general nu={nu}: Q {abs(q - q_ref) / abs(q_ref):.2e} dQ {abs(dq - dq_ref) / abs(dq_ref):.2e}")
+    assert abs(q - q_ref) <= 1e-8 * abs(q_ref)
+    assert abs(dq - dq_ref) <= 1e-8 * abs(dq_ref)
+
+
 @pytest.mark.parametrize("precond", [None, "block"])
 def test_fp64_solve_resumes_its_recurrence(precond):
     """Checkpoint / resume of the FP64 PCG: a solve stopped after half its
