@@ -584,10 +584,12 @@ def segment_bench(a):
     import torch
 
     import synth
-    from paper_1701_00285_amd import FP32, FP64, MFMA_BF16X3, MIXED_FLEXIBLE, PREC_COARSE, PcgOptions, Solver
+    from paper_1701_00285_amd import (FP32, FP64, MFMA_BF16X3, MIXED_FLEXIBLE, MIXED_RELIABLE, PREC_COARSE,
+                                      PcgOptions, Solver)
     torch.cuda.set_device(0)
     wl = synth.make_config(a.config, n=a.n or None, n_targets=a.targets or None)
     mixed = a.mixed if a.mixed >= 0 else (FP32 if wl.d < 8 else MFMA_BF16X3)
+    scheme = {"flexible": MIXED_FLEXIBLE, "reliable": MIXED_RELIABLE}[a.scheme]
     dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda")
     t0 = time.perf_counter()
     s = Solver(wl.points, wl.degree_w, wl.leaf_max, wl.nu, wl.rho, wl.sigma2, max_targets=wl.targets.shape[0])
@@ -634,7 +636,7 @@ def segment_bench(a):
         return out
     # mixed
     om = PcgOptions(rtol=1e-8, max_iter=a.max_iter, precision=mixed, inner_rtol=a.inner_rtol, precond=pc,
-                    mixed_scheme=MIXED_FLEXIBLE)
+                    mixed_scheme=scheme)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     gwm, infom, stm = s.solve(zw, om, allow_noconv=True)
@@ -644,7 +646,7 @@ def segment_bench(a):
     pr = s.predict(Z, T, o64, gamma_w0=gwm, allow_noconv=True)
     qm, dqm = s.quad_grad(zt, pr["gamma_tree"])
     torch.cuda.synchronize()
-    out.update({"mixed_precision": mixed, "inner_rtol": a.inner_rtol, "mixed_s": round(dt, 3),
+    out.update({"mixed_precision": mixed, "mixed_scheme": a.scheme, "inner_rtol": a.inner_rtol, "mixed_s": round(dt, 3),
                 "mixed_inner": infom["inner_iters"], "mixed_outer": infom["outer_iters"],
                 "mixed_fp64_matvecs": infom["fp64_matvecs"], "mixed_lowp_matvecs": infom["lowp_matvecs"],
                 "relres_fp64": infom["relres_fp64"], "converged": stm == 0, "Q_mixed": qm, "dQ_dlogrho_mixed": dqm})
