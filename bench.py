@@ -19,8 +19,8 @@ predictors, gradients) on the 65,536-point d = 3 workload under its own
 key, and the oracle's CPU baseline.
 
 `--solve` prints the whole-path line for one workload instead (the records
-under profiles/blup_solve_* come from it); `--sweep`, `--loglik` and
-`--cpu-oracle` are the other measurement modes.
+under profiles/blup_solve_* come from it); `--sweep`, `--loglik`,
+`--loglik-sparse` and `--cpu-oracle` are the other measurement modes.
 """
 from __future__ import annotations
 
@@ -38,13 +38,18 @@ PEAK_FP64_VALU_TFLOPS = 78.6      # 256 CU x 2.4 GHz x 64 lanes x 2 flop (FMA)
 
 
 def flops_per_unordered_pair(d: int, nu: float) -> int:
-    """Algorithmic flops of one distinct pair {i, j} of a symmetric product
-    (FMA = 2): d differences + d squared accumulations (3d), sqrt (1), exp (1),
-    the Matern polynomial (nu=1/2: 0; 3/2: 1+z and the product with e^-z = 2;
-    5/2: two FMA and the product = 5) and two accumulation FMAs (4), one for
-    y_i and one for y_j."""
+    """Algorithmic flops of one distinct pair {i, j} of the FP64 symmetric
+    product (FMA = 2): the squared distance, sqrt (1), exp (1), the Matern
+    polynomial (nu=1/2: 0; 3/2: 1+z and the product with e^-z = 2; 5/2: two
+    FMA and the product = 5) and two accumulation FMAs (4), one for y_i and
+    one for y_j.  The squared distance is d differences + d squared
+    accumulations (3d) for d < 8; from d = 8 on the kernel takes the
+    expanded form |a|^2 + |b|^2 - 2 a.b, d FMAs for the dot product, one
+    addition of the norms and one FMA (2d + 3; the norms themselves are per
+    point, not per pair)."""
     poly = {0.5: 0, 1.5: 2, 2.5: 5}[nu]
-    return 3 * d + 6 + poly
+    dist = 2 * d + 3 if d >= 8 else 3 * d
+    return dist + 6 + poly
 
 
 TRAFFIC_FILES = {"cfg2_n65536_d3_nu1.5": os.path.join(ROOT, "profiles", "traffic_sym_kernel_fp64_cfg2_n65536_d3.txt"),
@@ -362,6 +367,70 @@ def loglik_bench(k: int, n: int, reps: int = 3, quick: bool = False):
     m = s.mle_rho(z, t - 1, wl.rho / 10, wl.rho * 10, 1e-4)
     res["mle_rho_level_t_minus_1"] = {"rho_hat": m["rho"], "loglik": m["loglik"], "evals": m["evals"],
                                       "s": round(time.perf_counter() - t0, 3), "rho_workload": wl.rho}
+    print(json.dumps(res), flush=True)
+
+
+def loglik_sparse_bench(k: int, n: int, reps: int = 3, dense: bool = True):
+    """Estimator with the sparse block factorization: l~_n at levels t and
+    t - 1 for several tau, only the kept blocks formed and factored (host
+    analysis timed on its own: pattern, minimum-degree order, block
+    structure, wavelet vectors), each the median of `reps` calls after one
+    untimed call; with `dense`, the dense sparsified path on the same matrix
+    beside it (the N x N covariance must fit).  Flops: the block
+    factorization's (w^3/3 per diagonal block, w_i w_k^2 per block below it,
+    2 w_i w_j w_k per update) plus the assembly, 2 |S_a| |S_b| (w_b + 1) +
+    2 |S_a| w_a w_b per kept block pair (not counted in TFLOP/s)."""
+    import time
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1701_00285_amd import MlblupError, Solver
+    torch.cuda.set_device(0)
+    wl = synth.make_config(k, n=n, n_targets=1)
+    t0 = time.perf_counter()
+    s = Solver(wl.points, wl.degree_w, wl.leaf_max, wl.nu, wl.rho, wl.sigma2)
+    setup = time.perf_counter() - t0
+    z = torch.as_tensor(wl.z, dtype=torch.float64, device="cuda")
+    top = s.basis.levels - 1
+    res = {"workload": f"cfg{k} generator, n={n}, d={wl.d}, nu={wl.nu}, rho={wl.rho}, leaf={wl.leaf_max}, "
+                       f"p={s.p}", "setup_s": round(setup, 3), "cases": {}}
+    for level in (top, top - 1):
+        for tau in (0.02, 0.05, 0.1):
+            key = f"level {level} tau {tau}"
+            t0 = time.perf_counter()
+            info = s.loglik_sparse_info(level, tau)
+            ana = time.perf_counter() - t0
+            row = {"rows": info["rows"], "kept_fill": round(info["kept"] / info["rows"] ** 2, 5),
+                   "factor_entries": info["factor_entries"], "block_columns": info["block_columns"],
+                   "heights": info["heights"], "factor_gflop": round(info["flops"] / 1e9, 3),
+                   "analysis_s": round(ana, 3)}
+            try:
+                s.loglik_sparse(z, level, tau)
+                times = []
+                for _ in range(reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    out = s.loglik_sparse(z, level, tau)
+                    times.append(time.perf_counter() - t0)
+                ms = 1e3 * float(np.median(times))
+                row.update(ms=round(ms, 3), loglik=out["loglik"], logdet=out["logdet"], quad=out["quad"],
+                           factor_tflops=round(info["flops"] / (ms * 1e-3) / 1e12, 3))
+            except MlblupError as e:   # C~ not positive definite for this tau
+                row["error"] = str(e).split(":")[0]
+            if dense and "error" not in row:
+                s.loglik(z, level, tau=tau)
+                times = []
+                for _ in range(reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    d = s.loglik(z, level, tau=tau)
+                    times.append(time.perf_counter() - t0)
+                row.update(dense_ms=round(1e3 * float(np.median(times)), 3),
+                           rel_diff_loglik=abs(d["loglik"] - row["loglik"]) / abs(d["loglik"]))
+            res["cases"][key] = row
+            print(f"sparse loglik {key}: {row}", file=sys.stderr, flush=True)
     print(json.dumps(res), flush=True)
 
 
@@ -846,6 +915,11 @@ def main():
                          "the GPU predictor; one JSON line instead of the step")
     ap.add_argument("--loglik-quick", action="store_true",
                     help="with --loglik: levels t and 0 only, one timed call each")
+    ap.add_argument("--loglik-sparse", type=int, default=0,
+                    help="estimator with the sparse block factorization of the kept blocks: levels t and t - 1, "
+                         "several tau, on this many points of the workload's generator (one JSON line)")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="with --loglik-sparse: skip the dense sparsified path beside it (large n)")
     ap.add_argument("--segment", choices=("fp64-start", "fp64-resume", "mixed"), default=None,
                     help="one segment of a FP64 vs mixed comparison split over several runs (default workload 5): "
                          "the FP64 solve for --max-iter iterations, its exact continuation, or the mixed solve")
@@ -868,6 +942,10 @@ def main():
 
     if a.loglik:
         loglik_bench(a.config or 2, a.loglik, quick=a.loglik_quick)
+        return
+
+    if a.loglik_sparse:
+        loglik_sparse_bench(a.config or 2, a.loglik_sparse, dense=not a.no_dense)
         return
 
     if a.cpu_oracle:

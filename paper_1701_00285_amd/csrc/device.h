@@ -55,9 +55,10 @@ int64_t pair_workspace_bytes(int64_t m, int64_t n, int32_t d, int32_t precision,
 using SymTileLaunch = std::function<void(int, int, int, int, double*, double*, double*, double*)>;
 // deterministic tournament schedule over blocks of blk_pts points (pair_sym.hip);
 // rows_summed: the off-diagonal launches write one row partial for all their
-// rounds (slot 0) instead of one per round
+// rounds (slot 0) instead of one per round; diag_splits: column ranges per
+// diagonal tile (0: the default 4; at most 4)
 int sym_schedule(const PairArgs& a, int blk_pts, void* work, hipStream_t s, const SymTileLaunch& fn,
-                 bool rows_summed = false);
+                 bool rows_summed = false, int diag_splits = 0);
 bool sym_supported(int d);
 bool sym_worthwhile(int64_t n);
 int64_t sym_workspace_bytes(int64_t n, int outputs);
@@ -129,6 +130,17 @@ struct CoarseLayout {
   int64_t phi = 0, a = 0, scal = 0, flag = 0, gtab = 0, linv = 0, total = 0, batch = 0;
 };
 CoarseLayout coarse_layout(const Basis& B, int64_t nc);
+// sparse block Cholesky of C~^n_W (sparse_chol.hip): workspace layout (byte offsets) for a host analysis
+struct SparseLayout {
+  int64_t L = 0, linv = 0, psi = 0, zw = 0, scal = 0, zt = 0, y = 0, logd = 0, out = 0, flag = 0, gtab = 0;
+  int64_t w = 0, row0 = 0, ypos = 0, inv_off = 0, sup_beg = 0, sup_cnt = 0, psi_off = 0, col_ptr = 0;
+  int64_t blk_row = 0, blk_col = 0, blk_off = 0, row_ptr = 0, row_col = 0, row_blk = 0, lvl_blks = 0;
+  int64_t lvl_cols = 0, kept = 0, total = 0, nkept = 0;
+};
+SparseLayout sparse_layout(const Basis& B, const SparseSymbolic& S);
+// out = {l~, log det, quadratic form}; MLBLUP_EBREAKDOWN for a pivot that is not positive
+int loglik_sparse_device(const Basis& B, const TransformDev& T, const PairArgs& k, const SparseSymbolic& S,
+                         const double* z, void* work, const SparseLayout& Ly, double out[3], hipStream_t s);
 // Y = G^-T (nc x nc row-major, host) with G G^T = (W C W^T)[c0:c0+nc, c0:c0+nc]
 int coarse_inverse_factor(const Basis& B, const PairArgs& k, int64_t c0, int64_t nc, void* work, int64_t work_bytes,
                           std::vector<double>& Y, hipStream_t s);

@@ -2,6 +2,8 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -93,6 +95,45 @@ struct Pattern {
 };
 int32_t pattern_cells(const Basis& b, int32_t level);
 void build_pattern(const Basis& b, int32_t level, double tau, Pattern& P);
+
+// Block structure of the sparse Cholesky factor of C~^n_W (one block row and
+// column per cell with wavelets at levels >= level), in elimination order
+// (positions 0 .. nc-1), and the cells' wavelet vectors on their points.
+constexpr int32_t kSparseMaxBlock = 64;   // wavelets per cell handled by the block kernels
+struct SparseSymbolic {
+  int32_t level = -1;
+  double tau = 0.0;
+  int32_t nc = 0;                  // block columns
+  int64_t rows = 0;                // N~
+  int64_t kept_entries = 0;        // entries of C~^n_W kept by the pattern
+  int64_t factor_entries = 0;      // doubles of the block factor (full diagonal blocks)
+  double flops = 0.0;              // factorization flops of the block structure
+  std::vector<int32_t> order;      // position -> cell (the pattern's row order of cells)
+  std::vector<int32_t> node;       // position -> basis node
+  std::vector<int32_t> w;          // position -> wavelets (block size)
+  std::vector<int64_t> row0;       // position -> first row of the cell in C^n_W
+  std::vector<int64_t> ypos;       // position -> offset of its block in the position-ordered vectors
+  // blocks, column by column: the diagonal block, then the blocks below in ascending row position;
+  // block b is w[blk_row] x w[blk_col], row-major, at blk_off[b] doubles
+  std::vector<int64_t> col_ptr;
+  std::vector<int32_t> blk_row, blk_col;
+  std::vector<int64_t> blk_off;
+  std::vector<uint8_t> blk_kept;   // 1: a kept block of C~^n_W (assembled); 0: fill (starts at zero)
+  // row structure: for column j, entries row_ptr[j] .. row_ptr[j+1]: earlier column k (ascending)
+  // and the block (j, k)
+  std::vector<int64_t> row_ptr;
+  std::vector<int32_t> row_col;
+  std::vector<int64_t> row_blk;
+  // elimination-tree heights: the columns of height h and their blocks
+  std::vector<int64_t> lvl_ptr;
+  std::vector<int32_t> lvl_cols;
+  std::vector<int64_t> lvl_blk_ptr;
+  std::vector<int64_t> lvl_blks;
+  // wavelet vectors of each position's cell on its points (tree order), |S| x w row-major
+  std::vector<int64_t> psi_off;
+  std::vector<double> psi;
+};
+int sparse_analyse(const Basis& b, int32_t level, double tau, SparseSymbolic& S);
 int64_t basis_device_bytes(const Basis& b);
 
 // exponent tuples of the total-degree set, graded lexicographic
@@ -105,4 +146,7 @@ struct mlblup_tree_s {
 };
 struct mlblup_basis_s {
   mlb::Basis b;
+  // the last sparse analysis (level, tau) of the estimator, reused by later evaluations
+  std::mutex sparse_mu;
+  std::shared_ptr<const mlb::SparseSymbolic> sparse;
 };

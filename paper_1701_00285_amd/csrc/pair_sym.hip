@@ -2,7 +2,8 @@
 // evaluated once and feeds both row sums.
 //
 // Blocks of 256 RL points (tree order; RL = 4 rows per lane for d <= 6,
-// else 2).  A workgroup (4 waves x 64 lanes x RL rows) owns a row block S
+// 3 for d >= 16 in FP64, else 2).  A workgroup (4 waves x 64 lanes x RL
+// rows) owns a row block S
 // and one column block S'.  Column points stream
 // through LDS in chunks of 128; a wave walks each group of 64 columns in 64
 // steps in which lane l evaluates column (l + k*delta) mod 64 of the group
@@ -13,12 +14,18 @@
 // waves' column sums are added in fixed order through LDS.
 //
 // Schedule without atomics: diagonal tiles (S, S) are computed as full
-// squares (row sums only).  Off-diagonal tiles follow a round-robin
+// squares (row sums only), each split over 4 column ranges (2 for RL = 3).  Off-diagonal tiles follow a round-robin
 // tournament: in round r = 1..T/2, block S pairs with (S + r) mod T (for
 // even T the last round keeps S < T/2 only), so in one round every block
 // is a row block at most once and a column block at most once; each round
 // writes one row-partial and one column-partial vector, and the rounds are
 // summed in fixed order.  Results are bitwise reproducible.
+//
+// Squared distances in FP64: from coordinate differences for d < 8; for
+// d >= 8 from |a|^2 + |b|^2 - 2 a.b with both points taken relative to the
+// row block's first point (norms of the column points staged with them in
+// LDS), which halves the per-pair arithmetic of the distance; the few pairs
+// where that form cancels badly are recomputed from the differences.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,11 +38,16 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kChunk = 128; // columns staged per LDS fill
+constexpr int kDiagSplit = 4;  // column ranges of a diagonal tile (one partial slot each)
 
 // rows per lane: 4 for small d (amortises the LDS read and the rotation over
-// more pairs), 2 otherwise; a block holds 256 * RL points
-constexpr int rows_per_lane(int D) { return D <= 6 ? 4 : 2; }
+// more pairs); from d = 8 on the expanded-form FP64 kernel reads d + 2
+// doubles per column step, 3 rows per lane for d >= 16 keep that LDS traffic
+// below the LDS bandwidth; a block holds 256 * RL points
+constexpr int rows_per_lane(int D) { return D <= 6 ? 4 : (D >= 16 ? 3 : 2); }
 constexpr int rows_per_lane_lp(int D) { return D <= 6 ? 4 : 2; }
+// column ranges of a diagonal tile: whole chunks each
+constexpr int diag_split(int RL) { return RL == 3 ? 2 : kDiagSplit; }
 
 template <int D, int NU2, int OUT>
 __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts, const double* __restrict__ x,
@@ -43,9 +55,17 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
                                                  double* __restrict__ prow, double* __restrict__ pcol,
                                                  double* __restrict__ pdrow, double* __restrict__ pdcol,
                                                  const double* __restrict__ gtab) {
-  constexpr int SD = D + 1;
+  // D >= 8: squared distances from the expanded form |a|^2 + |b|^2 - 2 a.b
+  // (D FMAs instead of 2D), coordinates taken relative to the row block's
+  // first point; a pair whose result has lost more than 6 bits to
+  // cancellation (s < |a|^2 + |b|^2 times 2^-6, which includes every self
+  // pair and near neighbour) is recomputed from the coordinate differences
+  constexpr bool kGram = D >= 8;
+  constexpr int SD = kGram ? D + 2 : D + 1;  // coordinates, x (and |b|^2)
   constexpr int RL = rows_per_lane(D);
   constexpr int kBlk = 256 * RL;
+  constexpr double kGuard = 0.015625;
+  static_assert(kBlk % (diag_split(RL) * kChunk) == 0, "a diagonal tile splits into whole chunks");
   __shared__ double cp[kChunk * SD];
   __shared__ double cred[4][kChunk];
   __shared__ double cdred[4][kChunk];
@@ -70,13 +90,19 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
   // lane rotation direction: after one rotation lane l holds lane (l + delta)'s value
   const int delta = (wave_rotate1_i(lane) - lane) & 63;
 
-  double xr[RL][D], ar[RL];
+  // origin of the expanded form: the row block's first point (o < n)
+  const int64_t o = (int64_t)S * kBlk;
+  double xr[RL][D], ar[RL], nx[RL];
 #pragma unroll
   for (int q = 0; q < RL; ++q) {
     const int64_t i = (int64_t)S * kBlk + wave * (64 * RL) + q * 64 + lane;
     const int64_t ii = i < n ? i : n - 1;
+    nx[q] = 0.0;
 #pragma unroll
-    for (int k = 0; k < D; ++k) xr[q][k] = pts[ii * D + k] * zs;
+    for (int k = 0; k < D; ++k) {
+      xr[q][k] = kGram ? (pts[ii * D + k] - pts[o * D + k]) * zs : pts[ii * D + k] * zs;
+      nx[q] = fma(xr[q][k], xr[q][k], nx[q]);
+    }
     ar[q] = i < n ? x[i] : 0.0;
   }
   double racc[RL], rdacc[RL];
@@ -91,11 +117,20 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
     for (int e = tid; e < kChunk * D; e += kT) {
       const int j = e / D, k = e - j * D;
       const int64_t gj = cbase + c0 + j;
-      cp[j * SD + k] = gj < n ? pts[gj * D + k] * zs : 0.0;
+      cp[j * SD + k] = gj < n ? (kGram ? (pts[gj * D + k] - pts[o * D + k]) * zs : pts[gj * D + k] * zs) : 0.0;
     }
     for (int j = tid; j < kChunk; j += kT) {
       const int64_t gj = cbase + c0 + j;
       cp[j * SD + D] = gj < n ? x[gj] : 0.0;
+    }
+    if constexpr (kGram) {
+      __syncthreads();
+      for (int j = tid; j < kChunk; j += kT) {
+        double nb = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) nb = fma(cp[j * SD + k], cp[j * SD + k], nb);
+        cp[j * SD + D + 1] = nb;
+      }
     }
     __syncthreads();
 #pragma unroll 1
@@ -112,11 +147,28 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
         double cpart = 0.0, cdpart = 0.0;
 #pragma unroll
         for (int q = 0; q < RL; ++q) {
-          double s = 1e-300;
+          double s;
+          if constexpr (kGram) {
+            double g = 0.0;
 #pragma unroll
-          for (int t = 0; t < D; ++t) {
-            const double u = xr[q][t] - cv[t];
-            s = fma(u, u, s);
+            for (int t = 0; t < D; ++t) g = fma(xr[q][t], cv[t], g);
+            const double tt = nx[q] + cj[D + 1];
+            s = fma(-2.0, g, tt);
+            if (!(s > kGuard * tt)) {
+              s = 1e-300;
+#pragma unroll
+              for (int t = 0; t < D; ++t) {
+                const double u = xr[q][t] - cv[t];
+                s = fma(u, u, s);
+              }
+            }
+          } else {
+            s = 1e-300;
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+              const double u = xr[q][t] - cv[t];
+              s = fma(u, u, s);
+            }
           }
           double f = 0.0, g = 0.0;
           pair_value<NU2, OUT, false>(s, tab, f, g, gt);
@@ -185,16 +237,13 @@ __global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ p
   const int delta = (wave_rotate1_i(lane) - lane) & 63;
 
   const int64_t o = (int64_t)S * kBlk;  // first point of the row block (o < n)
-  double org[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) org[k] = pts[o * D + k];
   float xr[RL][D], ar[RL];
 #pragma unroll
   for (int q = 0; q < RL; ++q) {
     const int64_t i = o + wave * (64 * RL) + q * 64 + lane;
     const int64_t ii = i < n ? i : n - 1;
 #pragma unroll
-    for (int k = 0; k < D; ++k) xr[q][k] = (float)((pts[ii * D + k] - org[k]) * ws);
+    for (int k = 0; k < D; ++k) xr[q][k] = (float)((pts[ii * D + k] - pts[o * D + k]) * ws);
     ar[q] = i < n ? (float)x[i] : 0.0f;
   }
   double racc[RL], rdacc[RL];
@@ -208,7 +257,7 @@ __global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ p
     for (int e = tid; e < kChunk * D; e += kT) {
       const int j = e / D, k = e - j * D;
       const int64_t gj = cbase + c0 + j;
-      cp[j * SP + k] = gj < n ? (float)((pts[gj * D + k] - org[k]) * ws) : 0.0f;
+      cp[j * SP + k] = gj < n ? (float)((pts[gj * D + k] - pts[o * D + k]) * ws) : 0.0f;
     }
     for (int j = tid; j < kChunk; j += kT) {
       const int64_t gj = cbase + c0 + j;
@@ -359,7 +408,6 @@ LaunchFn pick_nu(int nu2, int out, int d) {
 }
 
 constexpr int kRoundsPerLaunch = 16;
-constexpr int kDiagSplit = 4;
 
 __global__ __launch_bounds__(kT) void sum_slots(const double* __restrict__ slots, int k, int64_t n,
                                                 double* __restrict__ acc) {
@@ -384,7 +432,8 @@ int64_t sym_workspace_bytes(int64_t n, int outputs) {
 }
 
 int sym_schedule(const PairArgs& a, int blk_pts, void* work, hipStream_t s, const SymTileLaunch& fn,
-                 bool rows_summed) {
+                 bool rows_summed, int diag_splits) {
+  const int nsplit = diag_splits > 0 ? std::min(diag_splits, kDiagSplit) : kDiagSplit;
   const int64_t n = a.n;
   const int T = (int)((n + blk_pts - 1) / blk_pts);
   const int64_t per = ((int64_t)(2 * kRoundsPerLaunch + 1 + kDiagSplit) * n * 8 + 255) / 256 * 256;
@@ -401,10 +450,10 @@ int sym_schedule(const PairArgs& a, int blk_pts, void* work, hipStream_t s, cons
   parts(base_v, vs, vd, vr, vc);
   parts(base_d, ds, dd, dr, dc);
   const unsigned g = (unsigned)((n + kT - 1) / kT);
-  // diagonal tiles, each split over kDiagSplit column ranges
-  fn(T, 0, kDiagSplit, 1, vs, nullptr, ds, nullptr);
-  if (a.outputs & 1) hipLaunchKernelGGL(sum_slots, dim3(g), dim3(kT), 0, s, vs, kDiagSplit, n, vd);
-  if (a.outputs & 2) hipLaunchKernelGGL(sum_slots, dim3(g), dim3(kT), 0, s, ds, kDiagSplit, n, dd);
+  // diagonal tiles, each split over nsplit column ranges
+  fn(T, 0, nsplit, 1, vs, nullptr, ds, nullptr);
+  if (a.outputs & 1) hipLaunchKernelGGL(sum_slots, dim3(g), dim3(kT), 0, s, vs, nsplit, n, vd);
+  if (a.outputs & 2) hipLaunchKernelGGL(sum_slots, dim3(g), dim3(kT), 0, s, ds, nsplit, n, dd);
   const int rounds = T / 2;
   int r0 = 1;
   do {
@@ -426,11 +475,13 @@ int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s) {
   const bool f32 = a.precision != MLBLUP_FP64;
   LaunchFn fn = f32 ? pick_nu<true>(a.nu2, a.outputs, a.d) : pick_nu<false>(a.nu2, a.outputs, a.d);
   if (!fn) return fail(MLBLUP_EINVAL, "symmetric pair kernel: dimension not compiled");
-  const int blk = 256 * (f32 ? rows_per_lane_lp(a.d) : rows_per_lane(a.d));
-  return sym_schedule(a, blk, work, s,
-                      [&](int T, int r0, int nr, int diag, double* prow, double* pcol, double* pdrow, double* pdcol) {
-                        fn(a.cols, a.x, a.n, T, r0, nr, diag, zs, prow, pcol, pdrow, pdcol, a.gtab, s);
-                      });
+  const int rl = f32 ? rows_per_lane_lp(a.d) : rows_per_lane(a.d);
+  return sym_schedule(
+      a, 256 * rl, work, s,
+      [&](int T, int r0, int nr, int diag, double* prow, double* pcol, double* pdrow, double* pdcol) {
+        fn(a.cols, a.x, a.n, T, r0, nr, diag, zs, prow, pcol, pdrow, pdcol, a.gtab, s);
+      },
+      false, diag_split(rl));
 }
 
 }  // namespace mlb

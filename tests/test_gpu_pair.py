@@ -149,6 +149,43 @@ def test_symmetric_square_product(n, d):
             assert row_relerr(host(yr), host(y1), host(full_scale)) < 2 * tol
 
 
+@pytest.mark.parametrize("d", [8, 12, 20])
+def test_symmetric_expanded_distance_near_pairs(d):
+    """From d = 8 on the FP64 square product forms squared distances as
+    |a|^2 + |b|^2 - 2 a.b relative to each row block's first point and
+    recomputes the pairs where that form cancels.  Points in tight clusters
+    (spreads 1e-7 .. 1e-2) around centres far apart, shuffled so that most
+    near pairs sit far from their block's first point, plus exact duplicates:
+    the cancelling pairs are many and must still match the oracle to the
+    FP64 tolerance, duplicates giving phi(0) exactly."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import DLOGRHO, FP64, VALUE, cov_matvec
+    g = np.random.default_rng(300 + d)
+    n, nc = 16896, 48
+    centres = 4.0 * g.random((nc, d))
+    lab = g.integers(0, nc, n)
+    spread = np.array([1e-7, 1e-5, 1e-3, 1e-2])[lab % 4]
+    pts = centres[lab] + spread[:, None] * g.standard_normal((n, d))
+    dup = g.choice(n, 800, replace=False)
+    pts[dup[:400]] = pts[dup[400:]]
+    x = synth.standard_normal(n, 301 + d)
+    say(f"expanded distance near pairs n={n} d={d}")
+    idx = np.unique(np.concatenate([np.arange(0, n, n // 48), dup[:40], dup[400:440]]))
+    P, X = dev(pts), dev(x)
+    for nu in (0.5, 2.5, np.inf):
+        rho = 0.02 if nu == np.inf else 0.05
+        ref = brute.cov_matvec(pts[idx], pts, x, nu, rho, 1.0)
+        dref = brute.cov_matvec(pts[idx], pts, x, nu, rho, 1.0, deriv=True)
+        sc = _scale(pts[idx], pts, x, nu, rho)
+        y, dy = cov_matvec(P, P, X, nu, rho, 1.0, precision=FP64, outputs=VALUE | DLOGRHO)
+        assert row_relerr(host(y)[idx], ref, sc) < FP64_TOL, nu
+        assert row_relerr(host(dy)[idx], dref, sc) < FP64_TOL, nu
+        # against the row-tiled path (differences throughout) on every row
+        yr, _ = cov_matvec(P, P.clone(), X, nu, rho, 1.0, precision=FP64)
+        full_scale, _ = cov_matvec(P, P.clone(), torch.abs(X), nu, rho, 1.0, precision=FP64)
+        assert row_relerr(host(y), host(yr), host(full_scale)) < 2 * FP64_TOL, nu
+
+
 @pytest.mark.parametrize("d", [8, 10, 16, 20, 25])
 @pytest.mark.parametrize("square", [False, True])
 def test_matrix_core_gram(d, square):
