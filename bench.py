@@ -370,7 +370,8 @@ def loglik_bench(k: int, n: int, reps: int = 3, quick: bool = False):
     print(json.dumps(res), flush=True)
 
 
-def loglik_sparse_bench(k: int, n: int, reps: int = 3, dense: bool = True):
+def loglik_sparse_bench(k: int, n: int, reps: int = 3, dense: bool = True, nu: float = 0.0, rho: float = 0.0,
+                        taus=(0.02, 0.05, 0.1)):
     """Estimator with the sparse block factorization: l~_n at levels t and
     t - 1 for several tau, only the kept blocks formed and factored (host
     analysis timed on its own: pattern, minimum-degree order, block
@@ -389,15 +390,17 @@ def loglik_sparse_bench(k: int, n: int, reps: int = 3, dense: bool = True):
     from paper_1701_00285_amd import MlblupError, Solver
     torch.cuda.set_device(0)
     wl = synth.make_config(k, n=n, n_targets=1)
+    nu = nu or wl.nu
+    rho = rho or wl.rho
     t0 = time.perf_counter()
-    s = Solver(wl.points, wl.degree_w, wl.leaf_max, wl.nu, wl.rho, wl.sigma2)
+    s = Solver(wl.points, wl.degree_w, wl.leaf_max, nu, rho, wl.sigma2)
     setup = time.perf_counter() - t0
     z = torch.as_tensor(wl.z, dtype=torch.float64, device="cuda")
     top = s.basis.levels - 1
-    res = {"workload": f"cfg{k} generator, n={n}, d={wl.d}, nu={wl.nu}, rho={wl.rho}, leaf={wl.leaf_max}, "
+    res = {"workload": f"cfg{k} generator, n={n}, d={wl.d}, nu={nu}, rho={rho}, leaf={wl.leaf_max}, "
                        f"p={s.p}", "setup_s": round(setup, 3), "cases": {}}
     for level in (top, top - 1):
-        for tau in (0.02, 0.05, 0.1):
+        for tau in taus:
             key = f"level {level} tau {tau}"
             t0 = time.perf_counter()
             info = s.loglik_sparse_info(level, tau)
@@ -918,6 +921,9 @@ def main():
     ap.add_argument("--loglik-sparse", type=int, default=0,
                     help="estimator with the sparse block factorization of the kept blocks: levels t and t - 1, "
                          "several tau, on this many points of the workload's generator (one JSON line)")
+    ap.add_argument("--rho", type=float, default=0.0,
+                    help="with --loglik-sparse: range of the covariance (default: the workload's)")
+    ap.add_argument("--taus", default="0.02,0.05,0.1", help="with --loglik-sparse: comma-separated tau values")
     ap.add_argument("--no-dense", action="store_true",
                     help="with --loglik-sparse: skip the dense sparsified path beside it (large n)")
     ap.add_argument("--segment", choices=("fp64-start", "fp64-resume", "mixed"), default=None,
@@ -945,7 +951,8 @@ def main():
         return
 
     if a.loglik_sparse:
-        loglik_sparse_bench(a.config or 2, a.loglik_sparse, dense=not a.no_dense)
+        loglik_sparse_bench(a.config or 2, a.loglik_sparse, dense=not a.no_dense, nu=a.nu, rho=a.rho,
+                            taus=tuple(float(v) for v in a.taus.split(",")))
         return
 
     if a.cpu_oracle:

@@ -348,6 +348,45 @@ int mlblup_blup_predict_dd(mlblup_basis b, const mlblup_matern* k, const double*
 int mlblup_loglik_workspace_bytes(mlblup_basis b, int32_t level, int64_t* bytes, int64_t* rows);
 int mlblup_loglik(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double tau,
                   double* out4_host, void* work_dev, int64_t work_bytes, void* stream);
+/* ---- estimator with the sparse factorization (Sec. 4.1 kept blocks; Sec. 6.1) ----
+ * The same l (or l~ for a finite tau) as mlblup_loglik, computed without any
+ * N x N or N~ x N~ array: only the blocks of C~^n_W that the tree search
+ * keeps (the rule of mlblup_loglik) are formed, each block of two cells
+ * B_a, B_b as Psi_a^T C(B_a, B_b) Psi_b from the cells' wavelet vectors on
+ * their points, and the matrix is factored by a block Cholesky over the
+ * cells (one block row and column per cell with wavelets at levels >=
+ * level; a minimum-degree order of the cell graph, the fill blocks that
+ * order creates, left-looking updates scheduled by elimination-tree
+ * height), with Z^n_W as a border row for the quadratic form.  Cost and
+ * storage follow the kept blocks and their fill, so a small tau makes it
+ * cheap; tau = INFINITY factors the whole C^n_W block by block (use
+ * mlblup_loglik there).  Every cell may own at most 64 wavelets: leaves of
+ * at most 64 points and a trend dimension p <= 64 (else MLBLUP_EINVAL).
+ * The analysis (pattern, order, block structure, wavelet vectors) is built
+ * on the host on the first call for a (level, tau) and kept with the basis
+ * for the following calls with the same pair.
+ * mlblup_loglik_sparse_workspace_bytes: *bytes of device workspace;
+ * info6_host (may be NULL) = {N~, kept entries of C~^n_W, doubles of the
+ * block factor (with its fill), block columns, elimination-tree heights,
+ * factorization flops}.  No device access.
+ * mlblup_loglik_sparse: z_dev N data values in tree order; out4_host = {l,
+ * log det, quadratic form, kept entries}.  Synchronises `stream`.
+ * MLBLUP_EINVAL as for mlblup_loglik or for a cell with more than 64
+ * wavelets; MLBLUP_EBREAKDOWN if a pivot is not positive. */
+int mlblup_loglik_sparse_workspace_bytes(mlblup_basis b, int32_t level, double tau, int64_t* bytes,
+                                         double* info6_host);
+int mlblup_loglik_sparse(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double tau,
+                         double* out4_host, void* work_dev, int64_t work_bytes, void* stream);
+/* mlblup_mle_rho and mlblup_mle_nu_rho with every evaluation of l~ by
+ * mlblup_loglik_sparse (same arguments and outputs; the workspace is that of
+ * mlblup_loglik_sparse_workspace_bytes for (level, tau); the analysis is built
+ * once). */
+int mlblup_mle_rho_sparse(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double tau,
+                          double rho_lo, double rho_hi, double log_rho_tol, double* out4_host, void* work_dev,
+                          int64_t work_bytes, void* stream);
+int mlblup_mle_nu_rho_sparse(mlblup_basis b, double sigma2, const double* z_dev, int32_t level, double tau,
+                             double nu_lo, double nu_hi, double nu_tol, double rho_lo, double rho_hi,
+                             double log_rho_tol, double* out5_host, void* work_dev, int64_t work_bytes, void* stream);
 /* The pattern of C~^n_W for the given level and tau (Sec. 4.1 search, the
  * rule of mlblup_loglik), on the host: *nnz = kept entries; mask_host (may be
  * NULL) receives the N~ x N~ row-major 0/1 matrix in the row order of

@@ -84,6 +84,12 @@ _SIGS = {
                                          _I64, _P]),
     "mlblup_loglik_workspace_bytes": (C.c_int, [_P, _I32, C.POINTER(_I64), C.POINTER(_I64)]),
     "mlblup_loglik": (C.c_int, [_P, C.POINTER(Matern), _P, _I32, C.c_double, _P, _P, _I64, _P]),
+    "mlblup_loglik_sparse_workspace_bytes": (C.c_int, [_P, _I32, C.c_double, C.POINTER(_I64), _P]),
+    "mlblup_loglik_sparse": (C.c_int, [_P, C.POINTER(Matern), _P, _I32, C.c_double, _P, _P, _I64, _P]),
+    "mlblup_mle_rho_sparse": (C.c_int, [_P, C.POINTER(Matern), _P, _I32, C.c_double, C.c_double, C.c_double,
+                                        C.c_double, _P, _P, _I64, _P]),
+    "mlblup_mle_nu_rho_sparse": (C.c_int, [_P, C.c_double, _P, _I32, C.c_double, C.c_double, C.c_double,
+                                           C.c_double, C.c_double, C.c_double, C.c_double, _P, _P, _I64, _P]),
     "mlblup_sparsity_pattern": (C.c_int, [_P, _I32, C.c_double, C.POINTER(_I64), _P]),
     "mlblup_mle_rho": (C.c_int, [_P, C.POINTER(Matern), _P, _I32, C.c_double, C.c_double, C.c_double, C.c_double, _P,
                                  _P, _I64, _P]),

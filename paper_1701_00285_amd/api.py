@@ -368,28 +368,65 @@ class Solver:
                                     _ptr(ws), ws.numel(), _stream()))
         return dict(loglik=out[0], logdet=out[1], quad=out[2], rows=self.loglik_workspace(level)[1], nnz=int(out[3]))
 
-    def mle_rho(self, z, level, rho_lo, rho_hi, log_rho_tol=1e-6, nu=None, tau=math.inf):
-        """Maximum-likelihood rho of the level's log-likelihood (golden
-        section on log rho): dict(rho, loglik, evals, bracket)."""
-        k = matern(self.nu if nu is None else nu, 1.0, self.sigma2)
-        ws = self._loglik_ws(level)
+    def loglik_sparse_info(self, level, tau):
+        """Sparse factorization of C~^n_W at (level, tau): dict(bytes, rows=N~,
+        kept, factor_entries, block_columns, heights, flops)."""
+        b = C.c_int64()
+        info = np.zeros(6)
+        check(L.lib().mlblup_loglik_sparse_workspace_bytes(self.basis.h, int(level), float(tau), C.byref(b),
+                                                           _np_ptr(info)))
+        return dict(bytes=b.value, rows=int(info[0]), kept=int(info[1]), factor_entries=int(info[2]),
+                    block_columns=int(info[3]), heights=int(info[4]), flops=float(info[5]))
+
+    def loglik_sparse(self, z, level, tau, rho=None, nu=None):
+        """The log-likelihood of loglik() with the sparse block factorization
+        of the kept blocks of C~^n_W (no N x N array): dict(loglik, logdet,
+        quad, rows=N~, nnz=kept entries)."""
+        k = self.kernel(rho)
+        if nu is not None:
+            k = matern(nu, k.rho, k.sigma2)
+        info = self.loglik_sparse_info(level, tau)
+        ws = self._sparse_ws(level, tau)
         out = np.zeros(4)
         zt = self.to_tree(z).contiguous()
-        check(L.lib().mlblup_mle_rho(self.basis.h, C.byref(k), _ptr(zt), int(level), float(tau), float(rho_lo),
-                                     float(rho_hi), float(log_rho_tol), _np_ptr(out), _ptr(ws), ws.numel(),
-                                     _stream()))
+        check(L.lib().mlblup_loglik_sparse(self.basis.h, C.byref(k), _ptr(zt), int(level), float(tau), _np_ptr(out),
+                                           _ptr(ws), ws.numel(), _stream()))
+        return dict(loglik=out[0], logdet=out[1], quad=out[2], rows=info["rows"], nnz=int(out[3]))
+
+    def _sparse_ws(self, level, tau):
+        torch = _torch()
+        need = self.loglik_sparse_info(level, tau)["bytes"]
+        ws = getattr(self, "_spws", None)
+        if ws is None or ws.numel() < need:
+            self._spws = None
+            ws = self._spws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return ws
+
+    def mle_rho(self, z, level, rho_lo, rho_hi, log_rho_tol=1e-6, nu=None, tau=math.inf, sparse=False):
+        """Maximum-likelihood rho of the level's log-likelihood (golden
+        section on log rho): dict(rho, loglik, evals, bracket).  sparse: each
+        evaluation by the sparse block factorization (finite tau)."""
+        k = matern(self.nu if nu is None else nu, 1.0, self.sigma2)
+        ws = self._sparse_ws(level, tau) if sparse else self._loglik_ws(level)
+        fn = L.lib().mlblup_mle_rho_sparse if sparse else L.lib().mlblup_mle_rho
+        out = np.zeros(4)
+        zt = self.to_tree(z).contiguous()
+        check(fn(self.basis.h, C.byref(k), _ptr(zt), int(level), float(tau), float(rho_lo), float(rho_hi),
+                 float(log_rho_tol), _np_ptr(out), _ptr(ws), ws.numel(), _stream()))
         return dict(rho=out[0], loglik=out[1], evals=int(out[2]), bracket=out[3])
 
-    def mle_nu_rho(self, z, level, nu_lo, nu_hi, rho_lo, rho_hi, nu_tol=1e-3, log_rho_tol=1e-4, tau=math.inf):
+    def mle_nu_rho(self, z, level, nu_lo, nu_hi, rho_lo, rho_hi, nu_tol=1e-3, log_rho_tol=1e-4, tau=math.inf,
+                   sparse=False):
         """Maximum-likelihood (nu, rho) of the level's log-likelihood by the
         profile likelihood (golden section over nu, each point the rho MLE):
-        dict(nu, rho, loglik, evals, bracket)."""
-        ws = self._loglik_ws(level)
+        dict(nu, rho, loglik, evals, bracket).  sparse: as in mle_rho."""
+        ws = self._sparse_ws(level, tau) if sparse else self._loglik_ws(level)
+        fn = L.lib().mlblup_mle_nu_rho_sparse if sparse else L.lib().mlblup_mle_nu_rho
         out = np.zeros(5)
         zt = self.to_tree(z).contiguous()
-        check(L.lib().mlblup_mle_nu_rho(self.basis.h, float(self.sigma2), _ptr(zt), int(level), float(tau),
-                                        float(nu_lo), float(nu_hi), float(nu_tol), float(rho_lo), float(rho_hi),
-                                        float(log_rho_tol), _np_ptr(out), _ptr(ws), ws.numel(), _stream()))
+        check(fn(self.basis.h, float(self.sigma2), _ptr(zt), int(level), float(tau), float(nu_lo), float(nu_hi),
+                 float(nu_tol), float(rho_lo), float(rho_hi), float(log_rho_tol), _np_ptr(out), _ptr(ws), ws.numel(),
+                 _stream()))
         return dict(nu=out[0], rho=out[1], loglik=out[2], evals=int(out[3]), bracket=out[4])
 
     # ---- solve / predict / grad ----

@@ -21,7 +21,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmlblup.so")
 SOURCES = ["tree.cpp", "basis.cpp", "sparsify.cpp", "abi.cpp", "precond_host.cpp", "genu.cpp", "ops.hip", "pair.hip", "pair_sym.hip", "precond.hip",
-           "pair_mfma.hip", "loglik.hip", "dd.hip"]
+           "pair_mfma.hip", "loglik.hip", "dd.hip", "sparse_chol.cpp", "sparse_chol.hip"]
 
 
 def hipcc() -> str:

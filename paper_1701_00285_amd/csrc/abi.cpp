@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <new>
 #include <string>
@@ -1105,54 +1106,100 @@ int mlblup_loglik(mlblup_basis b, const mlblup_matern* k, const double* z_dev, i
   return MLBLUP_OK;
 }
 
-int mlblup_mle_rho(mlblup_basis b, const mlblup_matern* k0, const double* z_dev, int32_t level, double tau,
-                   double rho_lo, double rho_hi, double log_rho_tol, double* out4_host, void* work_dev,
-                   int64_t work_bytes, void* stream) {
-  clear_error();
-  if (!out4_host) return fail(MLBLUP_EINVAL, "mle_rho: NULL output");
-  if (!(rho_lo > 0) || !(rho_hi > rho_lo) || !std::isfinite(rho_hi))
-    return fail(MLBLUP_EINVAL, "mle_rho: need 0 < rho_lo < rho_hi < inf");
-  if (!(log_rho_tol > 0)) return fail(MLBLUP_EINVAL, "mle_rho: log_rho_tol must be > 0");
-  TransformDev T;
-  LoglikLayout L;
-  PairArgs a;
-  int64_t nnz = 0;
-  int st = loglik_common(b, k0, z_dev, level, tau, work_dev, work_bytes, &T, &L, &a, &nnz, (hipStream_t)stream);
+// the sparse analysis of (level, tau), from the basis' cache or built now
+static int sparse_symbolic(mlblup_basis b, int32_t level, double tau, std::shared_ptr<const SparseSymbolic>* out) {
+  std::lock_guard<std::mutex> g(b->sparse_mu);
+  const bool same_tau = (std::isinf(tau) && b->sparse && std::isinf(b->sparse->tau)) || (b->sparse && b->sparse->tau == tau);
+  if (b->sparse && b->sparse->level == level && same_tau) {
+    *out = b->sparse;
+    return MLBLUP_OK;
+  }
+  auto S = std::make_shared<SparseSymbolic>();
+  const int st = sparse_analyse(b->b, level, tau, *S);
   if (st) return st;
-  const bool masked = std::isfinite(tau);
-  int evals = 0;
-  auto f = [&](double lr, double* v) {
-    PairArgs q = a;
-    q.rho = std::exp(lr);
-    double out[3];
-    const int s2 = loglik_device(b->b, T, q, level, z_dev, work_dev, L, masked, out, (hipStream_t)stream);
-    ++evals;
-    *v = out[0];
-    return s2;
-  };
-  // golden-section search for the maximum of l_n on [log rho_lo, log rho_hi]
+  b->sparse = S;
+  *out = S;
+  return MLBLUP_OK;
+}
+
+int mlblup_loglik_sparse_workspace_bytes(mlblup_basis b, int32_t level, double tau, int64_t* bytes,
+                                         double* info6_host) {
+  clear_error();
+  if (!b || !bytes) return fail(MLBLUP_EINVAL, "NULL argument");
+  if (level < 0 || level >= b->b.levels)
+    return fail(MLBLUP_EINVAL, "sparse loglik: level must be in [0, " + std::to_string(b->b.levels - 1) + "]");
+  if (!(tau >= 0)) return fail(MLBLUP_EINVAL, "sparse loglik: tau must be >= 0 (inf = no sparsification)");
+  std::shared_ptr<const SparseSymbolic> S;
+  int st = sparse_symbolic(b, level, tau, &S);
+  if (st) return st;
+  *bytes = sparse_layout(b->b, *S).total;
+  if (info6_host) {
+    info6_host[0] = (double)S->rows;
+    info6_host[1] = (double)S->kept_entries;
+    info6_host[2] = (double)S->factor_entries;
+    info6_host[3] = (double)S->nc;
+    info6_host[4] = S->lvl_ptr.empty() ? 0.0 : (double)(S->lvl_ptr.size() - 1);
+    info6_host[5] = S->flops;
+  }
+  return MLBLUP_OK;
+}
+
+int mlblup_loglik_sparse(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double tau,
+                         double* out4_host, void* work_dev, int64_t work_bytes, void* stream) {
+  clear_error();
+  if (!out4_host) return fail(MLBLUP_EINVAL, "sparse loglik: NULL output");
+  int st = check_basis_dev(b);
+  if (st) return st;
+  if ((st = check_kernel(k))) return st;
+  const Basis& B = b->b;
+  if (level < 0 || level >= B.levels)
+    return fail(MLBLUP_EINVAL, "sparse loglik: level must be in [0, " + std::to_string(B.levels - 1) + "]");
+  if (!(tau >= 0)) return fail(MLBLUP_EINVAL, "sparse loglik: tau must be >= 0 (inf = no sparsification)");
+  if (!z_dev) return fail(MLBLUP_EINVAL, "sparse loglik: NULL data vector");
+  std::shared_ptr<const SparseSymbolic> S;
+  if ((st = sparse_symbolic(b, level, tau, &S))) return st;
+  const SparseLayout Ly = sparse_layout(B, *S);
+  if (!work_dev || work_bytes < Ly.total)
+    return fail(MLBLUP_EINVAL, "sparse loglik: workspace too small (need " + std::to_string(Ly.total) + " bytes)");
+  const TransformDev T = transform_dev(B);
+  const PairArgs a{nullptr, 0, nullptr, B.n, B.d, nu2_of(k), k->rho, k->sigma2, MLBLUP_FP64, MLBLUP_VALUE,
+                   nullptr, nullptr, nullptr, k->nu, nullptr};
+  if ((st = loglik_sparse_device(B, T, a, *S, z_dev, work_dev, Ly, out4_host, (hipStream_t)stream))) return st;
+  out4_host[3] = (double)S->kept_entries;
+  return MLBLUP_OK;
+}
+
+// golden-section search for the maximum of f(log rho) on [log rho_lo, log rho_hi]
+static int golden_log_rho(const std::function<int(double, double*)>& f, double rho_lo, double rho_hi,
+                          double log_rho_tol, double* out4_host) {
   const double g = 0.6180339887498949;
+  int evals = 0;
+  auto ev = [&](double x, double* v) {
+    ++evals;
+    return f(x, v);
+  };
   double lo = std::log(rho_lo), hi = std::log(rho_hi);
   double x1 = hi - g * (hi - lo), x2 = lo + g * (hi - lo), f1, f2;
-  if ((st = f(x1, &f1)) || (st = f(x2, &f2))) return st;
+  int st;
+  if ((st = ev(x1, &f1)) || (st = ev(x2, &f2))) return st;
   while (hi - lo > log_rho_tol) {
     if (f1 >= f2) {
       hi = x2;
       x2 = x1;
       f2 = f1;
       x1 = hi - g * (hi - lo);
-      if ((st = f(x1, &f1))) return st;
+      if ((st = ev(x1, &f1))) return st;
     } else {
       lo = x1;
       x1 = x2;
       f1 = f2;
       x2 = lo + g * (hi - lo);
-      if ((st = f(x2, &f2))) return st;
+      if ((st = ev(x2, &f2))) return st;
     }
   }
   const double lr = 0.5 * (lo + hi);
   double fm;
-  if ((st = f(lr, &fm))) return st;
+  if ((st = ev(lr, &fm))) return st;
   out4_host[0] = std::exp(lr);
   out4_host[1] = fm;
   out4_host[2] = (double)evals;
@@ -1160,21 +1207,71 @@ int mlblup_mle_rho(mlblup_basis b, const mlblup_matern* k0, const double* z_dev,
   return MLBLUP_OK;
 }
 
-int mlblup_mle_nu_rho(mlblup_basis b, double sigma2, const double* z_dev, int32_t level, double tau, double nu_lo,
-                      double nu_hi, double nu_tol, double rho_lo, double rho_hi, double log_rho_tol,
-                      double* out5_host, void* work_dev, int64_t work_bytes, void* stream) {
+static int check_mle_rho_args(const double* out4_host, double rho_lo, double rho_hi, double log_rho_tol) {
+  if (!out4_host) return fail(MLBLUP_EINVAL, "mle_rho: NULL output");
+  if (!(rho_lo > 0) || !(rho_hi > rho_lo) || !std::isfinite(rho_hi))
+    return fail(MLBLUP_EINVAL, "mle_rho: need 0 < rho_lo < rho_hi < inf");
+  if (!(log_rho_tol > 0)) return fail(MLBLUP_EINVAL, "mle_rho: log_rho_tol must be > 0");
+  return MLBLUP_OK;
+}
+
+int mlblup_mle_rho(mlblup_basis b, const mlblup_matern* k0, const double* z_dev, int32_t level, double tau,
+                   double rho_lo, double rho_hi, double log_rho_tol, double* out4_host, void* work_dev,
+                   int64_t work_bytes, void* stream) {
   clear_error();
+  int st = check_mle_rho_args(out4_host, rho_lo, rho_hi, log_rho_tol);
+  if (st) return st;
+  TransformDev T;
+  LoglikLayout L;
+  PairArgs a;
+  int64_t nnz = 0;
+  if ((st = loglik_common(b, k0, z_dev, level, tau, work_dev, work_bytes, &T, &L, &a, &nnz, (hipStream_t)stream)))
+    return st;
+  const bool masked = std::isfinite(tau);
+  return golden_log_rho(
+      [&](double lr, double* v) {
+        PairArgs q = a;
+        q.rho = std::exp(lr);
+        double out[3];
+        const int s2 = loglik_device(b->b, T, q, level, z_dev, work_dev, L, masked, out, (hipStream_t)stream);
+        *v = out[0];
+        return s2;
+      },
+      rho_lo, rho_hi, log_rho_tol, out4_host);
+}
+
+int mlblup_mle_rho_sparse(mlblup_basis b, const mlblup_matern* k0, const double* z_dev, int32_t level, double tau,
+                          double rho_lo, double rho_hi, double log_rho_tol, double* out4_host, void* work_dev,
+                          int64_t work_bytes, void* stream) {
+  clear_error();
+  int st = check_mle_rho_args(out4_host, rho_lo, rho_hi, log_rho_tol);
+  if (st) return st;
+  if (!k0) return fail(MLBLUP_EINVAL, "mle_rho: NULL kernel");
+  // every evaluation validates its arguments; the analysis of (level, tau) is built once
+  const mlblup_matern k = *k0;
+  return golden_log_rho(
+      [&](double lr, double* v) {
+        mlblup_matern q = k;
+        q.rho = std::exp(lr);
+        double out[4];
+        const int s2 = mlblup_loglik_sparse(b, &q, z_dev, level, tau, out, work_dev, work_bytes, stream);
+        *v = out[0];
+        return s2;
+      },
+      rho_lo, rho_hi, log_rho_tol, out4_host);
+}
+
+// profile likelihood over nu: golden section, each point the rho maximum of `mle`
+static int golden_nu(const std::function<int(const mlblup_matern*, double*)>& mle, double sigma2, double nu_lo,
+                     double nu_hi, double nu_tol, double* out5_host) {
   if (!out5_host) return fail(MLBLUP_EINVAL, "mle_nu_rho: NULL output");
   if (!(nu_lo > 0) || !(nu_hi > nu_lo) || nu_hi > 8.0) return fail(MLBLUP_EINVAL, "mle_nu_rho: need 0 < nu_lo < nu_hi <= 8");
   if (!(nu_tol > 0)) return fail(MLBLUP_EINVAL, "mle_nu_rho: nu_tol must be > 0");
-  // profile likelihood: for each nu the rho MLE (golden section on log rho),
-  // then golden section over nu on that profile
   int evals = 0;
   auto profile = [&](double nu, double* val, double* rho) {
     const mlblup_matern k{nu, 1.0, sigma2};
     double o[4];
-    const int s2 =
-        mlblup_mle_rho(b, &k, z_dev, level, tau, rho_lo, rho_hi, log_rho_tol, o, work_dev, work_bytes, stream);
+    const int s2 = mle(&k, o);
     if (s2) return s2;
     evals += (int)o[2];
     *rho = o[0];
@@ -1212,6 +1309,29 @@ int mlblup_mle_nu_rho(mlblup_basis b, double sigma2, const double* z_dev, int32_
   out5_host[3] = (double)evals;
   out5_host[4] = hi - lo;
   return MLBLUP_OK;
+}
+
+int mlblup_mle_nu_rho(mlblup_basis b, double sigma2, const double* z_dev, int32_t level, double tau, double nu_lo,
+                      double nu_hi, double nu_tol, double rho_lo, double rho_hi, double log_rho_tol,
+                      double* out5_host, void* work_dev, int64_t work_bytes, void* stream) {
+  clear_error();
+  return golden_nu(
+      [&](const mlblup_matern* k, double* o) {
+        return mlblup_mle_rho(b, k, z_dev, level, tau, rho_lo, rho_hi, log_rho_tol, o, work_dev, work_bytes, stream);
+      },
+      sigma2, nu_lo, nu_hi, nu_tol, out5_host);
+}
+
+int mlblup_mle_nu_rho_sparse(mlblup_basis b, double sigma2, const double* z_dev, int32_t level, double tau,
+                             double nu_lo, double nu_hi, double nu_tol, double rho_lo, double rho_hi,
+                             double log_rho_tol, double* out5_host, void* work_dev, int64_t work_bytes, void* stream) {
+  clear_error();
+  return golden_nu(
+      [&](const mlblup_matern* k, double* o) {
+        return mlblup_mle_rho_sparse(b, k, z_dev, level, tau, rho_lo, rho_hi, log_rho_tol, o, work_dev, work_bytes,
+                                     stream);
+      },
+      sigma2, nu_lo, nu_hi, nu_tol, out5_host);
 }
 
 }  // extern "C"

@@ -222,3 +222,139 @@ def test_sparsified_mle_nu_rho_matches_oracle():
     assert abs(g["nu"] - o[0]) < 2e-2
     assert abs(math.log(g["rho"]) - math.log(o[1])) < 5e-3
     assert abs(g["loglik"] - o[2]) < 1e-8 * abs(o[2])
+
+
+# ---- sparse block factorization of C~^n_W (only the kept blocks are formed) --------
+
+@pytest.mark.parametrize("k,n,up,tau,nu", [c + (None,) for c in SPARSE] + [(2, 650, 0, 0.05, 1.25),
+                                                                          (2, 650, 1, 0.1, 1.25)])
+def test_sparse_factorization_matches_oracle(k, n, up, tau, nu):
+    """l~_n from the kept blocks and a block Cholesky over the cells equals
+    the oracle's dense sparsified l~_n (same kappa-scaled tolerance as the
+    dense path) and the dense GPU path on the same matrix."""
+    require_gpu()
+    wl, nu, tree, bas, s = _both(k, n, nu)
+    level = tree.max_depth - up
+    g = s.loglik_sparse(dev(wl.z), level, tau)
+    d = s.loglik(dev(wl.z), level, tau=tau)
+    o = OL.multilevel_loglik(wl.points, wl.z, nu, wl.rho, bas, level, tree=tree, tau=tau)
+    kap = _cond_sparse(wl, nu, tree, bas, level, tau)
+    tq = max(1e-12, 50 * kap * 2.2e-16)
+    td = tq * o[3]
+    info = s.loglik_sparse_info(level, tau)
+    say(f"sparse factor cfg{k} n={n} nu={nu} level={level} tau={tau} rows={g['rows']} nnz={g['nnz']} "
+        f"factor={info['factor_entries']} heights={info['heights']} kappa={kap:.1e} "
+        f"dlogdet={abs(g['logdet'] - o[1]):.1e} dquad={abs(g['quad'] - o[2]) / abs(o[2]):.1e}")
+    assert g["rows"] == o[3] == info["rows"]
+    assert g["nnz"] == d["nnz"] == info["kept"]
+    assert info["factor_entries"] >= info["kept"] // 2
+    for ref in ((o[0], o[1], o[2]), (d["loglik"], d["logdet"], d["quad"])):
+        assert abs(g["logdet"] - ref[1]) < td
+        assert abs(g["quad"] - ref[2]) < tq * abs(ref[2])
+        assert abs(g["loglik"] - ref[0]) < td + tq * abs(ref[2])
+
+
+def test_sparse_factorization_everything_kept_and_repeated_calls():
+    """tau beyond the domain keeps every block: the block factorization then
+    gives the exact l_n; a second call with the same (level, tau) reuses the
+    analysis and returns the same bits; another tau is analysed anew."""
+    require_gpu()
+    wl, nu, tree, bas, s = _both(2, 900)
+    z = dev(wl.z)
+    level = tree.max_depth - 1
+    a = s.loglik(z, level)
+    b = s.loglik_sparse(z, level, 4.0)
+    kap = _cond(wl, nu, bas, a["rows"])
+    tq = max(1e-12, 50 * kap * 2.2e-16)
+    assert b["nnz"] == a["rows"] ** 2
+    assert abs(a["logdet"] - b["logdet"]) < tq * a["rows"]
+    assert abs(a["quad"] - b["quad"]) < tq * abs(a["quad"])
+    c = s.loglik_sparse(z, level, 4.0)
+    assert (b["loglik"], b["logdet"], b["quad"]) == (c["loglik"], c["logdet"], c["quad"])
+    e = s.loglik_sparse(z, level, 0.1)
+    f = s.loglik(z, level, tau=0.1)
+    assert e["nnz"] == f["nnz"] < b["nnz"]
+    assert abs(e["loglik"] - f["loglik"]) < 1e-9 * abs(f["loglik"])
+
+
+@pytest.mark.parametrize("k,n,level,tau", [(1, 1000, 0, 0.0), (4, 700, -1, 0.02)])
+def test_sparse_factorization_breakdown(k, n, level, tau):
+    """The indefinite sparsified matrices of the dense test stop the block
+    factorization too (EBREAKDOWN), and the next call works."""
+    require_gpu()
+    from paper_1701_00285_amd import MlblupError
+    wl, nu, tree, bas, s = _both(k, n)
+    level = tree.max_depth if level < 0 else level
+    with pytest.raises(MlblupError, match="EBREAKDOWN"):
+        s.loglik_sparse(dev(wl.z), level, tau)
+    g = s.loglik_sparse(dev(wl.z), tree.max_depth, 0.0 if k == 1 else 0.2)
+    assert math.isfinite(g["loglik"])
+
+
+def test_sparse_factorization_rejects_large_cells():
+    """A cell with more than 64 wavelets (leaves of 125 points, 115 wavelets
+    each) is refused."""
+    require_gpu()
+    from paper_1701_00285_amd import MlblupError, Solver
+    wl = workload(2, n=1000, n_targets=1)
+    s = Solver(wl.points, wl.degree_w, 128, wl.nu, wl.rho, wl.sigma2)
+    with pytest.raises(MlblupError, match="EINVAL"):
+        s.loglik_sparse(dev(wl.z), 0, 0.05)
+
+
+@pytest.mark.parametrize("up", [0, 1])
+def test_sparse_factorization_at_16384_points(up):
+    """16,384 points of the d = 3 workload's generator, against the dense
+    GPU factorization of the same C~^n_W (sizes the oracle's eigenvalues
+    cannot reach in seconds), for rough and smooth kernels and several tau:
+    where the dense factorization finds C~^n_W indefinite the block one must
+    too, elsewhere the two agree; rough kernels keep it definite."""
+    require_gpu()
+    from paper_1701_00285_amd import MlblupError, Solver
+    wl = workload(2, n=16384, n_targets=1)
+    z = dev(wl.z)
+    compared = 0
+    for nu, rho, tau in ((0.5, 0.02, 0.02), (0.5, 0.02, 0.05), (0.5, 0.05, 0.05), (1.5, 0.2, 0.05)):
+        s = Solver(wl.points, wl.degree_w, wl.leaf_max, nu, rho, wl.sigma2)
+        level = s.basis.levels - 1 - up
+        try:
+            d = s.loglik(z, level, tau=tau)
+        except MlblupError as e:
+            assert "EBREAKDOWN" in str(e)
+            with pytest.raises(MlblupError, match="EBREAKDOWN"):
+                s.loglik_sparse(z, level, tau)
+            say(f"sparse factor 16384 nu={nu} rho={rho} level={level} tau={tau}: indefinite (both)")
+            continue
+        g = s.loglik_sparse(z, level, tau)
+        info = s.loglik_sparse_info(level, tau)
+        say(f"sparse factor 16384 nu={nu} rho={rho} level={level} tau={tau} rows={g['rows']} kept={g['nnz']} "
+            f"factor={info['factor_entries']} heights={info['heights']} logdet {g['logdet']:.10e} / "
+            f"{d['logdet']:.10e} quad {g['quad']:.10e} / {d['quad']:.10e}")
+        assert g["nnz"] == d["nnz"]
+        assert abs(g["logdet"] - d["logdet"]) < 1e-9 * g["rows"]
+        assert abs(g["quad"] - d["quad"]) < 1e-8 * abs(d["quad"])
+        compared += 1
+    assert compared >= 1
+
+
+def test_sparse_factorization_mle_rho_and_nu_rho():
+    """The golden-section MLEs with every l~ evaluation by the block
+    factorization: the rho MLE against the oracle's (tau = 0.05, level
+    t - 1, as in the dense test), the profile (nu, rho) MLE against the dense
+    GPU path's on the same sparsified likelihood (general-nu values)."""
+    require_gpu()
+    wl, nu, tree, bas, s = _both(1, 600)
+    level = tree.max_depth - 1
+    g = s.mle_rho(dev(wl.z), level, 0.01, 1.0, 1e-5, tau=0.05, sparse=True)
+    o = OL.mle_rho(wl.points, wl.z, nu, bas, level, 0.01, 1.0, 1e-5, tree=tree, tau=0.05)
+    say(f"sparse-factor mle rho gpu {g['rho']:.8f} oracle {o[0]:.8f} evals {g['evals']}")
+    assert abs(math.log(g["rho"]) - math.log(o[0])) < 3e-5
+    assert abs(g["loglik"] - o[1]) < 1e-9 * abs(o[1])
+    wl, nu, tree, bas, s = _both(1, 300)
+    level = tree.max_depth
+    a = s.mle_nu_rho(dev(wl.z), level, 0.3, 2.0, 0.02, 0.5, nu_tol=1e-2, log_rho_tol=1e-3, tau=0.05, sparse=True)
+    b = s.mle_nu_rho(dev(wl.z), level, 0.3, 2.0, 0.02, 0.5, nu_tol=1e-2, log_rho_tol=1e-3, tau=0.05)
+    say(f"sparse-factor mle (nu, rho) ({a['nu']:.6f}, {a['rho']:.6f}) dense ({b['nu']:.6f}, {b['rho']:.6f})")
+    assert a["evals"] == b["evals"]
+    assert abs(a["nu"] - b["nu"]) < 1e-6 and abs(math.log(a["rho"]) - math.log(b["rho"])) < 1e-6
+    assert abs(a["loglik"] - b["loglik"]) < 1e-9 * abs(b["loglik"])

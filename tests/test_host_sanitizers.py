@@ -1,6 +1,7 @@
 """Address and undefined-behaviour sanitizers over the host C++ of the
 library: kd-tree (tree.cpp), multilevel basis (basis.cpp), sparsity pattern
-of the estimator (sparsify.cpp) and the general-nu tables (genu.cpp), built
+of the estimator (sparsify.cpp), the analysis of its sparse factorization
+(sparse_chol.cpp) and the general-nu tables (genu.cpp), built
 for the host only with -fsanitize=address,undefined (hipcc --cuda-host-only;
 no device code, no GPU) and driven by tests/sanitize_host_driver.cpp over
 ordinary, tied, collinear, tiny and 20-dimensional point sets.  The
@@ -26,8 +27,7 @@ def _tool(*cands):
     return None
 
 
-@pytest.mark.slow
-def test_host_code_under_asan_ubsan(tmp_path):
+def _build_and_run(tmp_path, sources, driver, ok_line):
     hipcc = _tool("/opt/rocm/bin/hipcc", shutil.which("hipcc"))
     clang = _tool("/opt/rocm/llvm/bin/clang++")
     if not hipcc or not clang:
@@ -37,7 +37,7 @@ def test_host_code_under_asan_ubsan(tmp_path):
              "-Xarch_host", "-fno-sanitize-recover=undefined",
              "-I", os.path.join(ROOT, "include"), "-I", CSRC]
     objs = []
-    for src in SOURCES + [os.path.join(ROOT, "tests", "sanitize_host_driver.cpp")]:
+    for src in sources + [os.path.join(ROOT, "tests", driver)]:
         path = src if os.path.isabs(src) else os.path.join(CSRC, src)
         obj = str(tmp_path / (os.path.basename(path) + ".o"))
         r = subprocess.run([hipcc] + flags + ["-c", path, "-o", obj], capture_output=True, text=True)
@@ -51,5 +51,24 @@ def test_host_code_under_asan_ubsan(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
     out = r.stdout + r.stderr
     assert r.returncode == 0, out[-5000:]
-    assert "sanitize driver: ok" in out, out[-5000:]
+    assert ok_line in out, out[-5000:]
     assert "runtime error" not in out and "AddressSanitizer" not in out, out[-5000:]
+    return out
+
+
+@pytest.mark.slow
+def test_host_code_under_asan_ubsan(tmp_path):
+    _build_and_run(tmp_path, SOURCES, "sanitize_host_driver.cpp", "sanitize driver: ok")
+
+
+@pytest.mark.slow
+def test_sparse_factor_analysis_under_asan_ubsan(tmp_path):
+    """The host analysis of the sparse block Cholesky (sparse_chol.cpp):
+    wavelet vectors orthonormal with vanishing moments, the block structure
+    closed under elimination and scheduled by elimination-tree height, and
+    the block algorithm of the device kernels, run in plain loops with the
+    same indexing, equal to a dense Cholesky of the same sparsified matrix
+    (tests/sparse_host_driver.cpp), under the sanitizers."""
+    out = _build_and_run(tmp_path, ["tree.cpp", "basis.cpp", "sparsify.cpp", "sparse_chol.cpp"],
+                         "sparse_host_driver.cpp", "sparse driver: ok")
+    assert "logdet" in out
