@@ -379,8 +379,9 @@ def loglik_sparse_bench(k: int, n: int, reps: int = 3, dense: bool = True, nu: f
     untimed call; with `dense`, the dense sparsified path on the same matrix
     beside it (the N x N covariance must fit).  Flops: the block
     factorization's (w^3/3 per diagonal block, w_i w_k^2 per block below it,
-    2 w_i w_j w_k per update) plus the assembly, 2 |S_a| |S_b| (w_b + 1) +
-    2 |S_a| w_a w_b per kept block pair (not counted in TFLOP/s)."""
+    2 w_i w_j w_k per update) and the dense tail's T^3/3; the assembly,
+    2 |S_a| |S_b| (w_b + 1) + 2 |S_a| w_a w_b per kept block pair, is not
+    counted in TFLOP/s."""
     import time
 
     import numpy as np
@@ -407,7 +408,8 @@ def loglik_sparse_bench(k: int, n: int, reps: int = 3, dense: bool = True, nu: f
             ana = time.perf_counter() - t0
             row = {"rows": info["rows"], "kept_fill": round(info["kept"] / info["rows"] ** 2, 5),
                    "factor_entries": info["factor_entries"], "block_columns": info["block_columns"],
-                   "heights": info["heights"], "factor_gflop": round(info["flops"] / 1e9, 3),
+                   "heights": info["heights"], "block_gflop": round(info["flops"] / 1e9, 3),
+                   "tail_rows": info["tail_rows"], "tail_gflop": round(info["tail_flops"] / 1e9, 3),
                    "analysis_s": round(ana, 3)}
             try:
                 s.loglik_sparse(z, level, tau)
@@ -418,8 +420,9 @@ def loglik_sparse_bench(k: int, n: int, reps: int = 3, dense: bool = True, nu: f
                     out = s.loglik_sparse(z, level, tau)
                     times.append(time.perf_counter() - t0)
                 ms = 1e3 * float(np.median(times))
-                row.update(ms=round(ms, 3), loglik=out["loglik"], logdet=out["logdet"], quad=out["quad"],
-                           factor_tflops=round(info["flops"] / (ms * 1e-3) / 1e12, 3))
+                row.update(ms=round(ms, 3), loglik=float(out["loglik"]), logdet=float(out["logdet"]),
+                           quad=float(out["quad"]),
+                           factor_tflops=round((info["flops"] + info["tail_flops"]) / (ms * 1e-3) / 1e12, 3))
             except MlblupError as e:   # C~ not positive definite for this tau
                 row["error"] = str(e).split(":")[0]
             if dense and "error" not in row:
@@ -431,7 +434,7 @@ def loglik_sparse_bench(k: int, n: int, reps: int = 3, dense: bool = True, nu: f
                     d = s.loglik(z, level, tau=tau)
                     times.append(time.perf_counter() - t0)
                 row.update(dense_ms=round(1e3 * float(np.median(times)), 3),
-                           rel_diff_loglik=abs(d["loglik"] - row["loglik"]) / abs(d["loglik"]))
+                           rel_diff_loglik=float(abs(d["loglik"] - row["loglik"]) / abs(d["loglik"])))
             res["cases"][key] = row
             print(f"sparse loglik {key}: {row}", file=sys.stderr, flush=True)
     print(json.dumps(res), flush=True)

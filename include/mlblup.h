@@ -357,24 +357,30 @@ int mlblup_loglik(mlblup_basis b, const mlblup_matern* k, const double* z_dev, i
  * cells (one block row and column per cell with wavelets at levels >=
  * level; a minimum-degree order of the cell graph, the fill blocks that
  * order creates, left-looking updates scheduled by elimination-tree
- * height), with Z^n_W as a border row for the quadratic form.  Cost and
- * storage follow the kept blocks and their fill, so a small tau makes it
- * cheap; tau = INFINITY factors the whole C^n_W block by block (use
- * mlblup_loglik there).  Every cell may own at most 64 wavelets: leaves of
+ * height), with Z^n_W as a border row for the quadratic form.  The last
+ * columns of the order, which the fill makes nearly full, form a dense
+ * tail: from the position where that is estimated to pay, the block
+ * columns before it update it and the dense blocked Cholesky of
+ * mlblup_loglik factors it (at most 49,152 rows; the environment variable
+ * MLBLUP_SPARSE_TAIL=none or =all forces no tail or an all-dense one, for
+ * tests and measurement).  Cost and storage follow the kept blocks and
+ * their fill, so a small tau makes it cheap; tau = INFINITY factors the
+ * whole C^n_W (use mlblup_loglik there).  Every cell may own at most 64 wavelets: leaves of
  * at most 64 points and a trend dimension p <= 64 (else MLBLUP_EINVAL).
  * The analysis (pattern, order, block structure, wavelet vectors) is built
  * on the host on the first call for a (level, tau) and kept with the basis
  * for the following calls with the same pair.
  * mlblup_loglik_sparse_workspace_bytes: *bytes of device workspace;
- * info6_host (may be NULL) = {N~, kept entries of C~^n_W, doubles of the
- * block factor (with its fill), block columns, elimination-tree heights,
- * factorization flops}.  No device access.
+ * info8_host (may be NULL) = {N~, kept entries of C~^n_W, doubles of the
+ * block factor (with its fill), block columns before the dense tail,
+ * elimination-tree heights of those columns, their factorization flops,
+ * rows of the dense tail, its flops}.  No device access.
  * mlblup_loglik_sparse: z_dev N data values in tree order; out4_host = {l,
  * log det, quadratic form, kept entries}.  Synchronises `stream`.
  * MLBLUP_EINVAL as for mlblup_loglik or for a cell with more than 64
  * wavelets; MLBLUP_EBREAKDOWN if a pivot is not positive. */
 int mlblup_loglik_sparse_workspace_bytes(mlblup_basis b, int32_t level, double tau, int64_t* bytes,
-                                         double* info6_host);
+                                         double* info8_host);
 int mlblup_loglik_sparse(mlblup_basis b, const mlblup_matern* k, const double* z_dev, int32_t level, double tau,
                          double* out4_host, void* work_dev, int64_t work_bytes, void* stream);
 /* mlblup_mle_rho and mlblup_mle_nu_rho with every evaluation of l~ by

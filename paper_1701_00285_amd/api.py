@@ -370,13 +370,15 @@ class Solver:
 
     def loglik_sparse_info(self, level, tau):
         """Sparse factorization of C~^n_W at (level, tau): dict(bytes, rows=N~,
-        kept, factor_entries, block_columns, heights, flops)."""
+        kept, factor_entries, block_columns (before the dense tail), heights,
+        flops (of those columns), tail_rows, tail_flops)."""
         b = C.c_int64()
-        info = np.zeros(6)
+        info = np.zeros(8)
         check(L.lib().mlblup_loglik_sparse_workspace_bytes(self.basis.h, int(level), float(tau), C.byref(b),
                                                            _np_ptr(info)))
         return dict(bytes=b.value, rows=int(info[0]), kept=int(info[1]), factor_entries=int(info[2]),
-                    block_columns=int(info[3]), heights=int(info[4]), flops=float(info[5]))
+                    block_columns=int(info[3]), heights=int(info[4]), flops=float(info[5]), tail_rows=int(info[6]),
+                    tail_flops=float(info[7]))
 
     def loglik_sparse(self, z, level, tau, rho=None, nu=None):
         """The log-likelihood of loglik() with the sparse block factorization

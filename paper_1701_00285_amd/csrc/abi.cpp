@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <limits>
 #include <memory>
 #include <new>
 #include <string>
@@ -1107,15 +1108,26 @@ int mlblup_loglik(mlblup_basis b, const mlblup_matern* k, const double* z_dev, i
 }
 
 // the sparse analysis of (level, tau), from the basis' cache or built now
+// MLBLUP_SPARSE_TAIL=none | all overrides the choice of the dense tail (-1 = chosen by the analysis)
+static int sparse_tail_request() {
+  const char* e = std::getenv("MLBLUP_SPARSE_TAIL");
+  if (!e) return -1;
+  if (!std::strcmp(e, "none")) return -2;
+  if (!std::strcmp(e, "all")) return 0;
+  return -1;
+}
+
 static int sparse_symbolic(mlblup_basis b, int32_t level, double tau, std::shared_ptr<const SparseSymbolic>* out) {
   std::lock_guard<std::mutex> g(b->sparse_mu);
+  const int req = sparse_tail_request();
   const bool same_tau = (std::isinf(tau) && b->sparse && std::isinf(b->sparse->tau)) || (b->sparse && b->sparse->tau == tau);
-  if (b->sparse && b->sparse->level == level && same_tau) {
+  if (b->sparse && b->sparse->level == level && same_tau && b->sparse_req == req) {
     *out = b->sparse;
     return MLBLUP_OK;
   }
   auto S = std::make_shared<SparseSymbolic>();
-  const int st = sparse_analyse(b->b, level, tau, *S);
+  const int st = sparse_analyse(b->b, level, tau, *S, req == -2 ? std::numeric_limits<int32_t>::max() : req);
+  b->sparse_req = req;
   if (st) return st;
   b->sparse = S;
   *out = S;
@@ -1123,7 +1135,7 @@ static int sparse_symbolic(mlblup_basis b, int32_t level, double tau, std::share
 }
 
 int mlblup_loglik_sparse_workspace_bytes(mlblup_basis b, int32_t level, double tau, int64_t* bytes,
-                                         double* info6_host) {
+                                         double* info8_host) {
   clear_error();
   if (!b || !bytes) return fail(MLBLUP_EINVAL, "NULL argument");
   if (level < 0 || level >= b->b.levels)
@@ -1133,13 +1145,15 @@ int mlblup_loglik_sparse_workspace_bytes(mlblup_basis b, int32_t level, double t
   int st = sparse_symbolic(b, level, tau, &S);
   if (st) return st;
   *bytes = sparse_layout(b->b, *S).total;
-  if (info6_host) {
-    info6_host[0] = (double)S->rows;
-    info6_host[1] = (double)S->kept_entries;
-    info6_host[2] = (double)S->factor_entries;
-    info6_host[3] = (double)S->nc;
-    info6_host[4] = S->lvl_ptr.empty() ? 0.0 : (double)(S->lvl_ptr.size() - 1);
-    info6_host[5] = S->flops;
+  if (info8_host) {
+    info8_host[0] = (double)S->rows;
+    info8_host[1] = (double)S->kept_entries;
+    info8_host[2] = (double)S->factor_entries;
+    info8_host[3] = (double)S->tail;
+    info8_host[4] = S->lvl_ptr.empty() ? 0.0 : (double)(S->lvl_ptr.size() - 1);
+    info8_host[5] = S->flops;
+    info8_host[6] = (double)S->tail_rows;
+    info8_host[7] = S->flops_tail;
   }
   return MLBLUP_OK;
 }

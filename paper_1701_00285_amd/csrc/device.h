@@ -130,12 +130,18 @@ struct CoarseLayout {
   int64_t phi = 0, a = 0, scal = 0, flag = 0, gtab = 0, linv = 0, total = 0, batch = 0;
 };
 CoarseLayout coarse_layout(const Basis& B, int64_t nc);
+// Dense blocked Cholesky of the nt x nt lower triangle of C (row-major, ld nt) with row nt as a border
+// row (C holds (nt + 1) x nt doubles): dout = {2 sum log G_ii, |G^-1 c|^2}, c the border row; linv:
+// dense_cholesky_linv_doubles(nt) doubles; a pivot that is not positive sets flag[0] (loglik.hip)
+int dense_cholesky_logdet(double* C, int64_t nt, double* linv, int* flag, double* dout, hipStream_t s);
+int64_t dense_cholesky_linv_doubles(int64_t nt);
 // sparse block Cholesky of C~^n_W (sparse_chol.hip): workspace layout (byte offsets) for a host analysis
 struct SparseLayout {
   int64_t L = 0, linv = 0, psi = 0, zw = 0, scal = 0, zt = 0, y = 0, logd = 0, out = 0, flag = 0, gtab = 0;
   int64_t w = 0, row0 = 0, ypos = 0, inv_off = 0, sup_beg = 0, sup_cnt = 0, psi_off = 0, col_ptr = 0;
   int64_t blk_row = 0, blk_col = 0, blk_off = 0, row_ptr = 0, row_col = 0, row_blk = 0, lvl_blks = 0;
   int64_t lvl_cols = 0, kept = 0, total = 0, nkept = 0;
+  int64_t dense = 0, dense_linv = 0, dense_out = 0, tail_blks = 0, tail_cols = 0;   // the dense tail
 };
 SparseLayout sparse_layout(const Basis& B, const SparseSymbolic& S);
 // out = {l~, log det, quadratic form}; MLBLUP_EBREAKDOWN for a pivot that is not positive

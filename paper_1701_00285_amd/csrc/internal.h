@@ -124,7 +124,14 @@ struct SparseSymbolic {
   std::vector<int64_t> row_ptr;
   std::vector<int32_t> row_col;
   std::vector<int64_t> row_blk;
-  // elimination-tree heights: the columns of height h and their blocks
+  // dense tail: the columns [tail, nc) (tail_rows rows) are factored as one dense matrix after the
+  // block columns before them have updated it (tail = nc: none)
+  int32_t tail = 0;
+  int64_t tail_rows = 0;
+  double flops_tail = 0.0;         // tail_rows^3 / 3
+  std::vector<int64_t> tail_blks;  // the blocks of the tail columns
+  std::vector<int32_t> tail_cols;  // tail .. nc - 1
+  // elimination-tree heights of the columns before the tail: the columns of height h and their blocks
   std::vector<int64_t> lvl_ptr;
   std::vector<int32_t> lvl_cols;
   std::vector<int64_t> lvl_blk_ptr;
@@ -133,7 +140,12 @@ struct SparseSymbolic {
   std::vector<int64_t> psi_off;
   std::vector<double> psi;
 };
-int sparse_analyse(const Basis& b, int32_t level, double tau, SparseSymbolic& S);
+// dense_tail: -1 chooses the tail start by the estimated time (block columns at kSparseBlockRate,
+// the dense tail at kSparseDenseRate), 0 .. nc forces it (nc: no dense tail)
+constexpr double kSparseBlockRate = 1.5e12;   // flop/s of the block kernels (measured, 65,536 points)
+constexpr double kSparseDenseRate = 25e12;    // flop/s of the dense blocked Cholesky at 10^4 rows and more
+constexpr int64_t kSparseMaxTail = 49152;     // rows of the dense tail at most (18 GB)
+int sparse_analyse(const Basis& b, int32_t level, double tau, SparseSymbolic& S, int32_t dense_tail = -1);
 int64_t basis_device_bytes(const Basis& b);
 
 // exponent tuples of the total-degree set, graded lexicographic
@@ -149,4 +161,5 @@ struct mlblup_basis_s {
   // the last sparse analysis (level, tau) of the estimator, reused by later evaluations
   std::mutex sparse_mu;
   std::shared_ptr<const mlb::SparseSymbolic> sparse;
+  int sparse_req = -1;   // dense-tail request the cached analysis was built with
 };

@@ -591,6 +591,15 @@ static int cholesky_bordered(double* C, int64_t nt, int64_t nr, double* linv, in
   return hip_check(hipGetLastError(), "Cholesky launch");
 }
 
+int dense_cholesky_logdet(double* C, int64_t nt, double* linv, int* flag, double* dout, hipStream_t s) {
+  int st = cholesky_bordered(C, nt, nt + 1, linv, flag, s);
+  if (st) return st;
+  hipLaunchKernelGGL(logdet_quad, dim3(1), dim3(kT), 0, s, C, nt, nt, C + nt * nt, dout);
+  return hip_check(hipGetLastError(), "reduction launch");
+}
+
+int64_t dense_cholesky_linv_doubles(int64_t nt) { return std::max<int64_t>((nt + kNb - 1) / kNb, 1) * kNb * kNb; }
+
 int loglik_upload_pattern(const Pattern& P, void* work, const LoglikLayout& L, hipStream_t s) {
   if (P.nc != L.cells || (int64_t)P.rowcell.size() != L.rows)
     return fail(MLBLUP_EINVAL, "loglik: sparsity pattern does not match the level");

@@ -49,6 +49,41 @@ constexpr int rows_per_lane_lp(int D) { return D <= 6 ? 4 : 2; }
 // column ranges of a diagonal tile: whole chunks each
 constexpr int diag_split(int RL) { return RL == 3 ? 2 : kDiagSplit; }
 
+// (row block, round offset) of an off-diagonal workgroup of a launch of nr
+// rounds over T blocks.  Workgroups go to the 8 XCDs in turn (linear id mod
+// 8); the ids one XCD receives are renumbered consecutively and walked in
+// groups of 8 row blocks x 8 rounds, so the workgroups an XCD runs at one
+// time read 8 row blocks and 15 column blocks (S + round) instead of 64 of
+// each, and those stay in its L2.  The map is a bijection onto the grid for
+// any T and nr (the rows and rounds past whole groups are walked in order),
+// and each workgroup still writes its own partial slots, so the results do
+// not depend on it.
+__device__ __forceinline__ void tile_of(int T, int nr, int& S, int& y) {
+  const int total = T * nr;
+  const int i = (int)blockIdx.x + T * (int)blockIdx.y;
+  const int q = total / 8, rem = total % 8;
+  const int x = i % 8, j = i / 8;
+  const int v = x < rem ? x * (q + 1) + j : rem * (q + 1) + (x - rem) * q + j;
+  const int T8 = T / 8 * 8, n8 = nr / 8 * 8;
+  const int full = T8 * n8;
+  if (v < full) {
+    const int g = v / 64, w = v % 64;
+    S = (g % (T8 / 8)) * 8 + w / 8;
+    y = (g / (T8 / 8)) * 8 + w % 8;
+  } else {
+    int u = v - full;
+    const int a = (T - T8) * n8;  // row blocks past the groups, rounds inside them
+    if (u < a) {
+      S = T8 + u % (T - T8);
+      y = u / (T - T8);
+    } else {
+      u -= a;
+      S = u % T;
+      y = n8 + u / T;
+    }
+  }
+}
+
 template <int D, int NU2, int OUT>
 __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts, const double* __restrict__ x,
                                                  int64_t n, int T, int round0, int diag, double zs,
@@ -70,8 +105,10 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
   __shared__ double cred[4][kChunk];
   __shared__ double cdred[4][kChunk];
   __shared__ double tab[kExpTab];
-  const int S = blockIdx.x;
-  const int r = round0 + (diag ? 0 : (int)blockIdx.y);
+  // diagonal launches: row block blockIdx.x, column range blockIdx.y; others: tile_of
+  int S = blockIdx.x, yy = blockIdx.y;
+  if (!diag) tile_of(T, (int)gridDim.y, S, yy);
+  const int r = round0 + (diag ? 0 : yy);
   int Sp = S;
   if (!diag) {
     Sp = (S + r) % T;
@@ -110,7 +147,7 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
   for (int q = 0; q < RL; ++q) racc[q] = rdacc[q] = 0.0;
   const int64_t cbase = (int64_t)Sp * kBlk;
   // a diagonal tile is split over gridDim.y column ranges (one partial slot each)
-  const int cfirst = diag ? (int)blockIdx.y * (kBlk / (int)gridDim.y) : 0;
+  const int cfirst = diag ? yy * (kBlk / (int)gridDim.y) : 0;
   const int clast = diag ? cfirst + kBlk / (int)gridDim.y : kBlk;
   for (int c0 = cfirst; c0 < clast; c0 += kChunk) {
     __syncthreads();
@@ -192,7 +229,7 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
     if (!diag && tid < kChunk) {
       const int64_t gj = cbase + c0 + tid;
       if (gj < n) {
-        const int64_t slot = (int64_t)blockIdx.y * n + gj;
+        const int64_t slot = (int64_t)yy * n + gj;
         if constexpr (OUT & 1) pcol[slot] = ((cred[0][tid] + cred[1][tid]) + cred[2][tid]) + cred[3][tid];
         if constexpr (OUT & 2) pdcol[slot] = ((cdred[0][tid] + cdred[1][tid]) + cdred[2][tid]) + cdred[3][tid];
       }
@@ -202,7 +239,7 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
   for (int q = 0; q < RL; ++q) {
     const int64_t i = (int64_t)S * kBlk + wave * (64 * RL) + q * 64 + lane;
     if (i < n) {
-      const int64_t slot = (int64_t)blockIdx.y * n + i;
+      const int64_t slot = (int64_t)yy * n + i;
       if constexpr (OUT & 1) prow[slot] = racc[q];
       if constexpr (OUT & 2) pdrow[slot] = rdacc[q];
     }
@@ -226,8 +263,10 @@ __global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ p
   __shared__ __align__(16) float cp[kChunk * SP];
   __shared__ double cred[4][kChunk];
   __shared__ double cdred[4][kChunk];
-  const int S = blockIdx.x;
-  const int r = round0 + (diag ? 0 : (int)blockIdx.y);
+  // diagonal launches: row block blockIdx.x, column range blockIdx.y; others: tile_of
+  int S = blockIdx.x, yy = blockIdx.y;
+  if (!diag) tile_of(T, (int)gridDim.y, S, yy);
+  const int r = round0 + (diag ? 0 : yy);
   int Sp = S;
   if (!diag) {
     Sp = (S + r) % T;
@@ -250,7 +289,7 @@ __global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ p
 #pragma unroll
   for (int q = 0; q < RL; ++q) racc[q] = rdacc[q] = 0.0;
   const int64_t cbase = (int64_t)Sp * kBlk;
-  const int cfirst = diag ? (int)blockIdx.y * (kBlk / (int)gridDim.y) : 0;
+  const int cfirst = diag ? yy * (kBlk / (int)gridDim.y) : 0;
   const int clast = diag ? cfirst + kBlk / (int)gridDim.y : kBlk;
   for (int c0 = cfirst; c0 < clast; c0 += kChunk) {
     __syncthreads();
@@ -317,7 +356,7 @@ __global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ p
     if (!diag && tid < kChunk) {
       const int64_t gj = cbase + c0 + tid;
       if (gj < n) {
-        const int64_t slot = (int64_t)blockIdx.y * n + gj;
+        const int64_t slot = (int64_t)yy * n + gj;
         if constexpr (OUT & 1) pcol[slot] = ((cred[0][tid] + cred[1][tid]) + cred[2][tid]) + cred[3][tid];
         if constexpr (OUT & 2) pdcol[slot] = ((cdred[0][tid] + cdred[1][tid]) + cdred[2][tid]) + cdred[3][tid];
       }
@@ -327,7 +366,7 @@ __global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ p
   for (int q = 0; q < RL; ++q) {
     const int64_t i = o + wave * (64 * RL) + q * 64 + lane;
     if (i < n) {
-      const int64_t slot = (int64_t)blockIdx.y * n + i;
+      const int64_t slot = (int64_t)yy * n + i;
       if constexpr (OUT & 1) prow[slot] = racc[q];
       if constexpr (OUT & 2) pdrow[slot] = rdacc[q];
     }

@@ -16,9 +16,16 @@
 //     the earlier columns k whose pattern contains j) drives the
 //     left-looking updates, L_ij = A_ij - sum_k L_ik L_jk^T over the k in
 //     both row structures.
-//  3. Schedule: the elimination tree (parent = first column of the pattern)
-//     by height; the columns of one height depend on lower heights only.
-//  4. The wavelet vectors of every cell on the points of its subtree,
+//  3. Dense tail: the last columns of the order (the separators the
+//     minimum-degree order leaves to the end) are nearly full; from the
+//     position where that pays (by the estimated time of the block kernels
+//     against the dense blocked Cholesky) they form one dense matrix, which
+//     the block columns before it update and the dense factorization then
+//     finishes.
+//  4. Schedule of the block columns before the tail: the elimination tree
+//     (parent = first column of the pattern) by height; the columns of one
+//     height depend on lower heights only.
+//  5. The wavelet vectors of every cell on the points of its subtree,
 //     bottom-up from the basis' orthogonal blocks (a leaf's candidates are
 //     its points' unit vectors, an internal cell's the scaling vectors of
 //     its two children, left first), so that a kept block is
@@ -39,7 +46,7 @@ int32_t wavelets_of(const Basis& B, int32_t v) { return B.desc[v].m - B.desc[v].
 
 }  // namespace
 
-int sparse_analyse(const Basis& B, int32_t level, double tau, SparseSymbolic& S) {
+int sparse_analyse(const Basis& B, int32_t level, double tau, SparseSymbolic& S, int32_t dense_tail) {
   S = SparseSymbolic();
   S.level = level;
   S.tau = tau;
@@ -63,7 +70,10 @@ int sparse_analyse(const Basis& B, int32_t level, double tau, SparseSymbolic& S)
                                      std::to_string(kSparseMaxBlock) + ": leaf size and trend dimension up to 64)");
     S.rows += wc[c];
   }
-  if (nc == 0) return MLBLUP_OK;
+  if (nc == 0) {
+    S.tail = 0;
+    return MLBLUP_OK;
+  }
 
   // 1. minimum degree on the cell graph, with the fill
   const int words = (nc + 63) / 64;
@@ -166,7 +176,60 @@ int sparse_analyse(const Basis& B, int32_t level, double tau, SparseSymbolic& S)
       ++fillp[j];
     }
 
-  // 3. elimination tree heights
+  // factor flops per column: a w^3/3 factor, w_i w_k^2 per block below it, and per pair of its
+  // blocks (i >= j) 2 w_i w_j w_k for the update of block (i, j)
+  std::vector<double> colfl(nc, 0.0);
+  for (int32_t k = 0; k < nc; ++k) {
+    const double wk = S.w[k];
+    double fl = wk * wk * wk / 3.0;
+    double sw = 0.0, sw2 = 0.0;
+    for (int64_t b = S.col_ptr[k] + 1; b < S.col_ptr[k + 1]; ++b) {
+      const double wi = S.w[S.blk_row[b]];
+      fl += wi * wk * wk;
+      sw += wi;
+      sw2 += wi * wi;
+    }
+    fl += wk * (sw * sw + sw2);   // sum over i >= j of 2 w_i w_j w_k = w_k ((sum w)^2 + sum w^2)
+    colfl[k] = fl;
+  }
+  // 3. dense tail: the start q minimising (flops of the block columns before q) / kSparseBlockRate +
+  // rows(q)^3 / 3 / kSparseDenseRate, with at most kSparseMaxTail rows in the tail
+  {
+    int32_t best = nc;
+    double pre = 0.0, best_t = 0.0;
+    for (int32_t k = 0; k < nc; ++k) best_t += colfl[k];
+    best_t /= kSparseBlockRate;
+    if (dense_tail < 0) {
+      for (int32_t q = 0; q < nc; ++q) {
+        const double rows = (double)(S.rows - S.ypos[q]);
+        if (rows <= (double)kSparseMaxTail) {
+          const double est = pre / kSparseBlockRate + rows * rows * rows / 3.0 / kSparseDenseRate;
+          if (est < best_t) {
+            best_t = est;
+            best = q;
+          }
+        }
+        pre += colfl[q];
+      }
+    } else {
+      best = std::min<int32_t>(dense_tail, nc);
+      if (S.rows - (best < nc ? S.ypos[best] : S.rows) > kSparseMaxTail)
+        return fail(MLBLUP_EINVAL, "sparse loglik: forced dense tail above the row limit");
+    }
+    S.tail = best;
+    S.tail_rows = best < nc ? S.rows - S.ypos[best] : 0;
+    const double tr = (double)S.tail_rows;
+    S.flops_tail = tr * tr * tr / 3.0;
+    S.flops = 0.0;
+    for (int32_t k = 0; k < best; ++k) S.flops += colfl[k];
+    for (int32_t k = best; k < nc; ++k) {
+      S.tail_cols.push_back(k);
+      for (int64_t b = S.col_ptr[k]; b < S.col_ptr[k + 1]; ++b) S.tail_blks.push_back(b);
+    }
+  }
+
+  // 4. elimination tree heights of the columns before the tail
+  const int32_t ntail0 = S.tail;
   std::vector<int32_t> height(nc, 0);
   for (int32_t k = 0; k < nc; ++k) {
     if (S.col_ptr[k + 1] - S.col_ptr[k] > 1) {
@@ -174,13 +237,14 @@ int sparse_analyse(const Basis& B, int32_t level, double tau, SparseSymbolic& S)
       height[parent] = std::max(height[parent], height[k] + 1);
     }
   }
-  const int32_t hmax = *std::max_element(height.begin(), height.end());
+  int32_t hmax = -1;
+  for (int32_t k = 0; k < ntail0; ++k) hmax = std::max(hmax, height[k]);
   S.lvl_ptr.assign(hmax + 2, 0);
-  for (int32_t k = 0; k < nc; ++k) ++S.lvl_ptr[height[k] + 1];
+  for (int32_t k = 0; k < ntail0; ++k) ++S.lvl_ptr[height[k] + 1];
   for (int32_t h = 0; h <= hmax; ++h) S.lvl_ptr[h + 1] += S.lvl_ptr[h];
-  S.lvl_cols.resize(nc);
+  S.lvl_cols.resize(ntail0);
   std::vector<int64_t> lp(S.lvl_ptr.begin(), S.lvl_ptr.end() - 1);
-  for (int32_t k = 0; k < nc; ++k) S.lvl_cols[lp[height[k]]++] = k;
+  for (int32_t k = 0; k < ntail0; ++k) S.lvl_cols[lp[height[k]]++] = k;
   // per height: the blocks of its columns (diagonal first within a column), for the launches
   S.lvl_blk_ptr.assign(hmax + 2, 0);
   for (int32_t h = 0; h <= hmax; ++h) {
@@ -191,7 +255,7 @@ int sparse_analyse(const Basis& B, int32_t level, double tau, SparseSymbolic& S)
     }
     S.lvl_blk_ptr[h + 1] = S.lvl_blk_ptr[h] + c;
   }
-  S.lvl_blks.resize(nblk);
+  S.lvl_blks.resize(S.lvl_blk_ptr[hmax + 1]);
   {
     int64_t q2 = 0;
     for (int32_t h = 0; h <= hmax; ++h)
@@ -200,24 +264,8 @@ int sparse_analyse(const Basis& B, int32_t level, double tau, SparseSymbolic& S)
         for (int64_t b = S.col_ptr[k]; b < S.col_ptr[k + 1]; ++b) S.lvl_blks[q2++] = b;
       }
   }
-  // factor flops: per column a w^3/3 factor, w_i w_k^2 per block below it, and per pair of its
-  // blocks (i >= j) 2 w_i w_j w_k for the update of block (i, j)
-  double fl = 0.0;
-  for (int32_t k = 0; k < nc; ++k) {
-    const double wk = S.w[k];
-    fl += wk * wk * wk / 3.0;
-    double sw = 0.0, sw2 = 0.0;
-    for (int64_t b = S.col_ptr[k] + 1; b < S.col_ptr[k + 1]; ++b) {
-      const double wi = S.w[S.blk_row[b]];
-      fl += wi * wk * wk;
-      sw += wi;
-      sw2 += wi * wi;
-    }
-    fl += wk * (sw * sw + sw2);   // sum over i >= j of 2 w_i w_j w_k = w_k ((sum w)^2 + sum w^2)
-  }
-  S.flops = fl;
 
-  // 4. wavelet vectors of every cell on its points (and the scaling vectors they are built from)
+  // 5. wavelet vectors of every cell on its points (and the scaling vectors they are built from)
   const int32_t nn = (int32_t)B.desc.size();
   std::vector<std::vector<double>> phi(nn);
   S.psi_off.assign(nc + 1, 0);

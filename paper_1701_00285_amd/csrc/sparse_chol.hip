@@ -22,7 +22,13 @@
 //       inverse, y_j = L_jj^-1 (z_j - ...) and log L_jj[r][r];
 //     solve: every block below a diagonal, L_ij = A_ij L_jj^-T (a product
 //       with the inverse).
-//  3. One fixed-order reduction: sum log L_rr and |y|^2.
+//     The columns of the dense tail (the last ones of the order, nearly
+//     full) are not scheduled by height: one update launch applies the
+//     block columns before the tail to all of its blocks and its data rows,
+//     the blocks are scattered into a dense matrix with the data rows as a
+//     border row, and the dense blocked Cholesky of the estimator finishes it.
+//  3. Fixed-order reductions: sum log L_rr and |y|^2 over the block
+//     columns, plus the dense tail's.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -149,7 +155,9 @@ __global__ __launch_bounds__(kT) void sp_assemble(const double* __restrict__ pts
 }
 
 // ---- 2. left-looking factorization, one elimination-tree height at a time ----------
-// blocks [0, nblk): update block lvl[x]; then one data block per column cols[x - nblk]
+// blocks [0, nblk): update block lvl[x]; then one data block per column cols[x - nblk]; only the
+// columns k < kmax contribute (all earlier ones inside the block part; those before the dense tail
+// for the tail's blocks)
 __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const int32_t* __restrict__ w,
                                                 const int32_t* __restrict__ blk_row,
                                                 const int32_t* __restrict__ blk_col,
@@ -160,7 +168,7 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
                                                 int64_t nblk, const int32_t* __restrict__ cols,
                                                 const double* __restrict__ zw, const int64_t* __restrict__ row0,
                                                 const int64_t* __restrict__ ypos, const double* __restrict__ y,
-                                                double* __restrict__ zt) {
+                                                double* __restrict__ zt, int kmax) {
   __shared__ double La[kB * kLd];   // L_ik transposed: La[t][r]
   __shared__ double Lb[kB * kLd];   // L_jk transposed: Lb[t][c]
   __shared__ int64_t pa[64], pb[64];
@@ -176,6 +184,7 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
       double v = zw[row0[j] + t];
       for (int64_t p = row_ptr[j]; p < row_ptr[j + 1]; ++p) {
         const int k = row_col[p];
+        if (k >= kmax) break;
         const int wk = w[k];
         const double* lb = L + blk_off[row_blk[p]] + (int64_t)t * wk;
         const double* yk = y + ypos[k];
@@ -209,6 +218,7 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
       int n = 0;
       while (n < 64 && p < ei && q < ej) {
         const int kp = row_col[p], kq = row_col[q];
+        if (kp >= kmax || kq >= kmax) break;   // ascending lists: no match below kmax is left
         if (kp == kq) {
           pa[n] = row_blk[p];
           pb[n] = row_blk[q];
@@ -367,6 +377,28 @@ __global__ __launch_bounds__(kT) void sp_solve(double* __restrict__ L, const dou
       if (4 * tr + r < wi && 4 * tc + c < wj) A[(4 * tr + r) * wj + 4 * tc + c] = acc[r][c];
 }
 
+// the tail's blocks into the dense T x T matrix C (rows and columns from the position-ordered
+// offsets, minus y0), both triangles from the lower one
+__global__ __launch_bounds__(kT) void sp_scatter(const double* __restrict__ L, const int32_t* __restrict__ w,
+                                                 const int32_t* __restrict__ blk_row,
+                                                 const int32_t* __restrict__ blk_col,
+                                                 const int64_t* __restrict__ blk_off,
+                                                 const int64_t* __restrict__ ypos, const int64_t* __restrict__ list,
+                                                 int64_t y0, int64_t T, double* __restrict__ C) {
+  const int64_t b = list[blockIdx.x];
+  const int i = blk_row[b], j = blk_col[b];
+  const int wi = w[i], wj = w[j];
+  const int64_t r0 = ypos[i] - y0, c0 = ypos[j] - y0;
+  const double* A = L + blk_off[b];
+  for (int e = threadIdx.x; e < wi * wj; e += kT) {
+    const int r = e / wj, c = e - r * wj;
+    // a diagonal block's two triangles agree only up to rounding: the lower one is kept
+    if (i == j && c > r) continue;
+    C[(r0 + r) * T + c0 + c] = A[e];
+    C[(c0 + c) * T + r0 + r] = A[e];
+  }
+}
+
 // out = {sum logd, sum y^2} in a fixed order (one workgroup)
 __global__ __launch_bounds__(kT) void sp_reduce(const double* __restrict__ logd, const double* __restrict__ y,
                                                 int64_t n, double* __restrict__ out) {
@@ -446,6 +478,12 @@ SparseLayout sparse_layout(const Basis& B, const SparseSymbolic& S) {
   Ly.lvl_blks = take(nblk * 8);
   Ly.lvl_cols = take(nc * 4);
   Ly.kept = take(nkept * 8);
+  const int64_t T = S.tail_rows;
+  Ly.dense = take(T > 0 ? (T + 1) * T * 8 : 8);
+  Ly.dense_linv = take(T > 0 ? dense_cholesky_linv_doubles(T) * 8 : 8);
+  Ly.dense_out = take(16);
+  Ly.tail_blks = take((int64_t)S.tail_blks.size() * 8);
+  Ly.tail_cols = take((int64_t)S.tail_cols.size() * 4);
   Ly.total = o;
   Ly.nkept = nkept;
   return Ly;
@@ -483,7 +521,8 @@ int loglik_sparse_device(const Basis& B, const TransformDev& T, const PairArgs& 
       (st = put(w, Ly.blk_off, S.blk_off, s)) || (st = put(w, Ly.row_ptr, S.row_ptr, s)) ||
       (st = put(w, Ly.row_col, S.row_col, s)) || (st = put(w, Ly.row_blk, S.row_blk, s)) ||
       (st = put(w, Ly.lvl_blks, S.lvl_blks, s)) || (st = put(w, Ly.lvl_cols, S.lvl_cols, s)) ||
-      (st = put(w, Ly.kept, kept, s)))
+      (st = put(w, Ly.kept, kept, s)) || (st = put(w, Ly.tail_blks, S.tail_blks, s)) ||
+      (st = put(w, Ly.tail_cols, S.tail_cols, s)))
     return st;
   double* Ld = (double*)(w + Ly.L);
   double* Linv = (double*)(w + Ly.linv);
@@ -543,23 +582,46 @@ int loglik_sparse_device(const Basis& B, const TransformDev& T, const PairArgs& 
     const int64_t b0 = S.lvl_blk_ptr[h], nb = S.lvl_blk_ptr[h + 1] - b0;
     if (ncol == 0) continue;
     hipLaunchKernelGGL(sp_update, dim3((unsigned)(nb + ncol)), dim3(kT), 0, s, Ld, dw, brow, bcol, boff, rptr, rcol,
-                       rblk, lblk + b0, nb, lcol + c0, dz, row0, ypos, y, zt);
+                       rblk, lblk + b0, nb, lcol + c0, dz, row0, ypos, y, zt, (int)nc);
     hipLaunchKernelGGL(sp_factor, dim3((unsigned)ncol), dim3(kT), 0, s, Ld, Linv, ioff, dw, cptr, boff, lcol + c0,
                        ypos, zt, y, logd, flag);
     if (nb > ncol)
       hipLaunchKernelGGL(sp_solve, dim3((unsigned)nb), dim3(kT), 0, s, Ld, Linv, ioff, dw, brow, bcol, boff, lblk + b0);
   }
   if ((st = hip_check(hipGetLastError(), "sparse factorization launch"))) return st;
-  // 3. reduction
+  // dense tail: the updates from the block columns before it, then the dense bordered Cholesky
+  double tail_host[2] = {0.0, 0.0};
+  double* dtail = (double*)(w + Ly.dense_out);
+  const int64_t nT = S.tail_rows;
+  if (S.tail < nc && nT > 0) {
+    const int64_t ntb = (int64_t)S.tail_blks.size(), ntc = (int64_t)S.tail_cols.size();
+    const int64_t* tblk = (const int64_t*)(w + Ly.tail_blks);
+    const int32_t* tcol = (const int32_t*)(w + Ly.tail_cols);
+    hipLaunchKernelGGL(sp_update, dim3((unsigned)(ntb + ntc)), dim3(kT), 0, s, Ld, dw, brow, bcol, boff, rptr, rcol,
+                       rblk, tblk, ntb, tcol, dz, row0, ypos, y, zt, (int)S.tail);
+    double* C = (double*)(w + Ly.dense);
+    MLB_HIP(hipMemsetAsync(C, 0, nT * nT * 8, s));
+    hipLaunchKernelGGL(sp_scatter, dim3((unsigned)ntb), dim3(kT), 0, s, Ld, dw, brow, bcol, boff, ypos, tblk,
+                       S.ypos[S.tail], nT, C);
+    if ((st = hip_check(hipGetLastError(), "sparse tail launch"))) return st;
+    // the data rows of the tail as the border row
+    MLB_HIP(hipMemcpyAsync(C + nT * nT, zt + S.ypos[S.tail], nT * 8, hipMemcpyDeviceToDevice, s));
+    if ((st = dense_cholesky_logdet(C, nT, (double*)(w + Ly.dense_linv), flag, dtail, s))) return st;
+  }
+  // 3. reduction over the rows of the block columns
   double* dout = (double*)(w + Ly.out);
-  hipLaunchKernelGGL(sp_reduce, dim3(1), dim3(kT), 0, s, logd, y, S.rows, dout);
+  const int64_t nsp = S.tail < nc ? S.ypos[S.tail] : S.rows;
+  hipLaunchKernelGGL(sp_reduce, dim3(1), dim3(kT), 0, s, logd, y, nsp, dout);
   if ((st = hip_check(hipGetLastError(), "sparse reduction launch"))) return st;
   double host[2];
   int hflag = 0;
   MLB_HIP(hipMemcpyAsync(host, dout, sizeof(host), hipMemcpyDeviceToHost, s));
+  if (S.tail < nc && nT > 0) MLB_HIP(hipMemcpyAsync(tail_host, dtail, sizeof(tail_host), hipMemcpyDeviceToHost, s));
   MLB_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
   MLB_HIP(hipStreamSynchronize(s));
   if (hflag) return fail(MLBLUP_EBREAKDOWN, "sparse loglik: C~^n_W is not numerically positive definite");
+  host[0] += tail_host[0];
+  host[1] += tail_host[1];
   const double kLog2Pi = 1.8378770664093453;
   out[1] = host[0];
   out[2] = host[1];

@@ -50,10 +50,16 @@ static double cov(const double* a, const double* b, int d, double rho) {
   return std::exp(-std::sqrt(s) / rho);
 }
 
-static void check_case(const char* name, const mlb::Basis& B, int level, double tau, double rho) {
+// mode: 0 the tail start chosen by the analysis, 1 no dense tail, 2 all dense, 3 dense from the middle
+static void check_case(const char* name, const mlb::Basis& B, int level, double tau, double rho, int mode) {
   mlb::SparseSymbolic S;
-  const int st = mlb::sparse_analyse(B, level, tau, S);
+  int st = mlb::sparse_analyse(B, level, tau, S);
   CHECK(st == MLBLUP_OK, "%s: sparse_analyse status %d", name, st);
+  if (mode > 0) {
+    const int forced = mode == 1 ? S.nc : (mode == 2 ? 0 : S.nc / 2);
+    st = mlb::sparse_analyse(B, level, tau, S, forced);
+    CHECK(st == MLBLUP_OK && S.tail == forced, "%s: forced tail %d status %d", name, forced, st);
+  }
   const int nc = S.nc;
   const int d = B.d;
   if (nc == 0) return;
@@ -103,13 +109,13 @@ static void check_case(const char* name, const mlb::Basis& B, int level, double 
       if (S.blk_row[b] == i) return b;
     return -1;
   };
-  mlb::Pattern P;
-  mlb::build_pattern(B, level, tau, P);
+  mlb::Pattern Pat;
+  mlb::build_pattern(B, level, tau, Pat);
   std::vector<int> pos(nc);
   for (int k = 0; k < nc; ++k) pos[S.order[k]] = k;
   for (int x = 0; x < nc; ++x)
     for (int y = 0; y < nc; ++y)
-      if (P.keep[(size_t)x * nc + y]) {
+      if (Pat.keep[(size_t)x * nc + y]) {
         const int i = std::max(pos[x], pos[y]), j = std::min(pos[x], pos[y]);
         const int64_t b = find_blk(i, j);
         CHECK(b >= 0 && S.blk_kept[b], "%s: kept pair (%d,%d) has no kept block", name, x, y);
@@ -118,7 +124,7 @@ static void check_case(const char* name, const mlb::Basis& B, int level, double 
     const int i = S.blk_row[b], j = S.blk_col[b];
     CHECK(i >= j && S.blk_off[b + 1] - S.blk_off[b] == (int64_t)S.w[i] * S.w[j], "%s: block %lld shape", name,
           (long long)b);
-    CHECK(S.blk_kept[b] == P.keep[(size_t)S.order[i] * nc + S.order[j]] || i == j, "%s: kept flag of block %lld",
+    CHECK(S.blk_kept[b] == Pat.keep[(size_t)S.order[i] * nc + S.order[j]] || i == j, "%s: kept flag of block %lld",
           name, (long long)b);
   }
   for (int k = 0; k < nc; ++k) {
@@ -141,17 +147,22 @@ static void check_case(const char* name, const mlb::Basis& B, int level, double 
     }
   CHECK(rows_listed == nblk - nc, "%s: row structure lists %lld of %lld blocks", name, (long long)rows_listed,
         (long long)(nblk - nc));
+  const int P = S.tail;
+  CHECK(P >= 0 && P <= nc && (int)S.tail_cols.size() == nc - P, "%s: tail %d", name, P);
+  CHECK(S.tail_rows == (P < nc ? S.rows - S.ypos[P] : 0), "%s: tail rows", name);
+  for (int q = 0; q < nc - P; ++q) CHECK(S.tail_cols[q] == P + q, "%s: tail columns", name);
   std::vector<int> hof(nc, -1);
   const int heights = (int)S.lvl_ptr.size() - 1;
   for (int h = 0; h < heights; ++h)
     for (int64_t q = S.lvl_ptr[h]; q < S.lvl_ptr[h + 1]; ++q) {
-      CHECK(hof[S.lvl_cols[q]] < 0, "%s: column in two heights", name);
+      CHECK(S.lvl_cols[q] < P && hof[S.lvl_cols[q]] < 0, "%s: column in two heights or in the tail", name);
       hof[S.lvl_cols[q]] = h;
     }
-  for (int k = 0; k < nc; ++k) {
+  for (int k = 0; k < P; ++k) {
     CHECK(hof[k] >= 0, "%s: column %d in no height", name, k);
     for (int64_t b = S.col_ptr[k] + 1; b < S.col_ptr[k + 1]; ++b)
-      CHECK(hof[S.blk_row[b]] > hof[k], "%s: column %d not below %d in the tree", name, k, S.blk_row[b]);
+      CHECK(S.blk_row[b] >= P || hof[S.blk_row[b]] > hof[k], "%s: column %d not below %d in the tree", name, k,
+            S.blk_row[b]);
   }
   {
     std::vector<int> seen(nblk, 0);
@@ -161,6 +172,10 @@ static void check_case(const char* name, const mlb::Basis& B, int level, double 
         CHECK(hof[S.blk_col[b]] == h && !seen[b], "%s: block %lld listed at the wrong height", name, (long long)b);
         seen[b] = 1;
       }
+    for (int64_t b : S.tail_blks) {
+      CHECK(S.blk_col[b] >= P && !seen[b], "%s: tail block %lld", name, (long long)b);
+      seen[b] = 1;
+    }
     for (int64_t b = 0; b < nblk; ++b) CHECK(seen[b], "%s: block %lld in no height", name, (long long)b);
   }
 
@@ -297,9 +312,80 @@ static void check_case(const char* name, const mlb::Basis& B, int level, double 
     }
   }
   double ld = 0.0, qf = 0.0;
-  for (int64_t r = 0; r < nt; ++r) {
+  const int64_t nsp = P < nc ? S.ypos[P] : nt;
+  for (int64_t r = 0; r < nsp; ++r) {
     ld += 2.0 * logd[r];
     qf += y[r] * y[r];
+  }
+  if (P < nc) {
+    // the tail's blocks updated by the columns before it, its data rows, then a dense Cholesky
+    for (int64_t b : S.tail_blks) {
+      const int i = S.blk_row[b], j = S.blk_col[b];
+      const int wi = S.w[i], wj = S.w[j];
+      int64_t p = S.row_ptr[i], r = S.row_ptr[j];
+      while (p < S.row_ptr[i + 1] && r < S.row_ptr[j + 1] && S.row_col[p] < P && S.row_col[r] < P) {
+        if (S.row_col[p] == S.row_col[r]) {
+          const int k = S.row_col[p], wk = S.w[k];
+          for (int x = 0; x < wi; ++x)
+            for (int c = 0; c < wj; ++c) {
+              double s = 0.0;
+              for (int t2 = 0; t2 < wk; ++t2)
+                s += L[S.blk_off[S.row_blk[p]] + x * wk + t2] * L[S.blk_off[S.row_blk[r]] + c * wk + t2];
+              L[S.blk_off[b] + x * wj + c] -= s;
+            }
+          ++p;
+          ++r;
+        } else if (S.row_col[p] < S.row_col[r]) {
+          ++p;
+        } else {
+          ++r;
+        }
+      }
+    }
+    for (int j = P; j < nc; ++j)
+      for (int c = 0; c < S.w[j]; ++c) {
+        double v = z[S.ypos[j] + c];
+        for (int64_t p = S.row_ptr[j]; p < S.row_ptr[j + 1] && S.row_col[p] < P; ++p) {
+          const int k = S.row_col[p], wk = S.w[k];
+          for (int t2 = 0; t2 < wk; ++t2) v -= L[S.blk_off[S.row_blk[p]] + c * wk + t2] * y[S.ypos[k] + t2];
+        }
+        zt[S.ypos[j] + c] = v;
+      }
+    const int64_t T = S.tail_rows, y0 = S.ypos[P];
+    std::vector<double> D((size_t)T * T, 0.0);
+    for (int64_t b : S.tail_blks) {
+      const int i = S.blk_row[b], j = S.blk_col[b];
+      for (int r = 0; r < S.w[i]; ++r)
+        for (int c = 0; c < S.w[j]; ++c) {
+          if (i == j && c > r) continue;   // the lower triangle of a diagonal block, as the device does
+          const double v = L[S.blk_off[b] + r * S.w[j] + c];
+          D[(size_t)(S.ypos[i] - y0 + r) * T + S.ypos[j] - y0 + c] = v;
+          D[(size_t)(S.ypos[j] - y0 + c) * T + S.ypos[i] - y0 + r] = v;
+        }
+    }
+    std::vector<double> yt(T);
+    for (int64_t c = 0; c < T && !broke; ++c) {
+      double piv = D[c * T + c];
+      for (int64_t t2 = 0; t2 < c; ++t2) piv -= D[c * T + t2] * D[c * T + t2];
+      if (!(piv > 0.0)) {
+        broke = true;
+        break;
+      }
+      D[c * T + c] = std::sqrt(piv);
+      for (int64_t r = c + 1; r < T; ++r) {
+        double s = D[r * T + c];
+        for (int64_t t2 = 0; t2 < c; ++t2) s -= D[r * T + t2] * D[c * T + t2];
+        D[r * T + c] = s / D[c * T + c];
+      }
+    }
+    if (!broke)
+      for (int64_t r = 0; r < T; ++r) {
+        double s = zt[y0 + r];
+        for (int64_t t2 = 0; t2 < r; ++t2) s -= D[r * T + t2] * yt[t2];
+        yt[r] = s / D[r * T + r];
+        ld += 2.0 * std::log(D[r * T + r]);
+        qf += yt[r] * yt[r];
+      }
   }
   // dense Cholesky of the same matrix, data vector in the same order
   bool dbroke = false;
@@ -331,8 +417,8 @@ static void check_case(const char* name, const mlb::Basis& B, int level, double 
     dld += 2.0 * std::log(A[r * nt + r]);
     dqf += yy[r] * yy[r];
   }
-  std::printf("%s level %d tau %g: N~ %lld, blocks %lld, heights %d, logdet %.12g / %.12g, quad %.12g / %.12g\n", name,
-              level, tau, (long long)nt, (long long)nblk, heights, ld, dld, qf, dqf);
+  std::printf("%s level %d tau %g tail %d/%d: N~ %lld, blocks %lld, heights %d, logdet %.12g / %.12g, quad %.12g / %.12g\n",
+              name, level, tau, P, nc, (long long)nt, (long long)nblk, heights, ld, dld, qf, dqf);
   CHECK(std::fabs(ld - dld) <= 1e-9 * std::max(1.0, std::fabs(dld)), "%s: log det %g vs %g", name, ld, dld);
   CHECK(std::fabs(qf - dqf) <= 1e-9 * std::max(1.0, std::fabs(dqf)), "%s: quadratic form %g vs %g", name, qf, dqf);
 }
@@ -358,7 +444,7 @@ static void run(const char* name, int64_t n, int d, int leaf, int w, double rho,
   for (int level : {top, top - 1, top - 2, 0})
     for (double tau : {0.0, 0.05, 0.15, 1e9}) {
       if (level < 0) continue;
-      check_case(name, b, level, tau, rho);
+      for (int mode = 0; mode < 4; ++mode) check_case(name, b, level, tau, rho, mode);
     }
 }
 

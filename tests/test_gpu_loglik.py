@@ -358,3 +358,32 @@ def test_sparse_factorization_mle_rho_and_nu_rho():
     assert a["evals"] == b["evals"]
     assert abs(a["nu"] - b["nu"]) < 1e-6 and abs(math.log(a["rho"]) - math.log(b["rho"])) < 1e-6
     assert abs(a["loglik"] - b["loglik"]) < 1e-9 * abs(b["loglik"])
+
+
+@pytest.mark.parametrize("mode", ["none", "all", "auto"])
+@pytest.mark.parametrize("k,n,up,tau,nu", [(1, 1000, 0, 0.05, None), (2, 900, 1, 0.1, None), (4, 700, 1, 0.2, None),
+                                            (2, 650, 0, 0.05, 1.25)])
+def test_sparse_factorization_dense_tail_modes(monkeypatch, mode, k, n, up, tau, nu):
+    """The block factorization with no dense tail, with all of C~^n_W as the
+    dense tail (the block columns only assemble it), and with the tail the
+    analysis picks: the same l~ as the dense path on the same matrix."""
+    require_gpu()
+    if mode == "auto":
+        monkeypatch.delenv("MLBLUP_SPARSE_TAIL", raising=False)
+    else:
+        monkeypatch.setenv("MLBLUP_SPARSE_TAIL", mode)
+    wl, nu, tree, bas, s = _both(k, n, nu)
+    level = tree.max_depth - up
+    g = s.loglik_sparse(dev(wl.z), level, tau)
+    d = s.loglik(dev(wl.z), level, tau=tau)
+    info = s.loglik_sparse_info(level, tau)
+    kap = _cond_sparse(wl, nu, tree, bas, level, tau)
+    tq = max(1e-12, 50 * kap * 2.2e-16)
+    say(f"sparse factor tail={mode} cfg{k} n={n} level={level} tau={tau}: tail rows {info['tail_rows']} of "
+        f"{info['rows']}, block columns {info['block_columns']}")
+    if mode == "none":
+        assert info["tail_rows"] == 0
+    if mode == "all":
+        assert info["tail_rows"] == info["rows"] and info["block_columns"] == 0
+    assert abs(g["logdet"] - d["logdet"]) < tq * d["rows"]
+    assert abs(g["quad"] - d["quad"]) < tq * abs(d["quad"])
