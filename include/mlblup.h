@@ -181,8 +181,12 @@ int mlblup_build_multilevel_basis(mlblup_tree t, int32_t degree_w, double rank_r
  * image mlblup_basis_upload writes. */
 int mlblup_basis_info(mlblup_basis b, int32_t* p, int32_t* levels, int64_t* n_minus_p, int64_t* device_bytes);
 /* Algorithmic bytes of one apply_W or apply_Wt (Sec. 6.2): every cell's
- * m x m orthogonal block read once, 8 sum_cells m^2, plus the N-vector read
- * and the N-vector written, 16 N.  The HBM-roofline unit of the transform. */
+ * orthogonal block read once in the form the transform reads it: the
+ * compact WY form I - Y T Y^T of the K = min(m, p) Householder reflectors
+ * it is the product of (Y: K x m, T: K x K), 8 sum_cells (K m + K^2) (cells
+ * of more than 256 candidates: the dense block, 8 m^2), plus the N-vector
+ * read and the N-vector written, 16 N.  The HBM-roofline unit of the
+ * transform. */
 int mlblup_basis_transform_bytes(mlblup_basis b, int64_t* bytes);
 /* Number of wavelets at level q = 0..t (levels entries). */
 int mlblup_basis_level_counts(mlblup_basis b, int64_t* counts_host);

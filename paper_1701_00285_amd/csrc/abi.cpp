@@ -57,7 +57,7 @@ TransformDev transform_dev(const Basis& B) {
   T.lvl_begin_host = B.lvl_begin.data();
   T.levels = B.levels;
   T.V = (const double*)(img + B.off_V);
-  T.Vt = (const double*)(img + B.off_Vt);
+  T.H = (const double*)(img + B.off_H);
   T.children = (const int32_t*)(img + B.off_children);
   T.n_nodes = (int32_t)B.desc.size();
   return T;
@@ -149,8 +149,8 @@ void image_layout(Basis& B) {
   off = align_up(off + B.d * (int64_t)sizeof(double));
   B.off_V = off;
   off = align_up(off + nv * (int64_t)sizeof(double));
-  B.off_Vt = off;
-  off = align_up(off + nv * (int64_t)sizeof(double));
+  B.off_H = off;
+  off = align_up(off + (int64_t)B.H.size() * (int64_t)sizeof(double));
   B.off_pts = off;
   off = align_up(off + B.n * B.d * (int64_t)sizeof(double));
   B.off_children = off;
@@ -638,7 +638,7 @@ int mlblup_basis_transform_bytes(mlblup_basis b, int64_t* bytes) {
   clear_error();
   if (!b || !bytes) return fail(MLBLUP_EINVAL, "NULL argument");
   int64_t s = 0;
-  for (const auto& nd : b->b.desc) s += (int64_t)nd.m * nd.m;
+  for (const auto& nd : b->b.desc) s += transform_node_doubles(nd);
   *bytes = 8 * s + 16 * b->b.n;
   return MLBLUP_OK;
 }
@@ -716,14 +716,10 @@ int mlblup_basis_upload(mlblup_basis bb, void* dev_buf, int64_t bytes, void* str
   std::vector<int32_t> ex((size_t)B.p * B.d);
   for (int b = 0; b < B.p; ++b)
     for (int k = 0; k < B.d; ++k) ex[(size_t)b * B.d + k] = B.exps[b][k];
-  std::vector<double> vt(B.V.size());
-  for (const NodeDesc& D : B.desc)
-    for (int i = 0; i < D.m; ++i)
-      for (int j = 0; j < D.m; ++j) vt[D.v_off + (size_t)j * D.m + i] = B.V[D.v_off + (size_t)i * D.m + j];
   MLB_HIP(hipMemcpyAsync(base + B.off_exps, ex.data(), ex.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   MLB_HIP(hipMemcpyAsync(base + B.off_rootc, B.root_c.data(), B.d * sizeof(double), hipMemcpyHostToDevice, s));
   MLB_HIP(hipMemcpyAsync(base + B.off_V, B.V.data(), B.V.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  MLB_HIP(hipMemcpyAsync(base + B.off_Vt, vt.data(), vt.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  MLB_HIP(hipMemcpyAsync(base + B.off_H, B.H.data(), B.H.size() * sizeof(double), hipMemcpyHostToDevice, s));
   MLB_HIP(hipMemcpyAsync(base + B.off_pts, B.pts_tree.data(), B.pts_tree.size() * sizeof(double),
                          hipMemcpyHostToDevice, s));
   MLB_HIP(hipMemcpyAsync(base + B.off_children, B.left.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice, s));

@@ -211,6 +211,7 @@ int build_basis(const Tree& t, int32_t w, double rank_rtol, Basis& B) {
   // candidate counts and V offsets are known only bottom-up; process by level
   std::vector<int32_t> m_of(nn, 0), a_of(nn, 0);
   std::vector<std::vector<double>> Vblk(nn);
+  std::vector<std::vector<double>> Hblk(nn);
   std::vector<std::vector<double>> Ms(nn);   // p x a, row-major
   std::vector<std::vector<int32_t>> by_level(B.levels);
   for (int32_t v = 0; v < nn; ++v) by_level[t.depth[v]].push_back(v);
@@ -267,6 +268,31 @@ int build_basis(const Tree& t, int32_t w, double rank_rtol, Basis& B) {
         a_of[v] = a;
         Vblk[v].resize((size_t)m * m);
         form_q(m, p, A, tau, Vblk[v].data());
+        // the same V as a compact WY product (R. Schreiber and C. Van Loan, "A storage-efficient WY
+        // representation for products of Householder transformations", SIAM J. Sci. Stat. Comput.
+        // 10, 1989): V = H_0 ... H_{K-1} = I - Y T Y^T, Y = [h_0 ... h_{K-1}] (h_k = [0 (k entries),
+        // 1, A[k+1..m-1] of column k]), T upper triangular with T_kk = tau_k and column k above the
+        // diagonal -tau_k T_{0..k-1,0..k-1} Y_{0..k-1}^T h_k.  Stored as Y (K rows of m), then T (K x K).
+        Hblk[v].assign((size_t)K * m + (size_t)K * K, 0.0);
+        double* Y = Hblk[v].data();
+        double* Tm = Y + (size_t)K * m;
+        std::vector<double> yh(K);
+        for (int k = 0; k < K; ++k) {
+          double* h = Y + (size_t)k * m;
+          h[k] = 1.0;
+          for (int i = k + 1; i < m; ++i) h[i] = A[(size_t)k * m + i];
+          for (int j = 0; j < k; ++j) {
+            double s = 0.0;
+            for (int i = k; i < m; ++i) s += Y[(size_t)j * m + i] * h[i];
+            yh[j] = s;
+          }
+          for (int r = 0; r < k; ++r) {
+            double s = 0.0;
+            for (int j = r; j < k; ++j) s += Tm[(size_t)r * K + j] * yh[j];
+            Tm[(size_t)r * K + k] = -tau[k] * s;
+          }
+          Tm[(size_t)k * K + k] = tau[k];
+        }
         Ms[v].assign((size_t)p * a, 0.0);
         for (int j = 0; j < a; ++j)
           for (int k = j; k < p; ++k) Ms[v][(size_t)piv[k] * a + j] = A[(size_t)k * m + j];
@@ -317,20 +343,25 @@ int build_basis(const Tree& t, int32_t w, double rank_rtol, Basis& B) {
       soff += a_of[t.right[v]];
     }
   B.scal_total = soff;
-  int64_t voff = 0;
+  int64_t voff = 0, hoff = 0;
   for (int32_t v = 0; v < nn; ++v) {
     NodeDesc& D = B.desc[v];
     D.m = m_of[v];
     D.a = a_of[v];
     D.leaf = t.leaf(v) ? 1 : 0;
-    D.pad = 0;
+    D.nref = std::min(m_of[v], p);
     D.in_off = t.leaf(v) ? t.begin[v] : B.desc[t.left[v]].scal_off;
     D.v_off = voff;
     voff += (int64_t)m_of[v] * m_of[v];
+    D.h_off = hoff;
+    hoff += (int64_t)Hblk[v].size();
   }
   B.V.resize((size_t)voff);
-  for (int32_t v = 0; v < nn; ++v)
+  B.H.resize((size_t)hoff);
+  for (int32_t v = 0; v < nn; ++v) {
     std::copy(Vblk[v].begin(), Vblk[v].end(), B.V.begin() + B.desc[v].v_off);
+    std::copy(Hblk[v].begin(), Hblk[v].end(), B.H.begin() + B.desc[v].h_off);
+  }
   B.lvl_begin.assign(B.levels + 1, 0);
   B.level_nodes.clear();
   for (int q = 0; q < B.levels; ++q) {

@@ -99,11 +99,19 @@ struct TransformDev {
   const int32_t* level_nodes;
   const int32_t* lvl_begin_host;   // host array (levels + 1)
   int32_t levels;
-  const double* V;
-  const double* Vt;
+  const double* V;     // dense m x m blocks (cells too large for the reflector form)
+  const double* H;     // Householder reflectors and scales of every cell (NodeDesc::h_off)
   const int32_t* children = nullptr;  // left children (n_nodes), then right children; -1 for leaves
   int32_t n_nodes = 0;
 };
+// cells of up to kTransformMaxM candidates apply V as its reflectors (one 64-lane wave, up to 4
+// entries per lane); larger ones read the dense m x m block
+constexpr int32_t kTransformMaxM = 256;
+// doubles one transform reads for a cell: the compact WY form (K reflectors of length m and the
+// K x K triangle, stored full), or the m x m block
+inline int64_t transform_node_doubles(const NodeDesc& D) {
+  return D.m <= kTransformMaxM ? (int64_t)D.nref * D.m + (int64_t)D.nref * D.nref : (int64_t)D.m * D.m;
+}
 // vw = W v, vl = L v (vl may be null).  scal: scaling scratch.
 int transform_analysis(const TransformDev& T, const double* v, double* vw, double* vl, double* scal,
                        hipStream_t s);

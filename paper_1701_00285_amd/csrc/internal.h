@@ -41,11 +41,12 @@ struct NodeDesc {
   int64_t in_off;
   int64_t scal_off;
   int64_t w_off;     // first wavelet coefficient in W v
-  int64_t v_off;     // offset (doubles) of the m x m block in the V and V^T arrays
+  int64_t v_off;     // offset (doubles) of the m x m block in the V array
   int32_t m;
   int32_t a;
   int32_t leaf;
-  int32_t pad;
+  int32_t nref;      // Householder reflectors of V = H_0 ... H_{nref-1}: min(m, p)
+  int64_t h_off;     // offset (doubles) in H: V = I - Y T Y^T, Y (nref rows of m), then T (nref x nref)
 };
 
 struct Basis {
@@ -58,6 +59,10 @@ struct Basis {
   // per node (preorder index)
   std::vector<NodeDesc> desc;
   std::vector<double> V;          // row-major m x m blocks, V[i*m + j] = column j (candidate i)
+  // the same blocks as products of Householder reflectors V = H_0 H_1 ... H_{K-1}, H_k = I - tau_k h_k h_k^T,
+  // in compact WY form V = I - Y T Y^T: per node the K reflectors h_k of length m (zero above k, 1 at
+  // k) as the rows of Y, then the upper triangular K x K T (T_kk = tau_k), row-major
+  std::vector<double> H;
   std::vector<int64_t> level_counts;   // wavelets per level q
   // device schedule: node ids grouped by level, level q in [lvl_begin[q], lvl_begin[q+1])
   std::vector<int32_t> level_nodes;
@@ -77,7 +82,7 @@ struct Basis {
   void* dev_base = nullptr;
   int64_t dev_bytes = 0;
   // offsets inside the device image (bytes)
-  int64_t off_desc = 0, off_V = 0, off_Vt = 0, off_pts = 0, off_levels = 0, off_exps = 0;
+  int64_t off_desc = 0, off_V = 0, off_H = 0, off_pts = 0, off_levels = 0, off_exps = 0;
   int64_t off_rootc = 0;      // root-frame centre (d doubles, 256-byte aligned)
   int64_t off_children = 0;   // left, then right child of every node (-1 for leaves): 2 x nodes int32
   bool uploaded = false;

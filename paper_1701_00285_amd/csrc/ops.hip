@@ -1,16 +1,19 @@
 // Multilevel transform kernels (operators W and W^T, Sec. 3.1; steps (1)
 // and (3) of the product chain, Sec. 6.2) and the Krylov vector kernels.
 //
-// Transform: one launch per tree level.  Analysis (v -> W v, L v) runs from
-// the finest level to the root: a cell multiplies its candidate
-// coefficients (leaf: its points' entries of v; internal: the children's
-// scaling coefficients, stored contiguously) by V^T; the first a results
+// Transform: launches of three tree levels each.  Analysis (v -> W v, L v)
+// runs from the finest level to the root: a cell applies V^T to its
+// candidate coefficients (leaf: its points' entries of v; internal: the
+// children's scaling coefficients, stored contiguously); the first a results
 // are its scaling coefficients (passed up; at the root they are L v), the
 // rest its wavelet coefficients, written to their slot of W v.  Synthesis
-// (W^T) runs root to leaves with V.  One 64-lane wave per cell; lane j owns
-// output j (and j+64, ...); the m x m block is read once, coalesced along
-// the lanes (V for analysis, its transpose for synthesis), the m inputs are
-// wave-uniform loads.  The work is HBM-bound: 8 m^2 bytes per cell.
+// (W^T) runs root to leaves with V.  One 64-lane wave per cell.  V is
+// stored in the compact WY form of the Householder reflectors it was built
+// from, V = H_0 ... H_{K-1} = I - Y T Y^T (K = min(m, p) reflectors of length
+// m and a K x K triangle), so a cell reads K m + K^2 doubles instead of m^2:
+// the wave stages Y and T in LDS and applies them in three steps of serial
+// dot products (wy_apply).  Cells with more than 256 candidates read the
+// dense block instead.
 //
 // Reductions: every dot product is a fixed grid of kRedBlocks blocks, each
 // reducing a fixed slice in a fixed tree order, then one block adding the
@@ -35,41 +38,181 @@ namespace {
 constexpr int kT = 256;
 constexpr int kWavesPerBlock = 4;
 
+// sum over the 64 lanes in a fixed order (a tree into lane 0), the same value on every lane
+__device__ __forceinline__ double wave_allsum(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+  return __shfl(x, 0, 64);
+}
+
+constexpr int kPer = kTransformMaxM / 64;   // entries per lane of a cell's vector
+constexpr int kHBuf = 2048;                 // doubles of LDS per wave
+
+// x <- (I - Y T^T Y^T) x (analysis, V^T x) or (I - Y T Y^T) x (synthesis, V x) for one cell held by
+// one wave (x: entries lane + 64 q).  Three steps, each lane a serial dot product from LDS, so no
+// cross-lane reduction chain: w = Y^T x (lane k: row k of Y against x), u = T^T w or T w (lane k:
+// column or row k of the triangle against w), x -= Y u (lane i: column i of Y against u).  Y (row
+// stride m | 1, odd, so that the lanes reading different rows hit different banks), T and the three
+// vectors sit in the wave's LDS buffer.  A cell too large for the buffer applies its K reflectors
+// one after the other from global memory instead, each a wave-wide dot product.
+__device__ __forceinline__ void wy_apply(const double* __restrict__ Rg, int m, int K, int lane, bool analysis,
+                                         double* __restrict__ buf, double (&x)[kPer]) {
+  const int ys = m | 1;
+  const int64_t need = (int64_t)K * ys + (int64_t)K * K + m + 2 * K;
+  const double* Tg = Rg + (int64_t)K * m;
+  if (need <= kHBuf) {
+    double* Ys = buf;
+    double* Ts = Ys + K * ys;
+    double* xs = Ts + K * K;
+    double* ws = xs + m;
+    double* us = ws + K;
+    for (int e = lane; e < K * m; e += 64) {
+      const int k = e / m, i = e - k * m;
+      Ys[k * ys + i] = Rg[e];
+    }
+    for (int e = lane; e < K * K; e += 64) Ts[e] = Tg[e];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = lane + 64 * q;
+      if (i < m) xs[i] = x[q];
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int k = lane; k < K; k += 64) {
+      // two partial sums, 8 LDS reads in flight per step
+      double s0 = 0.0, s1 = 0.0;
+      int i = k;
+#pragma unroll 4
+      for (; i + 1 < m; i += 2) {
+        s0 = fma(Ys[k * ys + i], xs[i], s0);
+        s1 = fma(Ys[k * ys + i + 1], xs[i + 1], s1);
+      }
+      if (i < m) s0 = fma(Ys[k * ys + i], xs[i], s0);
+      const double s = s0 + s1;   // h_k is zero above k
+      ws[k] = s;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int k = lane; k < K; k += 64) {
+      double s = 0.0;
+      if (analysis) {
+        for (int j = 0; j <= k; ++j) s = fma(Ts[j * K + k], ws[j], s);
+      } else {
+        for (int j = k; j < K; ++j) s = fma(Ts[k * K + j], ws[j], s);
+      }
+      us[k] = s;
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = lane + 64 * q;
+      if (i < m) {
+        double s0 = x[q], s1 = 0.0;
+        const int kmax = i < K ? i + 1 : K;   // h_k[i] = 0 for k > i
+        int k = 0;
+#pragma unroll 4
+        for (; k + 1 < kmax; k += 2) {
+          s0 = fma(-Ys[k * ys + i], us[k], s0);
+          s1 = fma(-Ys[(k + 1) * ys + i], us[k + 1], s1);
+        }
+        if (k < kmax) s0 = fma(-Ys[k * ys + i], us[k], s0);
+        x[q] = s0 + s1;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    return;
+  }
+  for (int st = 0; st < K; ++st) {
+    const int k = analysis ? st : K - 1 - st;
+    const double tk = Tg[(int64_t)k * K + k];
+    if (tk == 0.0) continue;   // wave-uniform: an identity reflector
+    const double* h = Rg + (int64_t)k * m;
+    double hv[kPer];
+    double d = 0.0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = lane + 64 * q;
+      hv[q] = i < m ? h[i] : 0.0;
+      d = fma(hv[q], x[q], d);
+    }
+    const double c = tk * wave_allsum(d);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) x[q] = fma(-c, hv[q], x[q]);
+  }
+}
+
+// analysis of one cell: its candidate coefficients times V^T;
+// the first a results are its scaling coefficients (to the parent's slot, or L v at the root),
+// the rest its wavelet coefficients
 __device__ __forceinline__ void analysis_node(const NodeDesc& D, int lane, const double* __restrict__ V,
+                                              const double* __restrict__ H, double* __restrict__ buf,
                                               const double* __restrict__ v, double* __restrict__ scal,
                                               double* __restrict__ vw, double* __restrict__ vl) {
   const double* cin = D.leaf ? v + D.in_off : scal + D.in_off;
-  const double* B = V + D.v_off;
   const int m = D.m;
+  auto put = [&](int j, double val) {
+    if (j < D.a) {
+      if (D.scal_off >= 0) scal[D.scal_off + j] = val;
+      else if (vl) vl[j] = val;
+    } else {
+      vw[D.w_off + (j - D.a)] = val;
+    }
+  };
+  if (m <= kTransformMaxM) {
+    double x[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = lane + 64 * q;
+      x[q] = i < m ? cin[i] : 0.0;
+    }
+    wy_apply(H + D.h_off, m, D.nref, lane, true, buf, x);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int j = lane + 64 * q;
+      if (j < m) put(j, x[q]);
+    }
+    return;
+  }
+  const double* B = V + D.v_off;
   for (int j = lane; j < m; j += 64) {
     double acc = 0.0;
 #pragma unroll 8
     for (int i = 0; i < m; ++i) acc = fma(B[(int64_t)i * m + j], cin[i], acc);
-    if (j < D.a) {
-      if (D.scal_off >= 0) scal[D.scal_off + j] = acc;
-      else if (vl) vl[j] = acc;
-    } else {
-      vw[D.w_off + (j - D.a)] = acc;
-    }
+    put(j, acc);
   }
 }
 
-__device__ __forceinline__ void synthesis_node(const NodeDesc& D, int lane, const double* __restrict__ Vt,
+// synthesis of one cell: V times [scaling coefficients from the parent (zero at the root when
+// vl is null); wavelet coefficients], to the children's slots or to v
+__device__ __forceinline__ void synthesis_node(const NodeDesc& D, int lane, const double* __restrict__ V,
+                                               const double* __restrict__ H, double* __restrict__ buf,
                                                const double* __restrict__ vw, const double* __restrict__ vl,
                                                double* __restrict__ scal, double* __restrict__ v) {
-  const double* B = Vt + D.v_off;
   const int m = D.m, a = D.a;
   const double* cs = D.scal_off >= 0 ? scal + D.scal_off : vl;  // may be null at the root
   const double* cw = vw + D.w_off - a;
   double* out = D.leaf ? v + D.in_off : scal + D.in_off;
+  if (m <= kTransformMaxM) {
+    double x[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = lane + 64 * q;
+      x[q] = i < m ? (i < a ? (cs ? cs[i] : 0.0) : cw[i]) : 0.0;
+    }
+    wy_apply(H + D.h_off, m, D.nref, lane, false, buf, x);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = lane + 64 * q;
+      if (i < m) out[i] = x[q];
+    }
+    return;
+  }
+  const double* B = V + D.v_off;
   for (int i = lane; i < m; i += 64) {
     double acc = 0.0;
     if (cs) {
 #pragma unroll 8
-      for (int j = 0; j < a; ++j) acc = fma(B[(int64_t)j * m + i], cs[j], acc);
+      for (int j = 0; j < a; ++j) acc = fma(B[(int64_t)i * m + j], cs[j], acc);
     }
 #pragma unroll 8
-    for (int j = a; j < m; ++j) acc = fma(B[(int64_t)j * m + i], cw[j], acc);
+    for (int j = a; j < m; ++j) acc = fma(B[(int64_t)i * m + j], cw[j], acc);
     out[i] = acc;
   }
 }
@@ -95,14 +238,15 @@ __device__ __forceinline__ int32_t group_cell(const int32_t* __restrict__ childr
 __global__ __launch_bounds__(kT) void analysis_group(const NodeDesc* __restrict__ desc,
                                                      const int32_t* __restrict__ children, int32_t n_nodes,
                                                      const int32_t* __restrict__ roots, int nlev,
-                                                     const double* __restrict__ V, const double* __restrict__ v,
-                                                     double* __restrict__ scal, double* __restrict__ vw,
-                                                     double* __restrict__ vl) {
+                                                     const double* __restrict__ V, const double* __restrict__ H,
+                                                     const double* __restrict__ v, double* __restrict__ scal,
+                                                     double* __restrict__ vw, double* __restrict__ vl) {
+  __shared__ double hbuf[kWavesPerBlock][kHBuf];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int32_t r = roots[blockIdx.x];
   for (int rel = nlev - 1; rel >= 0; --rel) {
     const int32_t u = group_cell(children, n_nodes, r, rel, wave);
-    if (u >= 0) analysis_node(desc[u], lane, V, v, scal, vw, vl);
+    if (u >= 0) analysis_node(desc[u], lane, V, H, hbuf[wave], v, scal, vw, vl);
     __syncthreads();
   }
 }
@@ -110,14 +254,15 @@ __global__ __launch_bounds__(kT) void analysis_group(const NodeDesc* __restrict_
 __global__ __launch_bounds__(kT) void synthesis_group(const NodeDesc* __restrict__ desc,
                                                       const int32_t* __restrict__ children, int32_t n_nodes,
                                                       const int32_t* __restrict__ roots, int nlev,
-                                                      const double* __restrict__ Vt, const double* __restrict__ vw,
-                                                      const double* __restrict__ vl, double* __restrict__ scal,
-                                                      double* __restrict__ v) {
+                                                      const double* __restrict__ V, const double* __restrict__ H,
+                                                      const double* __restrict__ vw, const double* __restrict__ vl,
+                                                      double* __restrict__ scal, double* __restrict__ v) {
+  __shared__ double hbuf[kWavesPerBlock][kHBuf];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int32_t r = roots[blockIdx.x];
   for (int rel = 0; rel < nlev; ++rel) {
     const int32_t u = group_cell(children, n_nodes, r, rel, wave);
-    if (u >= 0) synthesis_node(desc[u], lane, Vt, vw, vl, scal, v);
+    if (u >= 0) synthesis_node(desc[u], lane, V, H, hbuf[wave], vw, vl, scal, v);
     __syncthreads();
   }
 }
@@ -295,7 +440,7 @@ int transform_analysis(const TransformDev& T, const double* v, double* vw, doubl
     const int32_t lb = T.lvl_begin_host[qlo], cnt = T.lvl_begin_host[qlo + 1] - lb;
     if (cnt <= 0) continue;
     hipLaunchKernelGGL(analysis_group, dim3((unsigned)cnt), dim3(kT), 0, s, T.desc, T.children, T.n_nodes,
-                       T.level_nodes + lb, qhi - qlo + 1, T.V, v, scal, vw, vl);
+                       T.level_nodes + lb, qhi - qlo + 1, T.V, T.H, v, scal, vw, vl);
   }
   return hip_check(hipGetLastError(), "analysis launch");
 }
@@ -307,7 +452,7 @@ int transform_synthesis(const TransformDev& T, const double* vw, const double* v
     const int32_t lb = T.lvl_begin_host[qlo], cnt = T.lvl_begin_host[qlo + 1] - lb;
     if (cnt <= 0) continue;
     hipLaunchKernelGGL(synthesis_group, dim3((unsigned)cnt), dim3(kT), 0, s, T.desc, T.children, T.n_nodes,
-                       T.level_nodes + lb, qhi - qlo + 1, T.Vt, vw, vl, scal, v);
+                       T.level_nodes + lb, qhi - qlo + 1, T.V, T.H, vw, vl, scal, v);
   }
   return hip_check(hipGetLastError(), "synthesis launch");
 }

@@ -5,6 +5,7 @@
 // or an undefined operation anywhere in those sources stops the run.
 // Compiled and run by tests/test_host_sanitizers.py.  Exit status 0 and the
 // line "sanitize driver: ok" mean no finding.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -42,6 +43,74 @@ static int run_case(const char* name, std::vector<double> pts, int64_t n, int d,
   }
   for (double v : b.V) g_sink += v;
   for (const auto& D : b.desc) g_sink += (double)(D.in_off + D.w_off + D.v_off + D.m + D.a);
+  // the compact WY form of every block: I - Y T Y^T equals V, and T's diagonal holds the reflectors'
+  // scales (H_k h_k = -h_k, i.e. tau_k h_k.h_k = 2 for every reflector that is not the identity)
+  double worst = 0.0;
+  for (const auto& D : b.desc) {
+    const int m = D.m, K = D.nref;
+    if (m == 0) continue;
+    if (K != std::min(m, b.p)) {
+      std::printf("%s: node with m=%d has %d reflectors\n", name, m, K);
+      return 1;
+    }
+    const double* Y = &b.H[(size_t)D.h_off];
+    const double* T = Y + (size_t)K * m;
+    for (int k = 0; k < K; ++k) {
+      double hh = 0.0;
+      for (int i = 0; i < m; ++i) hh += Y[(size_t)k * m + i] * Y[(size_t)k * m + i];
+      const double tk = T[(size_t)k * K + k];
+      if (tk != 0.0) worst = std::max(worst, std::fabs(tk * hh - 2.0));
+      for (int r = k + 1; r < K; ++r) worst = std::max(worst, std::fabs(T[(size_t)r * K + k]));   // upper
+    }
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        double s = i == j ? 1.0 : 0.0;
+        for (int k = 0; k < K; ++k) {
+          double tyj = 0.0;
+          for (int l = 0; l < K; ++l) tyj += T[(size_t)k * K + l] * Y[(size_t)l * m + j];
+          s -= Y[(size_t)k * m + i] * tyj;
+        }
+        worst = std::max(worst, std::fabs(s - b.V[(size_t)D.v_off + (size_t)i * m + j]));
+      }
+  }
+  // the transform kernels' three steps (w = Y^T x, u = T^T w or T w, x - Y u, with their index
+  // ranges) against V^T x and V x from the dense block
+  for (const auto& D : b.desc) {
+    const int m = D.m, K = D.nref;
+    if (m == 0 || m > 256) continue;
+    const double* Y = &b.H[(size_t)D.h_off];
+    const double* T = Y + (size_t)K * m;
+    std::vector<double> x(m), w(K), u(K);
+    for (int i = 0; i < m; ++i) x[i] = std::sin(0.7 * i + 0.1 * D.v_off);
+    for (int analysis = 0; analysis < 2; ++analysis) {
+      for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int i = k; i < m; ++i) s += Y[(size_t)k * m + i] * x[i];
+        w[k] = s;
+      }
+      for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        if (analysis)
+          for (int j = 0; j <= k; ++j) s += T[(size_t)j * K + k] * w[j];
+        else
+          for (int j = k; j < K; ++j) s += T[(size_t)k * K + j] * w[j];
+        u[k] = s;
+      }
+      for (int i = 0; i < m; ++i) {
+        double s = x[i];
+        const int kmax = i < K ? i + 1 : K;
+        for (int k = 0; k < kmax; ++k) s -= Y[(size_t)k * m + i] * u[k];
+        double ref = 0.0;
+        for (int j = 0; j < m; ++j)
+          ref += (analysis ? b.V[(size_t)D.v_off + (size_t)j * m + i] : b.V[(size_t)D.v_off + (size_t)i * m + j]) * x[j];
+        worst = std::max(worst, std::fabs(s - ref));
+      }
+    }
+  }
+  if (worst > 1e-12) {
+    std::printf("%s: compact WY form differs from V by %g\n", name, worst);
+    return 1;
+  }
   for (int32_t level = 0; level < b.levels; ++level) {
     for (double tau : {0.0, 0.05, 0.2, 1e9}) {
       mlb::Pattern P;

@@ -85,9 +85,11 @@ def test_basis_level_counts_complete_tree():
 
 
 def test_transform_bytes_count_every_block_once():
-    """Algorithmic bytes of one transform: 8 sum m^2 over the cells (a leaf's
-    m is its point count, an internal cell's the sum of its children's
-    scaling counts, a = min(m, p) for generic points) + 16 N."""
+    """Algorithmic bytes of one transform: every cell's block read once in
+    its compact WY form, K = min(m, p) reflectors of length m and the K x K
+    triangle, 8 sum (K m + K^2) over the cells (a leaf's m is its point
+    count, an internal cell's the sum of its children's scaling counts,
+    a = min(m, p) for generic points) + 16 N."""
     pts = synth.uniform_cloud(3000, 3, seed=10)
     t = Tree(pts, 40)
     b = Basis(t, 2)
@@ -97,11 +99,13 @@ def test_transform_bytes_count_every_block_once():
     def walk(v):
         if left[v] < 0:
             m = int(end[v] - begin[v])
-            return min(m, b.p), m * m
+            k = min(m, b.p)
+            return k, k * m + k * k
         al, sl = walk(left[v])
         ar, sr = walk(right[v])
         m = al + ar
-        return min(m, b.p), m * m + sl + sr
+        k = min(m, b.p)
+        return k, k * m + k * k + sl + sr
 
     _, s = walk(0)
     assert b.transform_bytes() == 8 * s + 16 * 3000
