@@ -250,3 +250,25 @@ def test_fp64_solve_resumes_its_recurrence(precond):
     assert float(torch.linalg.norm(g2 - full) / torch.linalg.norm(full)) < 1e-9
     with pytest.raises(MlblupError):
         s.solve(zw, PcgOptions(rtol=1e-10, max_iter=10, precision=FP64, state=state, resume=True))  # no x0
+
+
+def test_trend_of_351_terms_d25():
+    """The paper's largest-p setting class: d = 25, total degree 2 (p = 351
+    trend terms).  Leaves of up to 128 points hold no wavelets (s <= p, all
+    scaling), internal cells up to 702 candidates: the transform takes its
+    reflector chain (leaves) and dense-block (m > 256) paths.  FP64 predict
+    against the oracle's dense classic BLUP."""
+    torch = require_gpu()
+    from paper_1701_00285_amd import FP64, PcgOptions, Solver
+    n, d, nt = 1500, 25, 40
+    pts = synth.uniform_cloud(n, d, 2501)
+    tgt = synth.uniform_cloud(nt, d, 2502)
+    z = np.sin(3.0 * pts[:, 0]) + pts[:, 1] * pts[:, 2] + 0.3 * synth.standard_normal(n, 2503)
+    ref = OB.classic_blup(pts, z, tgt, 2, 0.5, 2.0)
+    s = Solver(pts, 2, 128, 0.5, 2.0, 1.0, max_targets=nt)
+    assert s.p == 351
+    say(f"p=351 d=25 n={n}: levels {s.basis.levels}, transform bytes {s.basis.transform_bytes()}")
+    out = s.predict(dev(z), dev(tgt), PcgOptions(rtol=1e-12, max_iter=4000, precision=FP64))
+    assert out["info"]["relres_fp64"] <= 1e-12
+    assert relerr(host(out["zhat"]), ref.zhat) < 1e-8
+    assert relerr(host(out["gamma"]), ref.gamma) < 1e-8
