@@ -48,16 +48,17 @@ constexpr int kPer = kTransformMaxM / 64;   // entries per lane of a cell's vect
 constexpr int kHBuf = 2048;                 // doubles of LDS per wave
 
 // x <- (I - Y T^T Y^T) x (analysis, V^T x) or (I - Y T Y^T) x (synthesis, V x) for one cell held by
-// one wave (x: entries lane + 64 q).  Three steps, each lane a serial dot product from LDS, so no
-// cross-lane reduction chain: w = Y^T x (lane k: row k of Y against x), u = T^T w or T w (lane k:
-// column or row k of the triangle against w), x -= Y u (lane i: column i of Y against u).  Y (row
-// stride m | 1, odd, so that the lanes reading different rows hit different banks), T and the three
-// vectors sit in the wave's LDS buffer.  A cell too large for the buffer applies its K reflectors
+// one wave (x: entries lane + 64 q).  Three steps of serial dot products from LDS, so no cross-lane
+// reduction chain: w = Y^T x (64 / K lanes share row k of Y, then their sums are added), u = T^T w
+// or T w (lane k: column or row k of the triangle against w), x -= Y u (lane i: column i of Y
+// against u).  Y (row stride m | 1, odd, so that the lanes reading different rows hit different
+// banks), T, the three vectors and the partial sums sit in the wave's LDS buffer.  A cell too large for the buffer applies its K reflectors
 // one after the other from global memory instead, each a wave-wide dot product.
 __device__ __forceinline__ void wy_apply(const double* __restrict__ Rg, int m, int K, int lane, bool analysis,
                                          double* __restrict__ buf, double (&x)[kPer]) {
   const int ys = m | 1;
-  const int64_t need = (int64_t)K * ys + (int64_t)K * K + m + 2 * K;
+  const int G = K > 0 && K <= 64 ? 64 / K : 1;   // lanes sharing one dot product of the first step
+  const int64_t need = (int64_t)K * ys + (int64_t)K * K + m + 2 * K + (int64_t)G * K;
   const double* Tg = Rg + (int64_t)K * m;
   if (need <= kHBuf) {
     double* Ys = buf;
@@ -65,6 +66,7 @@ __device__ __forceinline__ void wy_apply(const double* __restrict__ Rg, int m, i
     double* xs = Ts + K * K;
     double* ws = xs + m;
     double* us = ws + K;
+    double* ps = us + K;
     for (int e = lane; e < K * m; e += 64) {
       const int k = e / m, i = e - k * m;
       Ys[k * ys + i] = Rg[e];
@@ -76,18 +78,29 @@ __device__ __forceinline__ void wy_apply(const double* __restrict__ Rg, int m, i
       if (i < m) xs[i] = x[q];
     }
     __builtin_amdgcn_wave_barrier();
-    for (int k = lane; k < K; k += 64) {
-      // two partial sums, 8 LDS reads in flight per step
-      double s0 = 0.0, s1 = 0.0;
-      int i = k;
+    // w = Y^T x: G lanes per row k (lane l: k = l mod K, g = l / K) each sum every G-th entry from
+    // k on (h_k is zero above k), then lane k adds the G partial sums in order
+    if (G > 1) {
+      const int k = lane % K, g = lane / K;
+      if (g < G) {
+        double s = 0.0;
 #pragma unroll 4
-      for (; i + 1 < m; i += 2) {
-        s0 = fma(Ys[k * ys + i], xs[i], s0);
-        s1 = fma(Ys[k * ys + i + 1], xs[i + 1], s1);
+        for (int i = k + g; i < m; i += G) s = fma(Ys[k * ys + i], xs[i], s);
+        ps[g * K + k] = s;
       }
-      if (i < m) s0 = fma(Ys[k * ys + i], xs[i], s0);
-      const double s = s0 + s1;   // h_k is zero above k
-      ws[k] = s;
+      __builtin_amdgcn_wave_barrier();
+      if (lane < K) {
+        double s = ps[lane];
+        for (int q = 1; q < G; ++q) s += ps[q * K + lane];
+        ws[lane] = s;
+      }
+    } else {
+      for (int k = lane; k < K; k += 64) {
+        double s = 0.0;
+#pragma unroll 4
+        for (int i = k; i < m; ++i) s = fma(Ys[k * ys + i], xs[i], s);
+        ws[k] = s;
+      }
     }
     __builtin_amdgcn_wave_barrier();
     for (int k = lane; k < K; k += 64) {

@@ -83,9 +83,14 @@ static int run_case(const char* name, std::vector<double> pts, int64_t n, int d,
     std::vector<double> x(m), w(K), u(K);
     for (int i = 0; i < m; ++i) x[i] = std::sin(0.7 * i + 0.1 * D.v_off);
     for (int analysis = 0; analysis < 2; ++analysis) {
+      const int G = K <= 64 ? 64 / K : 1;   // lanes sharing a row of Y in the kernel
       for (int k = 0; k < K; ++k) {
         double s = 0.0;
-        for (int i = k; i < m; ++i) s += Y[(size_t)k * m + i] * x[i];
+        for (int g = 0; g < G; ++g) {
+          double part = 0.0;
+          for (int i = k + g; i < m; i += G) part += Y[(size_t)k * m + i] * x[i];
+          s += part;
+        }
         w[k] = s;
       }
       for (int k = 0; k < K; ++k) {
