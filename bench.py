@@ -371,7 +371,7 @@ def loglik_bench(k: int, n: int, reps: int = 3, quick: bool = False):
 
 
 def loglik_sparse_bench(k: int, n: int, reps: int = 3, dense: bool = True, nu: float = 0.0, rho: float = 0.0,
-                        taus=(0.02, 0.05, 0.1)):
+                        taus=(0.02, 0.05, 0.1), levels: int = 2):
     """Estimator with the sparse block factorization: l~_n at levels t and
     t - 1 for several tau, only the kept blocks formed and factored (host
     analysis timed on its own: pattern, minimum-degree order, block
@@ -400,7 +400,7 @@ def loglik_sparse_bench(k: int, n: int, reps: int = 3, dense: bool = True, nu: f
     top = s.basis.levels - 1
     res = {"workload": f"cfg{k} generator, n={n}, d={wl.d}, nu={nu}, rho={rho}, leaf={wl.leaf_max}, "
                        f"p={s.p}", "setup_s": round(setup, 3), "cases": {}}
-    for level in (top, top - 1):
+    for level in (top, top - 1)[:levels]:
         for tau in taus:
             key = f"level {level} tau {tau}"
             t0 = time.perf_counter()
@@ -929,6 +929,8 @@ def main():
     ap.add_argument("--taus", default="0.02,0.05,0.1", help="with --loglik-sparse: comma-separated tau values")
     ap.add_argument("--no-dense", action="store_true",
                     help="with --loglik-sparse: skip the dense sparsified path beside it (large n)")
+    ap.add_argument("--sparse-levels", type=int, choices=(1, 2), default=2,
+                    help="with --loglik-sparse: level t only (1) or levels t and t - 1 (2)")
     ap.add_argument("--segment", choices=("fp64-start", "fp64-resume", "mixed"), default=None,
                     help="one segment of a FP64 vs mixed comparison split over several runs (default workload 5): "
                          "the FP64 solve for --max-iter iterations, its exact continuation, or the mixed solve")
@@ -955,7 +957,7 @@ def main():
 
     if a.loglik_sparse:
         loglik_sparse_bench(a.config or 2, a.loglik_sparse, dense=not a.no_dense, nu=a.nu, rho=a.rho,
-                            taus=tuple(float(v) for v in a.taus.split(",")))
+                            taus=tuple(float(v) for v in a.taus.split(",")), levels=a.sparse_levels)
         return
 
     if a.cpu_oracle:

@@ -50,6 +50,8 @@ constexpr int kLd = kB + 1;           // LDS row stride (doubles)
 
 inline int64_t al256(int64_t b) { return (b + 255) / 256 * 256; }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 // ---- 1. assembly of the kept blocks ---------------------------------------------
 template <int NU2>
 __global__ __launch_bounds__(kT) void sp_assemble(const double* __restrict__ pts, int d, double zs, double sigma2,
@@ -197,14 +199,20 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
   const int64_t b = lvl[blockIdx.x];
   const int i = blk_row[b], j = blk_col[b];
   const int wi = w[i], wj = w[j];
-  const int tr = t >> 4, tc = t & 15;
   double* A = L + blk_off[b];
-  double acc[4][4];
+  // the sum of the products on the FP64 matrix cores: each wave a 32 x 32 quadrant of the 64 x 64
+  // block as 2 x 2 tiles of v_mfma_f64_16x16x4f64 (lane l supplies row l % 16, k l / 16 of the left
+  // operand and k l / 16, column l % 16 of the right one; a tile's result lands in lane l as rows
+  // l / 16 + 4 j, column l % 16, unlike the FP32 form), the k dimension in steps of 4 with zero rows
+  // past w_k
+  const int wave = t >> 6, lane = t & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  d4 acc[2][2];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      acc[r][c] = (4 * tr + r < wi && 4 * tc + c < wj) ? A[(4 * tr + r) * wj + 4 * tc + c] : 0.0;
+    for (int c = 0; c < 2; ++c) acc[a][c] = d4{0.0, 0.0, 0.0, 0.0};
   if (t == 0) {
     cur[0] = row_ptr[i];
     cur[1] = row_ptr[j];
@@ -241,6 +249,7 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
     if (n == 0) break;
     for (int m = 0; m < n; ++m) {
       const int wk = w[pk[m]];
+      const int wk4 = (wk + 3) & ~3;
       const double* la = L + blk_off[pa[m]];
       const double* lb = L + blk_off[pb[m]];
       __syncthreads();
@@ -252,25 +261,37 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
         const int r = e / wk, q = e - r * wk;
         Lb[q * kLd + r] = lb[e];
       }
+      for (int e = t; e < (wk4 - wk) * kB; e += kT) {   // the padded k rows are zero
+        const int q = wk + e / kB, r = e % kB;
+        La[q * kLd + r] = 0.0;
+        Lb[q * kLd + r] = 0.0;
+      }
       __syncthreads();
-      for (int q = 0; q < wk; ++q) {
-        double av[4], bv[4];
+      for (int k4 = 0; k4 < wk4; k4 += 4) {
+        double x[2], y[2];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) av[r] = La[q * kLd + 4 * tr + r];
+        for (int a = 0; a < 2; ++a) x[a] = La[(k4 + lk) * kLd + wr + a * 16 + li];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) bv[c] = Lb[q * kLd + 4 * tc + c];
+        for (int c = 0; c < 2; ++c) y[c] = Lb[(k4 + lk) * kLd + wc + c * 16 + li];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[r][c] = fma(-av[r], bv[c], acc[r][c]);
+          for (int c = 0; c < 2; ++c) acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a], y[c], acc[a][c], 0, 0, 0);
       }
     }
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      if (4 * tr + r < wi && 4 * tc + c < wj) A[(4 * tr + r) * wj + 4 * tc + c] = acc[r][c];
+    for (int jj = 0; jj < 4; ++jj) {
+      const int r = wr + a * 16 + lk + 4 * jj;
+      if (r >= wi) continue;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int col = wc + c * 16 + li;
+        if (col < wj) A[r * wj + col] -= acc[a][c][jj];
+      }
+    }
 }
 
 // Cholesky of the diagonal block of column cols[x], its inverse, y_j and log L_rr
