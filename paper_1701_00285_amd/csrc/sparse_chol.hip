@@ -157,6 +157,10 @@ __global__ __launch_bounds__(kT) void sp_assemble(const double* __restrict__ pts
 }
 
 // ---- 2. left-looking factorization, one elimination-tree height at a time ----------
+// the matched columns of one chunk: at most kMatch (the merge of one batch of 64 entries of row j's
+// structure adds at most 64, and a batch starts only while 64 places are left)
+constexpr int kMatch = 128;
+
 // blocks [0, nblk): update block lvl[x]; then one data block per column cols[x - nblk]; only the
 // columns k < kmax contribute (all earlier ones inside the block part; those before the dense tail
 // for the tail's blocks)
@@ -171,29 +175,33 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
                                                 const double* __restrict__ zw, const int64_t* __restrict__ row0,
                                                 const int64_t* __restrict__ ypos, const double* __restrict__ y,
                                                 double* __restrict__ zt, int kmax) {
-  __shared__ double La[kB * kLd];   // L_ik transposed: La[t][r]
-  __shared__ double Lb[kB * kLd];   // L_jk transposed: Lb[t][c]
-  __shared__ int64_t pa[64], pb[64];
-  __shared__ int32_t pk[64];
-  __shared__ int np;
+  __shared__ double La[kB * kLd];   // L_ik transposed: La[q][r]
+  __shared__ double Lb[kB * kLd];   // L_jk transposed: Lb[q][c]
+  __shared__ int64_t pa[kMatch], pb[kMatch];
+  __shared__ int32_t pk[kMatch];
+  __shared__ int np, fin;
   __shared__ int64_t cur[2];
   const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
   if ((int64_t)blockIdx.x >= nblk) {
-    // data block of column j: z_j - sum_k L_jk y_k
+    // data block of column j: z_j - sum_k L_jk y_k; wave v takes the entries v, v + 4, ... of row j's
+    // structure, lane r the row r, and the four partial sums are added in a fixed order
     const int j = cols[blockIdx.x - nblk];
     const int wj = w[j];
-    if (t < wj) {
-      double v = zw[row0[j] + t];
-      for (int64_t p = row_ptr[j]; p < row_ptr[j + 1]; ++p) {
+    double v = 0.0;
+    if (lane < wj) {
+      for (int64_t p = row_ptr[j] + wave; p < row_ptr[j + 1]; p += 4) {
         const int k = row_col[p];
         if (k >= kmax) break;
         const int wk = w[k];
-        const double* lb = L + blk_off[row_blk[p]] + (int64_t)t * wk;
+        const double* lb = L + blk_off[row_blk[p]] + (int64_t)lane * wk;
         const double* yk = y + ypos[k];
-        for (int q = 0; q < wk; ++q) v = fma(-lb[q], yk[q], v);
+        for (int q = 0; q < wk; ++q) v = fma(lb[q], yk[q], v);
       }
-      zt[ypos[j] + t] = v;
     }
+    La[wave * kB + lane] = v;
+    __syncthreads();
+    if (t < wj) zt[ypos[j] + t] = zw[row0[j] + t] - ((La[t] + La[kB + t]) + (La[2 * kB + t] + La[3 * kB + t]));
     return;
   }
   const int64_t b = lvl[blockIdx.x];
@@ -205,7 +213,6 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
   // operand and k l / 16, column l % 16 of the right one; a tile's result lands in lane l as rows
   // l / 16 + 4 j, column l % 16, unlike the FP32 form), the k dimension in steps of 4 with zero rows
   // past w_k
-  const int wave = t >> 6, lane = t & 63;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
   d4 acc[2][2];
@@ -216,67 +223,106 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
   if (t == 0) {
     cur[0] = row_ptr[i];
     cur[1] = row_ptr[j];
+    fin = 0;
   }
   const int64_t ei = row_ptr[i + 1], ej = row_ptr[j + 1];
+  // staging: thread t holds row sr = t / 4 of both blocks at the columns sq + 4 s
+  const int sr = t >> 2, sq = t & 3;
+  double ra[16], rb[16];
   for (;;) {
     __syncthreads();
-    if (t == 0) {
-      // the next matched columns k of the row structures of i and j
+    if (wave == 0) {
+      // the next matched columns k of the row structures of i and j (ascending lists of distinct
+      // columns): each lane takes one entry of j's list and finds it in i's by bisection; the
+      // matches keep the order of j's list
       int64_t p = cur[0], q = cur[1];
-      int n = 0;
-      while (n < 64 && p < ei && q < ej) {
-        const int kp = row_col[p], kq = row_col[q];
-        if (kp >= kmax || kq >= kmax) break;   // ascending lists: no match below kmax is left
-        if (kp == kq) {
-          pa[n] = row_blk[p];
-          pb[n] = row_blk[q];
-          pk[n] = kp;
-          ++n;
-          ++p;
-          ++q;
-        } else if (kp < kq) {
-          ++p;
-        } else {
-          ++q;
+      int n = 0, stop = fin;
+      while (!stop && n <= kMatch - 64) {
+        if (q >= ej) {
+          stop = 1;
+          break;
         }
+        const int64_t qq = q + lane;
+        int kq = qq < ej ? row_col[qq] : INT32_MAX;
+        if (kq >= kmax) kq = INT32_MAX;
+        int64_t lo = p, hi = ei;
+        while (lo < hi) {
+          const int64_t mid = lo + ((hi - lo) >> 1);
+          if (row_col[mid] < kq) lo = mid + 1;
+          else hi = mid;
+        }
+        const bool match = kq != INT32_MAX && lo < ei && row_col[lo] == kq;
+        const uint64_t bal = __ballot(match);
+        if (match) {
+          const int pos = n + __popcll(bal & ((1ull << lane) - 1ull));
+          pa[pos] = row_blk[lo];
+          pb[pos] = row_blk[qq];
+          pk[pos] = kq;
+        }
+        n += __popcll(bal);
+        // a lane past the end of j's list or at kmax ends the merge after this batch; otherwise the
+        // next batch starts after lane 63's entry, and its columns lie after lane 63's place in i's list
+        if (__ballot(kq == INT32_MAX)) stop = 1;
+        q += 64;
+        p = __shfl(lo, 63);
       }
-      cur[0] = p;
-      cur[1] = q;
-      np = n;
+      if (lane == 0) {
+        cur[0] = p;
+        cur[1] = q;
+        np = n;
+        fin = stop;
+      }
     }
     __syncthreads();
     const int n = np;
     if (n == 0) break;
+    // software pipeline: the blocks of match m + 1 are loaded into registers while the matrix cores
+    // work on match m from LDS
+    int wk = w[pk[0]];
+    {
+      const double* la = L + blk_off[pa[0]];
+      const double* lb = L + blk_off[pb[0]];
+#pragma unroll
+      for (int s4 = 0; s4 < 16; ++s4) {
+        const int q = sq + 4 * s4;
+        ra[s4] = (sr < wi && q < wk) ? la[sr * wk + q] : 0.0;
+        rb[s4] = (sr < wj && q < wk) ? lb[sr * wk + q] : 0.0;
+      }
+    }
     for (int m = 0; m < n; ++m) {
-      const int wk = w[pk[m]];
       const int wk4 = (wk + 3) & ~3;
-      const double* la = L + blk_off[pa[m]];
-      const double* lb = L + blk_off[pb[m]];
       __syncthreads();
-      for (int e = t; e < wi * wk; e += kT) {
-        const int r = e / wk, q = e - r * wk;
-        La[q * kLd + r] = la[e];
-      }
-      for (int e = t; e < wj * wk; e += kT) {
-        const int r = e / wk, q = e - r * wk;
-        Lb[q * kLd + r] = lb[e];
-      }
-      for (int e = t; e < (wk4 - wk) * kB; e += kT) {   // the padded k rows are zero
-        const int q = wk + e / kB, r = e % kB;
-        La[q * kLd + r] = 0.0;
-        Lb[q * kLd + r] = 0.0;
+#pragma unroll
+      for (int s4 = 0; s4 < 16; ++s4) {
+        const int q = sq + 4 * s4;
+        if (q < wk4) {   // columns past w_k are zero
+          La[q * kLd + sr] = ra[s4];
+          Lb[q * kLd + sr] = rb[s4];
+        }
       }
       __syncthreads();
+      if (m + 1 < n) {
+        const int wn = w[pk[m + 1]];
+        const double* la = L + blk_off[pa[m + 1]];
+        const double* lb = L + blk_off[pb[m + 1]];
+#pragma unroll
+        for (int s4 = 0; s4 < 16; ++s4) {
+          const int q = sq + 4 * s4;
+          ra[s4] = (sr < wi && q < wn) ? la[sr * wn + q] : 0.0;
+          rb[s4] = (sr < wj && q < wn) ? lb[sr * wn + q] : 0.0;
+        }
+        wk = wn;
+      }
       for (int k4 = 0; k4 < wk4; k4 += 4) {
-        double x[2], y[2];
+        double x[2], yv[2];
 #pragma unroll
         for (int a = 0; a < 2; ++a) x[a] = La[(k4 + lk) * kLd + wr + a * 16 + li];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) y[c] = Lb[(k4 + lk) * kLd + wc + c * 16 + li];
+        for (int c = 0; c < 2; ++c) yv[c] = Lb[(k4 + lk) * kLd + wc + c * 16 + li];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int c = 0; c < 2; ++c) acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a], y[c], acc[a][c], 0, 0, 0);
+          for (int c = 0; c < 2; ++c) acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a], yv[c], acc[a][c], 0, 0, 0);
       }
     }
   }
