@@ -366,7 +366,8 @@ int mlblup_loglik(mlblup_basis b, const mlblup_matern* k, const double* z_dev, i
  * tail: from the position where that is estimated to pay, the block
  * columns before it update it and the dense blocked Cholesky of
  * mlblup_loglik factors it (at most 49,152 rows; the environment variable
- * MLBLUP_SPARSE_TAIL=none or =all forces no tail or an all-dense one, for
+ * MLBLUP_SPARSE_TAIL=none or =all forces no tail or an all-dense one, and
+ * MLBLUP_SPARSE_TAIL_MAX=<rows> lowers the row limit of a chosen tail, for
  * tests and measurement).  Cost and storage follow the kept blocks and
  * their fill, so a small tau makes it cheap; tau = INFINITY factors the
  * whole C^n_W (use mlblup_loglik there).  Every cell may own at most 64 wavelets: leaves of

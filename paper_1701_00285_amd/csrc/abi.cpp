@@ -1113,17 +1113,29 @@ static int sparse_tail_request() {
   return -1;
 }
 
+// MLBLUP_SPARSE_TAIL_MAX=<rows> lowers the row limit of a chosen dense tail (at most kSparseMaxTail)
+static int64_t sparse_tail_cap() {
+  const char* e = std::getenv("MLBLUP_SPARSE_TAIL_MAX");
+  if (!e) return kSparseMaxTail;
+  char* end = nullptr;
+  const long long v = std::strtoll(e, &end, 10);
+  if (end == e || *end || v < 0) return kSparseMaxTail;
+  return std::min<int64_t>(v, kSparseMaxTail);
+}
+
 static int sparse_symbolic(mlblup_basis b, int32_t level, double tau, std::shared_ptr<const SparseSymbolic>* out) {
   std::lock_guard<std::mutex> g(b->sparse_mu);
   const int req = sparse_tail_request();
+  const int64_t cap = sparse_tail_cap();
   const bool same_tau = (std::isinf(tau) && b->sparse && std::isinf(b->sparse->tau)) || (b->sparse && b->sparse->tau == tau);
-  if (b->sparse && b->sparse->level == level && same_tau && b->sparse_req == req) {
+  if (b->sparse && b->sparse->level == level && same_tau && b->sparse_req == req && b->sparse_cap == cap) {
     *out = b->sparse;
     return MLBLUP_OK;
   }
   auto S = std::make_shared<SparseSymbolic>();
-  const int st = sparse_analyse(b->b, level, tau, *S, req == -2 ? std::numeric_limits<int32_t>::max() : req);
+  const int st = sparse_analyse(b->b, level, tau, *S, req == -2 ? std::numeric_limits<int32_t>::max() : req, cap);
   b->sparse_req = req;
+  b->sparse_cap = cap;
   if (st) return st;
   b->sparse = S;
   *out = S;

@@ -145,12 +145,16 @@ struct SparseSymbolic {
   std::vector<int64_t> psi_off;
   std::vector<double> psi;
 };
-// dense_tail: -1 chooses the tail start by the estimated time (block columns at kSparseBlockRate,
-// the dense tail at kSparseDenseRate), 0 .. nc forces it (nc: no dense tail)
-constexpr double kSparseBlockRate = 1.5e12;   // flop/s of the block kernels (measured, 65,536 points)
-constexpr double kSparseDenseRate = 25e12;    // flop/s of the dense blocked Cholesky at 10^4 rows and more
+// dense_tail: -1 chooses the tail start by the estimated time (block columns at kSparseBlockRate plus
+// kSparseHeightTime per elimination-tree height, the dense tail at kSparseDenseRate) among the tails
+// of at most max_tail rows, 0 .. nc forces it (nc: no dense tail).  The three constants are a least
+// squares fit to timings of 12 tail positions at 65,536 and 262,144 points on one MI355X.
+constexpr double kSparseBlockRate = 22e12;    // flop/s of the block kernels
+constexpr double kSparseHeightTime = 0.77e-3; // s per height (its three launches, their serial depth)
+constexpr double kSparseDenseRate = 38e12;    // flop/s of the dense blocked Cholesky
 constexpr int64_t kSparseMaxTail = 49152;     // rows of the dense tail at most (18 GB)
-int sparse_analyse(const Basis& b, int32_t level, double tau, SparseSymbolic& S, int32_t dense_tail = -1);
+int sparse_analyse(const Basis& b, int32_t level, double tau, SparseSymbolic& S, int32_t dense_tail = -1,
+                   int64_t max_tail = kSparseMaxTail);
 int64_t basis_device_bytes(const Basis& b);
 
 // exponent tuples of the total-degree set, graded lexicographic
@@ -167,4 +171,5 @@ struct mlblup_basis_s {
   std::mutex sparse_mu;
   std::shared_ptr<const mlb::SparseSymbolic> sparse;
   int sparse_req = -1;   // dense-tail request the cached analysis was built with
+  int64_t sparse_cap = mlb::kSparseMaxTail;   // and its row limit
 };

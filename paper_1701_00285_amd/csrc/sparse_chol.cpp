@@ -46,7 +46,8 @@ int32_t wavelets_of(const Basis& B, int32_t v) { return B.desc[v].m - B.desc[v].
 
 }  // namespace
 
-int sparse_analyse(const Basis& B, int32_t level, double tau, SparseSymbolic& S, int32_t dense_tail) {
+int sparse_analyse(const Basis& B, int32_t level, double tau, SparseSymbolic& S, int32_t dense_tail,
+                   int64_t max_tail) {
   S = SparseSymbolic();
   S.level = level;
   S.tau = tau;
@@ -192,24 +193,41 @@ int sparse_analyse(const Basis& B, int32_t level, double tau, SparseSymbolic& S,
     fl += wk * (sw * sw + sw2);   // sum over i >= j of 2 w_i w_j w_k = w_k ((sum w)^2 + sum w^2)
     colfl[k] = fl;
   }
-  // 3. dense tail: the start q minimising (flops of the block columns before q) / kSparseBlockRate +
-  // rows(q)^3 / 3 / kSparseDenseRate, with at most kSparseMaxTail rows in the tail
+  // elimination tree heights (the parent of a column is the first block row below its diagonal)
+  std::vector<int32_t> height(nc, 0);
+  for (int32_t k = 0; k < nc; ++k) {
+    if (S.col_ptr[k + 1] - S.col_ptr[k] > 1) {
+      const int32_t parent = S.blk_row[S.col_ptr[k] + 1];
+      height[parent] = std::max(height[parent], height[k] + 1);
+    }
+  }
+  // 3. dense tail: the start q minimising the estimated time (flops of the block columns before q) /
+  // kSparseBlockRate + (their heights) kSparseHeightTime + rows(q)^3 / 3 / kSparseDenseRate, with at
+  // most max_tail rows in the tail; a child precedes its parent in the order, so the heights of the
+  // columns before q are those of the whole tree
   {
     int32_t best = nc;
     double pre = 0.0, best_t = 0.0;
-    for (int32_t k = 0; k < nc; ++k) best_t += colfl[k];
-    best_t /= kSparseBlockRate;
+    int32_t hall = -1;
+    for (int32_t k = 0; k < nc; ++k) {
+      best_t += colfl[k];
+      hall = std::max(hall, height[k]);
+    }
+    best_t = best_t / kSparseBlockRate + (hall + 1) * kSparseHeightTime;
     if (dense_tail < 0) {
+      int32_t hpre = -1;
       for (int32_t q = 0; q < nc; ++q) {
         const double rows = (double)(S.rows - S.ypos[q]);
-        if (rows <= (double)kSparseMaxTail) {
-          const double est = pre / kSparseBlockRate + rows * rows * rows / 3.0 / kSparseDenseRate;
+        if (rows <= (double)std::min<int64_t>(max_tail, kSparseMaxTail)) {
+          const double est =
+              pre / kSparseBlockRate + (hpre + 1) * kSparseHeightTime + rows * rows * rows / 3.0 / kSparseDenseRate;
           if (est < best_t) {
             best_t = est;
             best = q;
           }
         }
         pre += colfl[q];
+        hpre = std::max(hpre, height[q]);
       }
     } else {
       best = std::min<int32_t>(dense_tail, nc);
@@ -228,15 +246,8 @@ int sparse_analyse(const Basis& B, int32_t level, double tau, SparseSymbolic& S,
     }
   }
 
-  // 4. elimination tree heights of the columns before the tail
+  // 4. the heights of the columns before the tail, one launch group each
   const int32_t ntail0 = S.tail;
-  std::vector<int32_t> height(nc, 0);
-  for (int32_t k = 0; k < nc; ++k) {
-    if (S.col_ptr[k + 1] - S.col_ptr[k] > 1) {
-      const int32_t parent = S.blk_row[S.col_ptr[k] + 1];
-      height[parent] = std::max(height[parent], height[k] + 1);
-    }
-  }
   int32_t hmax = -1;
   for (int32_t k = 0; k < ntail0; ++k) hmax = std::max(hmax, height[k]);
   S.lvl_ptr.assign(hmax + 2, 0);
