@@ -160,6 +160,8 @@ __global__ __launch_bounds__(kT) void sp_assemble(const double* __restrict__ pts
 // the matched columns of one chunk: at most kMatch (the merge of one batch of 64 entries of row j's
 // structure adds at most 64, and a batch starts only while 64 places are left)
 constexpr int kMatch = 128;
+// row i's structure is searched in LDS when it holds at most this many entries (else in memory)
+constexpr int kListCap = 2048;
 
 // blocks [0, nblk): update block lvl[x]; then one data block per column cols[x - nblk]; only the
 // columns k < kmax contribute (all earlier ones inside the block part; those before the dense tail
@@ -178,9 +180,10 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
   __shared__ double La[kB * kLd];   // L_ik transposed: La[q][r]
   __shared__ double Lb[kB * kLd];   // L_jk transposed: Lb[q][c]
   __shared__ int64_t pa[kMatch], pb[kMatch];
-  __shared__ int32_t pk[kMatch];
+  __shared__ int32_t pk[kMatch], pw[kMatch];   // matched column and its width
   __shared__ int np, fin;
   __shared__ int64_t cur[2];
+  __shared__ int32_t icols[kListCap];   // row i's structure (columns), when it fits
   const int t = threadIdx.x;
   const int wave = t >> 6, lane = t & 63;
   if ((int64_t)blockIdx.x >= nblk) {
@@ -207,6 +210,7 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
   const int64_t b = lvl[blockIdx.x];
   const int i = blk_row[b], j = blk_col[b];
   const int wi = w[i], wj = w[j];
+  const bool full = wi > 48 && wj > 48;   // every 16 x 16 tile holds rows of the block
   double* A = L + blk_off[b];
   // the sum of the products on the FP64 matrix cores: each wave a 32 x 32 quadrant of the 64 x 64
   // block as 2 x 2 tiles of v_mfma_f64_16x16x4f64 (lane l supplies row l % 16, k l / 16 of the left
@@ -225,7 +229,10 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
     cur[1] = row_ptr[j];
     fin = 0;
   }
-  const int64_t ei = row_ptr[i + 1], ej = row_ptr[j + 1];
+  const int64_t bi = row_ptr[i], ei = row_ptr[i + 1], ej = row_ptr[j + 1];
+  const bool ilds = ei - bi <= kListCap;   // block-uniform
+  if (ilds)
+    for (int64_t e = t; e < ei - bi; e += kT) icols[e] = row_col[bi + e];
   // staging: thread t holds row sr = t / 4 of both blocks at the columns sq + 4 s
   const int sr = t >> 2, sq = t & 3;
   double ra[16], rb[16];
@@ -233,8 +240,8 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
     __syncthreads();
     if (wave == 0) {
       // the next matched columns k of the row structures of i and j (ascending lists of distinct
-      // columns): each lane takes one entry of j's list and finds it in i's by bisection; the
-      // matches keep the order of j's list
+      // columns): each lane takes one entry of j's list and finds it in i's by bisection (in the
+      // LDS copy of i's list when it fits); the matches keep the order of j's list
       int64_t p = cur[0], q = cur[1];
       int n = 0, stop = fin;
       while (!stop && n <= kMatch - 64) {
@@ -246,18 +253,27 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
         int kq = qq < ej ? row_col[qq] : INT32_MAX;
         if (kq >= kmax) kq = INT32_MAX;
         int64_t lo = p, hi = ei;
-        while (lo < hi) {
-          const int64_t mid = lo + ((hi - lo) >> 1);
-          if (row_col[mid] < kq) lo = mid + 1;
-          else hi = mid;
+        if (ilds) {
+          while (lo < hi) {
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            if (icols[mid - bi] < kq) lo = mid + 1;
+            else hi = mid;
+          }
+        } else {
+          while (lo < hi) {
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            if (row_col[mid] < kq) lo = mid + 1;
+            else hi = mid;
+          }
         }
-        const bool match = kq != INT32_MAX && lo < ei && row_col[lo] == kq;
+        const bool match = kq != INT32_MAX && lo < ei && (ilds ? icols[lo - bi] : row_col[lo]) == kq;
         const uint64_t bal = __ballot(match);
         if (match) {
           const int pos = n + __popcll(bal & ((1ull << lane) - 1ull));
           pa[pos] = row_blk[lo];
           pb[pos] = row_blk[qq];
           pk[pos] = kq;
+          pw[pos] = w[kq];
         }
         n += __popcll(bal);
         // a lane past the end of j's list or at kmax ends the merge after this batch; otherwise the
@@ -278,19 +294,20 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
     if (n == 0) break;
     // software pipeline: the blocks of match m + 1 are loaded into registers while the matrix cores
     // work on match m from LDS
-    int wk = w[pk[0]];
-    {
-      const double* la = L + blk_off[pa[0]];
-      const double* lb = L + blk_off[pb[0]];
+    auto fetch = [&](int m) {
+      const int wn = pw[m];
+      const double* la = L + blk_off[pa[m]];
+      const double* lb = L + blk_off[pb[m]];
 #pragma unroll
       for (int s4 = 0; s4 < 16; ++s4) {
         const int q = sq + 4 * s4;
-        ra[s4] = (sr < wi && q < wk) ? la[sr * wk + q] : 0.0;
-        rb[s4] = (sr < wj && q < wk) ? lb[sr * wk + q] : 0.0;
+        ra[s4] = (sr < wi && q < wn) ? la[sr * wn + q] : 0.0;
+        rb[s4] = (sr < wj && q < wn) ? lb[sr * wn + q] : 0.0;
       }
-    }
+    };
+    fetch(0);
     for (int m = 0; m < n; ++m) {
-      const int wk4 = (wk + 3) & ~3;
+      const int wk = pw[m], wk4 = (wk + 3) & ~3;
       __syncthreads();
 #pragma unroll
       for (int s4 = 0; s4 < 16; ++s4) {
@@ -301,28 +318,36 @@ __global__ __launch_bounds__(kT) void sp_update(double* __restrict__ L, const in
         }
       }
       __syncthreads();
-      if (m + 1 < n) {
-        const int wn = w[pk[m + 1]];
-        const double* la = L + blk_off[pa[m + 1]];
-        const double* lb = L + blk_off[pb[m + 1]];
+      if (m + 1 < n) fetch(m + 1);
+      if (full) {
+        for (int k4 = 0; k4 < wk4; k4 += 4) {
+          double x[2], yv[2];
 #pragma unroll
-        for (int s4 = 0; s4 < 16; ++s4) {
-          const int q = sq + 4 * s4;
-          ra[s4] = (sr < wi && q < wn) ? la[sr * wn + q] : 0.0;
-          rb[s4] = (sr < wj && q < wn) ? lb[sr * wn + q] : 0.0;
+          for (int a = 0; a < 2; ++a) x[a] = La[(k4 + lk) * kLd + wr + a * 16 + li];
+#pragma unroll
+          for (int c = 0; c < 2; ++c) yv[c] = Lb[(k4 + lk) * kLd + wc + c * 16 + li];
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+              acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a], yv[c], acc[a][c], 0, 0, 0);
         }
-        wk = wn;
-      }
-      for (int k4 = 0; k4 < wk4; k4 += 4) {
-        double x[2], yv[2];
+      } else {
+        // a block of at most 48 rows or columns: the tiles wholly past w_i rows or w_j columns
+        // are skipped (wave-uniform)
+        for (int k4 = 0; k4 < wk4; k4 += 4) {
+          double x[2], yv[2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) x[a] = La[(k4 + lk) * kLd + wr + a * 16 + li];
+          for (int a = 0; a < 2; ++a) x[a] = La[(k4 + lk) * kLd + wr + a * 16 + li];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) yv[c] = Lb[(k4 + lk) * kLd + wc + c * 16 + li];
+          for (int c = 0; c < 2; ++c) yv[c] = Lb[(k4 + lk) * kLd + wc + c * 16 + li];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+          for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int c = 0; c < 2; ++c) acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a], yv[c], acc[a][c], 0, 0, 0);
+            for (int c = 0; c < 2; ++c)
+              if (wr + 16 * a < wi && wc + 16 * c < wj)
+                acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a], yv[c], acc[a][c], 0, 0, 0);
+        }
       }
     }
   }

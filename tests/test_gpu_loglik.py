@@ -360,16 +360,20 @@ def test_sparse_factorization_mle_rho_and_nu_rho():
     assert abs(a["loglik"] - b["loglik"]) < 1e-9 * abs(b["loglik"])
 
 
-@pytest.mark.parametrize("mode", ["none", "all", "auto"])
+@pytest.mark.parametrize("mode", ["none", "all", "auto", "cap128"])
 @pytest.mark.parametrize("k,n,up,tau,nu", [(1, 1000, 0, 0.05, None), (2, 900, 1, 0.1, None), (4, 700, 1, 0.2, None),
                                             (2, 650, 0, 0.05, 1.25)])
 def test_sparse_factorization_dense_tail_modes(monkeypatch, mode, k, n, up, tau, nu):
     """The block factorization with no dense tail, with all of C~^n_W as the
-    dense tail (the block columns only assemble it), and with the tail the
-    analysis picks: the same l~ as the dense path on the same matrix."""
+    dense tail (the block columns only assemble it), with the tail the
+    analysis picks, and with that choice limited to 128 rows: the same l~ as
+    the dense path on the same matrix."""
     require_gpu()
-    if mode == "auto":
+    monkeypatch.delenv("MLBLUP_SPARSE_TAIL_MAX", raising=False)
+    if mode in ("auto", "cap128"):
         monkeypatch.delenv("MLBLUP_SPARSE_TAIL", raising=False)
+        if mode == "cap128":
+            monkeypatch.setenv("MLBLUP_SPARSE_TAIL_MAX", "128")
     else:
         monkeypatch.setenv("MLBLUP_SPARSE_TAIL", mode)
     wl, nu, tree, bas, s = _both(k, n, nu)
@@ -385,5 +389,7 @@ def test_sparse_factorization_dense_tail_modes(monkeypatch, mode, k, n, up, tau,
         assert info["tail_rows"] == 0
     if mode == "all":
         assert info["tail_rows"] == info["rows"] and info["block_columns"] == 0
+    if mode == "cap128":
+        assert info["tail_rows"] <= 128
     assert abs(g["logdet"] - d["logdet"]) < tq * d["rows"]
     assert abs(g["quad"] - d["quad"]) < tq * abs(d["quad"])
