@@ -101,7 +101,9 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
   constexpr int kBlk = 256 * RL;
   constexpr double kGuard = 0.015625;
   static_assert(kBlk % (diag_split(RL) * kChunk) == 0, "a diagonal tile splits into whole chunks");
-  __shared__ double cp[kChunk * SD];
+  // column chunk: each group of 64 columns twice over (slots s and s + 64 hold column s), so that a
+  // lane's column index moves by one slot per step without wrapping
+  __shared__ double cp[2 * kChunk * SD];
   __shared__ double cred[4][kChunk];
   __shared__ double cdred[4][kChunk];
   __shared__ double tab[kExpTab];
@@ -137,8 +139,9 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
     nx[q] = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      xr[q][k] = kGram ? (pts[ii * D + k] - pts[o * D + k]) * zs : pts[ii * D + k] * zs;
-      nx[q] = fma(xr[q][k], xr[q][k], nx[q]);
+      const double v = kGram ? (pts[ii * D + k] - pts[o * D + k]) * zs : pts[ii * D + k] * zs;
+      nx[q] = fma(v, v, nx[q]);
+      xr[q][k] = kGram ? -2.0 * v : v;   // the expanded form keeps -2 a (exact)
     }
     ar[q] = i < n ? x[i] : 0.0;
   }
@@ -151,47 +154,69 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
   const int clast = diag ? cfirst + kBlk / (int)gridDim.y : kBlk;
   for (int c0 = cfirst; c0 < clast; c0 += kChunk) {
     __syncthreads();
+    // column j of the chunk goes to slots (j / 64) 128 + j % 64 and that + 64
     for (int e = tid; e < kChunk * D; e += kT) {
       const int j = e / D, k = e - j * D;
       const int64_t gj = cbase + c0 + j;
-      cp[j * SD + k] = gj < n ? (kGram ? (pts[gj * D + k] - pts[o * D + k]) * zs : pts[gj * D + k] * zs) : 0.0;
+      const double v = gj < n ? (kGram ? (pts[gj * D + k] - pts[o * D + k]) * zs : pts[gj * D + k] * zs) : 0.0;
+      const int sl = (j >> 6) * 128 + (j & 63);
+      cp[sl * SD + k] = v;
+      cp[(sl + 64) * SD + k] = v;
     }
     for (int j = tid; j < kChunk; j += kT) {
       const int64_t gj = cbase + c0 + j;
-      cp[j * SD + D] = gj < n ? x[gj] : 0.0;
+      const int sl = (j >> 6) * 128 + (j & 63);
+      const double v = gj < n ? x[gj] : 0.0;
+      cp[sl * SD + D] = v;
+      cp[(sl + 64) * SD + D] = v;
     }
     if constexpr (kGram) {
       __syncthreads();
       for (int j = tid; j < kChunk; j += kT) {
+        const int sl = (j >> 6) * 128 + (j & 63);
         double nb = 0.0;
 #pragma unroll
-        for (int k = 0; k < D; ++k) nb = fma(cp[j * SD + k], cp[j * SD + k], nb);
-        cp[j * SD + D + 1] = nb;
+        for (int k = 0; k < D; ++k) nb = fma(cp[sl * SD + k], cp[sl * SD + k], nb);
+        cp[sl * SD + D + 1] = nb;
+        cp[(sl + 64) * SD + D + 1] = nb;
       }
     }
     __syncthreads();
 #pragma unroll 1
     for (int sub = 0; sub < kChunk; sub += 64) {
       double cacc = 0.0, cdacc = 0.0;
-      int c = lane;
+      // step k visits column (lane + k delta) mod 64 of the group: slot lane + k (delta = 1) or
+      // lane + 64 - k (delta = -1 mod 64); slots are indexed (not stepped by pointer) so that the
+      // 128-bit alignment of a slot (SD even) stays visible to the compiler
+      const int ds = delta == 1 ? 1 : -1;
+      int sl = 2 * sub + lane + (delta == 1 ? 0 : 64);
+      {
 #pragma unroll 2
-      for (int k = 0; k < 64; ++k) {
-        const double* cj = &cp[(sub + c) * SD];
-        double cv[D];
+        for (int k = 0; k < 64; ++k, sl += ds) {
+          const double* cj = &cp[sl * SD];
+          double cv[D];
 #pragma unroll
-        for (int t = 0; t < D; ++t) cv[t] = cj[t];
-        const double aj = cj[D];
-        double cpart = 0.0, cdpart = 0.0;
+          for (int t = 0; t < D; ++t) cv[t] = cj[t];
+          const double aj = cj[D];
+          double cpart = 0.0, cdpart = 0.0;
 #pragma unroll
-        for (int q = 0; q < RL; ++q) {
-          double s;
-          if constexpr (kGram) {
-            double g = 0.0;
+          for (int q = 0; q < RL; ++q) {
+            double s;
+            if constexpr (kGram) {
+              // |a|^2 + |b|^2 - 2 a.b as one FMA chain from the norms (xr holds -2 a)
+              const double tt = nx[q] + cj[D + 1];
+              s = tt;
 #pragma unroll
-            for (int t = 0; t < D; ++t) g = fma(xr[q][t], cv[t], g);
-            const double tt = nx[q] + cj[D + 1];
-            s = fma(-2.0, g, tt);
-            if (!(s > kGuard * tt)) {
+              for (int t = 0; t < D; ++t) s = fma(xr[q][t], cv[t], s);
+              if (!(s > kGuard * tt)) {
+                s = 1e-300;
+#pragma unroll
+                for (int t = 0; t < D; ++t) {
+                  const double u = fma(0.5, xr[q][t], cv[t]);   // b - a, one rounding
+                  s = fma(u, u, s);
+                }
+              }
+            } else {
               s = 1e-300;
 #pragma unroll
               for (int t = 0; t < D; ++t) {
@@ -199,28 +224,20 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
                 s = fma(u, u, s);
               }
             }
-          } else {
-            s = 1e-300;
-#pragma unroll
-            for (int t = 0; t < D; ++t) {
-              const double u = xr[q][t] - cv[t];
-              s = fma(u, u, s);
+            double f = 0.0, g = 0.0;
+            pair_value<NU2, OUT, false>(s, tab, f, g, gt);
+            if constexpr (OUT & 1) {
+              racc[q] = fma(f, aj, racc[q]);
+              cpart = fma(f, ar[q], cpart);
+            }
+            if constexpr (OUT & 2) {
+              rdacc[q] = fma(g, aj, rdacc[q]);
+              cdpart = fma(g, ar[q], cdpart);
             }
           }
-          double f = 0.0, g = 0.0;
-          pair_value<NU2, OUT, false>(s, tab, f, g, gt);
-          if constexpr (OUT & 1) {
-            racc[q] = fma(f, aj, racc[q]);
-            cpart = fma(f, ar[q], cpart);
-          }
-          if constexpr (OUT & 2) {
-            rdacc[q] = fma(g, aj, rdacc[q]);
-            cdpart = fma(g, ar[q], cdpart);
-          }
+          if constexpr (OUT & 1) cacc = wave_rotate1(cacc + cpart);
+          if constexpr (OUT & 2) cdacc = wave_rotate1(cdacc + cdpart);
         }
-        if constexpr (OUT & 1) cacc = wave_rotate1(cacc + cpart);
-        if constexpr (OUT & 2) cdacc = wave_rotate1(cdacc + cdpart);
-        c = (c + delta) & 63;
       }
       if constexpr (OUT & 1) cred[wave][sub + lane] = cacc;
       if constexpr (OUT & 2) cdred[wave][sub + lane] = cdacc;
