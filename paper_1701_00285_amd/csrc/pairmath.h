@@ -133,15 +133,16 @@ __device__ __forceinline__ double exp_neg_f64(double z, const double* __restrict
 
 // sqrt(s) for s > 0 (callers keep s away from 0 by a 1e-300 offset): the
 // hardware reciprocal square root y (relative error below 2^-24 on gfx950,
-// measured over [1e-6, 1e8]), g = s y, then two Newton corrections
-// g += (s - g^2) y/2 with the same y/2: the relative error goes from
-// e <= 2^-24 to 1.5 e^2 and then 1.5 e^3 (below 2^-70).
+// measured over [1e-6, 1e8]) and g = s y; with r = 1 - g y (one FMA, r of
+// order 2^-23), sqrt(s) = g (1 - r)^(-1/2) = g (1 + r/2 + 3 r^2/8 + ...), and
+// the series cut after r^2 leaves a relative error of about (5/16) r^3, below
+// 2^-70: g + (g r)(1/2 + 3 r/8), 6 instructions (two Newton corrections of g
+// with y/2 took 7)
 __device__ __forceinline__ double sqrt_pos_f64(double s) {
   const double y = __builtin_amdgcn_rsq(s);
-  const double h = 0.5 * y;
-  double g = s * y;
-  g = fma(fma(-g, g, s), h, g);
-  return fma(fma(-g, g, s), h, g);
+  const double g = s * y;
+  const double r = fma(-g, y, 1.0);
+  return fma(g * r, fma(0.375, r, 0.5), g);
 }
 
 // Matern closed forms in z = sqrt(2 nu) r / rho (nu = NU2 / 2)
