@@ -60,6 +60,11 @@ using SymTileLaunch = std::function<void(int, int, int, int, double*, double*, d
 int sym_schedule(const PairArgs& a, int blk_pts, void* work, hipStream_t s, const SymTileLaunch& fn,
                  bool rows_summed = false, int diag_splits = 0);
 bool sym_supported(int d);
+// the compiled dimension of the pair kernels that a point set of dimension d runs in: its coordinates
+// are padded with zeros, which changes no distance or norm (0 past 32: no compiled kernel)
+constexpr int padded_dim(int d) {
+  return d <= 6 ? d : d <= 8 ? 8 : d <= 10 ? 10 : d <= 16 ? 16 : d <= 20 ? 20 : d <= 24 ? 24 : d <= 28 ? 28 : d <= 32 ? 32 : 0;
+}
 bool sym_worthwhile(int64_t n);
 int64_t sym_workspace_bytes(int64_t n, int outputs);
 int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s);

@@ -63,10 +63,11 @@ __device__ const double* stage_genu(const double* __restrict__ gtab) {
   }
 }
 
-// D > 0: compile-time dimension.  FP32T: FP32 transcendentals.
+// D > 0: compile-time dimension, at least the points' dimension dd (the coordinates past dd are
+// zero).  FP32T: FP32 transcendentals.
 template <int D, int NU2, int OUT, int R, bool FP32T>
 __global__ __launch_bounds__(kThreads) void pair_kernel(const double* __restrict__ rows, int64_t m,
-                                                        const double* __restrict__ cols, int64_t n,
+                                                        const double* __restrict__ cols, int64_t n, int dd,
                                                         const double* __restrict__ x, double* __restrict__ py,
                                                         double* __restrict__ pdy, double zs, int64_t cps,
                                                         const double* __restrict__ gtab) {
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const double* __restrict
     int64_t i = rbase + r * kThreads + tid;
     if (i >= m) i = m - 1;
 #pragma unroll
-    for (int k = 0; k < D; ++k) xr[r][k] = rows[i * D + k] * zs;
+    for (int k = 0; k < D; ++k) xr[r][k] = k < dd ? rows[i * dd + k] * zs : 0.0;
   }
   double acc[R], dacc[R];
 #pragma unroll
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const double* __restrict
     __syncthreads();
     for (int e = tid; e < kTile * D; e += kThreads) {
       const int j = e / D, k = e - j * D;
-      tile[j * SD + k] = (j < cnt) ? cols[(j0 + j) * D + k] * zs : 0.0;
+      tile[j * SD + k] = (j < cnt && k < dd) ? cols[(j0 + j) * dd + k] * zs : 0.0;
     }
     for (int j = tid; j < kTile; j += kThreads) tile[j * SD + D] = (j < cnt) ? x[j0 + j] : 0.0;
     __syncthreads();
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(const double* __restrict
 }
 
 // Any dimension (runtime d): row coordinates re-read from memory; slow
-// fallback for dimensions without a compiled specialisation.
+// fallback for dimensions past the largest compiled one (32).
 template <int NU2, int OUT, bool FP32T>
 __global__ __launch_bounds__(kThreads) void pair_kernel_any(const double* __restrict__ rows, int64_t m,
                                                             const double* __restrict__ cols, int64_t n, int d,
@@ -189,8 +190,8 @@ template <int D, int NU2, int OUT, bool F>
 void launch_fixed(const PairArgs& a, double zs, int S, int64_t cps, double* py, double* pdy, hipStream_t s) {
   constexpr int R = rows_per_thread(D);
   dim3 grid((unsigned)((a.m + kThreads * R - 1) / (kThreads * R)), (unsigned)S);
-  hipLaunchKernelGGL((pair_kernel<D, NU2, OUT, R, F>), grid, dim3(kThreads), 0, s, a.rows, a.m, a.cols, a.n, a.x,
-                     py, pdy, zs, cps, a.gtab);
+  hipLaunchKernelGGL((pair_kernel<D, NU2, OUT, R, F>), grid, dim3(kThreads), 0, s, a.rows, a.m, a.cols, a.n, a.d,
+                     a.x, py, pdy, zs, cps, a.gtab);
 }
 
 template <int NU2, int OUT, bool F>
@@ -202,7 +203,7 @@ void launch_any(const PairArgs& a, double zs, int S, int64_t cps, double* py, do
 
 template <int NU2, int OUT, bool F>
 void dispatch_d(const PairArgs& a, double zs, int S, int64_t cps, double* py, double* pdy, hipStream_t s) {
-  switch (a.d) {
+  switch (padded_dim(a.d)) {
     case 1: launch_fixed<1, NU2, OUT, F>(a, zs, S, cps, py, pdy, s); break;
     case 2: launch_fixed<2, NU2, OUT, F>(a, zs, S, cps, py, pdy, s); break;
     case 3: launch_fixed<3, NU2, OUT, F>(a, zs, S, cps, py, pdy, s); break;
@@ -213,6 +214,9 @@ void dispatch_d(const PairArgs& a, double zs, int S, int64_t cps, double* py, do
     case 10: launch_fixed<10, NU2, OUT, F>(a, zs, S, cps, py, pdy, s); break;
     case 16: launch_fixed<16, NU2, OUT, F>(a, zs, S, cps, py, pdy, s); break;
     case 20: launch_fixed<20, NU2, OUT, F>(a, zs, S, cps, py, pdy, s); break;
+    case 24: launch_fixed<24, NU2, OUT, F>(a, zs, S, cps, py, pdy, s); break;
+    case 28: launch_fixed<28, NU2, OUT, F>(a, zs, S, cps, py, pdy, s); break;
+    case 32: launch_fixed<32, NU2, OUT, F>(a, zs, S, cps, py, pdy, s); break;
     default: launch_any<NU2, OUT, F>(a, zs, S, cps, py, pdy, s); break;
   }
 }
@@ -240,14 +244,14 @@ void dispatch_nu(const PairArgs& a, double zs, int S, int64_t cps, double* py, d
   }
 }
 
-bool has_fixed(int d) { return d == 1 || d == 2 || d == 3 || d == 4 || d == 5 || d == 6 || d == 8 || d == 10 || d == 16 || d == 20; }
+bool has_fixed(int d) { return padded_dim(d) > 0; }
 
 }  // namespace
 
 int32_t pair_splits(int64_t m, int64_t n, int32_t d, int32_t precision) {
   (void)precision;
   if (m <= 0 || n <= 0) return 1;
-  const int R = has_fixed(d) ? (d <= 10 ? 2 : 1) : 1;
+  const int R = has_fixed(d) ? rows_per_thread(padded_dim(d)) : 1;
   const int64_t row_blocks = (m + (int64_t)kThreads * R - 1) / ((int64_t)kThreads * R);
   // aim for >= 2048 workgroups (8 per CU on 256 CUs), at least one column tile per split
   int64_t S = (2048 + row_blocks - 1) / row_blocks;

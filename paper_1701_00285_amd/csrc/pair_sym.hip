@@ -44,8 +44,9 @@ constexpr int kDiagSplit = 4;  // column ranges of a diagonal tile (one partial 
 // more pairs); from d = 8 on the expanded-form FP64 kernel reads d + 2
 // doubles per column step, 3 rows per lane for d >= 16 keep that LDS traffic
 // below the LDS bandwidth; a block holds 256 * RL points
-constexpr int rows_per_lane(int D) { return D <= 6 ? 4 : (D >= 16 ? 3 : 2); }
+constexpr int rows_per_lane(int D) { return D <= 6 ? 4 : (D >= 16 && D <= 20 ? 3 : 2); }
 constexpr int rows_per_lane_lp(int D) { return D <= 6 ? 4 : 2; }
+
 // column ranges of a diagonal tile: whole chunks each
 constexpr int diag_split(int RL) { return RL == 3 ? 2 : kDiagSplit; }
 
@@ -85,7 +86,7 @@ __device__ __forceinline__ void tile_of(int T, int nr, int& S, int& y) {
 }
 
 template <int D, int NU2, int OUT>
-__global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts, const double* __restrict__ x,
+__global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts, int dd, const double* __restrict__ x,
                                                  int64_t n, int T, int round0, int diag, double zs,
                                                  double* __restrict__ prow, double* __restrict__ pcol,
                                                  double* __restrict__ pdrow, double* __restrict__ pdcol,
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
     nx[q] = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      const double v = kGram ? (pts[ii * D + k] - pts[o * D + k]) * zs : pts[ii * D + k] * zs;
+      const double v = k >= dd ? 0.0 : kGram ? (pts[ii * dd + k] - pts[o * dd + k]) * zs : pts[ii * dd + k] * zs;
       nx[q] = fma(v, v, nx[q]);
       xr[q][k] = kGram ? -2.0 * v : v;   // the expanded form keeps -2 a (exact)
     }
@@ -158,7 +159,8 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
     for (int e = tid; e < kChunk * D; e += kT) {
       const int j = e / D, k = e - j * D;
       const int64_t gj = cbase + c0 + j;
-      const double v = gj < n ? (kGram ? (pts[gj * D + k] - pts[o * D + k]) * zs : pts[gj * D + k] * zs) : 0.0;
+      const double v = gj < n && k < dd ? (kGram ? (pts[gj * dd + k] - pts[o * dd + k]) * zs : pts[gj * dd + k] * zs)
+                                         : 0.0;
       const int sl = (j >> 6) * 128 + (j & 63);
       cp[sl * SD + k] = v;
       cp[(sl + 64) * SD + k] = v;
@@ -269,7 +271,7 @@ __global__ __launch_bounds__(kT) void sym_kernel(const double* __restrict__ pts,
 // to FP32; the pair value comes from pair_value_lp.  Row sums accumulate in FP32 over 16
 // columns and then in FP64; the travelling column sums are FP64.
 template <int D, int NU2, int OUT>
-__global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ pts, const double* __restrict__ x,
+__global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ pts, int dd, const double* __restrict__ x,
                                                     int64_t n, int T, int round0, int diag, double ws,
                                                     double* __restrict__ prow, double* __restrict__ pcol,
                                                     double* __restrict__ pdrow, double* __restrict__ pdcol) {
@@ -299,7 +301,7 @@ __global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ p
     const int64_t i = o + wave * (64 * RL) + q * 64 + lane;
     const int64_t ii = i < n ? i : n - 1;
 #pragma unroll
-    for (int k = 0; k < D; ++k) xr[q][k] = (float)((pts[ii * D + k] - pts[o * D + k]) * ws);
+    for (int k = 0; k < D; ++k) xr[q][k] = k < dd ? (float)((pts[ii * dd + k] - pts[o * dd + k]) * ws) : 0.0f;
     ar[q] = i < n ? (float)x[i] : 0.0f;
   }
   double racc[RL], rdacc[RL];
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ p
     for (int e = tid; e < kChunk * D; e += kT) {
       const int j = e / D, k = e - j * D;
       const int64_t gj = cbase + c0 + j;
-      cp[j * SP + k] = gj < n ? (float)((pts[gj * D + k] - pts[o * D + k]) * ws) : 0.0f;
+      cp[j * SP + k] = gj < n && k < dd ? (float)((pts[gj * dd + k] - pts[o * dd + k]) * ws) : 0.0f;
     }
     for (int j = tid; j < kChunk; j += kT) {
       const int64_t gj = cbase + c0 + j;
@@ -417,22 +419,22 @@ __global__ __launch_bounds__(kT) void sym_reduce(const double* __restrict__ prow
 }
 
 template <int D, int NU2, int OUT, bool F>
-void launch(const double* pts, const double* x, int64_t n, int T, int round0, int nr, int diag, double zs,
+void launch(const double* pts, int dd, const double* x, int64_t n, int T, int round0, int nr, int diag, double zs,
             double* prow, double* pcol, double* pdrow, double* pdcol, const double* gtab, hipStream_t s) {
   if constexpr (F)
-    hipLaunchKernelGGL((sym_kernel_lp<D, NU2, OUT>), dim3(T, nr), dim3(kT), 0, s, pts, x, n, T, round0, diag,
+    hipLaunchKernelGGL((sym_kernel_lp<D, NU2, OUT>), dim3(T, nr), dim3(kT), 0, s, pts, dd, x, n, T, round0, diag,
                        zs * lp_scale<NU2>(), prow, pcol, pdrow, pdcol);
   else
-    hipLaunchKernelGGL((sym_kernel<D, NU2, OUT>), dim3(T, nr), dim3(kT), 0, s, pts, x, n, T, round0, diag, zs, prow,
-                       pcol, pdrow, pdcol, gtab);
+    hipLaunchKernelGGL((sym_kernel<D, NU2, OUT>), dim3(T, nr), dim3(kT), 0, s, pts, dd, x, n, T, round0, diag, zs,
+                       prow, pcol, pdrow, pdcol, gtab);
 }
 
-using LaunchFn = void (*)(const double*, const double*, int64_t, int, int, int, int, double, double*, double*, double*,
-                          double*, const double*, hipStream_t);
+using LaunchFn = void (*)(const double*, int, const double*, int64_t, int, int, int, int, double, double*, double*,
+                          double*, double*, const double*, hipStream_t);
 
 template <int NU2, int OUT, bool F>
 LaunchFn pick_d(int d) {
-  switch (d) {
+  switch (padded_dim(d)) {
     case 1: return launch<1, NU2, OUT, F>;
     case 2: return launch<2, NU2, OUT, F>;
     case 3: return launch<3, NU2, OUT, F>;
@@ -443,6 +445,9 @@ LaunchFn pick_d(int d) {
     case 10: return launch<10, NU2, OUT, F>;
     case 16: return launch<16, NU2, OUT, F>;
     case 20: return launch<20, NU2, OUT, F>;
+    case 24: return launch<24, NU2, OUT, F>;
+    case 28: return launch<28, NU2, OUT, F>;
+    case 32: return launch<32, NU2, OUT, F>;
     default: return nullptr;
   }
 }
@@ -531,11 +536,12 @@ int sym_launch(const PairArgs& a, double zs, void* work, hipStream_t s) {
   const bool f32 = a.precision != MLBLUP_FP64;
   LaunchFn fn = f32 ? pick_nu<true>(a.nu2, a.outputs, a.d) : pick_nu<false>(a.nu2, a.outputs, a.d);
   if (!fn) return fail(MLBLUP_EINVAL, "symmetric pair kernel: dimension not compiled");
-  const int rl = f32 ? rows_per_lane_lp(a.d) : rows_per_lane(a.d);
+  const int dp = padded_dim(a.d);
+  const int rl = f32 ? rows_per_lane_lp(dp) : rows_per_lane(dp);
   return sym_schedule(
       a, 256 * rl, work, s,
       [&](int T, int r0, int nr, int diag, double* prow, double* pcol, double* pdrow, double* pdcol) {
-        fn(a.cols, a.x, a.n, T, r0, nr, diag, zs, prow, pcol, pdrow, pdcol, a.gtab, s);
+        fn(a.cols, a.d, a.x, a.n, T, r0, nr, diag, zs, prow, pcol, pdrow, pdcol, a.gtab, s);
       },
       false, diag_split(rl));
 }

@@ -120,11 +120,14 @@ def test_full_size_sampled_rows(k):
     assert row_relerr(host(yt)[it], tref, tsc) < FP64_TOL
 
 
-@pytest.mark.parametrize("n,d", [(16384, 3), (16385, 5), (16897, 3), (17408, 5), (16385, 10), (16896, 20)])
+@pytest.mark.parametrize("n,d", [(16384, 3), (16385, 5), (16897, 3), (17408, 5), (16385, 10), (16896, 20),
+                                 (16385, 7), (16896, 25)])
 def test_symmetric_square_product(n, d):
     """Square products (rows and cols the same array, n >= 16,384) take the
-    symmetric path; ragged last block, odd and even numbers of blocks.  The
-    oracle checks 96 sampled rows (full rows of the product)."""
+    symmetric path; ragged last block, odd and even numbers of blocks; d = 7
+    and 25 run in the kernels compiled for 8 and 28 with zero-padded
+    coordinates.  The oracle checks 96 sampled rows (full rows of the
+    product)."""
     torch = require_gpu()
     from paper_1701_00285_amd import DLOGRHO, FP32, FP64, VALUE, cov_matvec
     pts = synth.uniform_cloud(n, d, 40 + n)
@@ -149,7 +152,7 @@ def test_symmetric_square_product(n, d):
             assert row_relerr(host(yr), host(y1), host(full_scale)) < 2 * tol
 
 
-@pytest.mark.parametrize("d", [8, 12, 20])
+@pytest.mark.parametrize("d", [8, 12, 20, 25])
 def test_symmetric_expanded_distance_near_pairs(d):
     """From d = 8 on the FP64 square product forms squared distances as
     |a|^2 + |b|^2 - 2 a.b relative to each row block's first point and
