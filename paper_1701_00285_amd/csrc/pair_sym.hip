@@ -279,9 +279,11 @@ __global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ p
   constexpr int RL = rows_per_lane_lp(D);
   constexpr int kBlk = 256 * RL;
   constexpr int kSeg = 16;  // columns per FP32 row-sum segment
-  __shared__ __align__(16) float cp[kChunk * SP];
-  __shared__ double cred[4][kChunk];
-  __shared__ double cdred[4][kChunk];
+  // column chunk: each group of 64 columns twice over (slots s and s + 64 hold column s)
+  __shared__ __align__(16) float cp[2 * kChunk * SP];
+  // column partials per (wave, column group, segment of kSeg steps, column), FP32 within a segment
+  __shared__ float cseg[4][kChunk / 64][64 / kSeg][64];
+  __shared__ float cdseg[(OUT & 2) ? 4 : 1][kChunk / 64][64 / kSeg][64];
   // diagonal launches: row block blockIdx.x, column range blockIdx.y; others: tile_of
   int S = blockIdx.x, yy = blockIdx.y;
   if (!diag) tile_of(T, (int)gridDim.y, S, yy);
@@ -315,25 +317,35 @@ __global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ p
     for (int e = tid; e < kChunk * D; e += kT) {
       const int j = e / D, k = e - j * D;
       const int64_t gj = cbase + c0 + j;
-      cp[j * SP + k] = gj < n && k < dd ? (float)((pts[gj * dd + k] - pts[o * dd + k]) * ws) : 0.0f;
+      const float v = gj < n && k < dd ? (float)((pts[gj * dd + k] - pts[o * dd + k]) * ws) : 0.0f;
+      const int sl = (j >> 6) * 128 + (j & 63);
+      cp[sl * SP + k] = v;
+      cp[(sl + 64) * SP + k] = v;
     }
     for (int j = tid; j < kChunk; j += kT) {
       const int64_t gj = cbase + c0 + j;
-      cp[j * SP + D] = gj < n ? (float)x[gj] : 0.0f;
+      const float v = gj < n ? (float)x[gj] : 0.0f;
+      const int sl = (j >> 6) * 128 + (j & 63);
+      cp[sl * SP + D] = v;
+      cp[(sl + 64) * SP + D] = v;
     }
     __syncthreads();
 #pragma unroll 1
     for (int sub = 0; sub < kChunk; sub += 64) {
-      double cacc = 0.0, cdacc = 0.0;
-      int c = lane;
+      // step k visits column (lane + k delta) mod 64 of the group: slot lane + k (delta = 1) or
+      // lane + 64 - k (delta = -1 mod 64)
+      const int ds = delta == 1 ? 1 : -1;
+      int sl = 2 * sub + lane + (delta == 1 ? 0 : 64);
 #pragma unroll 1
       for (int seg = 0; seg < 64; seg += kSeg) {
         float rs[RL], rds[RL];
 #pragma unroll
         for (int q = 0; q < RL; ++q) rs[q] = rds[q] = 0.0f;
+        // the column sums travel with their columns in FP32 for one segment
+        float cacc = 0.0f, cdacc = 0.0f;
 #pragma unroll 4
-        for (int k = 0; k < kSeg; ++k) {
-          const float* cj = &cp[(sub + c) * SP];
+        for (int k = 0; k < kSeg; ++k, sl += ds) {
+          const float* cj = &cp[sl * SP];
           float cv[D];
 #pragma unroll
           for (int t = 0; t < D; ++t) cv[t] = cj[t];
@@ -358,26 +370,39 @@ __global__ __launch_bounds__(kT) void sym_kernel_lp(const double* __restrict__ p
               cdpart = fmaf(g, ar[q], cdpart);
             }
           }
-          if constexpr (OUT & 1) cacc = wave_rotate1(cacc + (double)cpart);
-          if constexpr (OUT & 2) cdacc = wave_rotate1(cdacc + (double)cdpart);
-          c = (c + delta) & 63;
+          if constexpr (OUT & 1) cacc = wave_rotate1_f(cacc + cpart);
+          if constexpr (OUT & 2) cdacc = wave_rotate1_f(cdacc + cdpart);
         }
 #pragma unroll
         for (int q = 0; q < RL; ++q) {
           if constexpr (OUT & 1) racc[q] += (double)rs[q];
           if constexpr (OUT & 2) rdacc[q] += (double)rds[q];
         }
+        // after seg + kSeg steps this lane holds the segment's sum of column lane + (seg + kSeg) delta
+        const int col = (lane + (seg + kSeg) * delta) & 63;
+        if constexpr (OUT & 1) cseg[wave][sub >> 6][seg / kSeg][col] = cacc;
+        if constexpr (OUT & 2) cdseg[wave][sub >> 6][seg / kSeg][col] = cdacc;
       }
-      if constexpr (OUT & 1) cred[wave][sub + lane] = cacc;
-      if constexpr (OUT & 2) cdred[wave][sub + lane] = cdacc;
     }
     __syncthreads();
     if (!diag && tid < kChunk) {
       const int64_t gj = cbase + c0 + tid;
       if (gj < n) {
         const int64_t slot = (int64_t)yy * n + gj;
-        if constexpr (OUT & 1) pcol[slot] = ((cred[0][tid] + cred[1][tid]) + cred[2][tid]) + cred[3][tid];
-        if constexpr (OUT & 2) pdcol[slot] = ((cdred[0][tid] + cdred[1][tid]) + cdred[2][tid]) + cdred[3][tid];
+        const int g = tid >> 6, cc = tid & 63;
+        // per wave the segments in order, then the waves in order (FP64)
+        auto colsum = [&](const float* a) {
+          double v[4];
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            v[w] = 0.0;
+#pragma unroll
+            for (int q = 0; q < 64 / kSeg; ++q) v[w] += (double)a[((w * (kChunk / 64) + g) * (64 / kSeg) + q) * 64 + cc];
+          }
+          return ((v[0] + v[1]) + v[2]) + v[3];
+        };
+        if constexpr (OUT & 1) pcol[slot] = colsum(&cseg[0][0][0][0]);
+        if constexpr (OUT & 2) pdcol[slot] = colsum(&cdseg[0][0][0][0]);
       }
     }
   }

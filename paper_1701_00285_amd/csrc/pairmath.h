@@ -268,6 +268,9 @@ __device__ __forceinline__ double wave_rotate1(double v) {
   const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x134, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ float wave_rotate1_f(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xF, 0xF, false));
+}
 __device__ __forceinline__ int wave_rotate1_i(int v) {
   return __builtin_amdgcn_mov_dpp(v, 0x134, 0xF, 0xF, false);
 }
