@@ -31,7 +31,8 @@ int prec_cross(const CrossTask* tasks, int32_t ntasks, int NR, const double* pts
 int prec_apply_blocks(const int64_t* w_off, const int32_t* mw, const int64_t* boff, int32_t cnt, const double* Binv,
                       const double* r, double* z, hipStream_t s);
 int prec_apply_diag(const double* inv, const double* r, double* z, int64_t n, hipStream_t s);
-int prec_gemv_rows(const float* M, int64_t n, int64_t ld, const double* x, double* out, hipStream_t s);
+// tri: 0 full, 1 lower triangular, 2 upper triangular (the other triangle holds exact zeros, not read)
+int prec_gemv_rows(const float* M, int64_t n, int64_t ld, const double* x, double* out, hipStream_t s, int tri = 0);
 
 // Host-side preconditioner object.
 struct Precond {

@@ -197,15 +197,22 @@ __global__ __launch_bounds__(kT) void apply_diag(const double* __restrict__ inv,
 // out[i] = sum_j M[i][j] x[j] for an n x n row-major M stored in FP32 with
 // rows of ld floats (ld a multiple of 4, zero padding): one wave per row,
 // 16-byte loads of four entries per lane, products and sums in FP64, a
-// fixed-order reduction across the wave; x has n entries
+// fixed-order reduction across the wave; x has n entries.  tri = 1: M is
+// lower triangular, tri = 2: upper triangular; the groups of four wholly
+// in the zero triangle are not read (a lane's sum only skips exact zeros,
+// so the result is the same as with tri = 0)
 __global__ __launch_bounds__(kT) void gemv_rows(const float* __restrict__ M, int64_t n, int64_t ld,
-                                               const double* __restrict__ x, double* __restrict__ out) {
+                                               const double* __restrict__ x, double* __restrict__ out, int tri) {
   const int64_t i = (int64_t)blockIdx.x * (kT / 64) + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (i >= n) return;
   const float4* row = (const float4*)(M + i * ld);
+  // groups [glo, ghi) hold the row's nonzeros
+  const int64_t glo = tri == 2 ? i / 4 : 0, ghi = tri == 1 ? i / 4 + 1 : ld / 4;
   double acc = 0.0;
-  for (int64_t c = lane; c < ld / 4; c += 64) {
+  int64_t c0 = lane;
+  if (glo > lane) c0 += (glo - lane + 63) / 64 * 64;
+  for (int64_t c = c0; c < ghi; c += 64) {
     const float4 v = row[c];
     const int64_t j = 4 * c;
     if (j + 3 < n) {
@@ -271,11 +278,12 @@ int prec_apply_blocks(const int64_t* w_off, const int32_t* mw, const int64_t* bo
   return hip_check(hipGetLastError(), "apply_blocks launch");
 }
 
-int prec_gemv_rows(const float* M, int64_t n, int64_t ld, const double* x, double* out, hipStream_t s) {
+int prec_gemv_rows(const float* M, int64_t n, int64_t ld, const double* x, double* out, hipStream_t s, int tri) {
   if (n <= 0) return MLBLUP_OK;
   if (ld < n || ld % 4) return fail(MLBLUP_EINVAL, "gemv_rows: row stride must be >= n and a multiple of 4");
+  if (tri < 0 || tri > 2) return fail(MLBLUP_EINVAL, "gemv_rows: tri must be 0, 1 or 2");
   const int64_t g = (n + kT / 64 - 1) / (kT / 64);
-  hipLaunchKernelGGL(gemv_rows, dim3((unsigned)g), dim3(kT), 0, s, M, n, ld, x, out);
+  hipLaunchKernelGGL(gemv_rows, dim3((unsigned)g), dim3(kT), 0, s, M, n, ld, x, out, tri);
   return hip_check(hipGetLastError(), "gemv_rows launch");
 }
 

@@ -400,10 +400,12 @@ int precond_apply(const Precond& P, const double* r, double* z, hipStream_t s) {
   if (P.kind == MLBLUP_PREC_JACOBI) return prec_apply_diag((const double*)(base + P.off_inv), r, z, P.nw, s);
   if (P.kind == MLBLUP_PREC_COARSE) {
     // z[0:nc] = X r_c as scratch (c0 >= nc), then z_c = Y (X r_c); the cell
-    // blocks then overwrite z[0:c0]
-    int st = prec_gemv_rows((const float*)(base + P.off_x), P.nc, P.ldc, r + P.c0, z, s);
+    // blocks then overwrite z[0:c0].  X = G^-1 is lower and Y = G^-T upper
+    // triangular (the forward substitution of the identity leaves exact zeros
+    // above G^-1's diagonal), so each product reads one triangle.
+    int st = prec_gemv_rows((const float*)(base + P.off_x), P.nc, P.ldc, r + P.c0, z, s, 1);
     if (st) return st;
-    if ((st = prec_gemv_rows((const float*)(base + P.off_y), P.nc, P.ldc, z, z + P.c0, s))) return st;
+    if ((st = prec_gemv_rows((const float*)(base + P.off_y), P.nc, P.ldc, z, z + P.c0, s, 2))) return st;
   }
   return prec_apply_blocks((const int64_t*)(base + P.off_woff), (const int32_t*)(base + P.off_mw),
                            (const int64_t*)(base + P.off_boff), (int32_t)P.node.size(),
